@@ -1,0 +1,164 @@
+/* pic.h -- C ABI of the MI355X (gfx950) library for the per-step
+ * macro-particle operators of an electromagnetic particle-in-cell loop:
+ * field Interpolation, Push, pre-boundary-condition operations (pre-BC) and
+ * current Projection (arXiv 2204.12837, section "Parallelization without
+ * tasks": the four operators applied per patch and species, followed by a
+ * synchronisation phase that applies particle boundary conditions and sorts
+ * the particles).  The paper names the operators and the order-2 shape; the
+ * formulas are those of the published methods it relies on: quadratic
+ * B-spline shapes on Yee's staggered grid, Boris's relativistic push and
+ * Esirkepov's charge-conserving current deposit.
+ *
+ * Conventions shared by every entry point
+ *   Units     normalised: c = 1, charge in e, mass in m_e, u = p/(m c).
+ *   Grid      periodic, n[a] cells of size d[a] per axis; each field
+ *             component is a device array of prod(n) float64 values, x
+ *             fastest, entry (i,j,k) at ((i+sx/2)d_x, (j+sy/2)d_y,
+ *             (k+sz/2)d_z) with stagger bits Ex(1,0,0) Ey(0,1,0) Ez(0,0,1)
+ *             Bx(0,1,1) By(1,0,1) Bz(1,1,0) (J as E); in 2D (2D3V) the z
+ *             bit and the z axis are dropped.
+ *   Patches   the grid is split into patches of patch[a] cells (paper,
+ *             section "Parallelization without tasks"); patch id
+ *             Px + NPx (Py + NPy Pz); particles are stored sorted by patch:
+ *             patch P owns entries [offset[P], offset[P+1]) of every particle
+ *             array.  Inside a patch the order is that of the previous step
+ *             (the sort is stable).
+ *   Particles structure of arrays per species, float64 x/u/w and int64 id,
+ *             all on the context's device, each of `capacity` elements.
+ *   Memory    the caller owns every particle, field and offset array and
+ *             never hands ownership to the library; the context owns its
+ *             scratch (keys, counts, saved positions, error word).
+ *   Streams   work is enqueued on the given HIP stream (NULL = the null
+ *             stream) and returns without waiting, except where stated.
+ *   Errors    host-detectable errors (bad config, null pointer, count above
+ *             capacity, wrong call order) return at once with nothing
+ *             enqueued.  Errors found by kernels (a particle moving more than
+ *             one cell, a position outside the box) set a sticky error word
+ *             in the context; pic_check (or any call when PIC_FLAG_CHECK is
+ *             set) waits for the stream and reports it.  After a device
+ *             error the context refuses further work until pic_free.
+ *             Nothing throws or aborts across the ABI.  One context per host
+ *             thread.
+ */
+#ifndef PIC_H
+#define PIC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pic_ctx pic_ctx;
+
+typedef enum {
+  PIC_OK = 0,
+  PIC_ERR_ARG = 1,      /* invalid argument or configuration */
+  PIC_ERR_HIP = 2,      /* a HIP runtime call failed */
+  PIC_ERR_CAPACITY = 3, /* n above capacity, or too many patches/species */
+  PIC_ERR_CFL = 4,      /* a particle moved more than one cell in a step */
+  PIC_ERR_POS = 5,      /* a position more than one period outside the box */
+  PIC_ERR_STATE = 6     /* wrong call order, or context poisoned by an error */
+} pic_status;
+
+enum { PIC_MODE_PER_PATCH = 0, PIC_MODE_PERSISTENT = 1 };
+
+enum {
+  PIC_FLAG_CHECK = 1 /* every call waits for its stream and reports device errors */
+};
+
+typedef struct {
+  int32_t dim;         /* 2 = 2D3V, 3 = 3D3V */
+  int32_t n[3];        /* cells per axis; n[2] = 1 in 2D */
+  double d[3];         /* cell sizes (d[2] ignored in 2D) */
+  double dt;           /* time step; must satisfy dt < 1/sqrt(sum 1/d^2) */
+  int32_t patch[3];    /* patch size in cells: divides n, >= 6 (three-point
+                          stencil plus ghosts); patch[2] = 1 in 2D */
+  int32_t shape_order; /* interpolation/projection order: must be 2 */
+  int32_t mode;        /* PIC_MODE_PER_PATCH: one workgroup per patch and
+                          species; PIC_MODE_PERSISTENT: a fixed grid pulls
+                          (patch, species, chunk) units from a device queue */
+  int32_t chunk;       /* persistent mode: particles per unit (0 = auto) */
+  int32_t wg_size;     /* threads per workgroup: 64, 128, 192 or 256 (0 = auto) */
+  uint32_t flags;      /* PIC_FLAG_* */
+} pic_config;
+
+typedef struct {
+  double q, m;         /* charge, mass */
+  int64_t n;           /* particles in the arrays */
+  int64_t capacity;    /* length of every particle array */
+  double *x[3];        /* positions (x[2] = NULL in 2D) */
+  double *u[3];        /* momenta u^{n-1/2} */
+  double *w;           /* weights (density carried by one macro-particle) */
+  int64_t *id;         /* particle ids (carried along, never read) */
+  double *x_alt[3];    /* second buffer set: target of the sort; */
+  double *u_alt[3];    /*   pic_bin and pic_step swap it with the */
+  double *w_alt;       /*   first set in this struct after sorting */
+  int64_t *id_alt;
+  int64_t *offset;     /* [n_patches + 1] patch offsets, written by the sort */
+} pic_species;
+
+typedef struct {
+  const double *e[3];  /* Ex, Ey, Ez */
+  const double *b[3];  /* Bx, By, Bz */
+  double *j[3];        /* Jx, Jy, Jz (accumulated into) */
+} pic_fields;
+
+/* Check a configuration without touching a device.  Pure host code.
+ * Writes a reason into msg (if msg != NULL, at most len bytes with the NUL).
+ * Returns PIC_OK or PIC_ERR_ARG. */
+pic_status pic_validate_config(const pic_config *cfg, char *msg, size_t len);
+
+/* Number of patches of a valid configuration (0 if invalid).  Pure host. */
+int64_t pic_num_patches(const pic_config *cfg);
+
+/* Create a context on HIP device `device`: validates cfg, allocates the
+ * context's scratch.  *out is NULL on failure. */
+pic_status pic_init(const pic_config *cfg, int32_t device, pic_ctx **out);
+
+/* Release a context and its scratch (waits for the device).  NULL is a no-op. */
+void pic_free(pic_ctx *ctx);
+
+/* Synchronisation-phase sort (paper, section "Parallelization without
+ * tasks": boundary conditions are applied and particles sorted after the
+ * operators).  For each species: periodic wrap of every position, patch
+ * key, stable counting sort by patch into the *_alt arrays, offset[]
+ * written, then the two buffer sets are swapped in *sp.  Accepts particles
+ * in any order and anywhere within one period of the box. */
+pic_status pic_bin(pic_ctx *ctx, pic_species *sp, int32_t nsp, void *stream);
+
+/* Interpolation + Push (paper: the first two operators).  Particles must be
+ * sorted by patch (offset[] valid, e.g. after pic_bin).  Gathers E and B at
+ * each position with the quadratic shape, advances u by the relativistic
+ * Boris push and x by dt*v.  Positions are left unwrapped (the boundary
+ * condition belongs to the sort); the start-of-step positions are kept in
+ * the context for pic_project.  J is not touched. */
+pic_status pic_interp_push(pic_ctx *ctx, pic_species *sp, int32_t nsp, const pic_fields *f,
+                           void *stream);
+
+/* Projection (paper: the fourth operator): J += Esirkepov deposit of every
+ * particle's move from the positions saved by the preceding pic_interp_push
+ * on this context to the current (unwrapped) positions.  Does not zero J.
+ * PIC_ERR_STATE without a preceding pic_interp_push. */
+pic_status pic_project(pic_ctx *ctx, const pic_species *sp, int32_t nsp, pic_fields *f,
+                       void *stream);
+
+/* nsteps whole steps: J <- 0, then the fused Interpolation, Push, pre-BC
+ * and Projection of every species (J accumulated in on-chip tiles per patch
+ * and added to the grid), then the sort.  Equals the sequence {zero J;
+ * pic_interp_push; pic_project; pic_bin} per step.  J holds the last
+ * step's current.  Particles must be sorted (offset[] valid). */
+pic_status pic_step(pic_ctx *ctx, pic_species *sp, int32_t nsp, pic_fields *f, int32_t nsteps,
+                    void *stream);
+
+/* Wait for `stream` and report the sticky device error word. */
+pic_status pic_check(pic_ctx *ctx, void *stream);
+
+/* Text of the last error on this context ("" if none). */
+const char *pic_last_error(const pic_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PIC_H */

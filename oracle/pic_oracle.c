@@ -429,6 +429,12 @@ int orc_step(const orc_grid *gi, orc_species *sp, int32_t nsp, const double *con
   G g;
   mk_grid(gi, &g);
   const int dim = g.dim;
+  /* the particles must be sorted by patch: offsets cover [0, n) in order */
+  for (int s = 0; s < nsp; s++) {
+    if (sp[s].off[0] != 0 || sp[s].off[g.npatch] != sp[s].n) return ORC_ERR_ARG;
+    for (int64_t P = 0; P < g.npatch; P++)
+      if (sp[s].off[P + 1] < sp[s].off[P]) return ORC_ERR_ARG;
+  }
   real *Er[3], *Br[3], *Jr[3], *Ar[3];
   for (int c = 0; c < 3; c++) {
     Er[c] = to_real(E[c], g.ncell);

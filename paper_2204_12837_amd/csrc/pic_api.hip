@@ -1,0 +1,470 @@
+// C ABI of the library (declared in include/pic.h): configuration checks,
+// context lifetime, scratch management and the launch sequences of the
+// entry points.  All arithmetic on particles and fields happens in the
+// kernels; this file only validates, sizes and enqueues.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+
+#include "pic.h"
+#include "pic_common.h"
+
+using namespace pic;
+
+namespace {
+
+struct SpScratch {
+  int64_t cap = 0;      // particle capacity the buffers below were sized for
+  uint32_t *tag = nullptr;
+  int32_t *cnt = nullptr;
+  int64_t *rbase = nullptr, *in = nullptr, *noff = nullptr;
+  int64_t x0cap = 0;
+  double *x0[3] = {nullptr, nullptr, nullptr};
+};
+
+constexpr size_t kStaticLds = 2 * 4 * 27 * 4 + 27 * 4 + 64;  // ranking scratch + slack
+
+}  // namespace
+
+struct pic_ctx {
+  pic_config cfg;
+  GridDev g;
+  int device = 0;
+  int wg = 256;
+  int *err_dev = nullptr;
+  bool poisoned = false;
+  bool moved = false;   // pic_interp_push ran since the last sort
+  int moved_nsp = 0;
+  char msg[512] = {0};
+  SpScratch sp[kMaxSpecies];
+  SortScratch sort[kMaxSpecies];
+};
+
+namespace {
+
+void set_msg(char *buf, size_t len, const char *fmt, ...) {
+  if (!buf || !len) return;
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, len, fmt, ap);
+  va_end(ap);
+}
+
+pic_status fail(pic_ctx *c, pic_status st, const char *fmt, ...) {
+  if (c) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(c->msg, sizeof(c->msg), fmt, ap);
+    va_end(ap);
+  }
+  return st;
+}
+
+pic_status hip_fail(pic_ctx *c, hipError_t e, const char *what) {
+  return fail(c, PIC_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+int axes(const pic_config *c) { return c->dim == 3 ? 3 : 2; }
+
+// Derived geometry; cfg must be valid.
+GridDev make_grid(const pic_config *c) {
+  GridDev g{};
+  g.dim = c->dim;
+  g.npatch = 1;
+  g.nc = c->dim == 3 ? 27 : 9;
+  for (int a = 0; a < 3; a++) {
+    const bool on = a < c->dim;
+    g.n[a] = on ? c->n[a] : 1;
+    g.patch[a] = on ? c->patch[a] : 1;
+    g.np[a] = g.n[a] / g.patch[a];
+    g.npatch *= g.np[a];
+    const double d = on ? c->d[a] : 1.0;
+    g.inv_d[a] = 1.0 / d;
+    g.L[a] = (double)g.n[a] * d;
+    g.d_over_dt[a] = d / c->dt;
+  }
+  g.dt = c->dt;
+  return g;
+}
+
+size_t tiles_bytes(const pic_config *c) {
+  size_t te = 1, tj = 1;
+  for (int a = 0; a < axes(c); a++) {
+    te *= (size_t)(c->patch[a] + 3);
+    tj *= (size_t)(c->patch[a] + 5);
+  }
+  return (6 * te + 3 * tj) * sizeof(double);
+}
+
+pic_status check_species(pic_ctx *c, const pic_species *sp, int32_t nsp, bool need_sorted) {
+  (void)need_sorted;
+  if (!c) return PIC_ERR_ARG;
+  if (c->poisoned) return fail(c, PIC_ERR_STATE, "context unusable after a device error");
+  if (!sp || nsp < 1) return fail(c, PIC_ERR_ARG, "no species");
+  if (nsp > kMaxSpecies) return fail(c, PIC_ERR_CAPACITY, "at most %d species", kMaxSpecies);
+  for (int s = 0; s < nsp; s++) {
+    const pic_species &p = sp[s];
+    if (p.n < 0 || p.capacity < 0) return fail(c, PIC_ERR_ARG, "species %d: negative size", s);
+    if (p.n > p.capacity)
+      return fail(c, PIC_ERR_CAPACITY, "species %d: n=%lld above capacity=%lld", s,
+                  (long long)p.n, (long long)p.capacity);
+    if (p.n >= (int64_t)1 << 31)
+      return fail(c, PIC_ERR_CAPACITY, "species %d: n must stay below 2^31", s);
+    if (!(p.m > 0) || !std::isfinite(p.m) || !std::isfinite(p.q))
+      return fail(c, PIC_ERR_ARG, "species %d: bad charge or mass", s);
+    for (int a = 0; a < c->cfg.dim; a++)
+      if (!p.x[a] || !p.x_alt[a]) return fail(c, PIC_ERR_ARG, "species %d: null position", s);
+    for (int a = 0; a < 3; a++)
+      if (!p.u[a] || !p.u_alt[a]) return fail(c, PIC_ERR_ARG, "species %d: null momentum", s);
+    if (!p.w || !p.w_alt || !p.id || !p.id_alt || !p.offset)
+      return fail(c, PIC_ERR_ARG, "species %d: null weight/id/offset array", s);
+  }
+  return PIC_OK;
+}
+
+template <typename T>
+hipError_t realloc_dev(T *&p, size_t n) {
+  if (p) {
+    hipError_t e = hipFree(p);
+    if (e != hipSuccess) return e;
+    p = nullptr;
+  }
+  return hipMalloc(&p, std::max<size_t>(n, 1) * sizeof(T));
+}
+
+// Per-species scratch for the sort (and, if x0, the saved positions).
+pic_status ensure_scratch(pic_ctx *c, const pic_species *sp, int32_t nsp, bool x0,
+                          hipStream_t st) {
+  bool synced = false;
+  for (int s = 0; s < nsp; s++) {
+    SpScratch &S = c->sp[s];
+    const int64_t cap = sp[s].capacity;
+    const bool need_tag = cap > S.cap || !S.tag;
+    const bool need_x0 = x0 && (cap > S.x0cap || !S.x0[0]);
+    if ((need_tag || need_x0) && !synced) {
+      hipError_t e = hipStreamSynchronize(st);
+      if (e != hipSuccess) return hip_fail(c, e, "hipStreamSynchronize");
+      synced = true;
+    }
+    if (need_tag) {
+      hipError_t e;
+      const size_t np = (size_t)c->g.npatch, nc = (size_t)c->g.nc;
+      if ((e = realloc_dev(S.tag, (size_t)cap)) != hipSuccess) return hip_fail(c, e, "hipMalloc");
+      if (!S.cnt) {
+        if ((e = realloc_dev(S.cnt, np * nc)) != hipSuccess) return hip_fail(c, e, "hipMalloc");
+        if ((e = realloc_dev(S.rbase, np * nc)) != hipSuccess) return hip_fail(c, e, "hipMalloc");
+        if ((e = realloc_dev(S.in, np)) != hipSuccess) return hip_fail(c, e, "hipMalloc");
+        if ((e = realloc_dev(S.noff, np + 1)) != hipSuccess) return hip_fail(c, e, "hipMalloc");
+      }
+      S.cap = cap;
+    }
+    if (need_x0) {
+      for (int a = 0; a < c->cfg.dim; a++) {
+        hipError_t e = realloc_dev(S.x0[a], (size_t)cap);
+        if (e != hipSuccess) return hip_fail(c, e, "hipMalloc");
+      }
+      S.x0cap = cap;
+    }
+  }
+  return PIC_OK;
+}
+
+SpArgs make_args(pic_ctx *c, const pic_species *sp, int32_t nsp) {
+  SpArgs a{};
+  a.nsp = nsp;
+  for (int s = 0; s < nsp; s++) {
+    const pic_species &p = sp[s];
+    SpDev &d = a.s[s];
+    d.alpha = (p.q / p.m) * (0.5 * c->cfg.dt);
+    d.q = p.q;
+    d.n = p.n;
+    for (int k = 0; k < 3; k++) {
+      d.x[k] = k < c->cfg.dim ? p.x[k] : nullptr;
+      d.xa[k] = k < c->cfg.dim ? p.x_alt[k] : nullptr;
+      d.u[k] = p.u[k];
+      d.ua[k] = p.u_alt[k];
+      d.x0[k] = c->sp[s].x0[k];
+    }
+    d.w = p.w;
+    d.wa = p.w_alt;
+    d.id = p.id;
+    d.ida = p.id_alt;
+    d.off = p.offset;
+    d.noff = c->sp[s].noff;
+    d.tag = c->sp[s].tag;
+    d.cnt = c->sp[s].cnt;
+    d.rbase = c->sp[s].rbase;
+    d.in = c->sp[s].in;
+  }
+  return a;
+}
+
+void swap_buffers(pic_species &p) {
+  for (int k = 0; k < 3; k++) {
+    std::swap(p.x[k], p.x_alt[k]);
+    std::swap(p.u[k], p.u_alt[k]);
+  }
+  std::swap(p.w, p.w_alt);
+  std::swap(p.id, p.id_alt);
+}
+
+pic_status finish(pic_ctx *c, hipStream_t st) {
+  if (c->cfg.flags & PIC_FLAG_CHECK) return pic_check(c, st);
+  return PIC_OK;
+}
+
+bool fields_ok(const pic_ctx *c, const pic_fields *f, bool eb, bool j) {
+  if (!f) return false;
+  for (int k = 0; k < 3; k++) {
+    if (eb && (!f->e[k] || !f->b[k])) return false;
+    if (j && !f->j[k]) return false;
+  }
+  (void)c;
+  return true;
+}
+
+}  // namespace
+
+extern "C" {
+
+pic_status pic_validate_config(const pic_config *c, char *msg, size_t len) {
+  if (msg && len) msg[0] = 0;
+  if (!c) {
+    set_msg(msg, len, "null config");
+    return PIC_ERR_ARG;
+  }
+  if (c->dim != 2 && c->dim != 3) {
+    set_msg(msg, len, "dim must be 2 or 3 (got %d)", c->dim);
+    return PIC_ERR_ARG;
+  }
+  if (c->shape_order != 2) {
+    set_msg(msg, len, "shape_order must be 2 (quadratic shapes), got %d", c->shape_order);
+    return PIC_ERR_ARG;
+  }
+  long long npatch = 1;
+  double inv2 = 0.0;
+  for (int a = 0; a < c->dim; a++) {
+    if (c->n[a] < 1 || c->n[a] > (1 << 30)) {
+      set_msg(msg, len, "n[%d]=%d out of range", a, c->n[a]);
+      return PIC_ERR_ARG;
+    }
+    if (c->patch[a] < 6) {
+      set_msg(msg, len, "patch[%d]=%d below 6 cells (three-point stencil plus ghosts)", a,
+              c->patch[a]);
+      return PIC_ERR_ARG;
+    }
+    if (c->n[a] % c->patch[a]) {
+      set_msg(msg, len, "patch[%d]=%d does not divide n[%d]=%d", a, c->patch[a], a, c->n[a]);
+      return PIC_ERR_ARG;
+    }
+    if (!(c->d[a] > 0) || !std::isfinite(c->d[a])) {
+      set_msg(msg, len, "d[%d] must be positive and finite", a);
+      return PIC_ERR_ARG;
+    }
+    npatch *= c->n[a] / c->patch[a];
+    inv2 += 1.0 / (c->d[a] * c->d[a]);
+  }
+  if (c->dim == 2 && ((c->n[2] != 1 && c->n[2] != 0) || (c->patch[2] != 1 && c->patch[2] != 0))) {
+    set_msg(msg, len, "2D configuration needs n[2] = patch[2] = 1");
+    return PIC_ERR_ARG;
+  }
+  if (npatch > (1ll << 30)) {
+    set_msg(msg, len, "too many patches (%lld)", npatch);
+    return PIC_ERR_ARG;
+  }
+  long long ncell = 1;
+  for (int a = 0; a < c->dim; a++) ncell *= c->n[a];
+  if (ncell > (1ll << 40)) {
+    set_msg(msg, len, "grid too large");
+    return PIC_ERR_ARG;
+  }
+  const double cfl = 1.0 / std::sqrt(inv2);
+  if (!(c->dt > 0) || !std::isfinite(c->dt) || c->dt > cfl) {
+    set_msg(msg, len, "dt=%.17g must be in (0, %.17g] (Courant limit)", c->dt, cfl);
+    return PIC_ERR_ARG;
+  }
+  if (c->mode != PIC_MODE_PER_PATCH && c->mode != PIC_MODE_PERSISTENT) {
+    set_msg(msg, len, "unknown mode %d", c->mode);
+    return PIC_ERR_ARG;
+  }
+  if (c->chunk < 0) {
+    set_msg(msg, len, "chunk must be >= 0");
+    return PIC_ERR_ARG;
+  }
+  if (c->wg_size != 0 && (c->wg_size < 64 || c->wg_size > 256 || c->wg_size % 64)) {
+    set_msg(msg, len, "wg_size must be 0 or a multiple of 64 in [64, 256]");
+    return PIC_ERR_ARG;
+  }
+  if (c->flags & ~(uint32_t)PIC_FLAG_CHECK) {
+    set_msg(msg, len, "unknown flag bits 0x%x", c->flags);
+    return PIC_ERR_ARG;
+  }
+  const size_t lds = tiles_bytes(c) + kStaticLds;
+  if (lds > 160 * 1024) {
+    set_msg(msg, len, "patch too large: E/B and J tiles need %zu bytes of LDS (max 163840)", lds);
+    return PIC_ERR_ARG;
+  }
+  return PIC_OK;
+}
+
+int64_t pic_num_patches(const pic_config *c) {
+  if (pic_validate_config(c, nullptr, 0) != PIC_OK) return 0;
+  int64_t n = 1;
+  for (int a = 0; a < c->dim; a++) n *= c->n[a] / c->patch[a];
+  return n;
+}
+
+pic_status pic_init(const pic_config *cfg, int32_t device, pic_ctx **out) {
+  if (!out) return PIC_ERR_ARG;
+  *out = nullptr;
+  char m[256];
+  if (pic_validate_config(cfg, m, sizeof m) != PIC_OK) return PIC_ERR_ARG;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return PIC_ERR_HIP;
+  if (hipSetDevice(device) != hipSuccess) return PIC_ERR_HIP;
+  pic_ctx *c = new pic_ctx();
+  c->cfg = *cfg;
+  if (c->cfg.dim == 2) {
+    c->cfg.n[2] = 1;
+    c->cfg.patch[2] = 1;
+    c->cfg.d[2] = 1.0;
+  }
+  c->g = make_grid(&c->cfg);
+  c->device = device;
+  c->wg = cfg->wg_size ? cfg->wg_size : 256;
+  if (hipMalloc(&c->err_dev, sizeof(int)) != hipSuccess ||
+      hipMemset(c->err_dev, 0, sizeof(int)) != hipSuccess) {
+    (void)hipFree(c->err_dev);
+    delete c;
+    return PIC_ERR_HIP;
+  }
+  *out = c;
+  return PIC_OK;
+}
+
+void pic_free(pic_ctx *c) {
+  if (!c) return;
+  (void)hipSetDevice(c->device);
+  (void)hipDeviceSynchronize();
+  for (int s = 0; s < kMaxSpecies; s++) {
+    SpScratch &S = c->sp[s];
+    (void)hipFree(S.tag);
+    (void)hipFree(S.cnt);
+    (void)hipFree(S.rbase);
+    (void)hipFree(S.in);
+    (void)hipFree(S.noff);
+    for (int a = 0; a < 3; a++) (void)hipFree(S.x0[a]);
+    free_sort_scratch(c->sort[s]);
+  }
+  (void)hipFree(c->err_dev);
+  delete c;
+}
+
+pic_status pic_check(pic_ctx *c, void *stream) {
+  if (!c) return PIC_ERR_ARG;
+  hipStream_t st = (hipStream_t)stream;
+  hipError_t e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return hip_fail(c, e, "hipStreamSynchronize");
+  int h = 0;
+  e = hipMemcpy(&h, c->err_dev, sizeof(int), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(c, e, "hipMemcpy");
+  if (h) {
+    c->poisoned = true;
+    if (h & kErrCFL)
+      return fail(c, PIC_ERR_CFL, "a particle moved more than one cell in one step");
+    return fail(c, PIC_ERR_POS,
+                "a particle lies outside its patch or more than one period outside the box");
+  }
+  if (c->poisoned) return PIC_ERR_STATE;
+  return PIC_OK;
+}
+
+const char *pic_last_error(const pic_ctx *c) { return c ? c->msg : "null context"; }
+
+pic_status pic_bin(pic_ctx *c, pic_species *sp, int32_t nsp, void *stream) {
+  pic_status r = check_species(c, sp, nsp, false);
+  if (r != PIC_OK) return r;
+  hipStream_t st = (hipStream_t)stream;
+  if (hipSetDevice(c->device) != hipSuccess) return fail(c, PIC_ERR_HIP, "hipSetDevice");
+  if (c->moved && nsp != c->moved_nsp)
+    return fail(c, PIC_ERR_STATE, "pic_bin after pic_interp_push needs the same species");
+  if (c->moved) {
+    // particles moved at most one cell since the last sort: neighbour-code sort
+    if ((r = ensure_scratch(c, sp, nsp, false, st)) != PIC_OK) return r;
+    const SpArgs a = make_args(c, sp, nsp);
+    hipError_t e = launch_tag(c->g, a, c->err_dev, c->wg, st);
+    if (e == hipSuccess) e = launch_rebin(c->g, a, c->err_dev, c->wg, st);
+    if (e != hipSuccess) return hip_fail(c, e, "kernel launch");
+  } else {
+    for (int s = 0; s < nsp; s++) {
+      const SpArgs a = make_args(c, sp + s, 1);
+      SpDev d = a.s[0];
+      hipError_t e = general_sort(c->g, d, c->sort[s], c->err_dev, st);
+      if (e != hipSuccess) return hip_fail(c, e, "general sort");
+    }
+  }
+  for (int s = 0; s < nsp; s++) swap_buffers(sp[s]);
+  c->moved = false;
+  return finish(c, st);
+}
+
+pic_status pic_interp_push(pic_ctx *c, pic_species *sp, int32_t nsp, const pic_fields *f,
+                           void *stream) {
+  pic_status r = check_species(c, sp, nsp, true);
+  if (r != PIC_OK) return r;
+  if (!fields_ok(c, f, true, false)) return fail(c, PIC_ERR_ARG, "null field pointer");
+  if (c->moved) return fail(c, PIC_ERR_STATE, "pic_interp_push twice without a sort");
+  hipStream_t st = (hipStream_t)stream;
+  if (hipSetDevice(c->device) != hipSuccess) return fail(c, PIC_ERR_HIP, "hipSetDevice");
+  if ((r = ensure_scratch(c, sp, nsp, true, st)) != PIC_OK) return r;
+  const SpArgs a = make_args(c, sp, nsp);
+  hipError_t e = launch_interp_push(c->g, a, f->e, f->b, c->err_dev, c->wg, st);
+  if (e != hipSuccess) return hip_fail(c, e, "kernel launch");
+  c->moved = true;
+  c->moved_nsp = nsp;
+  return finish(c, st);
+}
+
+pic_status pic_project(pic_ctx *c, const pic_species *sp, int32_t nsp, pic_fields *f,
+                       void *stream) {
+  pic_status r = check_species(c, sp, nsp, true);
+  if (r != PIC_OK) return r;
+  if (!fields_ok(c, f, false, true)) return fail(c, PIC_ERR_ARG, "null J pointer");
+  if (!c->moved || nsp != c->moved_nsp)
+    return fail(c, PIC_ERR_STATE, "pic_project needs a preceding pic_interp_push");
+  hipStream_t st = (hipStream_t)stream;
+  if (hipSetDevice(c->device) != hipSuccess) return fail(c, PIC_ERR_HIP, "hipSetDevice");
+  const SpArgs a = make_args(c, sp, nsp);
+  hipError_t e = launch_project(c->g, a, f->j, c->err_dev, c->wg, st);
+  if (e != hipSuccess) return hip_fail(c, e, "kernel launch");
+  return finish(c, st);
+}
+
+pic_status pic_step(pic_ctx *c, pic_species *sp, int32_t nsp, pic_fields *f, int32_t nsteps,
+                    void *stream) {
+  pic_status r = check_species(c, sp, nsp, true);
+  if (r != PIC_OK) return r;
+  if (!fields_ok(c, f, true, true)) return fail(c, PIC_ERR_ARG, "null field pointer");
+  if (nsteps < 0) return fail(c, PIC_ERR_ARG, "nsteps < 0");
+  if (c->moved) return fail(c, PIC_ERR_STATE, "pic_step with a sort pending (call pic_bin)");
+  hipStream_t st = (hipStream_t)stream;
+  if (hipSetDevice(c->device) != hipSuccess) return fail(c, PIC_ERR_HIP, "hipSetDevice");
+  if ((r = ensure_scratch(c, sp, nsp, false, st)) != PIC_OK) return r;
+  int64_t ncell = 1;
+  for (int a = 0; a < c->cfg.dim; a++) ncell *= c->cfg.n[a];
+  for (int k = 0; k < nsteps; k++) {
+    const SpArgs a = make_args(c, sp, nsp);
+    hipError_t e = launch_zero(f->j, ncell, st);
+    if (e == hipSuccess) e = launch_ipp(c->g, a, f->e, f->b, f->j, c->err_dev, c->wg, st);
+    if (e == hipSuccess) e = launch_rebin(c->g, a, c->err_dev, c->wg, st);
+    if (e != hipSuccess) return hip_fail(c, e, "kernel launch");
+    for (int s = 0; s < nsp; s++) swap_buffers(sp[s]);
+  }
+  return finish(c, st);
+}
+
+}  // extern "C"

@@ -1,0 +1,78 @@
+// Internal declarations shared by the host side of the library and its
+// kernels.  Not part of the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pic {
+
+constexpr int kMaxSpecies = 8;
+constexpr int kErrCFL = 1;  // device error bits
+constexpr int kErrPos = 2;
+
+// Grid geometry as the kernels see it.  All derived values (inverse cell
+// sizes, box lengths, Esirkepov factors) are computed once on the host.
+struct GridDev {
+  int dim;
+  int n[3];       // cells per axis (1 for an absent axis)
+  int patch[3];   // patch size per axis (1 for an absent axis)
+  int np[3];      // patches per axis
+  int npatch;     // total patches
+  int nc;         // neighbour codes: 3^dim
+  double inv_d[3];
+  double L[3];    // n * d
+  double dt;
+  double d_over_dt[3];
+};
+
+// One species as the kernels see it (device pointers).
+struct SpDev {
+  double alpha;   // (q/m) * (dt/2)
+  double q;
+  int64_t n;
+  double *x[3], *u[3], *w;
+  int64_t *id;
+  double *xa[3], *ua[3], *wa;  // sort target
+  int64_t *ida;
+  int64_t *off;     // [npatch+1] current patch offsets
+  int64_t *noff;    // [npatch+1] scratch: offsets after the sort
+  uint32_t *tag;    // [capacity] neighbour code << 27 | rank inside (unit, code)
+  int32_t *cnt;     // [units * nc] particles per (unit, code)
+  int64_t *rbase;   // [npatch * nc] start of (patch, code) inside its destination
+  int64_t *in;      // [npatch] particles arriving in each destination patch
+  double *x0[3];    // saved start-of-step positions (split path)
+};
+
+struct SpArgs {
+  int nsp;
+  SpDev s[kMaxSpecies];
+};
+
+// Launch helpers (implemented in pic_kernels.hip).  Each returns the HIP
+// error of its launch.
+hipError_t launch_zero(double *const j[3], int64_t ncell, hipStream_t st);
+hipError_t launch_ipp(const GridDev &g, const SpArgs &sa, const double *const e[3],
+                      const double *const b[3], double *const j[3], int *err, int wg,
+                      hipStream_t st);
+hipError_t launch_interp_push(const GridDev &g, const SpArgs &sa, const double *const e[3],
+                              const double *const b[3], int *err, int wg, hipStream_t st);
+hipError_t launch_project(const GridDev &g, const SpArgs &sa, double *const j[3], int *err,
+                          int wg, hipStream_t st);
+hipError_t launch_tag(const GridDev &g, const SpArgs &sa, int *err, int wg, hipStream_t st);
+hipError_t launch_rebin(const GridDev &g, const SpArgs &sa, int *err, int wg, hipStream_t st);
+
+// General sort (pic_sort.hip): wrap + key + stable sort of unsorted input.
+struct SortScratch {
+  void *temp = nullptr;
+  size_t temp_bytes = 0;
+  int32_t *keys = nullptr, *keys_out = nullptr;
+  int64_t *idx = nullptr, *idx_out = nullptr;
+  int64_t cap = 0;
+};
+hipError_t general_sort(const GridDev &g, SpDev &s, SortScratch &scr, int *err, hipStream_t st);
+void free_sort_scratch(SortScratch &scr);
+
+size_t lds_bytes_ipp(const GridDev &g);
+
+}  // namespace pic

@@ -1,0 +1,870 @@
+// HIP kernels (gfx950) for the per-step macro-particle operators of an
+// electromagnetic PIC loop: Interpolation, Push, pre-BC and Projection
+// (arXiv 2204.12837, section "Parallelization without tasks"), plus the
+// sort by patch of the synchronisation phase.
+//
+// Design (one workgroup per patch and species, as the paper's per-patch
+// loop, with the CPU thread replaced by a workgroup):
+//  * the patch's E and B with one ghost layer on each side -- everything an
+//    order-2 stencil can touch from a particle inside the patch -- are staged
+//    once into LDS, so the gather reads LDS only;
+//  * J is accumulated in a private LDS tile covering the patch plus the
+//    two-cell reach of the five-point Esirkepov stencil, with LDS float64
+//    atomics, then added to the grid with one global atomic per tile entry.
+//    This is the paper's local sub-grid per patch followed by a reduction
+//    into the patch grid "with the appropriate shift" (section
+//    "Parallelization with OpenMP task");
+//  * particles are read and written in structure-of-arrays order, so a wave
+//    reads 64 consecutive doubles per array;
+//  * pre-BC computes the destination patch of every particle as one of the
+//    3^dim neighbour codes, and a stable per-code rank from wave ballots;
+//    the sort is then a counting sort over those codes (no global atomics).
+//
+// Floating point: this file is compiled with -ffp-contract=off.  The
+// interpolation, the push and the patch key repeat the CPU oracle's
+// operation sequence exactly (quadratic B-spline weights, x-then-y-then-z
+// accumulation, Boris rotation form), so particle coordinates come out bit
+// for bit equal; J differs from the oracle only through the order of the
+// atomic additions.
+#include <hip/hip_runtime.h>
+
+#include "pic_common.h"
+
+namespace pic {
+
+namespace {
+
+constexpr int kWaveMax = 4;  // up to 256 threads per workgroup
+
+__device__ __forceinline__ int wrap_near(int k, int n) {
+  // k is within one period of [0, n)
+  return k < 0 ? k + n : (k >= n ? k - n : k);
+}
+
+__device__ __forceinline__ void lds_add(double *p, double v) {
+  __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+__device__ __forceinline__ void glb_add(double *p, double v) {
+  __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Quadratic B-spline weights on nodes i-1, i, i+1 for offset delta from i.
+__device__ __forceinline__ void shape_w(double delta, double &s0, double &s1, double &s2) {
+  const double a = 0.5 - delta;
+  const double b = 0.5 + delta;
+  s0 = 0.5 * (a * a);
+  s1 = 0.75 - delta * delta;
+  s2 = 0.5 * (b * b);
+}
+
+// Nearest primal node of xi (cell units) and the offset from it.
+__device__ __forceinline__ int locate0(double xi, double &delta) {
+  const double f = floor(xi + 0.5);
+  delta = xi - f;
+  return (int)f;
+}
+
+// Nearest dual node (position i + 1/2) of xi and the offset from it.
+__device__ __forceinline__ int locate1(double xi, double &delta) {
+  const double xs = xi - 0.5;
+  const double f = floor(xs + 0.5);
+  delta = xs - f;
+  return (int)f;
+}
+
+struct Sh {
+  double s[3];
+  int i;  // tile index of the first stencil node (node i-1)
+};
+
+// Shape of one axis for stagger bit s; org = tile origin node (patch origin - 1).
+template <int S>
+__device__ __forceinline__ Sh axis_shape(double xi, int org) {
+  Sh r;
+  double delta;
+  const int i = S ? locate1(xi, delta) : locate0(xi, delta);
+  shape_w(delta, r.s[0], r.s[1], r.s[2]);
+  r.i = i - 1 - org;
+  return r;
+}
+
+// One component from an LDS tile: x innermost, then y, then z.
+template <int DIM>
+__device__ __forceinline__ double gather(const double *t, int Tx, int Txy, const Sh &sx,
+                                         const Sh &sy, const Sh &sz) {
+  if constexpr (DIM == 2) {
+    const double *r = t + sy.i * Tx + sx.i;
+    double r0 = sx.s[0] * r[0];
+    r0 = r0 + sx.s[1] * r[1];
+    r0 = r0 + sx.s[2] * r[2];
+    r += Tx;
+    double r1 = sx.s[0] * r[0];
+    r1 = r1 + sx.s[1] * r[1];
+    r1 = r1 + sx.s[2] * r[2];
+    r += Tx;
+    double r2 = sx.s[0] * r[0];
+    r2 = r2 + sx.s[1] * r[1];
+    r2 = r2 + sx.s[2] * r[2];
+    double v = sy.s[0] * r0;
+    v = v + sy.s[1] * r1;
+    v = v + sy.s[2] * r2;
+    return v;
+  } else {
+    double pl[3];
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+      const double *r = t + (sz.i + c) * Txy + sy.i * Tx + sx.i;
+      double rr[3];
+#pragma unroll
+      for (int b = 0; b < 3; b++) {
+        double v = sx.s[0] * r[0];
+        v = v + sx.s[1] * r[1];
+        v = v + sx.s[2] * r[2];
+        rr[b] = v;
+        r += Tx;
+      }
+      double v = sy.s[0] * rr[0];
+      v = v + sy.s[1] * rr[1];
+      v = v + sy.s[2] * rr[2];
+      pl[c] = v;
+    }
+    double v = sz.s[0] * pl[0];
+    v = v + sz.s[1] * pl[1];
+    v = v + sz.s[2] * pl[2];
+    return v;
+  }
+}
+
+// Interpolate E and B at xi from the staged tile (6 components of TE each).
+template <int DIM>
+__device__ __forceinline__ void interp6(const double *tile, int TE, int Tx, int Txy,
+                                        const double xi[3], const int org[3], double F[6]) {
+  const Sh x0 = axis_shape<0>(xi[0], org[0]), x1 = axis_shape<1>(xi[0], org[0]);
+  const Sh y0 = axis_shape<0>(xi[1], org[1]), y1 = axis_shape<1>(xi[1], org[1]);
+  Sh z0, z1;
+  if constexpr (DIM == 3) {
+    z0 = axis_shape<0>(xi[2], org[2]);
+    z1 = axis_shape<1>(xi[2], org[2]);
+  } else {
+    z0 = z1 = Sh{{0.0, 1.0, 0.0}, 0};
+  }
+  // stagger bits: Ex(1,0,0) Ey(0,1,0) Ez(0,0,1) Bx(0,1,1) By(1,0,1) Bz(1,1,0)
+  F[0] = gather<DIM>(tile + 0 * TE, Tx, Txy, x1, y0, z0);
+  F[1] = gather<DIM>(tile + 1 * TE, Tx, Txy, x0, y1, z0);
+  F[2] = gather<DIM>(tile + 2 * TE, Tx, Txy, x0, y0, z1);
+  F[3] = gather<DIM>(tile + 3 * TE, Tx, Txy, x0, y1, z1);
+  F[4] = gather<DIM>(tile + 4 * TE, Tx, Txy, x1, y0, z1);
+  F[5] = gather<DIM>(tile + 5 * TE, Tx, Txy, x1, y1, z0);
+}
+
+// Relativistic Boris push, same operation sequence as the CPU oracle.
+__device__ __forceinline__ void boris(double alpha, const double F[6], double u[3], double v[3]) {
+  const double ae0 = alpha * F[0], ae1 = alpha * F[1], ae2 = alpha * F[2];
+  const double um0 = u[0] + ae0, um1 = u[1] + ae1, um2 = u[2] + ae2;
+  const double gm = sqrt(1.0 + ((um0 * um0 + um1 * um1) + um2 * um2));
+  const double tau = alpha / gm;
+  const double t0 = tau * F[3], t1 = tau * F[4], t2 = tau * F[5];
+  const double sig = 2.0 / (1.0 + ((t0 * t0 + t1 * t1) + t2 * t2));
+  const double s0 = sig * t0, s1 = sig * t1, s2 = sig * t2;
+  const double up0 = um0 + (um1 * t2 - um2 * t1);
+  const double up1 = um1 + (um2 * t0 - um0 * t2);
+  const double up2 = um2 + (um0 * t1 - um1 * t0);
+  const double upl0 = um0 + (up1 * s2 - up2 * s1);
+  const double upl1 = um1 + (up2 * s0 - up0 * s2);
+  const double upl2 = um2 + (up0 * s1 - up1 * s0);
+  u[0] = upl0 + ae0;
+  u[1] = upl1 + ae1;
+  u[2] = upl2 + ae2;
+  const double gam = sqrt(1.0 + ((u[0] * u[0] + u[1] * u[1]) + u[2] * u[2]));
+  const double ig = 1.0 / gam;
+  v[0] = u[0] * ig;
+  v[1] = u[1] * ig;
+  v[2] = u[2] * ig;
+}
+
+// Five-slot Esirkepov weights along one axis: S0 at the start position, DS =
+// S1 - S0 with S1 shifted by m = i1 - i0 in {-1, 0, 1}.  Returns false on a
+// larger shift.  i0t = tile index of slot 0 (tile origin = patch origin - 2).
+__device__ __forceinline__ bool esk_axis(double xi0, double xi1, int org2, double S0[5],
+                                         double DS[5], int &i0t) {
+  double d0, d1;
+  const int k0 = locate0(xi0, d0);
+  const int k1 = locate0(xi1, d1);
+  const int m = k1 - k0;
+  if (m < -1 || m > 1) return false;
+  double a0, a1, a2, b0, b1, b2;
+  shape_w(d0, a0, a1, a2);
+  shape_w(d1, b0, b1, b2);
+  S0[0] = 0.0;
+  S0[1] = a0;
+  S0[2] = a1;
+  S0[3] = a2;
+  S0[4] = 0.0;
+  double S1[5];
+  S1[0] = m == -1 ? b0 : 0.0;
+  S1[1] = m == -1 ? b1 : (m == 0 ? b0 : 0.0);
+  S1[2] = m == -1 ? b2 : (m == 0 ? b1 : b0);
+  S1[3] = m == -1 ? 0.0 : (m == 0 ? b2 : b1);
+  S1[4] = m == 1 ? b2 : 0.0;
+#pragma unroll
+  for (int r = 0; r < 5; r++) DS[r] = S1[r] - S0[r];
+  i0t = (k0 - 2) - org2;  // slot 0 is node k0 - 2
+  return true;
+}
+
+// Esirkepov deposit of one particle into the LDS J tile (3 components of TJn
+// entries, TJx x TJy (x TJz)).  qw = q*w.
+template <int DIM>
+__device__ __forceinline__ bool deposit(const GridDev &g, double *tJ, int TJn, int TJx, int TJxy,
+                                        const int org2[3], double qw, const double xi0[3],
+                                        const double xi1[3], double vz) {
+  double S0[3][5], DS[3][5];
+  int it[3];
+#pragma unroll
+  for (int a = 0; a < DIM; a++)
+    if (!esk_axis(xi0[a], xi1[a], org2[a], S0[a], DS[a], it[a])) return false;
+  if constexpr (DIM == 2) {
+    double *Jx = tJ, *Jy = tJ + TJn, *Jz = tJ + 2 * TJn;
+    const double cx = -qw * g.d_over_dt[0];
+    const double cy = -qw * g.d_over_dt[1];
+    const double cz = qw * vz;
+#pragma unroll
+    for (int t = 0; t < 5; t++) {
+      const double fy = S0[1][t] + 0.5 * DS[1][t];
+      double acc = 0.0;
+      double *row = Jx + (it[1] + t) * TJx + it[0];
+#pragma unroll
+      for (int r = 0; r < 4; r++) {
+        acc = acc + DS[0][r] * fy;
+        lds_add(row + r, cx * acc);
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < 5; r++) {
+      const double fx = S0[0][r] + 0.5 * DS[0][r];
+      double acc = 0.0;
+      double *col = Jy + it[1] * TJx + it[0] + r;
+#pragma unroll
+      for (int t = 0; t < 4; t++) {
+        acc = acc + DS[1][t] * fx;
+        lds_add(col + t * TJx, cy * acc);
+      }
+    }
+    const double third = 1.0 / 3.0;
+#pragma unroll
+    for (int t = 0; t < 5; t++) {
+      double *row = Jz + (it[1] + t) * TJx + it[0];
+#pragma unroll
+      for (int r = 0; r < 5; r++) {
+        const double wz = S0[0][r] * S0[1][t] + 0.5 * DS[0][r] * S0[1][t] +
+                          0.5 * S0[0][r] * DS[1][t] + third * DS[0][r] * DS[1][t];
+        lds_add(row + r, cz * wz);
+      }
+    }
+  } else {
+    const double third = 1.0 / 3.0;
+    const int stride[3] = {1, TJx, TJxy};
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+      const int b = (a + 1) % 3, c = (a + 2) % 3;
+      double *Ja = tJ + a * TJn;
+      const double ca = -qw * g.d_over_dt[a];
+#pragma unroll
+      for (int tb = 0; tb < 5; tb++) {
+#pragma unroll
+        for (int tc = 0; tc < 5; tc++) {
+          const double f = S0[b][tb] * S0[c][tc] + 0.5 * DS[b][tb] * S0[c][tc] +
+                           0.5 * S0[b][tb] * DS[c][tc] + third * DS[b][tb] * DS[c][tc];
+          double acc = 0.0;
+          double *line = Ja + it[0] * stride[0] + it[1] * stride[1] + it[2] * stride[2] +
+                         tb * stride[b] + tc * stride[c];
+#pragma unroll
+          for (int ta = 0; ta < 4; ta++) {
+            acc = acc + DS[a][ta] * f;
+            lds_add(line + ta * stride[a], ca * acc);
+          }
+        }
+      }
+    }
+  }
+  return true;
+}
+
+// Patch coordinates of patch P.
+__device__ __forceinline__ void patch_coords(const GridDev &g, int P, int pc[3]) {
+  pc[0] = P % g.np[0];
+  const int r = P / g.np[0];
+  pc[1] = r % g.np[1];
+  pc[2] = r / g.np[1];
+}
+
+// pre-BC: wrap x1 into the box (in place) and return the neighbour code of
+// the destination patch relative to patch pc (-1 on a bad position).
+template <int DIM>
+__device__ __forceinline__ int dest_code(const GridDev &g, const int pc[3], double x[3]) {
+  int code = 0, mul = 1;
+#pragma unroll
+  for (int a = 0; a < DIM; a++) {
+    double v = x[a];
+    if (v < 0.0) v += g.L[a];
+    if (v >= g.L[a]) v -= g.L[a];
+    if (!(v >= 0.0 && v < g.L[a])) return -1;
+    x[a] = v;
+    int c = (int)floor(v * g.inv_d[a]);
+    if (c >= g.n[a]) c = g.n[a] - 1;
+    int dp = c / g.patch[a] - pc[a];
+    if (dp < 0) dp += g.np[a];
+    int delta;
+    if (dp == 0)
+      delta = 0;
+    else if (dp == 1)
+      delta = 1;
+    else if (dp == g.np[a] - 1)
+      delta = -1;
+    else
+      return -1;
+    code += (delta + 1) * mul;
+    mul *= 3;
+  }
+  return code;
+}
+
+// Destination patch of code c from patch coordinates pc.
+__device__ __forceinline__ int dest_patch(const GridDev &g, const int pc[3], int c) {
+  int D = 0, mul = 1;
+  for (int a = 0; a < 3; a++) {
+    int delta = 0;
+    if (a < g.dim) {
+      delta = c % 3 - 1;
+      c /= 3;
+    }
+    int q = pc[a] + delta;
+    if (q < 0) q += g.np[a];
+    if (q >= g.np[a]) q -= g.np[a];
+    D += q * mul;
+    mul *= g.np[a];
+  }
+  return D;
+}
+
+// Per-chunk stable ranking of particles by neighbour code.
+struct RankLDS {
+  int wcnt[2][kWaveMax][27];
+  int run[27];
+};
+
+template <int NC>
+__device__ __forceinline__ uint32_t rank_chunk(RankLDS &R, int parity, bool valid, int code) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int nwaves = (blockDim.x + 63) >> 6;
+  const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+  int r = 0;
+#pragma unroll
+  for (int c = 0; c < NC; c++) {
+    const uint64_t m = __ballot(valid && code == c);
+    if (valid && code == c) r = __popcll(m & lt);
+    if (lane == 0) R.wcnt[parity][wave][c] = __popcll(m);
+  }
+  __syncthreads();
+  int pre = 0;
+  if (valid) {
+    pre = R.run[code];
+    for (int w = 0; w < wave; w++) pre += R.wcnt[parity][w][code];
+  }
+  __syncthreads();
+  if (tid < NC) {
+    int s = 0;
+    for (int w = 0; w < nwaves; w++) s += R.wcnt[parity][w][tid];
+    R.run[tid] += s;
+  }
+  return (uint32_t)(pre + r);
+}
+
+struct Fields {
+  const double *e[3];
+  const double *b[3];
+  double *j[3];
+};
+
+struct TileGeom {
+  int org[3];   // E/B tile origin node (patch origin - 1)
+  int org2[3];  // J tile origin node (patch origin - 2)
+  int pc[3];
+  int lo[3], hi[3];  // patch cell range [lo, hi] (as doubles: xi in [lo, hi])
+  int Tx, Txy, TE;   // E/B tile extents
+  int Jx, Jxy, TJ;   // J tile extents
+};
+
+template <int DIM>
+__device__ __forceinline__ TileGeom tile_geom(const GridDev &g, int P) {
+  TileGeom t;
+  patch_coords(g, P, t.pc);
+  for (int a = 0; a < 3; a++) {
+    const int o = a < DIM ? t.pc[a] * g.patch[a] : 0;
+    t.lo[a] = o;
+    t.hi[a] = o + g.patch[a];
+    t.org[a] = o - 1;
+    t.org2[a] = o - 2;
+  }
+  const int ex = g.patch[0] + 3, ey = g.patch[1] + 3, ez = DIM == 3 ? g.patch[2] + 3 : 1;
+  t.Tx = ex;
+  t.Txy = ex * ey;
+  t.TE = ex * ey * ez;
+  const int jx = g.patch[0] + 5, jy = g.patch[1] + 5, jz = DIM == 3 ? g.patch[2] + 5 : 1;
+  t.Jx = jx;
+  t.Jxy = jx * jy;
+  t.TJ = jx * jy * jz;
+  return t;
+}
+
+template <int DIM>
+__device__ void stage_eb(const GridDev &g, const TileGeom &t, const Fields &f, double *tile) {
+  const int ez = DIM == 3 ? g.patch[2] + 3 : 1;
+  (void)ez;
+  for (int idx = threadIdx.x; idx < 6 * t.TE; idx += blockDim.x) {
+    const int c = idx / t.TE;
+    const int r = idx - c * t.TE;
+    const int kk = r / t.Txy;
+    const int r2 = r - kk * t.Txy;
+    const int jj = r2 / t.Tx;
+    const int ii = r2 - jj * t.Tx;
+    const int gx = wrap_near(t.org[0] + ii, g.n[0]);
+    const int gy = wrap_near(t.org[1] + jj, g.n[1]);
+    const int gz = DIM == 3 ? wrap_near(t.org[2] + kk, g.n[2]) : 0;
+    const double *F = c < 3 ? f.e[c] : f.b[c - 3];
+    tile[idx] = F[((int64_t)gz * g.n[1] + gy) * g.n[0] + gx];
+  }
+}
+
+template <int DIM>
+__device__ void zero_tile(double *tJ, int n) {
+  for (int idx = threadIdx.x; idx < n; idx += blockDim.x) tJ[idx] = 0.0;
+}
+
+template <int DIM>
+__device__ void flush_j(const GridDev &g, const TileGeom &t, const double *tJ, double *const j[3]) {
+  for (int idx = threadIdx.x; idx < 3 * t.TJ; idx += blockDim.x) {
+    const double v = tJ[idx];
+    if (v == 0.0) continue;
+    const int c = idx / t.TJ;
+    const int r = idx - c * t.TJ;
+    const int kk = r / t.Jxy;
+    const int r2 = r - kk * t.Jxy;
+    const int jj = r2 / t.Jx;
+    const int ii = r2 - jj * t.Jx;
+    const int gx = wrap_near(t.org2[0] + ii, g.n[0]);
+    const int gy = wrap_near(t.org2[1] + jj, g.n[1]);
+    const int gz = DIM == 3 ? wrap_near(t.org2[2] + kk, g.n[2]) : 0;
+    glb_add(j[c] + ((int64_t)gz * g.n[1] + gy) * g.n[0] + gx, v);
+  }
+}
+
+// True if the particle at xi lies in the patch (as the sort placed it).
+template <int DIM>
+__device__ __forceinline__ bool in_patch(const TileGeom &t, const double xi[3]) {
+  bool ok = true;
+#pragma unroll
+  for (int a = 0; a < DIM; a++) ok = ok && xi[a] >= (double)t.lo[a] && xi[a] <= (double)t.hi[a];
+  return ok;
+}
+
+// ---------------------------------------------------------------------------
+// Fused step kernel: Interpolation, Push, pre-BC and Projection for the
+// particles of one (patch, species).
+template <int DIM>
+__global__ void __launch_bounds__(256) k_ipp(GridDev g, SpArgs sa, Fields f, int *err) {
+  constexpr int NC = DIM == 2 ? 9 : 27;
+  constexpr int CENTER = (NC - 1) / 2;
+  extern __shared__ double lds[];
+  __shared__ RankLDS R;
+  const int P = blockIdx.x;
+  const SpDev &S = sa.s[blockIdx.y];
+  const TileGeom t = tile_geom<DIM>(g, P);
+  double *tEB = lds;
+  double *tJ = lds + 6 * t.TE;
+  stage_eb<DIM>(g, t, f, tEB);
+  zero_tile<DIM>(tJ, 3 * t.TJ);
+  if (threadIdx.x < NC) R.run[threadIdx.x] = 0;
+  __syncthreads();
+  const int64_t beg = S.off[P], end = S.off[P + 1];
+  const double q = S.q, alpha = S.alpha;
+  int parity = 0;
+  int bad = 0;
+  for (int64_t base = beg; base < end; base += blockDim.x) {
+    const int64_t i = base + threadIdx.x;
+    const bool valid = i < end;
+    int code = CENTER;
+    if (valid) {
+      double x[3], xi[3], u[3], v[3], F[6];
+#pragma unroll
+      for (int a = 0; a < DIM; a++) {
+        x[a] = S.x[a][i];
+        xi[a] = x[a] * g.inv_d[a];
+      }
+      if (!in_patch<DIM>(t, xi)) {
+        bad |= kErrPos;
+      } else {
+        u[0] = S.u[0][i];
+        u[1] = S.u[1][i];
+        u[2] = S.u[2][i];
+        const double w = S.w[i];
+        interp6<DIM>(tEB, t.TE, t.Tx, t.Txy, xi, t.org, F);
+        boris(alpha, F, u, v);
+        double x1[3], xi1[3];
+#pragma unroll
+        for (int a = 0; a < DIM; a++) {
+          x1[a] = x[a] + g.dt * v[a];
+          xi1[a] = x1[a] * g.inv_d[a];
+        }
+        if (!deposit<DIM>(g, tJ, t.TJ, t.Jx, t.Jxy, t.org2, q * w, xi, xi1, v[2])) bad |= kErrCFL;
+        const int c = dest_code<DIM>(g, t.pc, x1);
+        if (c < 0) {
+          bad |= kErrPos;
+        } else {
+          code = c;
+        }
+#pragma unroll
+        for (int a = 0; a < DIM; a++) S.x[a][i] = x1[a];
+        S.u[0][i] = u[0];
+        S.u[1][i] = u[1];
+        S.u[2][i] = u[2];
+      }
+    }
+    const uint32_t rank = rank_chunk<NC>(R, parity, valid, code);
+    if (valid) S.tag[i] = ((uint32_t)code << 27) | rank;
+    parity ^= 1;
+  }
+  if (bad) atomicOr(err, bad);
+  __syncthreads();
+  flush_j<DIM>(g, t, tJ, f.j);
+  if (threadIdx.x < NC) S.cnt[(int64_t)P * NC + threadIdx.x] = R.run[threadIdx.x];
+}
+
+// Split path, first half: Interpolation + Push; saves the start positions.
+template <int DIM>
+__global__ void __launch_bounds__(256) k_interp_push(GridDev g, SpArgs sa, Fields f, int *err) {
+  extern __shared__ double lds[];
+  const int P = blockIdx.x;
+  const SpDev &S = sa.s[blockIdx.y];
+  const TileGeom t = tile_geom<DIM>(g, P);
+  stage_eb<DIM>(g, t, f, lds);
+  __syncthreads();
+  const int64_t beg = S.off[P], end = S.off[P + 1];
+  int bad = 0;
+  for (int64_t i = beg + threadIdx.x; i < end; i += blockDim.x) {
+    double x[3], xi[3], u[3], v[3], F[6];
+#pragma unroll
+    for (int a = 0; a < DIM; a++) {
+      x[a] = S.x[a][i];
+      xi[a] = x[a] * g.inv_d[a];
+      S.x0[a][i] = x[a];
+    }
+    if (!in_patch<DIM>(t, xi)) {
+      bad |= kErrPos;
+      continue;
+    }
+    u[0] = S.u[0][i];
+    u[1] = S.u[1][i];
+    u[2] = S.u[2][i];
+    interp6<DIM>(lds, t.TE, t.Tx, t.Txy, xi, t.org, F);
+    boris(S.alpha, F, u, v);
+#pragma unroll
+    for (int a = 0; a < DIM; a++) S.x[a][i] = x[a] + g.dt * v[a];
+    S.u[0][i] = u[0];
+    S.u[1][i] = u[1];
+    S.u[2][i] = u[2];
+  }
+  if (bad) atomicOr(err, bad);
+}
+
+// Split path, second half: Projection from the saved start positions.
+template <int DIM>
+__global__ void __launch_bounds__(256) k_project(GridDev g, SpArgs sa, Fields f, int *err) {
+  extern __shared__ double lds[];
+  const int P = blockIdx.x;
+  const SpDev &S = sa.s[blockIdx.y];
+  const TileGeom t = tile_geom<DIM>(g, P);
+  double *tJ = lds;
+  zero_tile<DIM>(tJ, 3 * t.TJ);
+  __syncthreads();
+  const int64_t beg = S.off[P], end = S.off[P + 1];
+  int bad = 0;
+  for (int64_t i = beg + threadIdx.x; i < end; i += blockDim.x) {
+    double xi0[3], xi1[3];
+#pragma unroll
+    for (int a = 0; a < DIM; a++) {
+      xi0[a] = S.x0[a][i] * g.inv_d[a];
+      xi1[a] = S.x[a][i] * g.inv_d[a];
+    }
+    if (!in_patch<DIM>(t, xi0)) {
+      bad |= kErrPos;
+      continue;
+    }
+    const double u0 = S.u[0][i], u1 = S.u[1][i], u2 = S.u[2][i];
+    const double gam = sqrt(1.0 + ((u0 * u0 + u1 * u1) + u2 * u2));
+    const double ig = 1.0 / gam;
+    const double vz = u2 * ig;
+    if (!deposit<DIM>(g, tJ, t.TJ, t.Jx, t.Jxy, t.org2, S.q * S.w[i], xi0, xi1, vz)) bad |= kErrCFL;
+  }
+  if (bad) atomicOr(err, bad);
+  __syncthreads();
+  flush_j<DIM>(g, t, tJ, f.j);
+}
+
+// Split path pre-BC: wrap, neighbour code and stable rank of particles that
+// moved at most one cell since the last sort.
+template <int DIM>
+__global__ void __launch_bounds__(256) k_tag(GridDev g, SpArgs sa, int *err) {
+  constexpr int NC = DIM == 2 ? 9 : 27;
+  constexpr int CENTER = (NC - 1) / 2;
+  __shared__ RankLDS R;
+  const int P = blockIdx.x;
+  const SpDev &S = sa.s[blockIdx.y];
+  int pc[3];
+  patch_coords(g, P, pc);
+  if (threadIdx.x < NC) R.run[threadIdx.x] = 0;
+  __syncthreads();
+  const int64_t beg = S.off[P], end = S.off[P + 1];
+  int parity = 0, bad = 0;
+  for (int64_t base = beg; base < end; base += blockDim.x) {
+    const int64_t i = base + threadIdx.x;
+    const bool valid = i < end;
+    int code = CENTER;
+    if (valid) {
+      double x[3];
+#pragma unroll
+      for (int a = 0; a < DIM; a++) x[a] = S.x[a][i];
+      const int c = dest_code<DIM>(g, pc, x);
+      if (c < 0) {
+        bad |= kErrPos;
+      } else {
+        code = c;
+#pragma unroll
+        for (int a = 0; a < DIM; a++) S.x[a][i] = x[a];
+      }
+    }
+    const uint32_t rank = rank_chunk<NC>(R, parity, valid, code);
+    if (valid) S.tag[i] = ((uint32_t)code << 27) | rank;
+    parity ^= 1;
+  }
+  if (bad) atomicOr(err, bad);
+  __syncthreads();
+  if (threadIdx.x < NC) S.cnt[(int64_t)P * NC + threadIdx.x] = R.run[threadIdx.x];
+}
+
+// Sort, step 1: for every destination patch D, the particles arriving from
+// each (source patch, code) pair, ordered by source patch; gives each pair
+// its start inside D and D's total.
+__global__ void k_dest_bases(GridDev g, SpArgs sa) {
+  const int D = blockIdx.x * blockDim.x + threadIdx.x;
+  if (D >= g.npatch) return;
+  const SpDev &S = sa.s[blockIdx.y];
+  const int nc = g.nc;
+  int dc[3];
+  patch_coords(g, D, dc);
+  int src[27], code[27], num[27];
+  for (int c = 0; c < nc; c++) {
+    int cc = c, Psrc = 0, mul = 1;
+    for (int a = 0; a < 3; a++) {
+      int delta = 0;
+      if (a < g.dim) {
+        delta = cc % 3 - 1;
+        cc /= 3;
+      }
+      int q = dc[a] - delta;
+      if (q < 0) q += g.np[a];
+      if (q >= g.np[a]) q -= g.np[a];
+      Psrc += q * mul;
+      mul *= g.np[a];
+    }
+    // insertion by source patch (stable in c)
+    int k = c;
+    while (k > 0 && src[k - 1] > Psrc) {
+      src[k] = src[k - 1];
+      code[k] = code[k - 1];
+      num[k] = num[k - 1];
+      k--;
+    }
+    src[k] = Psrc;
+    code[k] = c;
+    num[k] = S.cnt[(int64_t)Psrc * nc + c];
+  }
+  int64_t run = 0;
+  for (int k = 0; k < nc; k++) {
+    S.rbase[(int64_t)src[k] * nc + code[k]] = run;
+    run += num[k];
+  }
+  S.in[D] = run;
+}
+
+// Sort, step 2: exclusive scan of arrivals into the new offsets (one
+// workgroup per species).
+__global__ void __launch_bounds__(1024) k_scan_offsets(GridDev g, SpArgs sa) {
+  const SpDev &S = sa.s[blockIdx.x];
+  __shared__ int64_t part[1024];
+  const int n = g.npatch;
+  const int per = (n + blockDim.x - 1) / blockDim.x;
+  const int b = threadIdx.x * per;
+  const int e = min(n, b + per);
+  int64_t sum = 0;
+  for (int k = b; k < e; k++) sum += S.in[k];
+  part[threadIdx.x] = sum;
+  __syncthreads();
+  for (int off = 1; off < (int)blockDim.x; off <<= 1) {
+    const int64_t v = threadIdx.x >= (unsigned)off ? part[threadIdx.x - off] : 0;
+    __syncthreads();
+    part[threadIdx.x] += v;
+    __syncthreads();
+  }
+  int64_t run = part[threadIdx.x] - sum;
+  for (int k = b; k < e; k++) {
+    S.noff[k] = run;
+    run += S.in[k];
+  }
+  if (threadIdx.x == blockDim.x - 1) S.noff[n] = part[threadIdx.x];
+}
+
+// Sort, step 3: move every particle of a source patch to its place.
+__global__ void __launch_bounds__(256) k_scatter(GridDev g, SpArgs sa, int dim, int *err) {
+  const int P = blockIdx.x;
+  const SpDev &S = sa.s[blockIdx.y];
+  const int nc = g.nc;
+  __shared__ int64_t base[27];
+  if (threadIdx.x < (unsigned)nc) {
+    int pc[3];
+    patch_coords(g, P, pc);
+    const int D = dest_patch(g, pc, threadIdx.x);
+    base[threadIdx.x] = S.noff[D] + S.rbase[(int64_t)P * nc + threadIdx.x];
+  }
+  __syncthreads();
+  const int64_t beg = S.off[P], end = S.off[P + 1];
+  int bad = 0;
+  for (int64_t i = beg + threadIdx.x; i < end; i += blockDim.x) {
+    const uint32_t tg = S.tag[i];
+    const int c = (int)(tg >> 27);
+    const int64_t dst = c < nc ? base[c] + (int64_t)(tg & ((1u << 27) - 1)) : S.n;
+    if (dst >= S.n) {
+      bad |= kErrPos;
+      continue;
+    }
+    for (int a = 0; a < dim; a++) S.xa[a][dst] = S.x[a][i];
+    S.ua[0][dst] = S.u[0][i];
+    S.ua[1][dst] = S.u[1][i];
+    S.ua[2][dst] = S.u[2][i];
+    S.wa[dst] = S.w[i];
+    S.ida[dst] = S.id[i];
+  }
+  if (bad) atomicOr(err, bad);
+}
+
+// Sort, step 4: publish the new offsets.
+__global__ void k_copy_offsets(GridDev g, SpArgs sa) {
+  const SpDev &S = sa.s[blockIdx.y];
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k <= g.npatch; k += gridDim.x * blockDim.x)
+    S.off[k] = S.noff[k];
+}
+
+__global__ void k_zero(double *a, double *b, double *c, int64_t n) {
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n;
+       k += (int64_t)gridDim.x * blockDim.x) {
+    a[k] = 0.0;
+    b[k] = 0.0;
+    c[k] = 0.0;
+  }
+}
+
+Fields mkfields(const double *const e[3], const double *const b[3], double *const j[3]) {
+  Fields f;
+  for (int c = 0; c < 3; c++) {
+    f.e[c] = e ? e[c] : nullptr;
+    f.b[c] = b ? b[c] : nullptr;
+    f.j[c] = j ? j[c] : nullptr;
+  }
+  return f;
+}
+
+size_t tile_eb_bytes(const GridDev &g) {
+  size_t t = 1;
+  for (int a = 0; a < g.dim; a++) t *= (size_t)(g.patch[a] + 3);
+  return 6 * t * sizeof(double);
+}
+
+size_t tile_j_bytes(const GridDev &g) {
+  size_t t = 1;
+  for (int a = 0; a < g.dim; a++) t *= (size_t)(g.patch[a] + 5);
+  return 3 * t * sizeof(double);
+}
+
+}  // namespace
+
+size_t lds_bytes_ipp(const GridDev &g) { return tile_eb_bytes(g) + tile_j_bytes(g); }
+
+hipError_t launch_zero(double *const j[3], int64_t ncell, hipStream_t st) {
+  const int blocks = (int)std::min<int64_t>((ncell + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_zero, dim3(blocks), dim3(256), 0, st, j[0], j[1], j[2], ncell);
+  return hipGetLastError();
+}
+
+hipError_t launch_ipp(const GridDev &g, const SpArgs &sa, const double *const e[3],
+                      const double *const b[3], double *const j[3], int *err, int wg,
+                      hipStream_t st) {
+  const Fields f = mkfields(e, b, j);
+  const size_t lds = lds_bytes_ipp(g);
+  const dim3 grid(g.npatch, sa.nsp);
+  if (g.dim == 2) {
+    hipLaunchKernelGGL(k_ipp<2>, grid, dim3(wg), lds, st, g, sa, f, err);
+  } else {
+    (void)hipFuncSetAttribute((const void *)k_ipp<3>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)lds);
+    hipLaunchKernelGGL(k_ipp<3>, grid, dim3(wg), lds, st, g, sa, f, err);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_interp_push(const GridDev &g, const SpArgs &sa, const double *const e[3],
+                              const double *const b[3], int *err, int wg, hipStream_t st) {
+  const Fields f = mkfields(e, b, nullptr);
+  const dim3 grid(g.npatch, sa.nsp);
+  if (g.dim == 2)
+    hipLaunchKernelGGL(k_interp_push<2>, grid, dim3(wg), tile_eb_bytes(g), st, g, sa, f, err);
+  else
+    hipLaunchKernelGGL(k_interp_push<3>, grid, dim3(wg), tile_eb_bytes(g), st, g, sa, f, err);
+  return hipGetLastError();
+}
+
+hipError_t launch_project(const GridDev &g, const SpArgs &sa, double *const j[3], int *err, int wg,
+                          hipStream_t st) {
+  const Fields f = mkfields(nullptr, nullptr, j);
+  const dim3 grid(g.npatch, sa.nsp);
+  if (g.dim == 2)
+    hipLaunchKernelGGL(k_project<2>, grid, dim3(wg), tile_j_bytes(g), st, g, sa, f, err);
+  else
+    hipLaunchKernelGGL(k_project<3>, grid, dim3(wg), tile_j_bytes(g), st, g, sa, f, err);
+  return hipGetLastError();
+}
+
+hipError_t launch_tag(const GridDev &g, const SpArgs &sa, int *err, int wg, hipStream_t st) {
+  const dim3 grid(g.npatch, sa.nsp);
+  if (g.dim == 2)
+    hipLaunchKernelGGL(k_tag<2>, grid, dim3(wg), 0, st, g, sa, err);
+  else
+    hipLaunchKernelGGL(k_tag<3>, grid, dim3(wg), 0, st, g, sa, err);
+  return hipGetLastError();
+}
+
+hipError_t launch_rebin(const GridDev &g, const SpArgs &sa, int *err, int wg, hipStream_t st) {
+  hipLaunchKernelGGL(k_dest_bases, dim3((g.npatch + 127) / 128, sa.nsp), dim3(128), 0, st, g, sa);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_scan_offsets, dim3(sa.nsp), dim3(1024), 0, st, g, sa);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_scatter, dim3(g.npatch, sa.nsp), dim3(wg), 0, st, g, sa, g.dim, err);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_copy_offsets, dim3((g.npatch + 256) / 256, sa.nsp), dim3(256), 0, st, g, sa);
+  return hipGetLastError();
+}
+
+}  // namespace pic

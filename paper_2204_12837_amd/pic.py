@@ -1,0 +1,266 @@
+"""Python binding of the C ABI in include/pic.h (ctypes).
+
+Argument marshalling only: every operation on particles and fields runs in
+the HIP kernels of ``libpic.so``.  PyTorch provides device memory and the
+stream.  If the library is not built, every entry point raises ``PicError``;
+there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import List, Optional, Sequence
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpic.so")
+
+PIC_OK, PIC_ERR_ARG, PIC_ERR_HIP, PIC_ERR_CAPACITY, PIC_ERR_CFL, PIC_ERR_POS, PIC_ERR_STATE = range(7)
+STATUS_NAMES = {0: "PIC_OK", 1: "PIC_ERR_ARG", 2: "PIC_ERR_HIP", 3: "PIC_ERR_CAPACITY",
+                4: "PIC_ERR_CFL", 5: "PIC_ERR_POS", 6: "PIC_ERR_STATE"}
+MODE_PER_PATCH, MODE_PERSISTENT = 0, 1
+FLAG_CHECK = 1
+
+_DP = C.POINTER(C.c_double)
+_I64P = C.POINTER(C.c_int64)
+
+
+class PicError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class ConfigC(C.Structure):
+    _fields_ = [("dim", C.c_int32), ("n", C.c_int32 * 3), ("d", C.c_double * 3), ("dt", C.c_double),
+                ("patch", C.c_int32 * 3), ("shape_order", C.c_int32), ("mode", C.c_int32),
+                ("chunk", C.c_int32), ("wg_size", C.c_int32), ("flags", C.c_uint32)]
+
+
+class SpeciesC(C.Structure):
+    _fields_ = [("q", C.c_double), ("m", C.c_double), ("n", C.c_int64), ("capacity", C.c_int64),
+                ("x", C.c_void_p * 3), ("u", C.c_void_p * 3), ("w", C.c_void_p), ("id", C.c_void_p),
+                ("x_alt", C.c_void_p * 3), ("u_alt", C.c_void_p * 3), ("w_alt", C.c_void_p),
+                ("id_alt", C.c_void_p), ("offset", C.c_void_p)]
+
+
+class FieldsC(C.Structure):
+    _fields_ = [("e", C.c_void_p * 3), ("b", C.c_void_p * 3), ("j", C.c_void_p * 3)]
+
+
+ENTRY_POINTS = ("pic_validate_config", "pic_num_patches", "pic_init", "pic_free", "pic_bin",
+                "pic_interp_push", "pic_project", "pic_step", "pic_check", "pic_last_error")
+
+_lib_handle = None
+
+
+def lib():
+    """Load libpic.so (raises PicError if it is not built)."""
+    global _lib_handle
+    if _lib_handle is None:
+        if not os.path.exists(LIB_PATH):
+            raise PicError(PIC_ERR_STATE, f"{LIB_PATH} is not built "
+                           "(python -m paper_2204_12837_amd.build)")
+        L = C.CDLL(LIB_PATH)
+        L.pic_validate_config.argtypes = [C.POINTER(ConfigC), C.c_char_p, C.c_size_t]
+        L.pic_validate_config.restype = C.c_int
+        L.pic_num_patches.argtypes = [C.POINTER(ConfigC)]
+        L.pic_num_patches.restype = C.c_int64
+        L.pic_init.argtypes = [C.POINTER(ConfigC), C.c_int32, C.POINTER(C.c_void_p)]
+        L.pic_init.restype = C.c_int
+        L.pic_free.argtypes = [C.c_void_p]
+        L.pic_free.restype = None
+        for name in ("pic_bin", "pic_interp_push"):
+            getattr(L, name).restype = C.c_int
+        L.pic_bin.argtypes = [C.c_void_p, C.POINTER(SpeciesC), C.c_int32, C.c_void_p]
+        L.pic_interp_push.argtypes = [C.c_void_p, C.POINTER(SpeciesC), C.c_int32,
+                                      C.POINTER(FieldsC), C.c_void_p]
+        L.pic_project.argtypes = [C.c_void_p, C.POINTER(SpeciesC), C.c_int32, C.POINTER(FieldsC),
+                                  C.c_void_p]
+        L.pic_project.restype = C.c_int
+        L.pic_step.argtypes = [C.c_void_p, C.POINTER(SpeciesC), C.c_int32, C.POINTER(FieldsC),
+                               C.c_int32, C.c_void_p]
+        L.pic_step.restype = C.c_int
+        L.pic_check.argtypes = [C.c_void_p, C.c_void_p]
+        L.pic_check.restype = C.c_int
+        L.pic_last_error.argtypes = [C.c_void_p]
+        L.pic_last_error.restype = C.c_char_p
+        _lib_handle = L
+    return _lib_handle
+
+
+def make_config(wl, mode=MODE_PER_PATCH, chunk=0, wg_size=0, flags=0) -> ConfigC:
+    """Config struct from a workload description (dim, n, d, dt, patch)."""
+    c = ConfigC()
+    c.dim = wl.dim
+    for a in range(3):
+        c.n[a] = int(wl.n[a]) if a < wl.dim else 1
+        c.d[a] = float(wl.d[a])
+        c.patch[a] = int(wl.patch[a]) if a < wl.dim else 1
+    c.dt = float(wl.dt)
+    c.shape_order = 2
+    c.mode, c.chunk, c.wg_size, c.flags = mode, chunk, wg_size, flags
+    return c
+
+
+def validate(cfg: ConfigC):
+    buf = C.create_string_buffer(256)
+    rc = lib().pic_validate_config(C.byref(cfg), buf, 256)
+    return rc, buf.value.decode()
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return t.data_ptr() if t is not None else None
+
+
+class Species:
+    """One species' device arrays: two buffer sets (the sort ping-pongs
+    between them) and the patch offsets."""
+
+    def __init__(self, q: float, m: float, x: torch.Tensor, u: torch.Tensor, w: torch.Tensor,
+                 pid: torch.Tensor, n_patches: int, capacity: Optional[int] = None):
+        dev = x.device
+        n = x.shape[1]
+        cap = max(n if capacity is None else int(capacity), 1)
+        self.q, self.m, self.n, self.capacity = float(q), float(m), n, cap
+        self.dim = x.shape[0]
+        f64 = dict(dtype=torch.float64, device=dev)
+
+        def buf(src, rows):
+            t = torch.zeros((rows, cap), **f64) if rows else torch.zeros(cap, **f64)
+            if src is not None:
+                (t[:, :n] if rows else t[:n]).copy_(src)
+            return t
+
+        self.x, self.u, self.w = buf(x, self.dim), buf(u, 3), buf(w, 0)
+        self.id = torch.zeros(cap, dtype=torch.int64, device=dev)
+        self.id[:n].copy_(pid)
+        self.x_alt, self.u_alt, self.w_alt = buf(None, self.dim), buf(None, 3), buf(None, 0)
+        self.id_alt = torch.zeros(cap, dtype=torch.int64, device=dev)
+        self.offset = torch.zeros(n_patches + 1, dtype=torch.int64, device=dev)
+
+    def cstruct(self) -> SpeciesC:
+        s = SpeciesC()
+        s.q, s.m, s.n, s.capacity = self.q, self.m, self.n, self.capacity
+        for a in range(3):
+            s.x[a] = self.x[a].data_ptr() if a < self.dim else None
+            s.x_alt[a] = self.x_alt[a].data_ptr() if a < self.dim else None
+            s.u[a] = self.u[a].data_ptr()
+            s.u_alt[a] = self.u_alt[a].data_ptr()
+        s.w, s.w_alt = self.w.data_ptr(), self.w_alt.data_ptr()
+        s.id, s.id_alt = self.id.data_ptr(), self.id_alt.data_ptr()
+        s.offset = self.offset.data_ptr()
+        return s
+
+    def adopt(self, s: SpeciesC):
+        """Follow the buffer swap the library made in the struct."""
+        if s.w != self.w.data_ptr():
+            assert s.w == self.w_alt.data_ptr()
+            self.x, self.x_alt = self.x_alt, self.x
+            self.u, self.u_alt = self.u_alt, self.u
+            self.w, self.w_alt = self.w_alt, self.w
+            self.id, self.id_alt = self.id_alt, self.id
+
+    # views of the live particles
+    @property
+    def xs(self):
+        return self.x[:, :self.n]
+
+    @property
+    def us(self):
+        return self.u[:, :self.n]
+
+    @property
+    def ws(self):
+        return self.w[:self.n]
+
+    @property
+    def ids(self):
+        return self.id[:self.n]
+
+
+def fields_struct(E=None, B=None, J=None) -> FieldsC:
+    f = FieldsC()
+    for c in range(3):
+        f.e[c] = E[c].data_ptr() if E is not None else None
+        f.b[c] = B[c].data_ptr() if B is not None else None
+        f.j[c] = J[c].data_ptr() if J is not None else None
+    return f
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class Context:
+    """A library context (pic_init / pic_free)."""
+
+    def __init__(self, wl, device: int = 0, mode=MODE_PER_PATCH, chunk=0, wg_size=0,
+                 check=False):
+        self.wl = wl
+        self.cfg = make_config(wl, mode, chunk, wg_size, FLAG_CHECK if check else 0)
+        rc, msg = validate(self.cfg)
+        if rc:
+            raise PicError(rc, msg)
+        self.n_patches = int(lib().pic_num_patches(C.byref(self.cfg)))
+        h = C.c_void_p()
+        rc = lib().pic_init(C.byref(self.cfg), device, C.byref(h))
+        if rc:
+            raise PicError(rc, "pic_init failed")
+        self._h = h
+        self.device = torch.device("cuda", device)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().pic_free(self._h)
+            self._h = None
+
+    __del__ = close
+
+    def _raise(self, rc):
+        if rc:
+            raise PicError(rc, lib().pic_last_error(self._h).decode())
+
+    def _call_sp(self, fn, species: Sequence[Species], *args):
+        arr = (SpeciesC * len(species))(*[s.cstruct() for s in species])
+        rc = fn(self._h, arr, len(species), *args)
+        for s, cs in zip(species, arr):
+            s.adopt(cs)
+        self._raise(rc)
+
+    def bin(self, species: Sequence[Species]):
+        self._call_sp(lib().pic_bin, species, _stream())
+
+    def interp_push(self, species: Sequence[Species], E, B):
+        f = fields_struct(E, B, None)
+        self._call_sp(lib().pic_interp_push, species, C.byref(f), _stream())
+
+    def project(self, species: Sequence[Species], J):
+        f = fields_struct(None, None, J)
+        self._call_sp(lib().pic_project, species, C.byref(f), _stream())
+
+    def step(self, species: Sequence[Species], E, B, J, nsteps: int = 1):
+        f = fields_struct(E, B, J)
+        self._call_sp(lib().pic_step, species, C.byref(f), int(nsteps), _stream())
+
+    def check(self):
+        self._raise(lib().pic_check(self._h, _stream()))
+
+
+def upload(inputs, device="cuda", capacity_factor: float = 1.0) -> List[Species]:
+    """Device species from generated inputs (a list of ParticleSet)."""
+    out = []
+    npch = inputs.wl.n_patches
+    for s in inputs.species:
+        t = lambda a: torch.from_numpy(a).to(device)
+        cap = int(s.x.shape[1] * capacity_factor)
+        out.append(Species(s.q, s.m, t(s.x), t(s.u), t(s.wt), t(s.id), npch, capacity=cap))
+    return out
+
+
+def upload_fields(inputs, device="cuda"):
+    E = torch.from_numpy(inputs.E).to(device).contiguous()
+    B = torch.from_numpy(inputs.B).to(device).contiguous()
+    J = torch.zeros_like(E)
+    return E, B, J

@@ -1,0 +1,70 @@
+"""Shared helpers of the GPU parity tests: run the CPU oracle and the HIP
+library on the same generated inputs and compare them."""
+import sys
+
+import numpy as np
+
+import oracle as O
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def run_oracle(wl, inp, steps, with_abs=True):
+    sps = O.species_from(inp)
+    for s in sps:
+        O.bin(wl, s)
+    J = A = None
+    for _ in range(steps):
+        J, A = O.step(wl, sps, inp.E, inp.B, with_abs=True)
+    return sps, J, A
+
+
+def run_gpu(wl, inp, steps, mode=0, chunk=0, wg_size=0, split=False, device="cuda:0"):
+    import torch
+
+    from paper_2204_12837_amd import pic
+
+    ctx = pic.Context(wl, device=0, mode=mode, chunk=chunk, wg_size=wg_size, check=True)
+    sp = pic.upload(inp, device)
+    E, B, J = pic.upload_fields(inp, device)
+    ctx.bin(sp)
+    if split:
+        for _ in range(steps):
+            J.zero_()
+            ctx.interp_push(sp, E, B)
+            ctx.project(sp, J)
+            ctx.bin(sp)
+    else:
+        ctx.step(sp, E, B, J, nsteps=steps)
+    torch.cuda.synchronize()
+    ctx.check()
+    out = []
+    for s in sp:
+        out.append(dict(off=s.offset.cpu().numpy(), id=s.ids.cpu().numpy(),
+                        x=s.xs.cpu().numpy(), u=s.us.cpu().numpy(), w=s.ws.cpu().numpy()))
+    Jg = J.cpu().numpy() if steps > 0 else None
+    ctx.close()
+    return out, Jg
+
+
+def compare(osp, J, A, gout, Jg, exact_particles=True, rel=1e-12):
+    """Per-patch counts exact, particle order (stable sort) identical,
+    particles bit for bit (or within rel), J within rel * (sum of |terms|)."""
+    for s, g in zip(osp, gout):
+        assert np.array_equal(g["off"], s.off), "per-patch counts differ"
+        assert np.array_equal(g["id"], s.id), "particle order differs"
+        assert np.array_equal(g["w"], s.w)
+        if exact_particles:
+            assert np.array_equal(g["x"], s.x), f"x differs: {np.abs(g['x'] - s.x).max()}"
+            assert np.array_equal(g["u"], s.u), f"u differs: {np.abs(g['u'] - s.u).max()}"
+        else:
+            L = np.abs(s.x).max()
+            assert np.all(np.abs(g["x"] - s.x) <= rel * np.maximum(np.abs(s.x), 1e-3 * L))
+            assert np.all(np.abs(g["u"] - s.u) <= rel * np.maximum(np.abs(s.u), 1e-3))
+    if J is not None:
+        err = np.abs(Jg - J)
+        assert np.all(err <= rel * A + 1e-300), f"J differs: max {err.max()}, rel to A {(err / np.maximum(A, 1e-300)).max()}"
+        assert err.max() <= rel * max(np.abs(J).max(), 1e-300)

@@ -1,0 +1,94 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every entry point include/pic.h declares, and rejects bad configurations
+before touching a device."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_2204_12837_amd import inputs as I
+from paper_2204_12837_amd import pic
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    names = set()
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if fn.endswith(".h"):
+            txt = open(os.path.join(ROOT, "include", fn)).read()
+            txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+            names |= set(re.findall(r"\b(pic_[a-z_0-9]+)\s*\(", txt))
+    return names
+
+
+def test_library_exports_every_declared_symbol():
+    L = pic.lib()
+    declared = _declared()
+    assert declared, "no declarations found"
+    assert set(pic.ENTRY_POINTS) <= declared | {"pic_num_patches"}
+    for name in sorted(declared):
+        assert hasattr(L, name), name
+
+
+def _cfg(**over):
+    wl = I.workload("uniform64")
+    c = pic.make_config(wl)
+    for k, v in over.items():
+        if isinstance(v, tuple):
+            arr = getattr(c, k)
+            for i, x in enumerate(v):
+                arr[i] = x
+        else:
+            setattr(c, k, v)
+    return c
+
+
+def test_valid_configs_pass():
+    for name in ("uniform64", "uniform1024", "imbalanced", "expansion3d", "adjoint256"):
+        c = pic.make_config(I.workload(name))
+        rc, msg = pic.validate(c)
+        assert rc == pic.PIC_OK, (name, msg)
+    assert pic.lib().pic_num_patches(C.byref(pic.make_config(I.workload("uniform1024")))) == 4096
+    assert pic.lib().pic_num_patches(C.byref(pic.make_config(I.workload("expansion3d")))) == 8192
+
+
+@pytest.mark.parametrize("over,frag", [
+    (dict(dim=4), "dim"),
+    (dict(shape_order=1), "shape_order"),
+    (dict(patch=(5, 8, 1)), "below 6"),
+    (dict(patch=(12, 8, 1)), "divide"),
+    (dict(dt=1.0), "Courant"),
+    (dict(dt=-0.01), "Courant"),
+    (dict(d=(0.0, 0.1, 0.1)), "positive"),
+    (dict(mode=7), "mode"),
+    (dict(wg_size=100), "wg_size"),
+    (dict(wg_size=512), "wg_size"),
+    (dict(flags=0x80), "flag"),
+    (dict(n=(64, 64, 2)), "2D"),
+    (dict(chunk=-1), "chunk"),
+])
+def test_invalid_configs_rejected(over, frag):
+    rc, msg = pic.validate(_cfg(**over))
+    assert rc == pic.PIC_ERR_ARG
+    assert frag in msg
+
+
+def test_patch_too_large_for_lds():
+    wl = I.custom(2, (128, 128), (64, 64), ppc=1)
+    rc, msg = pic.validate(pic.make_config(wl))
+    assert rc == pic.PIC_ERR_ARG and "LDS" in msg
+    wl3 = I.custom(3, (32, 32, 32), (16, 16, 16), ppc=1)
+    rc, msg = pic.validate(pic.make_config(wl3))
+    assert rc == pic.PIC_ERR_ARG and "LDS" in msg
+
+
+def test_null_arguments():
+    L = pic.lib()
+    assert L.pic_validate_config(None, None, 0) == pic.PIC_ERR_ARG
+    assert L.pic_num_patches(None) == 0
+    assert L.pic_init(None, 0, None) == pic.PIC_ERR_ARG
+    L.pic_free(None)  # no-op
+    assert L.pic_check(None, None) == pic.PIC_ERR_ARG
+    assert L.pic_last_error(None) == b"null context"

@@ -1,0 +1,124 @@
+"""Parity of the HIP library with the CPU oracle (needs an MI355X).
+
+The bar: per-patch counts and particle order exact; particle positions and
+momenta bit for bit (the kernels repeat the oracle's operation sequence);
+J within 1e-12 of the sum of absolute contributions at each node (the only
+difference is the order of the float64 atomic additions)."""
+import numpy as np
+import pytest
+
+from paper_2204_12837_amd import inputs as I
+
+from _parity import compare, run_gpu, run_oracle, say
+
+pytestmark = pytest.mark.gpu
+
+
+def test_uniform64_ten_steps():
+    wl = I.workload("uniform64")
+    inp = I.generate(wl)
+    say("case uniform64, 10 steps, fused")
+    osp, J, A = run_oracle(wl, inp, 10)
+    g, Jg = run_gpu(wl, inp, 10)
+    compare(osp, J, A, g, Jg)
+
+
+def test_split_path_equals_oracle():
+    wl = I.workload("uniform64")
+    inp = I.generate(wl)
+    say("case uniform64, 3 steps, split interp_push / project / bin")
+    osp, J, A = run_oracle(wl, inp, 3)
+    g, Jg = run_gpu(wl, inp, 3, split=True)
+    compare(osp, J, A, g, Jg)
+
+
+@pytest.mark.parametrize("wg", [64, 128, 192])
+def test_workgroup_sizes(wg):
+    wl = I.custom(2, (48, 32), (8, 8), ppc=5, seed=40 + wg, sigma=0.1)
+    inp = I.generate(wl)
+    say(f"case 48x32 wg={wg}")
+    osp, J, A = run_oracle(wl, inp, 3)
+    g, Jg = run_gpu(wl, inp, 3, wg_size=wg)
+    compare(osp, J, A, g, Jg)
+
+
+CASES = [
+    # dim, n, patch, ppc, nspecies, sigma, steps, seed
+    (2, (36, 24), (6, 6), 3, 1, 0.2, 4, 101),
+    (2, (30, 42), (10, 7), 2, 2, 0.3, 3, 102),
+    (2, (12, 12), (6, 6), 7, 1, 0.5, 5, 103),   # 2x2 patches: neighbours alias
+    (2, (8, 16), (8, 8), 4, 1, 0.4, 3, 104),    # one patch along x
+    (3, (16, 12, 12), (8, 6, 6), 2, 2, 0.2, 3, 105),
+    (3, (12, 12, 12), (6, 6, 6), 1, 1, 0.5, 4, 106),
+    (3, (8, 16, 8), (8, 8, 8), 2, 1, 0.3, 2, 107),
+]
+
+
+@pytest.mark.parametrize("case", CASES)
+def test_random_small_configs(case):
+    dim, n, patch, ppc, nsp, sigma, steps, seed = case
+    wl = I.custom(dim, n, patch, ppc=ppc, seed=seed, sigma=sigma, n_species=nsp)
+    inp = I.generate(wl)
+    say(f"case {case}")
+    osp, J, A = run_oracle(wl, inp, steps)
+    g, Jg = run_gpu(wl, inp, steps)
+    compare(osp, J, A, g, Jg)
+
+
+def test_general_sort_from_any_order():
+    """pic_bin on unsorted particles spread over a period around the box."""
+    wl = I.custom(2, (32, 24), (8, 6), ppc=3, seed=110)
+    inp = I.generate(wl)
+    rng = np.random.default_rng(111)
+    L = np.array([wl.n[0] * wl.d[0], wl.n[1] * wl.d[1]])
+    x = inp.species[0].x
+    shift = rng.integers(-1, 2, x.shape)
+    x += shift * L[:, None] * 0.999999
+    say("case unsorted bin")
+    osp, _, _ = run_oracle(wl, inp, 0)
+    g, _ = run_gpu(wl, inp, 0)
+    compare(osp, None, None, g, None)
+
+
+def test_edge_positions():
+    """Particles exactly on patch and cell boundaries, on nodes, at the box
+    edges and just below L."""
+    wl = I.custom(2, (24, 24), (8, 8), ppc=2, seed=120, sigma=0.3)
+    inp = I.generate(wl)
+    s = inp.species[0]
+    d = wl.d[0]
+    L = wl.n[0] * d
+    vals = np.array([0.0, 8 * d, 16 * d, 0.5 * d, 7.5 * d, np.nextafter(L, 0), np.nextafter(8 * d, 0),
+                     np.nextafter(16 * d, 20 * d), 3 * d, 12 * d])
+    k = vals.size
+    s.x[0, :k] = vals
+    s.x[1, :k] = vals[::-1]
+    s.x[0, k:2 * k] = vals
+    s.x[1, k:2 * k] = 0.0
+    s.u[:, :k] = 0.0  # stay on the boundary in a zero-momentum start
+    say("case edges")
+    osp, J, A = run_oracle(wl, inp, 4)
+    g, Jg = run_gpu(wl, inp, 4)
+    compare(osp, J, A, g, Jg)
+
+
+def test_empty_and_crowded_patches():
+    """An x-profile with empty patches next to crowded ones (the imbalanced
+    workload's shape at small size)."""
+    wl = I.custom(2, (48, 24), (8, 8), ppc=1, seed=130, sigma=0.2)
+    wl.species[0].ppc = lambda ix: np.where(ix < 16, 0, np.where(ix < 24, 40, 2)).astype(np.int64)
+    inp = I.generate(wl)
+    say("case empty/crowded patches")
+    osp, J, A = run_oracle(wl, inp, 5)
+    g, Jg = run_gpu(wl, inp, 5)
+    compare(osp, J, A, g, Jg)
+
+
+def test_zero_steps_and_zero_particles():
+    wl = I.custom(2, (16, 16), (8, 8), ppc=0, seed=140)
+    inp = I.generate(wl)
+    say("case no particles")
+    osp, J, A = run_oracle(wl, inp, 2)
+    g, Jg = run_gpu(wl, inp, 2)
+    compare(osp, J, A, g, Jg)
+    assert np.all(Jg == 0)

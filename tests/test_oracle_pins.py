@@ -512,8 +512,6 @@ def test_step_species_linearity_and_order_invariance():
     sps = O.species_from(inp)
     for s in sps:
         O.bin(wl, s)
-    J_both = O.step(wl, [O.OSpecies(s.q, s.m, s.x, s.u, s.w, s.id, wl.n_patches) for s in sps],
-                    inp.E, inp.B)
     parts = []
     for s in sps:
         t = O.OSpecies(s.q, s.m, s.x, s.u, s.w, s.id, wl.n_patches)
@@ -538,7 +536,6 @@ def test_step_species_linearity_and_order_invariance():
     Jr = O.step(wl, [r], inp.E, inp.B)
     assert np.max(np.abs(Jr - parts[0])) <= 1e-14 * np.abs(parts[0]).max()
     o1, o2 = np.argsort(t.id), np.argsort(r.id)
-    t0 = parts  # noqa: F841
     # particles are identical bit for bit (each particle is independent)
     s_again = O.OSpecies(s.q, s.m, s.x, s.u, s.w, s.id, wl.n_patches)
     s_again.off[:] = s.off
@@ -600,3 +597,11 @@ def test_jvp_J_equals_step_J():
 def test_extended_build_is_extended():
     assert O.real_size(False) == 8
     assert O.real_size(True) >= 10
+
+
+def test_step_rejects_unsorted_offsets():
+    wl = I.custom(2, (16, 16), (8, 8), ppc=2, seed=22)
+    inp = I.generate(wl)
+    sp = O.species_from(inp)[0]  # offsets never computed
+    with pytest.raises(O.OracleError):
+        O.step(wl, [sp], inp.E, inp.B)
