@@ -1,0 +1,191 @@
+#!/usr/bin/env python
+"""Throughput of the PIC macro-particle step on one MI355X.
+
+One step = J <- 0, the fused Interpolation + Push + pre-BC + Projection of
+every particle, and the sort by patch (the synchronisation phase), i.e. one
+`pic_step`.  Inputs are generated (seeded, synthetic) and resident in HBM
+before the timed region starts.
+
+Prints one JSON line: particle-steps/s of the whole step, the roofline of
+the dominant kernel (the fused step kernel, HBM-bound), the imbalanced
+workload next to the uniform one, and the CPU oracle timed on a bounded
+sample on the host.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import platform
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "particle-steps/s (interp+push+project) + % HBM peak; imbalanced vs uniform"
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, vendor figure
+
+
+def algorithmic_bytes(wl, n_particles: int) -> int:
+    """Bytes the fused step kernel must move once: per particle read x (dim),
+    u (3), w and write x (dim), u (3); per cell read E, B (6) and write J (3),
+    all float64."""
+    dim = wl.dim
+    per_particle = 8 * ((dim + 3 + 1) + (dim + 3))
+    per_cell = 8 * (6 + 3)
+    return per_particle * n_particles + per_cell * wl.n_cells
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("pic_kernels.hip", "pic_common.h"):
+        with open(os.path.join(ROOT, "paper_2204_12837_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload: str):
+    """HBM bytes per launch of the fused kernel from the committed rocprofv3
+    counter summary, if it was taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", f"k_ipp_{workload}_traffic.json")
+    try:
+        with open(path) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_source_sha") != kernel_source_hash():
+        return None
+    return t.get("bytes_per_launch")
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
+
+
+def run_gpu(wl, steps: int, warmup: int, mode: int = 0, chunk: int = 0):
+    import torch
+
+    from paper_2204_12837_amd import inputs as I
+    from paper_2204_12837_amd import pic
+
+    inp = I.generate(wl)
+    n = sum(s.x.shape[1] for s in inp.species)
+    ctx = pic.Context(wl, device=0, mode=mode, chunk=chunk)
+    sp = pic.upload(inp, "cuda:0")
+    E, B, J = pic.upload_fields(inp, "cuda:0")
+    del inp
+    ctx.bin(sp)
+    if warmup:
+        ctx.step(sp, E, B, J, nsteps=warmup)
+    torch.cuda.synchronize()
+    ctx.check()
+    ctx.timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.step(sp, E, B, J, nsteps=steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ctx.check()
+    tim = ctx.timing_read()
+    ctx.timing(False)
+    ctx.close()
+    return n, t1 - t0, tim
+
+
+def cpu_baseline(sample_steps: int):
+    """The CPU oracle (serial, one core) on a strip of the uniform workload:
+    1024 x 64 cells with the same density, momenta and fields, periodic."""
+    import oracle as O
+    from paper_2204_12837_amd import inputs as I
+
+    wl = I.workload("uniform1024", n=(1024, 64, 1), seed=2002)
+    inp = I.generate(wl)
+    sps = O.species_from(inp)
+    for s in sps:
+        O.bin(wl, s)
+    n = sum(s.n for s in sps)
+    t0 = time.perf_counter()
+    for _ in range(sample_steps):
+        O.step(wl, sps, inp.E, inp.B)
+    dt = time.perf_counter() - t0
+    return {"value": n * sample_steps / dt, "unit": "particle-steps/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"uniform plasma strip 1024x64 cells, 32 ppc ({n} particles), "
+                      f"{sample_steps} steps, serial scalar C on {cpu_model()}",
+            "seconds": round(dt, 3)}
+
+
+def main(argv=None) -> int:
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="uniform1024")
+    ap.add_argument("--no-imbalanced", action="store_true", help="skip the imbalanced workload")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-steps", type=int, default=8)
+    args = ap.parse_args(argv)
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(see DESIGN.md for how the step would shard)", file=sys.stderr)
+        return 2
+
+    from paper_2204_12837_amd import inputs as I
+
+    wl = I.workload(args.workload)
+    n, secs, tim = run_gpu(wl, args.steps, args.warmup)
+    value = n * args.steps / secs
+    ipp_ms, ipp_n = tim["ipp"]
+    ipp_avg = ipp_ms / max(ipp_n, 1)
+    abytes = algorithmic_bytes(wl, n)
+    achieved = abytes / (ipp_avg * 1e-3) / 1e9
+    traffic = measured_traffic(args.workload)
+    per_kernel = {k: round(v[0] / max(v[1], 1), 4) for k, v in tim.items() if v[1]}
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "particle-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": secs / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "dim": wl.dim, "cells": list(wl.n[:wl.dim]),
+                   "patch": list(wl.patch[:wl.dim]), "particles": n,
+                   "species": len(wl.species), "mode": "per_patch"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": "k_ipp", "algorithmic_bytes": abytes, "avg_ms": ipp_avg},
+        "kernel_ms": per_kernel,
+        "interp_push_project_rate": n / (ipp_avg * 1e-3),
+    }
+    if not args.no_imbalanced:
+        wli = I.workload("imbalanced")
+        ni, si, ti = run_gpu(wli, args.steps, args.warmup)
+        ns_u = secs / (n * args.steps) * 1e9
+        ns_i = si / (ni * args.steps) * 1e9
+        out["imbalanced"] = {"workload": "imbalanced", "particles": ni, "mode": "per_patch",
+                             "ns_per_particle_step": ns_i, "uniform_ns_per_particle_step": ns_u,
+                             "ratio_vs_uniform": ns_i / ns_u,
+                             "kernel_ms": {k: round(v[0] / max(v[1], 1), 4)
+                                           for k, v in ti.items() if v[1]}}
+    out["cpu_baseline"] = None if args.no_cpu_baseline else cpu_baseline(args.cpu_steps)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

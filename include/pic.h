@@ -152,6 +152,27 @@ pic_status pic_project(pic_ctx *ctx, const pic_species *sp, int32_t nsp, pic_fie
 pic_status pic_step(pic_ctx *ctx, pic_species *sp, int32_t nsp, pic_fields *f, int32_t nsteps,
                     void *stream);
 
+/* Kernel classes whose launches the context can time. */
+enum {
+  PIC_KERNEL_ZERO = 0,        /* J <- 0 */
+  PIC_KERNEL_IPP = 1,         /* fused Interpolation + Push + pre-BC + Projection */
+  PIC_KERNEL_REBIN = 2,       /* neighbour-code counting sort (bases, scan, scatter) */
+  PIC_KERNEL_INTERP_PUSH = 3, /* split path: Interpolation + Push */
+  PIC_KERNEL_PROJECT = 4,     /* split path: Projection */
+  PIC_KERNEL_TAG = 5,         /* split path: pre-BC codes and ranks */
+  PIC_KERNEL_SORT = 6,        /* general sort of unsorted input */
+  PIC_KERNEL_COUNT = 7
+};
+
+/* Observability: when on, every later launch of a kernel class is bracketed
+ * by HIP events recorded on the caller's stream.  Turning it on clears the
+ * totals.  Costs two event records per launch. */
+pic_status pic_timing_enable(pic_ctx *ctx, int32_t on);
+
+/* Total milliseconds and number of launches of a kernel class since timing
+ * was enabled.  Waits for the recorded events. */
+pic_status pic_timing_read(pic_ctx *ctx, int32_t kernel, double *total_ms, int64_t *launches);
+
 /* Wait for `stream` and report the sticky device error word. */
 pic_status pic_check(pic_ctx *ctx, void *stream);
 

@@ -9,6 +9,8 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <utility>
+#include <vector>
 
 #include "pic.h"
 #include "pic_common.h"
@@ -30,8 +32,19 @@ constexpr size_t kStaticLds = 2 * 4 * 27 * 4 + 27 * 4 + 64;  // ranking scratch 
 
 }  // namespace
 
+// Event pairs around timed launches, per kernel class.
+struct Timing {
+  bool on = false;
+  std::vector<hipEvent_t> pool;   // reusable events
+  size_t used = 0;
+  std::vector<std::pair<int, size_t>> marks;  // (kernel class, index of start event)
+  double ms[PIC_KERNEL_COUNT] = {0};
+  int64_t launches[PIC_KERNEL_COUNT] = {0};
+};
+
 struct pic_ctx {
   pic_config cfg;
+  Timing tm;
   GridDev g;
   int device = 0;
   int wg = 256;
@@ -212,6 +225,48 @@ void swap_buffers(pic_species &p) {
   std::swap(p.id, p.id_alt);
 }
 
+// Fold finished event pairs into the totals (waits for them).
+void timing_collect(pic_ctx *c) {
+  Timing &t = c->tm;
+  for (auto &m : t.marks) {
+    float ms = 0.f;
+    if (hipEventSynchronize(t.pool[m.second + 1]) == hipSuccess &&
+        hipEventElapsedTime(&ms, t.pool[m.second], t.pool[m.second + 1]) == hipSuccess) {
+      t.ms[m.first] += ms;
+      t.launches[m.first] += 1;
+    }
+  }
+  t.marks.clear();
+  t.used = 0;
+}
+
+// Record one event of a timed launch; returns its pool index (or -1).
+long timing_event(pic_ctx *c, hipStream_t st) {
+  Timing &t = c->tm;
+  if (!t.on) return -1;
+  if (t.used == t.pool.size()) {
+    if (t.pool.size() >= 4096) timing_collect(c);
+    if (t.used == t.pool.size()) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) return -1;
+      t.pool.push_back(e);
+    }
+  }
+  const size_t k = t.used++;
+  if (hipEventRecord(t.pool[k], st) != hipSuccess) return -1;
+  return (long)k;
+}
+
+// Bracket the launches made by fn() with events when timing is on.
+template <typename F>
+hipError_t timed(pic_ctx *c, int kind, hipStream_t st, F &&fn) {
+  const long a = timing_event(c, st);
+  hipError_t e = fn();
+  const long b = timing_event(c, st);
+  if (a >= 0 && b == a + 1) c->tm.marks.push_back({kind, (size_t)a});
+  return e;
+}
+
 pic_status finish(pic_ctx *c, hipStream_t st) {
   if (c->cfg.flags & PIC_FLAG_CHECK) return pic_check(c, st);
   return PIC_OK;
@@ -360,8 +415,30 @@ void pic_free(pic_ctx *c) {
     for (int a = 0; a < 3; a++) (void)hipFree(S.x0[a]);
     free_sort_scratch(c->sort[s]);
   }
+  for (hipEvent_t e : c->tm.pool) (void)hipEventDestroy(e);
   (void)hipFree(c->err_dev);
   delete c;
+}
+
+pic_status pic_timing_enable(pic_ctx *c, int32_t on) {
+  if (!c) return PIC_ERR_ARG;
+  if (hipSetDevice(c->device) != hipSuccess) return fail(c, PIC_ERR_HIP, "hipSetDevice");
+  timing_collect(c);
+  for (int k = 0; k < PIC_KERNEL_COUNT; k++) {
+    c->tm.ms[k] = 0;
+    c->tm.launches[k] = 0;
+  }
+  c->tm.on = on != 0;
+  return PIC_OK;
+}
+
+pic_status pic_timing_read(pic_ctx *c, int32_t kernel, double *total_ms, int64_t *launches) {
+  if (!c || kernel < 0 || kernel >= PIC_KERNEL_COUNT) return PIC_ERR_ARG;
+  if (hipSetDevice(c->device) != hipSuccess) return fail(c, PIC_ERR_HIP, "hipSetDevice");
+  timing_collect(c);
+  if (total_ms) *total_ms = c->tm.ms[kernel];
+  if (launches) *launches = c->tm.launches[kernel];
+  return PIC_OK;
 }
 
 pic_status pic_check(pic_ctx *c, void *stream) {
@@ -396,14 +473,18 @@ pic_status pic_bin(pic_ctx *c, pic_species *sp, int32_t nsp, void *stream) {
     // particles moved at most one cell since the last sort: neighbour-code sort
     if ((r = ensure_scratch(c, sp, nsp, false, st)) != PIC_OK) return r;
     const SpArgs a = make_args(c, sp, nsp);
-    hipError_t e = launch_tag(c->g, a, c->err_dev, c->wg, st);
-    if (e == hipSuccess) e = launch_rebin(c->g, a, c->err_dev, c->wg, st);
+    hipError_t e =
+        timed(c, PIC_KERNEL_TAG, st, [&] { return launch_tag(c->g, a, c->err_dev, c->wg, st); });
+    if (e == hipSuccess)
+      e = timed(c, PIC_KERNEL_REBIN, st,
+                [&] { return launch_rebin(c->g, a, c->err_dev, c->wg, st); });
     if (e != hipSuccess) return hip_fail(c, e, "kernel launch");
   } else {
     for (int s = 0; s < nsp; s++) {
       const SpArgs a = make_args(c, sp + s, 1);
       SpDev d = a.s[0];
-      hipError_t e = general_sort(c->g, d, c->sort[s], c->err_dev, st);
+      hipError_t e = timed(c, PIC_KERNEL_SORT, st,
+                           [&] { return general_sort(c->g, d, c->sort[s], c->err_dev, st); });
       if (e != hipSuccess) return hip_fail(c, e, "general sort");
     }
   }
@@ -422,7 +503,9 @@ pic_status pic_interp_push(pic_ctx *c, pic_species *sp, int32_t nsp, const pic_f
   if (hipSetDevice(c->device) != hipSuccess) return fail(c, PIC_ERR_HIP, "hipSetDevice");
   if ((r = ensure_scratch(c, sp, nsp, true, st)) != PIC_OK) return r;
   const SpArgs a = make_args(c, sp, nsp);
-  hipError_t e = launch_interp_push(c->g, a, f->e, f->b, c->err_dev, c->wg, st);
+  hipError_t e = timed(c, PIC_KERNEL_INTERP_PUSH, st, [&] {
+    return launch_interp_push(c->g, a, f->e, f->b, c->err_dev, c->wg, st);
+  });
   if (e != hipSuccess) return hip_fail(c, e, "kernel launch");
   c->moved = true;
   c->moved_nsp = nsp;
@@ -439,7 +522,8 @@ pic_status pic_project(pic_ctx *c, const pic_species *sp, int32_t nsp, pic_field
   hipStream_t st = (hipStream_t)stream;
   if (hipSetDevice(c->device) != hipSuccess) return fail(c, PIC_ERR_HIP, "hipSetDevice");
   const SpArgs a = make_args(c, sp, nsp);
-  hipError_t e = launch_project(c->g, a, f->j, c->err_dev, c->wg, st);
+  hipError_t e = timed(c, PIC_KERNEL_PROJECT, st,
+                       [&] { return launch_project(c->g, a, f->j, c->err_dev, c->wg, st); });
   if (e != hipSuccess) return hip_fail(c, e, "kernel launch");
   return finish(c, st);
 }
@@ -458,9 +542,14 @@ pic_status pic_step(pic_ctx *c, pic_species *sp, int32_t nsp, pic_fields *f, int
   for (int a = 0; a < c->cfg.dim; a++) ncell *= c->cfg.n[a];
   for (int k = 0; k < nsteps; k++) {
     const SpArgs a = make_args(c, sp, nsp);
-    hipError_t e = launch_zero(f->j, ncell, st);
-    if (e == hipSuccess) e = launch_ipp(c->g, a, f->e, f->b, f->j, c->err_dev, c->wg, st);
-    if (e == hipSuccess) e = launch_rebin(c->g, a, c->err_dev, c->wg, st);
+    hipError_t e = timed(c, PIC_KERNEL_ZERO, st, [&] { return launch_zero(f->j, ncell, st); });
+    if (e == hipSuccess)
+      e = timed(c, PIC_KERNEL_IPP, st, [&] {
+        return launch_ipp(c->g, a, f->e, f->b, f->j, c->err_dev, c->wg, st);
+      });
+    if (e == hipSuccess)
+      e = timed(c, PIC_KERNEL_REBIN, st,
+                [&] { return launch_rebin(c->g, a, c->err_dev, c->wg, st); });
     if (e != hipSuccess) return hip_fail(c, e, "kernel launch");
     for (int s = 0; s < nsp; s++) swap_buffers(sp[s]);
   }

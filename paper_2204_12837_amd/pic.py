@@ -50,7 +50,9 @@ class FieldsC(C.Structure):
 
 
 ENTRY_POINTS = ("pic_validate_config", "pic_num_patches", "pic_init", "pic_free", "pic_bin",
-                "pic_interp_push", "pic_project", "pic_step", "pic_check", "pic_last_error")
+                "pic_interp_push", "pic_project", "pic_step", "pic_check", "pic_last_error",
+                "pic_timing_enable", "pic_timing_read")
+KERNELS = {"zero": 0, "ipp": 1, "rebin": 2, "interp_push": 3, "project": 4, "tag": 5, "sort": 6}
 
 _lib_handle = None
 
@@ -84,6 +86,11 @@ def lib():
         L.pic_step.restype = C.c_int
         L.pic_check.argtypes = [C.c_void_p, C.c_void_p]
         L.pic_check.restype = C.c_int
+        L.pic_timing_enable.argtypes = [C.c_void_p, C.c_int32]
+        L.pic_timing_enable.restype = C.c_int
+        L.pic_timing_read.argtypes = [C.c_void_p, C.c_int32, C.POINTER(C.c_double),
+                                      C.POINTER(C.c_int64)]
+        L.pic_timing_read.restype = C.c_int
         L.pic_last_error.argtypes = [C.c_void_p]
         L.pic_last_error.restype = C.c_char_p
         _lib_handle = L
@@ -246,6 +253,18 @@ class Context:
 
     def check(self):
         self._raise(lib().pic_check(self._h, _stream()))
+
+    def timing(self, on: bool = True):
+        self._raise(lib().pic_timing_enable(self._h, 1 if on else 0))
+
+    def timing_read(self):
+        """{kernel class: (total ms, launches)} since timing was enabled."""
+        out = {}
+        for name, k in KERNELS.items():
+            ms, n = C.c_double(), C.c_int64()
+            self._raise(lib().pic_timing_read(self._h, k, C.byref(ms), C.byref(n)))
+            out[name] = (ms.value, n.value)
+        return out
 
 
 def upload(inputs, device="cuda", capacity_factor: float = 1.0) -> List[Species]:
