@@ -259,7 +259,8 @@ void orc_boris_traj(double q, double m, double dt, int32_t dim, const double E[3
  *      Jy likewise along y; Jz[...] += q w vz Wz.
  * 3D:  Wx = DSx (S0y S0z + DSy S0z/2 + S0y DSz/2 + DSy DSz/3), y, z cyclic,
  *      each J component the running sum along its own axis.
- * Jx entry i sits at (i + 1/2) dx, as Ex.  A[c] collects |contribution|. */
+ * Jx entry i sits at (i + 1/2) dx, as Ex.  A[c] collects, per node, the
+ * absolute values of all products entering the node's contributions. */
 typedef struct {
   int64_t i0[3];
   real S0[3][5], DS[3][5];
@@ -286,11 +287,14 @@ static int build_stencil(const G *g, const real x0[3], const real x1[3], stencil
   return ORC_OK;
 }
 
+/* J[c] += v at node (i,j,k); A[c] += a, where a is the sum of the absolute
+ * values of every product that entered v (the scale of v's rounding error,
+ * which stays meaningful where the exact value of v is zero). */
 static void add_node(const G *g, real *const J[3], real *const A[3], int c, int64_t i, int64_t j,
-                     int64_t k, real v) {
+                     int64_t k, real v, real a) {
   int64_t at = node(g, i, j, k);
   J[c][at] += v;
-  if (A) A[c][at] += fabs(v);
+  if (A) A[c][at] += a;
 }
 
 static int deposit(const G *g, real q, real w, const real x0[3], const real x1[3], real vz,
@@ -306,24 +310,28 @@ static int deposit(const G *g, real q, real w, const real x0[3], const real x1[3
     const real cy = -(q * w) * (g->d[1] / g->dt);
     const real cz = (q * w) * vz;
     for (int t = 0; t < 5; t++) {
-      real acc = 0;
+      real acc = 0, sc = 0;
       for (int r = 0; r < 4; r++) {
         acc = acc + DS[0][r] * (S0[1][t] + half * DS[1][t]);
-        add_node(g, J, A, 0, i0[0] - 2 + r, i0[1] - 2 + t, 0, cx * acc);
+        sc += fabs(DS[0][r]) * (fabs(S0[1][t]) + half * fabs(DS[1][t]));
+        add_node(g, J, A, 0, i0[0] - 2 + r, i0[1] - 2 + t, 0, cx * acc, fabs(cx) * sc);
       }
     }
     for (int r = 0; r < 5; r++) {
-      real acc = 0;
+      real acc = 0, sc = 0;
       for (int t = 0; t < 4; t++) {
         acc = acc + DS[1][t] * (S0[0][r] + half * DS[0][r]);
-        add_node(g, J, A, 1, i0[0] - 2 + r, i0[1] - 2 + t, 0, cy * acc);
+        sc += fabs(DS[1][t]) * (fabs(S0[0][r]) + half * fabs(DS[0][r]));
+        add_node(g, J, A, 1, i0[0] - 2 + r, i0[1] - 2 + t, 0, cy * acc, fabs(cy) * sc);
       }
     }
     for (int t = 0; t < 5; t++)
       for (int r = 0; r < 5; r++) {
         real wz = S0[0][r] * S0[1][t] + half * DS[0][r] * S0[1][t] + half * S0[0][r] * DS[1][t] +
                   third * DS[0][r] * DS[1][t];
-        add_node(g, J, A, 2, i0[0] - 2 + r, i0[1] - 2 + t, 0, cz * wz);
+        real sc = fabs(S0[0][r] * S0[1][t]) + half * fabs(DS[0][r] * S0[1][t]) +
+                  half * fabs(S0[0][r] * DS[1][t]) + third * fabs(DS[0][r] * DS[1][t]);
+        add_node(g, J, A, 2, i0[0] - 2 + r, i0[1] - 2 + t, 0, cz * wz, fabs(cz) * sc);
       }
     return ORC_OK;
   }
@@ -334,16 +342,20 @@ static int deposit(const G *g, real q, real w, const real x0[3], const real x1[3
     const int b = (a + 1) % 3, c = (a + 2) % 3;
     for (int tb = 0; tb < 5; tb++)
       for (int tc = 0; tc < 5; tc++) {
-        real acc = 0;
+        real acc = 0, sc = 0;
+        const real fsc = fabs(S0[b][tb] * S0[c][tc]) + half * fabs(DS[b][tb] * S0[c][tc]) +
+                         half * fabs(S0[b][tb] * DS[c][tc]) + third * fabs(DS[b][tb] * DS[c][tc]);
         for (int ta = 0; ta < 4; ta++) {
           real wa = DS[a][ta] * (S0[b][tb] * S0[c][tc] + half * DS[b][tb] * S0[c][tc] +
                                  half * S0[b][tb] * DS[c][tc] + third * DS[b][tb] * DS[c][tc]);
           acc = acc + wa;
+          sc += fabs(DS[a][ta]) * fsc;
           int64_t o[3];
           o[a] = ta;
           o[b] = tb;
           o[c] = tc;
-          add_node(g, J, A, a, i0[0] - 2 + o[0], i0[1] - 2 + o[1], i0[2] - 2 + o[2], c3[a] * acc);
+          add_node(g, J, A, a, i0[0] - 2 + o[0], i0[1] - 2 + o[1], i0[2] - 2 + o[2], c3[a] * acc,
+                   fabs(c3[a]) * sc);
         }
       }
   }

@@ -66,7 +66,8 @@ void orc_boris_traj(double q, double m, double dt, int32_t dim, const double E[3
 
 /* Esirkepov deposit of one particle moving from x0 (wrapped) to x1
  * (unwrapped), out-of-plane velocity vz (2D only).  J[c] += contribution;
- * A[c] += |contribution| if A != NULL.  Returns ORC_ERR_CFL if the particle
+ * if A != NULL, A[c] += the sum of the absolute values of the products that
+ * make up the contribution (the scale of its rounding error).  Returns ORC_ERR_CFL if the particle
  * moves more than one node along an axis. */
 int orc_deposit(const orc_grid *g, double q, double w, const double x0[3],
                 const double x1[3], double vz, double *const J[3], double *const A[3]);
@@ -78,8 +79,8 @@ int orc_bin(const orc_grid *g, orc_species *s);
 /* One PIC step of the macro-particle operators for nsp species already
  * sorted by patch (s->off valid): J <- 0, then per patch, per species,
  * Interpolation, Push, pre-BC, Projection; then the periodic boundary
- * condition and the sort.  A (optional) receives the per-node sum of
- * |contributions|. */
+ * condition and the sort.  A (optional) receives, per node, the sum of the
+ * absolute values of all products that entered J there. */
 int orc_step(const orc_grid *g, orc_species *sp, int32_t nsp, const double *const E[3],
              const double *const B[3], double *const J[3], double *const A[3]);
 
