@@ -124,6 +124,25 @@ def cpu_baseline(sample_steps: int):
             "seconds": round(dt, 3)}
 
 
+def copy_calibration(gib: float) -> int:
+    """A plain float64 device-to-device copy of known size: reads and writes
+    `gib` GiB each per launch."""
+    import torch
+
+    n = int(gib * 2 ** 30 / 8)
+    src = torch.rand(n, dtype=torch.float64, device="cuda:0")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(5):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / 5
+    print(json.dumps({"copy_bytes_each_way": n * 8, "ms": dt * 1e3,
+                      "GBps_read_plus_write": 2 * n * 8 / dt / 1e9}), flush=True)
+    return 0
+
+
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -133,7 +152,12 @@ def main(argv=None) -> int:
     ap.add_argument("--no-imbalanced", action="store_true", help="skip the imbalanced workload")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=8)
+    ap.add_argument("--copy-calibration", type=float, default=0.0, metavar="GIB",
+                    help="only run a plain device copy of this many GiB (5 times), to scale "
+                         "HBM traffic counters")
     args = ap.parse_args(argv)
+    if args.copy_calibration > 0:
+        return copy_calibration(args.copy_calibration)
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
               "(see DESIGN.md for how the step would shard)", file=sys.stderr)

@@ -183,11 +183,14 @@ __device__ __forceinline__ void boris(double alpha, const double F[6], double u[
   v[2] = u[2] * ig;
 }
 
-// Five-slot Esirkepov weights along one axis: S0 at the start position, DS =
-// S1 - S0 with S1 shifted by m = i1 - i0 in {-1, 0, 1}.  Returns false on a
-// larger shift.  i0t = tile index of slot 0 (tile origin = patch origin - 2).
-__device__ __forceinline__ bool esk_axis(double xi0, double xi1, int org2, double S0[5],
-                                         double DS[5], int &i0t) {
+// Esirkepov weights along one axis on the four nodes that the start and end
+// stencils can cover.  With i0, i1 the nearest primal nodes of the start and
+// end positions and m = i1 - i0 in {-1, 0, 1}, the window starts at node
+// b = i0 - 1 + min(m, 0); S0 (start shape), DS = S1 - S0 are given on nodes
+// b..b+3 (for m = 0 the fourth entry is zero).  Returns false on a larger
+// shift.  it = tile index of node b (tile origin = patch origin - 2).
+__device__ __forceinline__ bool esk_axis(double xi0, double xi1, int org2, double S0[4],
+                                         double DS[4], int &it) {
   double d0, d1;
   const int k0 = locate0(xi0, d0);
   const int k1 = locate0(xi1, d1);
@@ -196,30 +199,31 @@ __device__ __forceinline__ bool esk_axis(double xi0, double xi1, int org2, doubl
   double a0, a1, a2, b0, b1, b2;
   shape_w(d0, a0, a1, a2);
   shape_w(d1, b0, b1, b2);
-  S0[0] = 0.0;
-  S0[1] = a0;
-  S0[2] = a1;
-  S0[3] = a2;
-  S0[4] = 0.0;
-  double S1[5];
-  S1[0] = m == -1 ? b0 : 0.0;
-  S1[1] = m == -1 ? b1 : (m == 0 ? b0 : 0.0);
-  S1[2] = m == -1 ? b2 : (m == 0 ? b1 : b0);
-  S1[3] = m == -1 ? 0.0 : (m == 0 ? b2 : b1);
-  S1[4] = m == 1 ? b2 : 0.0;
+  const bool lo = m < 0;  // window shifted one node down
+  S0[0] = lo ? 0.0 : a0;
+  S0[1] = lo ? a0 : a1;
+  S0[2] = lo ? a1 : a2;
+  S0[3] = lo ? a2 : 0.0;
+  double S1[4];
+  S1[0] = m > 0 ? 0.0 : b0;
+  S1[1] = m > 0 ? b0 : b1;
+  S1[2] = m > 0 ? b1 : b2;
+  S1[3] = m > 0 ? b2 : 0.0;
 #pragma unroll
-  for (int r = 0; r < 5; r++) DS[r] = S1[r] - S0[r];
-  i0t = (k0 - 2) - org2;  // slot 0 is node k0 - 2
+  for (int r = 0; r < 4; r++) DS[r] = S1[r] - S0[r];
+  it = (k0 - 1 + (lo ? -1 : 0)) - org2;
   return true;
 }
 
 // Esirkepov deposit of one particle into the LDS J tile (3 components of TJn
-// entries, TJx x TJy (x TJz)).  qw = q*w.
+// entries, TJx x TJy (x TJz)).  qw = q*w.  The running sum along each
+// component's own axis vanishes at the last window node, so each component
+// has 3 nonzero entries along its axis: 2D 12 + 12 + 16 adds, 3D 3 x 48.
 template <int DIM>
 __device__ __forceinline__ bool deposit(const GridDev &g, double *tJ, int TJn, int TJx, int TJxy,
                                         const int org2[3], double qw, const double xi0[3],
                                         const double xi1[3], double vz) {
-  double S0[3][5], DS[3][5];
+  double S0[3][4], DS[3][4];
   int it[3];
 #pragma unroll
   for (int a = 0; a < DIM; a++)
@@ -230,33 +234,33 @@ __device__ __forceinline__ bool deposit(const GridDev &g, double *tJ, int TJn, i
     const double cy = -qw * g.d_over_dt[1];
     const double cz = qw * vz;
 #pragma unroll
-    for (int t = 0; t < 5; t++) {
+    for (int t = 0; t < 4; t++) {
       const double fy = S0[1][t] + 0.5 * DS[1][t];
       double acc = 0.0;
       double *row = Jx + (it[1] + t) * TJx + it[0];
 #pragma unroll
-      for (int r = 0; r < 4; r++) {
+      for (int r = 0; r < 3; r++) {
         acc = acc + DS[0][r] * fy;
         lds_add(row + r, cx * acc);
       }
     }
 #pragma unroll
-    for (int r = 0; r < 5; r++) {
+    for (int r = 0; r < 4; r++) {
       const double fx = S0[0][r] + 0.5 * DS[0][r];
       double acc = 0.0;
       double *col = Jy + it[1] * TJx + it[0] + r;
 #pragma unroll
-      for (int t = 0; t < 4; t++) {
+      for (int t = 0; t < 3; t++) {
         acc = acc + DS[1][t] * fx;
         lds_add(col + t * TJx, cy * acc);
       }
     }
     const double third = 1.0 / 3.0;
 #pragma unroll
-    for (int t = 0; t < 5; t++) {
+    for (int t = 0; t < 4; t++) {
       double *row = Jz + (it[1] + t) * TJx + it[0];
 #pragma unroll
-      for (int r = 0; r < 5; r++) {
+      for (int r = 0; r < 4; r++) {
         const double wz = S0[0][r] * S0[1][t] + 0.5 * DS[0][r] * S0[1][t] +
                           0.5 * S0[0][r] * DS[1][t] + third * DS[0][r] * DS[1][t];
         lds_add(row + r, cz * wz);
@@ -271,16 +275,16 @@ __device__ __forceinline__ bool deposit(const GridDev &g, double *tJ, int TJn, i
       double *Ja = tJ + a * TJn;
       const double ca = -qw * g.d_over_dt[a];
 #pragma unroll
-      for (int tb = 0; tb < 5; tb++) {
+      for (int tb = 0; tb < 4; tb++) {
 #pragma unroll
-        for (int tc = 0; tc < 5; tc++) {
+        for (int tc = 0; tc < 4; tc++) {
           const double f = S0[b][tb] * S0[c][tc] + 0.5 * DS[b][tb] * S0[c][tc] +
                            0.5 * S0[b][tb] * DS[c][tc] + third * DS[b][tb] * DS[c][tc];
           double acc = 0.0;
           double *line = Ja + it[0] * stride[0] + it[1] * stride[1] + it[2] * stride[2] +
                          tb * stride[b] + tc * stride[c];
 #pragma unroll
-          for (int ta = 0; ta < 4; ta++) {
+          for (int ta = 0; ta < 3; ta++) {
             acc = acc + DS[a][ta] * f;
             lds_add(line + ta * stride[a], ca * acc);
           }
