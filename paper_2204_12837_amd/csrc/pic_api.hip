@@ -168,7 +168,8 @@ pic_status ensure_scratch(pic_ctx *c, const pic_species *sp, int32_t nsp, bool x
       const size_t np = (size_t)c->g.npatch, nc = (size_t)c->g.nc;
       if ((e = realloc_dev(S.tag, (size_t)cap)) != hipSuccess) return hip_fail(c, e, "hipMalloc");
       if (!S.cnt) {
-        if ((e = realloc_dev(S.cnt, np * nc)) != hipSuccess) return hip_fail(c, e, "hipMalloc");
+        if ((e = realloc_dev(S.cnt, np * nc * (size_t)c->g.upp)) != hipSuccess)
+          return hip_fail(c, e, "hipMalloc");
         if ((e = realloc_dev(S.rbase, np * nc)) != hipSuccess) return hip_fail(c, e, "hipMalloc");
         if ((e = realloc_dev(S.in, np)) != hipSuccess) return hip_fail(c, e, "hipMalloc");
         if ((e = realloc_dev(S.noff, np + 1)) != hipSuccess) return hip_fail(c, e, "hipMalloc");
@@ -391,6 +392,7 @@ pic_status pic_init(const pic_config *cfg, int32_t device, pic_ctx **out) {
   c->g = make_grid(&c->cfg);
   c->device = device;
   c->wg = cfg->wg_size ? cfg->wg_size : 256;
+  c->g.upp = c->wg / 64;
   if (hipMalloc(&c->err_dev, sizeof(int)) != hipSuccess ||
       hipMemset(c->err_dev, 0, sizeof(int)) != hipSuccess) {
     (void)hipFree(c->err_dev);

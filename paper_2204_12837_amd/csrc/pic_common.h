@@ -20,6 +20,8 @@ struct GridDev {
   int np[3];      // patches per axis
   int npatch;     // total patches
   int nc;         // neighbour codes: 3^dim
+  int upp;        // ranking units per patch (waves per workgroup): each wave ranks
+                  // its own contiguous share of a patch's particles
   double inv_d[3];
   double L[3];    // n * d
   double dt;
@@ -38,7 +40,7 @@ struct SpDev {
   int64_t *off;     // [npatch+1] current patch offsets
   int64_t *noff;    // [npatch+1] scratch: offsets after the sort
   uint32_t *tag;    // [capacity] neighbour code << 27 | rank inside (unit, code)
-  int32_t *cnt;     // [units * nc] particles per (unit, code)
+  int32_t *cnt;     // [npatch * upp * nc] particles per (ranking unit, code)
   int64_t *rbase;   // [npatch * nc] start of (patch, code) inside its destination
   int64_t *in;      // [npatch] particles arriving in each destination patch
   double *x0[3];    // saved start-of-step positions (split path)

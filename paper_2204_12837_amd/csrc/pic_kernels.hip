@@ -17,8 +17,10 @@
 //  * particles are read and written in structure-of-arrays order, so a wave
 //    reads 64 consecutive doubles per array;
 //  * pre-BC computes the destination patch of every particle as one of the
-//    3^dim neighbour codes, and a stable per-code rank from wave ballots;
-//    the sort is then a counting sort over those codes (no global atomics).
+//    3^dim neighbour codes, and a stable per-code rank from wave ballots.
+//    Each wave ranks its own contiguous share of the patch (a "ranking
+//    unit"), so the particle loop has no workgroup barrier; the sort is then a
+//    counting sort over (unit, code) (no global atomics).
 //
 // Floating point: this file is compiled with -ffp-contract=off.  The
 // interpolation, the push and the patch key repeat the CPU oracle's
@@ -35,6 +37,12 @@ namespace pic {
 namespace {
 
 constexpr int kWaveMax = 4;  // up to 256 threads per workgroup
+
+// Unit length: each of a workgroup's nw waves ranks a contiguous share of a
+// patch's n particles, a multiple of 64 long.
+__device__ __forceinline__ int unit_len(int n, int nw) {
+  return ((n + 64 * nw - 1) / (64 * nw)) * 64;
+}
 
 __device__ __forceinline__ int wrap_near(int k, int n) {
   // k is within one period of [0, n)
@@ -136,26 +144,73 @@ __device__ __forceinline__ double gather(const double *t, int Tx, int Txy, const
   }
 }
 
-// Interpolate E and B at xi from the staged tile (6 components of TE each).
+// Gather a pair of components stored interleaved (a, b) per node (2D: the
+// pairs (Ex, By) and (Ey, Bx) share their staggering), with the same
+// operation order as gather<2> for each of them.
+__device__ __forceinline__ void gather_pair(const double2 *t, int Tx, const Sh &sx, const Sh &sy,
+                                            double &fa, double &fb) {
+  const double2 *r = t + sy.i * Tx + sx.i;
+  double ra[3], rb[3];
+#pragma unroll
+  for (int b = 0; b < 3; b++) {
+    const double2 q0 = r[0], q1 = r[1], q2 = r[2];
+    double va = sx.s[0] * q0.x;
+    va = va + sx.s[1] * q1.x;
+    va = va + sx.s[2] * q2.x;
+    double vb = sx.s[0] * q0.y;
+    vb = vb + sx.s[1] * q1.y;
+    vb = vb + sx.s[2] * q2.y;
+    ra[b] = va;
+    rb[b] = vb;
+    r += Tx;
+  }
+  double a = sy.s[0] * ra[0];
+  a = a + sy.s[1] * ra[1];
+  a = a + sy.s[2] * ra[2];
+  double bb = sy.s[0] * rb[0];
+  bb = bb + sy.s[1] * rb[1];
+  bb = bb + sy.s[2] * rb[2];
+  fa = a;
+  fb = bb;
+}
+
+// Shapes of a position on every axis: primal (p) and dual (d) stagger.
+struct Shapes {
+  Sh p[3], d[3];
+};
+
+template <int DIM>
+__device__ __forceinline__ Shapes shapes_at(const double xi[3], const int org[3]) {
+  Shapes s;
+#pragma unroll
+  for (int a = 0; a < DIM; a++) {
+    s.p[a] = axis_shape<0>(xi[a], org[a]);
+    s.d[a] = axis_shape<1>(xi[a], org[a]);
+  }
+  if constexpr (DIM == 2) s.p[2] = s.d[2] = Sh{{0.0, 1.0, 0.0}, 0};
+  return s;
+}
+
+// E/B tile layout.  2D: [(Ex,By) pairs | (Ey,Bx) pairs | Ez | Bz], each block
+// TE nodes; 3D: Ex, Ey, Ez, Bx, By, Bz, TE doubles each.
+// Stagger bits: Ex(1,0,0) Ey(0,1,0) Ez(0,0,1) Bx(0,1,1) By(1,0,1) Bz(1,1,0).
 template <int DIM>
 __device__ __forceinline__ void interp6(const double *tile, int TE, int Tx, int Txy,
-                                        const double xi[3], const int org[3], double F[6]) {
-  const Sh x0 = axis_shape<0>(xi[0], org[0]), x1 = axis_shape<1>(xi[0], org[0]);
-  const Sh y0 = axis_shape<0>(xi[1], org[1]), y1 = axis_shape<1>(xi[1], org[1]);
-  Sh z0, z1;
-  if constexpr (DIM == 3) {
-    z0 = axis_shape<0>(xi[2], org[2]);
-    z1 = axis_shape<1>(xi[2], org[2]);
+                                        const Shapes &s, double F[6]) {
+  if constexpr (DIM == 2) {
+    const double2 *pr = reinterpret_cast<const double2 *>(tile);
+    gather_pair(pr, Tx, s.d[0], s.p[1], F[0], F[4]);       // Ex, By
+    gather_pair(pr + TE, Tx, s.p[0], s.d[1], F[1], F[3]);  // Ey, Bx
+    F[2] = gather<2>(tile + 4 * TE, Tx, Txy, s.p[0], s.p[1], s.p[2]);  // Ez
+    F[5] = gather<2>(tile + 5 * TE, Tx, Txy, s.d[0], s.d[1], s.p[2]);  // Bz
   } else {
-    z0 = z1 = Sh{{0.0, 1.0, 0.0}, 0};
+    F[0] = gather<3>(tile + 0 * TE, Tx, Txy, s.d[0], s.p[1], s.p[2]);
+    F[1] = gather<3>(tile + 1 * TE, Tx, Txy, s.p[0], s.d[1], s.p[2]);
+    F[2] = gather<3>(tile + 2 * TE, Tx, Txy, s.p[0], s.p[1], s.d[2]);
+    F[3] = gather<3>(tile + 3 * TE, Tx, Txy, s.p[0], s.d[1], s.d[2]);
+    F[4] = gather<3>(tile + 4 * TE, Tx, Txy, s.d[0], s.p[1], s.d[2]);
+    F[5] = gather<3>(tile + 5 * TE, Tx, Txy, s.d[0], s.d[1], s.p[2]);
   }
-  // stagger bits: Ex(1,0,0) Ey(0,1,0) Ez(0,0,1) Bx(0,1,1) By(1,0,1) Bz(1,1,0)
-  F[0] = gather<DIM>(tile + 0 * TE, Tx, Txy, x1, y0, z0);
-  F[1] = gather<DIM>(tile + 1 * TE, Tx, Txy, x0, y1, z0);
-  F[2] = gather<DIM>(tile + 2 * TE, Tx, Txy, x0, y0, z1);
-  F[3] = gather<DIM>(tile + 3 * TE, Tx, Txy, x0, y1, z1);
-  F[4] = gather<DIM>(tile + 4 * TE, Tx, Txy, x1, y0, z1);
-  F[5] = gather<DIM>(tile + 5 * TE, Tx, Txy, x1, y1, z0);
 }
 
 // Relativistic Boris push, same operation sequence as the CPU oracle.
@@ -183,116 +238,117 @@ __device__ __forceinline__ void boris(double alpha, const double F[6], double u[
   v[2] = u[2] * ig;
 }
 
-// Esirkepov weights along one axis on the four nodes that the start and end
-// stencils can cover.  With i0, i1 the nearest primal nodes of the start and
-// end positions and m = i1 - i0 in {-1, 0, 1}, the window starts at node
-// b = i0 - 1 + min(m, 0); S0 (start shape), DS = S1 - S0 are given on nodes
-// b..b+3 (for m = 0 the fourth entry is zero).  Returns false on a larger
-// shift.  it = tile index of node b (tile origin = patch origin - 2).
-__device__ __forceinline__ bool esk_axis(double xi0, double xi1, int org2, double S0[4],
-                                         double DS[4], int &it) {
-  double d0, d1;
-  const int k0 = locate0(xi0, d0);
+// Esirkepov quantities along one axis on the four nodes that the start and
+// end stencils can cover.  p0 is the start position's primal shape (nearest
+// node i0, weights on i0-1..i0+1, p0.i = E/B-tile index of node i0-1); i1 is
+// the end position's nearest node, m = i1 - i0 in {-1, 0, 1}.  The window
+// starts at node i0 - 1 + min(m, 0) and holds S0 (start weights), DS = S1 - S0
+// and A = S0 + DS/2 (the path-averaged weight); for m = 0 its fourth node
+// carries zeros.  it = J-tile index of the window's first node (the J tile
+// starts one node before the E/B tile).  False on a larger shift.
+struct Win {
+  double S0[4], DS[4], A[4];
+  int it;
+};
+
+__device__ __forceinline__ bool esk_win(const Sh &p0, double xi1, int i0, Win &w) {
+  double d1;
   const int k1 = locate0(xi1, d1);
-  const int m = k1 - k0;
+  const int m = k1 - i0;
   if (m < -1 || m > 1) return false;
-  double a0, a1, a2, b0, b1, b2;
-  shape_w(d0, a0, a1, a2);
+  double b0, b1, b2;
   shape_w(d1, b0, b1, b2);
-  const bool lo = m < 0;  // window shifted one node down
-  S0[0] = lo ? 0.0 : a0;
-  S0[1] = lo ? a0 : a1;
-  S0[2] = lo ? a1 : a2;
-  S0[3] = lo ? a2 : 0.0;
-  double S1[4];
-  S1[0] = m > 0 ? 0.0 : b0;
-  S1[1] = m > 0 ? b0 : b1;
-  S1[2] = m > 0 ? b1 : b2;
-  S1[3] = m > 0 ? b2 : 0.0;
+  const bool lo = m < 0, hi = m > 0;
+  const double a0 = p0.s[0], a1 = p0.s[1], a2 = p0.s[2];
+  w.S0[0] = lo ? 0.0 : a0;
+  w.S0[1] = lo ? a0 : a1;
+  w.S0[2] = lo ? a1 : a2;
+  w.S0[3] = lo ? a2 : 0.0;
+  const double S1[4] = {hi ? 0.0 : b0, hi ? b0 : b1, hi ? b1 : b2, hi ? b2 : 0.0};
 #pragma unroll
-  for (int r = 0; r < 4; r++) DS[r] = S1[r] - S0[r];
-  it = (k0 - 1 + (lo ? -1 : 0)) - org2;
+  for (int r = 0; r < 4; r++) {
+    w.DS[r] = S1[r] - w.S0[r];
+    w.A[r] = __builtin_fma(0.5, w.DS[r], w.S0[r]);
+  }
+  w.it = p0.i + (lo ? 0 : 1);
   return true;
 }
 
-// Esirkepov deposit of one particle into the LDS J tile (3 components of TJn
-// entries, TJx x TJy (x TJz)).  qw = q*w.  The running sum along each
-// component's own axis vanishes at the last window node, so each component
-// has 3 nonzero entries along its axis: 2D 12 + 12 + 16 adds, 3D 3 x 48.
+// Esirkepov deposit of one particle into the LDS J tile, in factored form:
+// with A = S0 + DS/2 on each axis,
+//   2D  Wx = DSx (x) Ay, Wy = Ax (x) DSy, Wz = Ax (x) Ay + DSx (x) DSy / 12,
+//   3D  Wx = DSx (x) (Ay (x) Az + DSy (x) DSz / 12), y and z cyclic,
+// which equals Esirkepov's weights (expand A); J along a component's own axis
+// is the running sum of its W times -q w d/dt, so 3 of the 4 window nodes are
+// nonzero.  Adds per particle: 2D 12 + 12 + 16, 3D 3 x 48.
 template <int DIM>
-__device__ __forceinline__ bool deposit(const GridDev &g, double *tJ, int TJn, int TJx, int TJxy,
-                                        const int org2[3], double qw, const double xi0[3],
-                                        const double xi1[3], double vz) {
-  double S0[3][4], DS[3][4];
-  int it[3];
-#pragma unroll
-  for (int a = 0; a < DIM; a++)
-    if (!esk_axis(xi0[a], xi1[a], org2[a], S0[a], DS[a], it[a])) return false;
+__device__ __forceinline__ void deposit(const GridDev &g, double *tJ, int TJn, int TJx, int TJxy,
+                                        double qw, const Win *w, double vz) {
   if constexpr (DIM == 2) {
-    double *Jx = tJ, *Jy = tJ + TJn, *Jz = tJ + 2 * TJn;
+    double *Jx = tJ + w[1].it * TJx + w[0].it;
+    double *Jy = Jx + TJn, *Jz = Jx + 2 * TJn;
     const double cx = -qw * g.d_over_dt[0];
     const double cy = -qw * g.d_over_dt[1];
     const double cz = qw * vz;
+    const double cz12 = cz * (1.0 / 12.0);
+    double Cx[3], Cy[3];
+    Cx[0] = w[0].DS[0];
+    Cx[1] = Cx[0] + w[0].DS[1];
+    Cx[2] = Cx[1] + w[0].DS[2];
+    Cy[0] = w[1].DS[0];
+    Cy[1] = Cy[0] + w[1].DS[1];
+    Cy[2] = Cy[1] + w[1].DS[2];
 #pragma unroll
-    for (int t = 0; t < 4; t++) {
-      const double fy = S0[1][t] + 0.5 * DS[1][t];
-      double acc = 0.0;
-      double *row = Jx + (it[1] + t) * TJx + it[0];
-#pragma unroll
-      for (int r = 0; r < 3; r++) {
-        acc = acc + DS[0][r] * fy;
-        lds_add(row + r, cx * acc);
-      }
+    for (int k = 0; k < 3; k++) {
+      Cx[k] *= cx;
+      Cy[k] *= cy;
     }
+#pragma unroll
+    for (int t = 0; t < 4; t++)
+#pragma unroll
+      for (int r = 0; r < 3; r++) lds_add(Jx + t * TJx + r, Cx[r] * w[1].A[t]);
+#pragma unroll
+    for (int t = 0; t < 3; t++)
+#pragma unroll
+      for (int r = 0; r < 4; r++) lds_add(Jy + t * TJx + r, w[0].A[r] * Cy[t]);
+    double az[4], dz[4];
 #pragma unroll
     for (int r = 0; r < 4; r++) {
-      const double fx = S0[0][r] + 0.5 * DS[0][r];
-      double acc = 0.0;
-      double *col = Jy + it[1] * TJx + it[0] + r;
-#pragma unroll
-      for (int t = 0; t < 3; t++) {
-        acc = acc + DS[1][t] * fx;
-        lds_add(col + t * TJx, cy * acc);
-      }
+      az[r] = cz * w[0].A[r];
+      dz[r] = cz12 * w[0].DS[r];
     }
-    const double third = 1.0 / 3.0;
 #pragma unroll
-    for (int t = 0; t < 4; t++) {
-      double *row = Jz + (it[1] + t) * TJx + it[0];
+    for (int t = 0; t < 4; t++)
 #pragma unroll
-      for (int r = 0; r < 4; r++) {
-        const double wz = S0[0][r] * S0[1][t] + 0.5 * DS[0][r] * S0[1][t] +
-                          0.5 * S0[0][r] * DS[1][t] + third * DS[0][r] * DS[1][t];
-        lds_add(row + r, cz * wz);
-      }
-    }
+      for (int r = 0; r < 4; r++)
+        lds_add(Jz + t * TJx + r, __builtin_fma(az[r], w[1].A[t], dz[r] * w[1].DS[t]));
   } else {
-    const double third = 1.0 / 3.0;
     const int stride[3] = {1, TJx, TJxy};
+    double *J0 = tJ + w[2].it * TJxy + w[1].it * TJx + w[0].it;
 #pragma unroll
     for (int a = 0; a < 3; a++) {
       const int b = (a + 1) % 3, c = (a + 2) % 3;
-      double *Ja = tJ + a * TJn;
       const double ca = -qw * g.d_over_dt[a];
+      double C[3];
+      C[0] = w[a].DS[0];
+      C[1] = C[0] + w[a].DS[1];
+      C[2] = C[1] + w[a].DS[2];
+#pragma unroll
+      for (int k = 0; k < 3; k++) C[k] *= ca;
+      double *Ja = J0 + a * TJn;
 #pragma unroll
       for (int tb = 0; tb < 4; tb++) {
+        const double db12 = w[b].DS[tb] * (1.0 / 12.0);
 #pragma unroll
         for (int tc = 0; tc < 4; tc++) {
-          const double f = S0[b][tb] * S0[c][tc] + 0.5 * DS[b][tb] * S0[c][tc] +
-                           0.5 * S0[b][tb] * DS[c][tc] + third * DS[b][tb] * DS[c][tc];
-          double acc = 0.0;
-          double *line = Ja + it[0] * stride[0] + it[1] * stride[1] + it[2] * stride[2] +
-                         tb * stride[b] + tc * stride[c];
+          const double f = __builtin_fma(w[b].A[tb], w[c].A[tc], db12 * w[c].DS[tc]);
+          double *line = Ja + tb * stride[b] + tc * stride[c];
 #pragma unroll
-          for (int ta = 0; ta < 3; ta++) {
-            acc = acc + DS[a][ta] * f;
-            lds_add(line + ta * stride[a], ca * acc);
-          }
+          for (int ta = 0; ta < 3; ta++) lds_add(line + ta * stride[a], C[ta] * f);
         }
       }
     }
   }
-  return true;
 }
 
 // Patch coordinates of patch P.
@@ -304,9 +360,13 @@ __device__ __forceinline__ void patch_coords(const GridDev &g, int P, int pc[3])
 }
 
 // pre-BC: wrap x1 into the box (in place) and return the neighbour code of
-// the destination patch relative to patch pc (-1 on a bad position).
+// the destination patch of a particle of the patch whose first cell is lo
+// (-1 on a bad position).  The destination is the patch of the wrapped
+// position's cell c = min(floor(x inv_d), n-1); with the particle at most
+// one cell from its patch, d = (c - lo) mod n picks it without a division:
+// d < p stays, p <= d < 2p is the next patch, d >= n - p the previous one.
 template <int DIM>
-__device__ __forceinline__ int dest_code(const GridDev &g, const int pc[3], double x[3]) {
+__device__ __forceinline__ int dest_code(const GridDev &g, const int lo[3], double x[3]) {
   int code = 0, mul = 1;
 #pragma unroll
   for (int a = 0; a < DIM; a++) {
@@ -317,14 +377,15 @@ __device__ __forceinline__ int dest_code(const GridDev &g, const int pc[3], doub
     x[a] = v;
     int c = (int)floor(v * g.inv_d[a]);
     if (c >= g.n[a]) c = g.n[a] - 1;
-    int dp = c / g.patch[a] - pc[a];
-    if (dp < 0) dp += g.np[a];
+    int d = c - lo[a];
+    if (d < 0) d += g.n[a];
+    const int p = g.patch[a];
     int delta;
-    if (dp == 0)
+    if (d < p)
       delta = 0;
-    else if (dp == 1)
+    else if (d < 2 * p)
       delta = 1;
-    else if (dp == g.np[a] - 1)
+    else if (d >= g.n[a] - p)
       delta = -1;
     else
       return -1;
@@ -352,37 +413,23 @@ __device__ __forceinline__ int dest_patch(const GridDev &g, const int pc[3], int
   return D;
 }
 
-// Per-chunk stable ranking of particles by neighbour code.
-struct RankLDS {
-  int wcnt[2][kWaveMax][27];
-  int run[27];
-};
-
-template <int NC>
-__device__ __forceinline__ uint32_t rank_chunk(RankLDS &R, int parity, bool valid, int code) {
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int nwaves = (blockDim.x + 63) >> 6;
+// Stable rank of each lane's particle among the wave's earlier particles with
+// the same code, plus the ranking unit's running count per code (lane c of
+// `run` holds code c's count).  One ballot per distinct code in the wave.
+__device__ __forceinline__ uint32_t wave_rank(bool valid, int code, int lane, int &run) {
+  uint64_t todo = __ballot(valid);
   const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
-  int r = 0;
-#pragma unroll
-  for (int c = 0; c < NC; c++) {
-    const uint64_t m = __ballot(valid && code == c);
-    if (valid && code == c) r = __popcll(m & lt);
-    if (lane == 0) R.wcnt[parity][wave][c] = __popcll(m);
+  uint32_t r = 0;
+  while (todo) {
+    const int leader = __ffsll((unsigned long long)todo) - 1;
+    const int lc = __builtin_amdgcn_readlane(code, leader);
+    const uint64_t m = __ballot(valid && code == lc);
+    const int base = __builtin_amdgcn_readlane(run, lc);
+    if (valid && code == lc) r = (uint32_t)(base + __popcll(m & lt));
+    if (lane == lc) run += __popcll(m);
+    todo &= ~m;
   }
-  __syncthreads();
-  int pre = 0;
-  if (valid) {
-    pre = R.run[code];
-    for (int w = 0; w < wave; w++) pre += R.wcnt[parity][w][code];
-  }
-  __syncthreads();
-  if (tid < NC) {
-    int s = 0;
-    for (int w = 0; w < nwaves; w++) s += R.wcnt[parity][w][tid];
-    R.run[tid] += s;
-  }
-  return (uint32_t)(pre + r);
+  return r;
 }
 
 struct Fields {
@@ -424,8 +471,6 @@ __device__ __forceinline__ TileGeom tile_geom(const GridDev &g, int P) {
 
 template <int DIM>
 __device__ void stage_eb(const GridDev &g, const TileGeom &t, const Fields &f, double *tile) {
-  const int ez = DIM == 3 ? g.patch[2] + 3 : 1;
-  (void)ez;
   for (int idx = threadIdx.x; idx < 6 * t.TE; idx += blockDim.x) {
     const int c = idx / t.TE;
     const int r = idx - c * t.TE;
@@ -437,7 +482,22 @@ __device__ void stage_eb(const GridDev &g, const TileGeom &t, const Fields &f, d
     const int gy = wrap_near(t.org[1] + jj, g.n[1]);
     const int gz = DIM == 3 ? wrap_near(t.org[2] + kk, g.n[2]) : 0;
     const double *F = c < 3 ? f.e[c] : f.b[c - 3];
-    tile[idx] = F[((int64_t)gz * g.n[1] + gy) * g.n[0] + gx];
+    const double v = F[((int64_t)gz * g.n[1] + gy) * g.n[0] + gx];
+    if constexpr (DIM == 2) {
+      // Ex -> pair 0 .x, By -> pair 0 .y, Ey -> pair 1 .x, Bx -> pair 1 .y
+      int at;
+      switch (c) {
+        case 0: at = 2 * r; break;
+        case 4: at = 2 * r + 1; break;
+        case 1: at = 2 * t.TE + 2 * r; break;
+        case 3: at = 2 * t.TE + 2 * r + 1; break;
+        case 2: at = 4 * t.TE + r; break;
+        default: at = 5 * t.TE + r; break;
+      }
+      tile[at] = v;
+    } else {
+      tile[idx] = v;
+    }
   }
 }
 
@@ -475,13 +535,13 @@ __device__ __forceinline__ bool in_patch(const TileGeom &t, const double xi[3]) 
 
 // ---------------------------------------------------------------------------
 // Fused step kernel: Interpolation, Push, pre-BC and Projection for the
-// particles of one (patch, species).
+// particles of one (patch, species).  Each wave walks its own ranking unit,
+// 64 consecutive particles per iteration.
 template <int DIM>
 __global__ void __launch_bounds__(256) k_ipp(GridDev g, SpArgs sa, Fields f, int *err) {
   constexpr int NC = DIM == 2 ? 9 : 27;
   constexpr int CENTER = (NC - 1) / 2;
-  extern __shared__ double lds[];
-  __shared__ RankLDS R;
+  extern __shared__ __align__(16) double lds[];
   const int P = blockIdx.x;
   const SpDev &S = sa.s[blockIdx.y];
   const TileGeom t = tile_geom<DIM>(g, P);
@@ -489,15 +549,17 @@ __global__ void __launch_bounds__(256) k_ipp(GridDev g, SpArgs sa, Fields f, int
   double *tJ = lds + 6 * t.TE;
   stage_eb<DIM>(g, t, f, tEB);
   zero_tile<DIM>(tJ, 3 * t.TJ);
-  if (threadIdx.x < NC) R.run[threadIdx.x] = 0;
   __syncthreads();
   const int64_t beg = S.off[P], end = S.off[P + 1];
+  const int nw = blockDim.x >> 6, wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int L = unit_len((int)(end - beg), nw);
+  const int64_t ub = beg + (int64_t)wv * L;
+  const int64_t ue = ub + L < end ? ub + L : end;
   const double q = S.q, alpha = S.alpha;
-  int parity = 0;
-  int bad = 0;
-  for (int64_t base = beg; base < end; base += blockDim.x) {
-    const int64_t i = base + threadIdx.x;
-    const bool valid = i < end;
+  int run = 0, bad = 0;
+  for (int64_t base = ub; base < ue; base += 64) {
+    const int64_t i = base + lane;
+    const bool valid = i < ue;
     int code = CENTER;
     if (valid) {
       double x[3], xi[3], u[3], v[3], F[6];
@@ -513,16 +575,22 @@ __global__ void __launch_bounds__(256) k_ipp(GridDev g, SpArgs sa, Fields f, int
         u[1] = S.u[1][i];
         u[2] = S.u[2][i];
         const double w = S.w[i];
-        interp6<DIM>(tEB, t.TE, t.Tx, t.Txy, xi, t.org, F);
+        const Shapes sh = shapes_at<DIM>(xi, t.org);
+        interp6<DIM>(tEB, t.TE, t.Tx, t.Txy, sh, F);
         boris(alpha, F, u, v);
-        double x1[3], xi1[3];
+        double x1[3];
+        Win win[DIM];
+        bool ok = true;
 #pragma unroll
         for (int a = 0; a < DIM; a++) {
           x1[a] = x[a] + g.dt * v[a];
-          xi1[a] = x1[a] * g.inv_d[a];
+          ok = ok && esk_win(sh.p[a], x1[a] * g.inv_d[a], sh.p[a].i + 1 + t.org[a], win[a]);
         }
-        if (!deposit<DIM>(g, tJ, t.TJ, t.Jx, t.Jxy, t.org2, q * w, xi, xi1, v[2])) bad |= kErrCFL;
-        const int c = dest_code<DIM>(g, t.pc, x1);
+        if (ok)
+          deposit<DIM>(g, tJ, t.TJ, t.Jx, t.Jxy, q * w, win, v[2]);
+        else
+          bad |= kErrCFL;
+        const int c = dest_code<DIM>(g, t.lo, x1);
         if (c < 0) {
           bad |= kErrPos;
         } else {
@@ -535,20 +603,19 @@ __global__ void __launch_bounds__(256) k_ipp(GridDev g, SpArgs sa, Fields f, int
         S.u[2][i] = u[2];
       }
     }
-    const uint32_t rank = rank_chunk<NC>(R, parity, valid, code);
+    const uint32_t rank = wave_rank(valid, code, lane, run);
     if (valid) S.tag[i] = ((uint32_t)code << 27) | rank;
-    parity ^= 1;
   }
+  if (lane < NC) S.cnt[((int64_t)P * nw + wv) * NC + lane] = run;
   if (bad) atomicOr(err, bad);
   __syncthreads();
   flush_j<DIM>(g, t, tJ, f.j);
-  if (threadIdx.x < NC) S.cnt[(int64_t)P * NC + threadIdx.x] = R.run[threadIdx.x];
 }
 
 // Split path, first half: Interpolation + Push; saves the start positions.
 template <int DIM>
 __global__ void __launch_bounds__(256) k_interp_push(GridDev g, SpArgs sa, Fields f, int *err) {
-  extern __shared__ double lds[];
+  extern __shared__ __align__(16) double lds[];
   const int P = blockIdx.x;
   const SpDev &S = sa.s[blockIdx.y];
   const TileGeom t = tile_geom<DIM>(g, P);
@@ -571,7 +638,8 @@ __global__ void __launch_bounds__(256) k_interp_push(GridDev g, SpArgs sa, Field
     u[0] = S.u[0][i];
     u[1] = S.u[1][i];
     u[2] = S.u[2][i];
-    interp6<DIM>(lds, t.TE, t.Tx, t.Txy, xi, t.org, F);
+    const Shapes sh = shapes_at<DIM>(xi, t.org);
+    interp6<DIM>(lds, t.TE, t.Tx, t.Txy, sh, F);
     boris(S.alpha, F, u, v);
 #pragma unroll
     for (int a = 0; a < DIM; a++) S.x[a][i] = x[a] + g.dt * v[a];
@@ -585,7 +653,7 @@ __global__ void __launch_bounds__(256) k_interp_push(GridDev g, SpArgs sa, Field
 // Split path, second half: Projection from the saved start positions.
 template <int DIM>
 __global__ void __launch_bounds__(256) k_project(GridDev g, SpArgs sa, Fields f, int *err) {
-  extern __shared__ double lds[];
+  extern __shared__ __align__(16) double lds[];
   const int P = blockIdx.x;
   const SpDev &S = sa.s[blockIdx.y];
   const TileGeom t = tile_geom<DIM>(g, P);
@@ -595,12 +663,9 @@ __global__ void __launch_bounds__(256) k_project(GridDev g, SpArgs sa, Fields f,
   const int64_t beg = S.off[P], end = S.off[P + 1];
   int bad = 0;
   for (int64_t i = beg + threadIdx.x; i < end; i += blockDim.x) {
-    double xi0[3], xi1[3];
+    double xi0[3];
 #pragma unroll
-    for (int a = 0; a < DIM; a++) {
-      xi0[a] = S.x0[a][i] * g.inv_d[a];
-      xi1[a] = S.x[a][i] * g.inv_d[a];
-    }
+    for (int a = 0; a < DIM; a++) xi0[a] = S.x0[a][i] * g.inv_d[a];
     if (!in_patch<DIM>(t, xi0)) {
       bad |= kErrPos;
       continue;
@@ -609,7 +674,17 @@ __global__ void __launch_bounds__(256) k_project(GridDev g, SpArgs sa, Fields f,
     const double gam = sqrt(1.0 + ((u0 * u0 + u1 * u1) + u2 * u2));
     const double ig = 1.0 / gam;
     const double vz = u2 * ig;
-    if (!deposit<DIM>(g, tJ, t.TJ, t.Jx, t.Jxy, t.org2, S.q * S.w[i], xi0, xi1, vz)) bad |= kErrCFL;
+    Win win[DIM];
+    bool ok = true;
+#pragma unroll
+    for (int a = 0; a < DIM; a++) {
+      const Sh p0 = axis_shape<0>(xi0[a], t.org[a]);
+      ok = ok && esk_win(p0, S.x[a][i] * g.inv_d[a], p0.i + 1 + t.org[a], win[a]);
+    }
+    if (ok)
+      deposit<DIM>(g, tJ, t.TJ, t.Jx, t.Jxy, S.q * S.w[i], win, vz);
+    else
+      bad |= kErrCFL;
   }
   if (bad) atomicOr(err, bad);
   __syncthreads();
@@ -617,29 +692,29 @@ __global__ void __launch_bounds__(256) k_project(GridDev g, SpArgs sa, Fields f,
 }
 
 // Split path pre-BC: wrap, neighbour code and stable rank of particles that
-// moved at most one cell since the last sort.
+// moved at most one cell since the last sort (same ranking units as k_ipp).
 template <int DIM>
 __global__ void __launch_bounds__(256) k_tag(GridDev g, SpArgs sa, int *err) {
   constexpr int NC = DIM == 2 ? 9 : 27;
   constexpr int CENTER = (NC - 1) / 2;
-  __shared__ RankLDS R;
   const int P = blockIdx.x;
   const SpDev &S = sa.s[blockIdx.y];
-  int pc[3];
-  patch_coords(g, P, pc);
-  if (threadIdx.x < NC) R.run[threadIdx.x] = 0;
-  __syncthreads();
+  const TileGeom t = tile_geom<DIM>(g, P);
   const int64_t beg = S.off[P], end = S.off[P + 1];
-  int parity = 0, bad = 0;
-  for (int64_t base = beg; base < end; base += blockDim.x) {
-    const int64_t i = base + threadIdx.x;
-    const bool valid = i < end;
+  const int nw = blockDim.x >> 6, wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int L = unit_len((int)(end - beg), nw);
+  const int64_t ub = beg + (int64_t)wv * L;
+  const int64_t ue = ub + L < end ? ub + L : end;
+  int run = 0, bad = 0;
+  for (int64_t base = ub; base < ue; base += 64) {
+    const int64_t i = base + lane;
+    const bool valid = i < ue;
     int code = CENTER;
     if (valid) {
       double x[3];
 #pragma unroll
       for (int a = 0; a < DIM; a++) x[a] = S.x[a][i];
-      const int c = dest_code<DIM>(g, pc, x);
+      const int c = dest_code<DIM>(g, t.lo, x);
       if (c < 0) {
         bad |= kErrPos;
       } else {
@@ -648,13 +723,11 @@ __global__ void __launch_bounds__(256) k_tag(GridDev g, SpArgs sa, int *err) {
         for (int a = 0; a < DIM; a++) S.x[a][i] = x[a];
       }
     }
-    const uint32_t rank = rank_chunk<NC>(R, parity, valid, code);
+    const uint32_t rank = wave_rank(valid, code, lane, run);
     if (valid) S.tag[i] = ((uint32_t)code << 27) | rank;
-    parity ^= 1;
   }
+  if (lane < NC) S.cnt[((int64_t)P * nw + wv) * NC + lane] = run;
   if (bad) atomicOr(err, bad);
-  __syncthreads();
-  if (threadIdx.x < NC) S.cnt[(int64_t)P * NC + threadIdx.x] = R.run[threadIdx.x];
 }
 
 // Sort, step 1: for every destination patch D, the particles arriving from
@@ -664,7 +737,7 @@ __global__ void k_dest_bases(GridDev g, SpArgs sa) {
   const int D = blockIdx.x * blockDim.x + threadIdx.x;
   if (D >= g.npatch) return;
   const SpDev &S = sa.s[blockIdx.y];
-  const int nc = g.nc;
+  const int nc = g.nc, upp = g.upp;
   int dc[3];
   patch_coords(g, D, dc);
   int src[27], code[27], num[27];
@@ -682,6 +755,8 @@ __global__ void k_dest_bases(GridDev g, SpArgs sa) {
       Psrc += q * mul;
       mul *= g.np[a];
     }
+    int tot = 0;
+    for (int w = 0; w < upp; w++) tot += S.cnt[((int64_t)Psrc * upp + w) * nc + c];
     // insertion by source patch (stable in c)
     int k = c;
     while (k > 0 && src[k - 1] > Psrc) {
@@ -692,7 +767,7 @@ __global__ void k_dest_bases(GridDev g, SpArgs sa) {
     }
     src[k] = Psrc;
     code[k] = c;
-    num[k] = S.cnt[(int64_t)Psrc * nc + c];
+    num[k] = tot;
   }
   int64_t run = 0;
   for (int k = 0; k < nc; k++) {
@@ -729,25 +804,32 @@ __global__ void __launch_bounds__(1024) k_scan_offsets(GridDev g, SpArgs sa) {
   if (threadIdx.x == blockDim.x - 1) S.noff[n] = part[threadIdx.x];
 }
 
-// Sort, step 3: move every particle of a source patch to its place.
+// Sort, step 3: move every particle of a source patch to its place:
+// destination start + start of (patch, code) inside it + earlier ranking
+// units' counts of that code + the particle's rank.
 __global__ void __launch_bounds__(256) k_scatter(GridDev g, SpArgs sa, int dim, int *err) {
   const int P = blockIdx.x;
   const SpDev &S = sa.s[blockIdx.y];
-  const int nc = g.nc;
-  __shared__ int64_t base[27];
-  if (threadIdx.x < (unsigned)nc) {
+  const int nc = g.nc, upp = g.upp;
+  __shared__ int64_t base[kWaveMax * 27];
+  if (threadIdx.x < (unsigned)(nc * upp)) {
+    const int w = threadIdx.x / nc, c = threadIdx.x - w * nc;
     int pc[3];
     patch_coords(g, P, pc);
-    const int D = dest_patch(g, pc, threadIdx.x);
-    base[threadIdx.x] = S.noff[D] + S.rbase[(int64_t)P * nc + threadIdx.x];
+    const int D = dest_patch(g, pc, c);
+    int64_t b = S.noff[D] + S.rbase[(int64_t)P * nc + c];
+    for (int k = 0; k < w; k++) b += S.cnt[((int64_t)P * upp + k) * nc + c];
+    base[threadIdx.x] = b;
   }
   __syncthreads();
   const int64_t beg = S.off[P], end = S.off[P + 1];
+  const int L = unit_len((int)(end - beg), upp);
   int bad = 0;
   for (int64_t i = beg + threadIdx.x; i < end; i += blockDim.x) {
     const uint32_t tg = S.tag[i];
     const int c = (int)(tg >> 27);
-    const int64_t dst = c < nc ? base[c] + (int64_t)(tg & ((1u << 27) - 1)) : S.n;
+    const int w = (int)(i - beg) / L;
+    const int64_t dst = c < nc && w < upp ? base[w * nc + c] + (int64_t)(tg & ((1u << 27) - 1)) : S.n;
     if (dst >= S.n) {
       bad |= kErrPos;
       continue;
