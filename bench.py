@@ -71,34 +71,58 @@ def cpu_model() -> str:
     return platform.processor() or "unknown"
 
 
-def run_gpu(wl, steps: int, warmup: int, mode: int = 0, chunk: int = 0):
+def run_gpu(wl, steps: int, warmup: int, mode: int = 0, chunk: int = 0, wg: int = 0,
+            inp=None, graph: bool = False):
+    """Timed pic_step on fresh device copies of the generated inputs.  With
+    graph=False the library times each kernel class with HIP events on the
+    launch stream; with graph=True steps replay captured graphs (no per-kernel
+    timing)."""
     import torch
 
     from paper_2204_12837_amd import inputs as I
     from paper_2204_12837_amd import pic
 
-    inp = I.generate(wl)
+    inp = I.generate(wl) if inp is None else inp
     n = sum(s.x.shape[1] for s in inp.species)
-    ctx = pic.Context(wl, device=0, mode=mode, chunk=chunk)
+    ctx = pic.Context(wl, device=0, mode=mode, chunk=chunk, wg_size=wg, graph=graph)
     sp = pic.upload(inp, "cuda:0")
     E, B, J = pic.upload_fields(inp, "cuda:0")
-    del inp
     ctx.bin(sp)
     if warmup:
         ctx.step(sp, E, B, J, nsteps=warmup)
     torch.cuda.synchronize()
     ctx.check()
-    ctx.timing(True)
+    if not graph:
+        ctx.timing(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     ctx.step(sp, E, B, J, nsteps=steps)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ctx.check()
-    tim = ctx.timing_read()
+    tim = ctx.timing_read() if not graph else {}
     ctx.timing(False)
     ctx.close()
+    del sp, E, B, J
+    torch.cuda.empty_cache()
     return n, t1 - t0, tim
+
+
+def tune_persistent(wl, inp):
+    """Autotuned (chunk, wg) for the persistent launch on these inputs."""
+    import torch
+
+    from paper_2204_12837_amd import autotune, pic
+
+    sp = pic.upload(inp, "cuda:0")
+    E, B, J = pic.upload_fields(inp, "cuda:0")
+    ctx = pic.Context(wl)
+    ctx.bin(sp)
+    ctx.close()
+    res = autotune.tune(wl, sp, E, B, J, steps=3, use_cache=False)
+    del sp, E, B, J
+    torch.cuda.empty_cache()
+    return res
 
 
 def cpu_baseline(sample_steps: int):
@@ -198,14 +222,33 @@ def main(argv=None) -> int:
     }
     if not args.no_imbalanced:
         wli = I.workload("imbalanced")
-        ni, si, ti = run_gpu(wli, args.steps, args.warmup)
+        inpi = I.generate(wli)
+        ni, si, ti = run_gpu(wli, args.steps, args.warmup, inp=inpi)
+        tuned = tune_persistent(wli, inpi)
+        _, sp_, tp = run_gpu(wli, args.steps, args.warmup, mode=1, chunk=tuned["chunk"],
+                             wg=tuned["wg"], inp=inpi)
         ns_u = secs / (n * args.steps) * 1e9
-        ns_i = si / (ni * args.steps) * 1e9
-        out["imbalanced"] = {"workload": "imbalanced", "particles": ni, "mode": "per_patch",
-                             "ns_per_particle_step": ns_i, "uniform_ns_per_particle_step": ns_u,
-                             "ratio_vs_uniform": ns_i / ns_u,
-                             "kernel_ms": {k: round(v[0] / max(v[1], 1), 4)
-                                           for k, v in ti.items() if v[1]}}
+        ipp_u = ipp_avg / n * 1e6
+        per_k = lambda t: {k: round(v[0] / max(v[1], 1), 4) for k, v in t.items() if v[1]}
+        ipp_pp = ti["ipp"][0] / ti["ipp"][1]
+        ipp_pe = tp["ipp"][0] / tp["ipp"][1]
+        out["imbalanced"] = {
+            "workload": "imbalanced", "particles": ni,
+            "uniform_ns_per_particle_step": ns_u,
+            "per_patch": {"ns_per_particle_step": si / (ni * args.steps) * 1e9,
+                          "kernel_ms": per_k(ti)},
+            "persistent": {"ns_per_particle_step": sp_ / (ni * args.steps) * 1e9,
+                           "chunk": tuned["chunk"], "wg": tuned["wg"], "kernel_ms": per_k(tp),
+                           "autotune_trials": tuned["trials"]},
+            # fused-kernel time per particle, the quantity the task scheduling balances
+            "ipp_ns_per_particle": {"uniform_per_patch": ipp_u,
+                                    "imbalanced_per_patch": ipp_pp / ni * 1e6,
+                                    "imbalanced_persistent": ipp_pe / ni * 1e6},
+            "ipp_ratio_persistent_vs_uniform": (ipp_pe / ni) / (ipp_avg / n),
+            "ipp_speedup_persistent_vs_per_patch": ipp_pp / ipp_pe,
+            "step_ratio_persistent_vs_uniform": (sp_ / ni) / (secs / n),
+            "step_speedup_persistent_vs_per_patch": si / sp_,
+        }
     out["cpu_baseline"] = None if args.no_cpu_baseline else cpu_baseline(args.cpu_steps)
     print(json.dumps(out), flush=True)
     return 0

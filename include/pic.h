@@ -65,7 +65,10 @@ typedef enum {
 enum { PIC_MODE_PER_PATCH = 0, PIC_MODE_PERSISTENT = 1 };
 
 enum {
-  PIC_FLAG_CHECK = 1 /* every call waits for its stream and reports device errors */
+  PIC_FLAG_CHECK = 1, /* every call waits for its stream and reports device errors */
+  PIC_FLAG_GRAPH = 2  /* pic_step replays a captured HIP graph of two steps (the
+                         buffer swap makes two steps the period); the graph is
+                         recaptured when any array pointer or count changes */
 };
 
 typedef struct {
@@ -79,7 +82,8 @@ typedef struct {
   int32_t mode;        /* PIC_MODE_PER_PATCH: one workgroup per patch and
                           species; PIC_MODE_PERSISTENT: a fixed grid pulls
                           (patch, species, chunk) units from a device queue */
-  int32_t chunk;       /* persistent mode: particles per unit (0 = auto) */
+  int32_t chunk;       /* persistent mode: particles per work unit, a multiple
+                          of 256 (0 = auto: 2048) */
   int32_t wg_size;     /* threads per workgroup: 64, 128, 192 or 256 (0 = auto) */
   uint32_t flags;      /* PIC_FLAG_* */
 } pic_config;
@@ -148,7 +152,11 @@ pic_status pic_project(pic_ctx *ctx, const pic_species *sp, int32_t nsp, pic_fie
  * and Projection of every species (J accumulated in on-chip tiles per patch
  * and added to the grid), then the sort.  Equals the sequence {zero J;
  * pic_interp_push; pic_project; pic_bin} per step.  J holds the last
- * step's current.  Particles must be sorted (offset[] valid). */
+ * step's current.  Particles must be sorted (offset[] valid, e.g. by
+ * pic_bin on this context).  In persistent mode the fused kernel runs on a
+ * fixed grid that pulls (patch, chunk) units from a device queue built by the
+ * sort.  With PIC_FLAG_GRAPH (and timing off) pairs of steps replay a
+ * captured HIP graph. */
 pic_status pic_step(pic_ctx *ctx, pic_species *sp, int32_t nsp, pic_fields *f, int32_t nsteps,
                     void *stream);
 

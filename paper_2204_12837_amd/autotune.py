@@ -1,0 +1,101 @@
+"""Autotuner for the persistent launch: picks the work-unit size (chunk, in
+particles) and the workgroup size for a workload by timing the fused kernel
+on the live particles, and caches the choice in a JSON file keyed by the GPU
+architecture, the dimension, the patch shape and a coarse histogram of the
+per-patch populations.
+
+The paper tunes its task granularity (the bin width) by hand per physical
+set-up; this does the same search automatically.  All timing is done by
+the library's own HIP-event timing of the fused kernel class.
+"""
+from __future__ import annotations
+
+import json
+import math
+import os
+from typing import Dict, List, Optional, Sequence, Tuple
+
+import numpy as np
+import torch
+
+from . import pic
+
+CHUNKS = (512, 1024, 2048, 4096, 8192)
+WGS = (128, 256)
+
+
+def cache_path() -> str:
+    p = os.environ.get("PIC_TUNE_CACHE")
+    if p:
+        return p
+    base = os.environ.get("XDG_CACHE_HOME", os.path.join(os.path.expanduser("~"), ".cache"))
+    return os.path.join(base, "pic_mi355x", "tune.json")
+
+
+def population_key(counts: np.ndarray) -> str:
+    """Coarse shape of the per-patch population histogram: log2 of the mean
+    occupied-patch population, log2 of max/mean (half steps) and the empty
+    fraction (tenths)."""
+    counts = np.asarray(counts, dtype=np.int64)
+    occ = counts[counts > 0]
+    if occ.size == 0:
+        return "empty"
+    mean = occ.mean()
+    lm = int(round(math.log2(max(mean, 1))))
+    sk = round(2 * math.log2(max(counts.max() / mean, 1.0))) / 2
+    ef = int(round(10 * (1 - occ.size / counts.size)))
+    return f"m{lm}_s{sk}_e{ef}"
+
+
+def _key(wl, counts) -> str:
+    arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    patch = "x".join(str(p) for p in wl.patch[:wl.dim])
+    return f"{arch}|{wl.dim}d|p{patch}|{population_key(counts)}"
+
+
+def _load(path: str) -> Dict:
+    try:
+        with open(path) as fh:
+            return json.load(fh)
+    except (OSError, ValueError):
+        return {}
+
+
+def tune(wl, species: Sequence[pic.Species], E, B, J, steps: int = 3,
+         chunks: Sequence[int] = CHUNKS, wgs: Sequence[int] = WGS, use_cache: bool = True,
+         path: Optional[str] = None) -> Dict:
+    """Best (chunk, wg) for the persistent launch on these particles.  The
+    particles advance by (1 + steps) steps per candidate."""
+    path = path or cache_path()
+    counts = np.concatenate([np.diff(s.offset.cpu().numpy()) for s in species])
+    key = _key(wl, counts)
+    cache = _load(path)
+    if use_cache and key in cache:
+        out = dict(cache[key])
+        out["cached"] = True
+        return out
+    trials: List[Tuple[float, int, int]] = []
+    for wg in wgs:
+        for chunk in chunks:
+            ctx = pic.Context(wl, mode=pic.MODE_PERSISTENT, chunk=chunk, wg_size=wg)
+            ctx.bin(species)
+            ctx.step(species, E, B, J, nsteps=1)
+            ctx.timing(True)
+            ctx.step(species, E, B, J, nsteps=steps)
+            ms, n = ctx.timing_read()["ipp"]
+            ctx.check()
+            ctx.close()
+            trials.append((ms / max(n, 1), chunk, wg))
+    ms, chunk, wg = min(trials)
+    out = {"chunk": chunk, "wg": wg, "ipp_ms": ms, "key": key,
+           "trials": [{"chunk": c, "wg": w, "ipp_ms": round(t, 4)} for t, c, w in trials]}
+    cache[key] = out
+    try:
+        os.makedirs(os.path.dirname(path), exist_ok=True)
+        with open(path, "w") as fh:
+            json.dump(cache, fh, indent=1)
+    except OSError:
+        pass
+    out = dict(out)
+    out["cached"] = False
+    return out

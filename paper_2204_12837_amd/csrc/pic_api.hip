@@ -21,11 +21,13 @@ namespace {
 
 struct SpScratch {
   int64_t cap = 0;      // particle capacity the buffers below were sized for
+  int64_t maxseg = 0;   // ranking segments the count arrays hold
   uint32_t *tag = nullptr;
-  int32_t *cnt = nullptr;
+  int32_t *sstart = nullptr, *cnt = nullptr, *pre = nullptr, *tot = nullptr;
   int64_t *rbase = nullptr, *in = nullptr, *noff = nullptr;
   int64_t x0cap = 0;
   double *x0[3] = {nullptr, nullptr, nullptr};
+  int64_t ubase = 0, maxunits = 0;  // persistent mode: place in the unit list
 };
 
 constexpr size_t kStaticLds = 2 * 4 * 27 * 4 + 27 * 4 + 64;  // ranking scratch + slack
@@ -42,9 +44,19 @@ struct Timing {
   int64_t launches[PIC_KERNEL_COUNT] = {0};
 };
 
+// A captured two-step graph and the pointers/counts it was captured with.
+struct GraphCache {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  std::vector<uintptr_t> key;
+};
+
 struct pic_ctx {
   pic_config cfg;
   Timing tm;
+  GraphCache gc[2];  // one per buffer parity (the step swaps the buffer sets)
+  int gc_next = 0;
+  hipStream_t cap_stream = nullptr;  // stream used only to capture graphs
   GridDev g;
   int device = 0;
   int wg = 256;
@@ -55,6 +67,10 @@ struct pic_ctx {
   char msg[512] = {0};
   SpScratch sp[kMaxSpecies];
   SortScratch sort[kMaxSpecies];
+  Unit *units = nullptr;  // persistent mode: work-unit list of all species
+  int64_t units_cap = 0;
+  int *qctl = nullptr;    // per species: ticket, number of units
+  int pgrid = 0;          // persistent grid size
 };
 
 namespace {
@@ -149,10 +165,12 @@ hipError_t realloc_dev(T *&p, size_t n) {
   return hipMalloc(&p, std::max<size_t>(n, 1) * sizeof(T));
 }
 
-// Per-species scratch for the sort (and, if x0, the saved positions).
+// Per-species scratch for the sort (and, if x0, the saved positions); in
+// persistent mode also the work-unit list.
 pic_status ensure_scratch(pic_ctx *c, const pic_species *sp, int32_t nsp, bool x0,
                           hipStream_t st) {
   bool synced = false;
+  bool units_changed = false;
   for (int s = 0; s < nsp; s++) {
     SpScratch &S = c->sp[s];
     const int64_t cap = sp[s].capacity;
@@ -166,15 +184,24 @@ pic_status ensure_scratch(pic_ctx *c, const pic_species *sp, int32_t nsp, bool x
     if (need_tag) {
       hipError_t e;
       const size_t np = (size_t)c->g.npatch, nc = (size_t)c->g.nc;
+      const int64_t maxseg = (int64_t)np + cap / kSeg + 1;
       if ((e = realloc_dev(S.tag, (size_t)cap)) != hipSuccess) return hip_fail(c, e, "hipMalloc");
-      if (!S.cnt) {
-        if ((e = realloc_dev(S.cnt, np * nc * (size_t)c->g.upp)) != hipSuccess)
-          return hip_fail(c, e, "hipMalloc");
+      if ((e = realloc_dev(S.cnt, (size_t)maxseg * nc)) != hipSuccess)
+        return hip_fail(c, e, "hipMalloc");
+      if ((e = realloc_dev(S.pre, (size_t)maxseg * nc)) != hipSuccess)
+        return hip_fail(c, e, "hipMalloc");
+      if (!S.rbase) {
+        if ((e = realloc_dev(S.sstart, np + 1)) != hipSuccess) return hip_fail(c, e, "hipMalloc");
+        if ((e = realloc_dev(S.tot, np * nc)) != hipSuccess) return hip_fail(c, e, "hipMalloc");
         if ((e = realloc_dev(S.rbase, np * nc)) != hipSuccess) return hip_fail(c, e, "hipMalloc");
         if ((e = realloc_dev(S.in, np)) != hipSuccess) return hip_fail(c, e, "hipMalloc");
         if ((e = realloc_dev(S.noff, np + 1)) != hipSuccess) return hip_fail(c, e, "hipMalloc");
       }
       S.cap = cap;
+      S.maxseg = maxseg;
+      const int64_t mu = (int64_t)np + (maxseg + c->g.spc - 1) / c->g.spc + 1;
+      if (mu != S.maxunits) units_changed = true;
+      S.maxunits = mu;
     }
     if (need_x0) {
       for (int a = 0; a < c->cfg.dim; a++) {
@@ -182,6 +209,22 @@ pic_status ensure_scratch(pic_ctx *c, const pic_species *sp, int32_t nsp, bool x
         if (e != hipSuccess) return hip_fail(c, e, "hipMalloc");
       }
       S.x0cap = cap;
+    }
+  }
+  if (c->cfg.mode == PIC_MODE_PERSISTENT && (units_changed || !c->units)) {
+    int64_t tot = 0;
+    for (int s = 0; s < nsp; s++) {
+      c->sp[s].ubase = tot;
+      tot += c->sp[s].maxunits;
+    }
+    if (tot > c->units_cap) {
+      if (!synced) {
+        hipError_t e = hipStreamSynchronize(st);
+        if (e != hipSuccess) return hip_fail(c, e, "hipStreamSynchronize");
+      }
+      hipError_t e = realloc_dev(c->units, (size_t)tot);
+      if (e != hipSuccess) return hip_fail(c, e, "hipMalloc");
+      c->units_cap = tot;
     }
   }
   return PIC_OK;
@@ -210,9 +253,13 @@ SpArgs make_args(pic_ctx *c, const pic_species *sp, int32_t nsp) {
     d.off = p.offset;
     d.noff = c->sp[s].noff;
     d.tag = c->sp[s].tag;
+    d.sstart = c->sp[s].sstart;
     d.cnt = c->sp[s].cnt;
+    d.pre = c->sp[s].pre;
+    d.tot = c->sp[s].tot;
     d.rbase = c->sp[s].rbase;
     d.in = c->sp[s].in;
+    d.ubase = (int32_t)c->sp[s].ubase;
   }
   return a;
 }
@@ -283,6 +330,112 @@ bool fields_ok(const pic_ctx *c, const pic_fields *f, bool eb, bool j) {
   return true;
 }
 
+// Enqueue one whole step (J <- 0, fused kernel, sort, layout) on st for the
+// buffer assignment in sp; the caller swaps the buffers afterwards.
+hipError_t enqueue_step(pic_ctx *c, const pic_species *sp, int32_t nsp, const pic_fields *f,
+                        hipStream_t st) {
+  int64_t ncell = 1;
+  for (int a = 0; a < c->cfg.dim; a++) ncell *= c->cfg.n[a];
+  const SpArgs a = make_args(c, sp, nsp);
+  const bool pers = c->cfg.mode == PIC_MODE_PERSISTENT;
+  hipError_t e = timed(c, PIC_KERNEL_ZERO, st, [&] { return launch_zero(f->j, ncell, st); });
+  if (e == hipSuccess)
+    e = timed(c, PIC_KERNEL_IPP, st, [&] {
+      return pers ? launch_ipp_persistent(c->g, a, f->e, f->b, f->j, c->err_dev, c->units,
+                                          c->qctl, c->pgrid, c->wg, st)
+                  : launch_ipp(c->g, a, f->e, f->b, f->j, c->err_dev, c->wg, st);
+    });
+  if (e == hipSuccess)
+    e = timed(c, PIC_KERNEL_REBIN, st, [&] {
+      hipError_t r2 = launch_rebin(c->g, a, c->err_dev, c->wg, st);
+      if (r2 == hipSuccess) r2 = launch_layout(c->g, a, pers ? c->units : nullptr, c->qctl, st);
+      return r2;
+    });
+  return e;
+}
+
+// Everything a captured graph depends on.
+std::vector<uintptr_t> graph_key(const pic_ctx *c, const pic_species *sp, int32_t nsp,
+                                 const pic_fields *f) {
+  std::vector<uintptr_t> k;
+  k.push_back((uintptr_t)nsp);
+  for (int s = 0; s < nsp; s++) {
+    const pic_species &p = sp[s];
+    k.push_back((uintptr_t)p.n);
+    for (int a = 0; a < 3; a++) {
+      k.push_back((uintptr_t)p.x[a]);
+      k.push_back((uintptr_t)p.x_alt[a]);
+      k.push_back((uintptr_t)p.u[a]);
+      k.push_back((uintptr_t)p.u_alt[a]);
+    }
+    k.push_back((uintptr_t)p.w);
+    k.push_back((uintptr_t)p.w_alt);
+    k.push_back((uintptr_t)p.id);
+    k.push_back((uintptr_t)p.id_alt);
+    k.push_back((uintptr_t)p.offset);
+    k.push_back((uintptr_t)c->sp[s].tag);
+    k.push_back((uintptr_t)c->sp[s].cnt);
+    uint64_t qb, mb;
+    std::memcpy(&qb, &p.q, sizeof qb);
+    std::memcpy(&mb, &p.m, sizeof mb);
+    k.push_back((uintptr_t)qb);
+    k.push_back((uintptr_t)mb);
+  }
+  for (int a = 0; a < 3; a++) {
+    k.push_back((uintptr_t)f->e[a]);
+    k.push_back((uintptr_t)f->b[a]);
+    k.push_back((uintptr_t)f->j[a]);
+  }
+  k.push_back((uintptr_t)c->units);
+  return k;
+}
+
+// Capture two steps (buffers A->B, then B->A) into a graph, unless one of
+// the two cached graphs was captured with the same pointers; returns it.
+pic_status ensure_graph(pic_ctx *c, const pic_species *sp, int32_t nsp, const pic_fields *f,
+                        hipGraphExec_t *out) {
+  std::vector<uintptr_t> key = graph_key(c, sp, nsp, f);
+  for (GraphCache &gc : c->gc)
+    if (gc.exec && key == gc.key) {
+      *out = gc.exec;
+      return PIC_OK;
+    }
+  GraphCache &slot = c->gc[c->gc_next];
+  c->gc_next ^= 1;
+  if (slot.exec) (void)hipGraphExecDestroy(slot.exec);
+  if (slot.graph) (void)hipGraphDestroy(slot.graph);
+  slot = GraphCache{};
+  hipError_t e;
+  if (!c->cap_stream && (e = hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking)) !=
+                            hipSuccess)
+    return hip_fail(c, e, "hipStreamCreate");
+  pic_species tmp[kMaxSpecies];
+  for (int s = 0; s < nsp; s++) tmp[s] = sp[s];
+  if ((e = hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal)) != hipSuccess)
+    return hip_fail(c, e, "hipStreamBeginCapture");
+  hipError_t eq = hipSuccess;
+  for (int k = 0; k < 2 && eq == hipSuccess; k++) {
+    eq = enqueue_step(c, tmp, nsp, f, c->cap_stream);
+    for (int s = 0; s < nsp; s++) swap_buffers(tmp[s]);
+  }
+  hipGraph_t g = nullptr;
+  e = hipStreamEndCapture(c->cap_stream, &g);
+  if (eq != hipSuccess || e != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    return hip_fail(c, eq != hipSuccess ? eq : e, "graph capture");
+  }
+  hipGraphExec_t x = nullptr;
+  if ((e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0)) != hipSuccess) {
+    (void)hipGraphDestroy(g);
+    return hip_fail(c, e, "hipGraphInstantiate");
+  }
+  slot.graph = g;
+  slot.exec = x;
+  slot.key = std::move(key);
+  *out = x;
+  return PIC_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -347,15 +500,15 @@ pic_status pic_validate_config(const pic_config *c, char *msg, size_t len) {
     set_msg(msg, len, "unknown mode %d", c->mode);
     return PIC_ERR_ARG;
   }
-  if (c->chunk < 0) {
-    set_msg(msg, len, "chunk must be >= 0");
+  if (c->chunk < 0 || c->chunk % kSeg) {
+    set_msg(msg, len, "chunk must be 0 (auto) or a positive multiple of %d", kSeg);
     return PIC_ERR_ARG;
   }
   if (c->wg_size != 0 && (c->wg_size < 64 || c->wg_size > 256 || c->wg_size % 64)) {
     set_msg(msg, len, "wg_size must be 0 or a multiple of 64 in [64, 256]");
     return PIC_ERR_ARG;
   }
-  if (c->flags & ~(uint32_t)PIC_FLAG_CHECK) {
+  if (c->flags & ~(uint32_t)(PIC_FLAG_CHECK | PIC_FLAG_GRAPH)) {
     set_msg(msg, len, "unknown flag bits 0x%x", c->flags);
     return PIC_ERR_ARG;
   }
@@ -392,13 +545,18 @@ pic_status pic_init(const pic_config *cfg, int32_t device, pic_ctx **out) {
   c->g = make_grid(&c->cfg);
   c->device = device;
   c->wg = cfg->wg_size ? cfg->wg_size : 256;
-  c->g.upp = c->wg / 64;
+  const int chunk = cfg->chunk ? cfg->chunk : 2048;
+  c->g.spc = std::max(1, chunk / kSeg);
   if (hipMalloc(&c->err_dev, sizeof(int)) != hipSuccess ||
-      hipMemset(c->err_dev, 0, sizeof(int)) != hipSuccess) {
+      hipMemset(c->err_dev, 0, sizeof(int)) != hipSuccess ||
+      hipMalloc(&c->qctl, 2 * kMaxSpecies * sizeof(int)) != hipSuccess ||
+      hipMemset(c->qctl, 0, 2 * kMaxSpecies * sizeof(int)) != hipSuccess) {
     (void)hipFree(c->err_dev);
+    (void)hipFree(c->qctl);
     delete c;
     return PIC_ERR_HIP;
   }
+  if (c->cfg.mode == PIC_MODE_PERSISTENT) c->pgrid = persistent_grid(c->g, c->wg);
   *out = c;
   return PIC_OK;
 }
@@ -411,6 +569,9 @@ void pic_free(pic_ctx *c) {
     SpScratch &S = c->sp[s];
     (void)hipFree(S.tag);
     (void)hipFree(S.cnt);
+    (void)hipFree(S.pre);
+    (void)hipFree(S.tot);
+    (void)hipFree(S.sstart);
     (void)hipFree(S.rbase);
     (void)hipFree(S.in);
     (void)hipFree(S.noff);
@@ -418,6 +579,13 @@ void pic_free(pic_ctx *c) {
     free_sort_scratch(c->sort[s]);
   }
   for (hipEvent_t e : c->tm.pool) (void)hipEventDestroy(e);
+  for (GraphCache &gc : c->gc) {
+    if (gc.exec) (void)hipGraphExecDestroy(gc.exec);
+    if (gc.graph) (void)hipGraphDestroy(gc.graph);
+  }
+  if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+  (void)hipFree(c->units);
+  (void)hipFree(c->qctl);
   (void)hipFree(c->err_dev);
   delete c;
 }
@@ -482,6 +650,7 @@ pic_status pic_bin(pic_ctx *c, pic_species *sp, int32_t nsp, void *stream) {
                 [&] { return launch_rebin(c->g, a, c->err_dev, c->wg, st); });
     if (e != hipSuccess) return hip_fail(c, e, "kernel launch");
   } else {
+    if ((r = ensure_scratch(c, sp, nsp, false, st)) != PIC_OK) return r;
     for (int s = 0; s < nsp; s++) {
       const SpArgs a = make_args(c, sp + s, 1);
       SpDev d = a.s[0];
@@ -489,6 +658,12 @@ pic_status pic_bin(pic_ctx *c, pic_species *sp, int32_t nsp, void *stream) {
                            [&] { return general_sort(c->g, d, c->sort[s], c->err_dev, st); });
       if (e != hipSuccess) return hip_fail(c, e, "general sort");
     }
+  }
+  {
+    const SpArgs a = make_args(c, sp, nsp);
+    hipError_t e = launch_layout(c->g, a, c->cfg.mode == PIC_MODE_PERSISTENT ? c->units : nullptr,
+                                 c->qctl, st);
+    if (e != hipSuccess) return hip_fail(c, e, "kernel launch");
   }
   for (int s = 0; s < nsp; s++) swap_buffers(sp[s]);
   c->moved = false;
@@ -540,18 +715,17 @@ pic_status pic_step(pic_ctx *c, pic_species *sp, int32_t nsp, pic_fields *f, int
   hipStream_t st = (hipStream_t)stream;
   if (hipSetDevice(c->device) != hipSuccess) return fail(c, PIC_ERR_HIP, "hipSetDevice");
   if ((r = ensure_scratch(c, sp, nsp, false, st)) != PIC_OK) return r;
-  int64_t ncell = 1;
-  for (int a = 0; a < c->cfg.dim; a++) ncell *= c->cfg.n[a];
-  for (int k = 0; k < nsteps; k++) {
-    const SpArgs a = make_args(c, sp, nsp);
-    hipError_t e = timed(c, PIC_KERNEL_ZERO, st, [&] { return launch_zero(f->j, ncell, st); });
-    if (e == hipSuccess)
-      e = timed(c, PIC_KERNEL_IPP, st, [&] {
-        return launch_ipp(c->g, a, f->e, f->b, f->j, c->err_dev, c->wg, st);
-      });
-    if (e == hipSuccess)
-      e = timed(c, PIC_KERNEL_REBIN, st,
-                [&] { return launch_rebin(c->g, a, c->err_dev, c->wg, st); });
+  int k = 0;
+  if ((c->cfg.flags & PIC_FLAG_GRAPH) && !c->tm.on && nsteps >= 2) {
+    hipGraphExec_t x = nullptr;
+    if ((r = ensure_graph(c, sp, nsp, f, &x)) != PIC_OK) return r;
+    for (; k + 2 <= nsteps; k += 2) {
+      hipError_t e = hipGraphLaunch(x, st);
+      if (e != hipSuccess) return hip_fail(c, e, "hipGraphLaunch");
+    }
+  }
+  for (; k < nsteps; k++) {
+    hipError_t e = enqueue_step(c, sp, nsp, f, st);
     if (e != hipSuccess) return hip_fail(c, e, "kernel launch");
     for (int s = 0; s < nsp; s++) swap_buffers(sp[s]);
   }

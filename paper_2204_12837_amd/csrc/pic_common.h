@@ -8,6 +8,7 @@
 namespace pic {
 
 constexpr int kMaxSpecies = 8;
+constexpr int kSeg = 256;   // particles per ranking segment (multiple of 64)
 constexpr int kErrCFL = 1;  // device error bits
 constexpr int kErrPos = 2;
 
@@ -20,8 +21,7 @@ struct GridDev {
   int np[3];      // patches per axis
   int npatch;     // total patches
   int nc;         // neighbour codes: 3^dim
-  int upp;        // ranking units per patch (waves per workgroup): each wave ranks
-                  // its own contiguous share of a patch's particles
+  int spc;        // persistent mode: ranking segments per work unit
   double inv_d[3];
   double L[3];    // n * d
   double dt;
@@ -39,11 +39,20 @@ struct SpDev {
   int64_t *ida;
   int64_t *off;     // [npatch+1] current patch offsets
   int64_t *noff;    // [npatch+1] scratch: offsets after the sort
-  uint32_t *tag;    // [capacity] neighbour code << 27 | rank inside (unit, code)
-  int32_t *cnt;     // [npatch * upp * nc] particles per (ranking unit, code)
+  uint32_t *tag;    // [capacity] neighbour code << 27 | rank inside (segment, code)
+  int32_t *sstart;  // [npatch+1] first ranking segment of each patch (kSeg particles each)
+  int32_t *cnt;     // [max segments * nc] particles per (segment, code)
+  int32_t *pre;     // [max segments * nc] earlier segments' count of the code, same patch
+  int32_t *tot;     // [npatch * nc] particles per (patch, code)
   int64_t *rbase;   // [npatch * nc] start of (patch, code) inside its destination
   int64_t *in;      // [npatch] particles arriving in each destination patch
   double *x0[3];    // saved start-of-step positions (split path)
+  int32_t ubase;    // persistent mode: first work unit of this species
+};
+
+// A persistent-mode work unit: ranking segments [k0, k1) of patch P of species s.
+struct Unit {
+  int32_t s, P, k0, k1;
 };
 
 struct SpArgs {
@@ -57,6 +66,16 @@ hipError_t launch_zero(double *const j[3], int64_t ncell, hipStream_t st);
 hipError_t launch_ipp(const GridDev &g, const SpArgs &sa, const double *const e[3],
                       const double *const b[3], double *const j[3], int *err, int wg,
                       hipStream_t st);
+// Persistent variant: `grid` workgroups pop units from units[0 .. qctl[1]) with
+// the ticket qctl[0] (reset by launch_layout).
+hipError_t launch_ipp_persistent(const GridDev &g, const SpArgs &sa, const double *const e[3],
+                                 const double *const b[3], double *const j[3], int *err,
+                                 const Unit *units, int *qctl, int grid, int wg, hipStream_t st);
+int persistent_grid(const GridDev &g, int wg);
+// Segment starts (and, if units != nullptr, the work-unit list, its length in
+// qctl[1] and a zero ticket in qctl[0]) from the current patch offsets.
+hipError_t launch_layout(const GridDev &g, const SpArgs &sa, Unit *units, int *qctl,
+                         hipStream_t st);
 hipError_t launch_interp_push(const GridDev &g, const SpArgs &sa, const double *const e[3],
                               const double *const b[3], int *err, int wg, hipStream_t st);
 hipError_t launch_project(const GridDev &g, const SpArgs &sa, double *const j[3], int *err,

@@ -36,14 +36,6 @@ namespace pic {
 
 namespace {
 
-constexpr int kWaveMax = 4;  // up to 256 threads per workgroup
-
-// Unit length: each of a workgroup's nw waves ranks a contiguous share of a
-// patch's n particles, a multiple of 64 long.
-__device__ __forceinline__ int unit_len(int n, int nw) {
-  return ((n + 64 * nw - 1) / (64 * nw)) * 64;
-}
-
 __device__ __forceinline__ int wrap_near(int k, int n) {
   // k is within one period of [0, n)
   return k < 0 ? k + n : (k >= n ? k - n : k);
@@ -534,13 +526,81 @@ __device__ __forceinline__ bool in_patch(const TileGeom &t, const double xi[3]) 
 }
 
 // ---------------------------------------------------------------------------
-// Fused step kernel: Interpolation, Push, pre-BC and Projection for the
-// particles of one (patch, species).  Each wave walks its own ranking unit,
-// 64 consecutive particles per iteration.
+// Fused step: Interpolation, Push, pre-BC and Projection of ranking segments
+// [k0, k1) of patch P (each segment kSeg consecutive particles; the waves of
+// the workgroup take segments in turn, 64 particles per iteration, and rank
+// each segment on their own, so the loop has no barrier).  The E/B tile of P
+// is in tEB, the J tile tJ accumulates.
 template <int DIM>
-__global__ void __launch_bounds__(256) k_ipp(GridDev g, SpArgs sa, Fields f, int *err) {
+__device__ __forceinline__ void ipp_segments(const GridDev &g, const SpDev &S, const TileGeom &t,
+                                             const double *tEB, double *tJ, int P, int k0, int k1,
+                                             int &bad) {
   constexpr int NC = DIM == 2 ? 9 : 27;
   constexpr int CENTER = (NC - 1) / 2;
+  const int64_t beg = S.off[P], end = S.off[P + 1];
+  const int nw = blockDim.x >> 6, wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int sbase = S.sstart[P];
+  const double q = S.q, alpha = S.alpha;
+  for (int k = k0 + wv; k < k1; k += nw) {
+    const int64_t sb = beg + (int64_t)k * kSeg;
+    const int64_t se = sb + kSeg < end ? sb + kSeg : end;
+    int run = 0;
+    for (int64_t base = sb; base < se; base += 64) {
+      const int64_t i = base + lane;
+      const bool valid = i < se;
+      int code = CENTER;
+      if (valid) {
+        double x[3], xi[3], u[3], v[3], F[6];
+#pragma unroll
+        for (int a = 0; a < DIM; a++) {
+          x[a] = S.x[a][i];
+          xi[a] = x[a] * g.inv_d[a];
+        }
+        if (!in_patch<DIM>(t, xi)) {
+          bad |= kErrPos;
+        } else {
+          u[0] = S.u[0][i];
+          u[1] = S.u[1][i];
+          u[2] = S.u[2][i];
+          const double w = S.w[i];
+          const Shapes sh = shapes_at<DIM>(xi, t.org);
+          interp6<DIM>(tEB, t.TE, t.Tx, t.Txy, sh, F);
+          boris(alpha, F, u, v);
+          double x1[3];
+          Win win[DIM];
+          bool ok = true;
+#pragma unroll
+          for (int a = 0; a < DIM; a++) {
+            x1[a] = x[a] + g.dt * v[a];
+            ok = ok && esk_win(sh.p[a], x1[a] * g.inv_d[a], sh.p[a].i + 1 + t.org[a], win[a]);
+          }
+          if (ok)
+            deposit<DIM>(g, tJ, t.TJ, t.Jx, t.Jxy, q * w, win, v[2]);
+          else
+            bad |= kErrCFL;
+          const int c = dest_code<DIM>(g, t.lo, x1);
+          if (c < 0) {
+            bad |= kErrPos;
+          } else {
+            code = c;
+          }
+#pragma unroll
+          for (int a = 0; a < DIM; a++) S.x[a][i] = x1[a];
+          S.u[0][i] = u[0];
+          S.u[1][i] = u[1];
+          S.u[2][i] = u[2];
+        }
+      }
+      const uint32_t rank = wave_rank(valid, code, lane, run);
+      if (valid) S.tag[i] = ((uint32_t)code << 27) | rank;
+    }
+    if (lane < NC) S.cnt[(int64_t)(sbase + k) * NC + lane] = run;
+  }
+}
+
+// Per-patch launch: one workgroup per (patch, species), all its segments.
+template <int DIM>
+__global__ void __launch_bounds__(256) k_ipp(GridDev g, SpArgs sa, Fields f, int *err) {
   extern __shared__ __align__(16) double lds[];
   const int P = blockIdx.x;
   const SpDev &S = sa.s[blockIdx.y];
@@ -550,66 +610,56 @@ __global__ void __launch_bounds__(256) k_ipp(GridDev g, SpArgs sa, Fields f, int
   stage_eb<DIM>(g, t, f, tEB);
   zero_tile<DIM>(tJ, 3 * t.TJ);
   __syncthreads();
-  const int64_t beg = S.off[P], end = S.off[P + 1];
-  const int nw = blockDim.x >> 6, wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int L = unit_len((int)(end - beg), nw);
-  const int64_t ub = beg + (int64_t)wv * L;
-  const int64_t ue = ub + L < end ? ub + L : end;
-  const double q = S.q, alpha = S.alpha;
-  int run = 0, bad = 0;
-  for (int64_t base = ub; base < ue; base += 64) {
-    const int64_t i = base + lane;
-    const bool valid = i < ue;
-    int code = CENTER;
-    if (valid) {
-      double x[3], xi[3], u[3], v[3], F[6];
-#pragma unroll
-      for (int a = 0; a < DIM; a++) {
-        x[a] = S.x[a][i];
-        xi[a] = x[a] * g.inv_d[a];
-      }
-      if (!in_patch<DIM>(t, xi)) {
-        bad |= kErrPos;
-      } else {
-        u[0] = S.u[0][i];
-        u[1] = S.u[1][i];
-        u[2] = S.u[2][i];
-        const double w = S.w[i];
-        const Shapes sh = shapes_at<DIM>(xi, t.org);
-        interp6<DIM>(tEB, t.TE, t.Tx, t.Txy, sh, F);
-        boris(alpha, F, u, v);
-        double x1[3];
-        Win win[DIM];
-        bool ok = true;
-#pragma unroll
-        for (int a = 0; a < DIM; a++) {
-          x1[a] = x[a] + g.dt * v[a];
-          ok = ok && esk_win(sh.p[a], x1[a] * g.inv_d[a], sh.p[a].i + 1 + t.org[a], win[a]);
-        }
-        if (ok)
-          deposit<DIM>(g, tJ, t.TJ, t.Jx, t.Jxy, q * w, win, v[2]);
-        else
-          bad |= kErrCFL;
-        const int c = dest_code<DIM>(g, t.lo, x1);
-        if (c < 0) {
-          bad |= kErrPos;
-        } else {
-          code = c;
-        }
-#pragma unroll
-        for (int a = 0; a < DIM; a++) S.x[a][i] = x1[a];
-        S.u[0][i] = u[0];
-        S.u[1][i] = u[1];
-        S.u[2][i] = u[2];
-      }
-    }
-    const uint32_t rank = wave_rank(valid, code, lane, run);
-    if (valid) S.tag[i] = ((uint32_t)code << 27) | rank;
-  }
-  if (lane < NC) S.cnt[((int64_t)P * nw + wv) * NC + lane] = run;
+  int bad = 0;
+  ipp_segments<DIM>(g, S, t, tEB, tJ, P, 0, S.sstart[P + 1] - S.sstart[P], bad);
   if (bad) atomicOr(err, bad);
   __syncthreads();
   flush_j<DIM>(g, t, tJ, f.j);
+}
+
+// Persistent launch: a fixed grid of workgroups pops (patch, segment range)
+// units of each species in turn from a device ticket (qctl[2s], with
+// qctl[2s+1] units listed at units + ubase) until every list is exhausted.
+// The E/B tile is restaged and the J tile flushed only when the patch changes
+// between a workgroup's consecutive units (E/B and J do not depend on the
+// species).
+template <int DIM>
+__global__ void __launch_bounds__(256) k_ipp_persistent(GridDev g, SpArgs sa, Fields f, int *err,
+                                                        const Unit *units, int *qctl) {
+  extern __shared__ __align__(16) double lds[];
+  __shared__ int s_unit;
+  int curP = -1;
+  TileGeom t = tile_geom<DIM>(g, 0);
+  double *tEB = lds;
+  double *tJ = lds + 6 * t.TE;
+  int bad = 0;
+  for (int s = 0; s < sa.nsp; s++) {
+    const int n_units = qctl[2 * s + 1];
+    const Unit *ul = units + sa.s[s].ubase;
+    for (;;) {
+      if (threadIdx.x == 0) s_unit = atomicAdd(&qctl[2 * s], 1);
+      __syncthreads();
+      const int u = s_unit;
+      __syncthreads();  // every thread has read s_unit before the next pop
+      if (u >= n_units) break;
+      const Unit un = ul[u];
+      if (un.P != curP) {
+        if (curP >= 0) {
+          flush_j<DIM>(g, t, tJ, f.j);
+          __syncthreads();  // flush has read the J tile before it is zeroed
+        }
+        t = tile_geom<DIM>(g, un.P);
+        stage_eb<DIM>(g, t, f, tEB);
+        zero_tile<DIM>(tJ, 3 * t.TJ);
+        __syncthreads();
+        curP = un.P;
+      }
+      ipp_segments<DIM>(g, sa.s[s], t, tEB, tJ, un.P, un.k0, un.k1, bad);
+      __syncthreads();  // this unit's deposits are done before any flush
+    }
+  }
+  if (curP >= 0) flush_j<DIM>(g, t, tJ, f.j);
+  if (bad) atomicOr(err, bad);
 }
 
 // Split path, first half: Interpolation + Push; saves the start positions.
@@ -691,8 +741,9 @@ __global__ void __launch_bounds__(256) k_project(GridDev g, SpArgs sa, Fields f,
   flush_j<DIM>(g, t, tJ, f.j);
 }
 
-// Split path pre-BC: wrap, neighbour code and stable rank of particles that
-// moved at most one cell since the last sort (same ranking units as k_ipp).
+// Split path pre-BC: wrap, neighbour code and stable rank (per ranking
+// segment, as in the fused kernel) of particles that moved at most one cell
+// since the last sort.
 template <int DIM>
 __global__ void __launch_bounds__(256) k_tag(GridDev g, SpArgs sa, int *err) {
   constexpr int NC = DIM == 2 ? 9 : 27;
@@ -702,32 +753,54 @@ __global__ void __launch_bounds__(256) k_tag(GridDev g, SpArgs sa, int *err) {
   const TileGeom t = tile_geom<DIM>(g, P);
   const int64_t beg = S.off[P], end = S.off[P + 1];
   const int nw = blockDim.x >> 6, wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int L = unit_len((int)(end - beg), nw);
-  const int64_t ub = beg + (int64_t)wv * L;
-  const int64_t ue = ub + L < end ? ub + L : end;
-  int run = 0, bad = 0;
-  for (int64_t base = ub; base < ue; base += 64) {
-    const int64_t i = base + lane;
-    const bool valid = i < ue;
-    int code = CENTER;
-    if (valid) {
-      double x[3];
+  const int sbase = S.sstart[P], nseg = S.sstart[P + 1] - sbase;
+  int bad = 0;
+  for (int k = wv; k < nseg; k += nw) {
+    const int64_t sb = beg + (int64_t)k * kSeg;
+    const int64_t se = sb + kSeg < end ? sb + kSeg : end;
+    int run = 0;
+    for (int64_t base = sb; base < se; base += 64) {
+      const int64_t i = base + lane;
+      const bool valid = i < se;
+      int code = CENTER;
+      if (valid) {
+        double x[3];
 #pragma unroll
-      for (int a = 0; a < DIM; a++) x[a] = S.x[a][i];
-      const int c = dest_code<DIM>(g, t.lo, x);
-      if (c < 0) {
-        bad |= kErrPos;
-      } else {
-        code = c;
+        for (int a = 0; a < DIM; a++) x[a] = S.x[a][i];
+        const int c = dest_code<DIM>(g, t.lo, x);
+        if (c < 0) {
+          bad |= kErrPos;
+        } else {
+          code = c;
 #pragma unroll
-        for (int a = 0; a < DIM; a++) S.x[a][i] = x[a];
+          for (int a = 0; a < DIM; a++) S.x[a][i] = x[a];
+        }
       }
+      const uint32_t rank = wave_rank(valid, code, lane, run);
+      if (valid) S.tag[i] = ((uint32_t)code << 27) | rank;
     }
-    const uint32_t rank = wave_rank(valid, code, lane, run);
-    if (valid) S.tag[i] = ((uint32_t)code << 27) | rank;
+    if (lane < NC) S.cnt[(int64_t)(sbase + k) * NC + lane] = run;
   }
-  if (lane < NC) S.cnt[((int64_t)P * nw + wv) * NC + lane] = run;
   if (bad) atomicOr(err, bad);
+}
+
+// Sort, step 0: per (patch, code), the running count over the patch's
+// segments (pre) and the total (tot).  One thread per patch and code.
+__global__ void k_seg_prefix(GridDev g, SpArgs sa) {
+  const SpDev &S = sa.s[blockIdx.y];
+  const int nc = g.nc;
+  const int id = blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= g.npatch * nc) return;
+  const int P = id / nc, c = id - P * nc;
+  const int s0 = S.sstart[P], s1 = S.sstart[P + 1];
+  int run = 0;
+  for (int k = s0; k < s1; k++) {
+    const int64_t at = (int64_t)k * nc + c;
+    const int v = S.cnt[at];
+    S.pre[at] = run;
+    run += v;
+  }
+  S.tot[id] = run;
 }
 
 // Sort, step 1: for every destination patch D, the particles arriving from
@@ -737,7 +810,7 @@ __global__ void k_dest_bases(GridDev g, SpArgs sa) {
   const int D = blockIdx.x * blockDim.x + threadIdx.x;
   if (D >= g.npatch) return;
   const SpDev &S = sa.s[blockIdx.y];
-  const int nc = g.nc, upp = g.upp;
+  const int nc = g.nc;
   int dc[3];
   patch_coords(g, D, dc);
   int src[27], code[27], num[27];
@@ -755,8 +828,6 @@ __global__ void k_dest_bases(GridDev g, SpArgs sa) {
       Psrc += q * mul;
       mul *= g.np[a];
     }
-    int tot = 0;
-    for (int w = 0; w < upp; w++) tot += S.cnt[((int64_t)Psrc * upp + w) * nc + c];
     // insertion by source patch (stable in c)
     int k = c;
     while (k > 0 && src[k - 1] > Psrc) {
@@ -767,7 +838,7 @@ __global__ void k_dest_bases(GridDev g, SpArgs sa) {
     }
     src[k] = Psrc;
     code[k] = c;
-    num[k] = tot;
+    num[k] = S.tot[(int64_t)Psrc * nc + c];
   }
   int64_t run = 0;
   for (int k = 0; k < nc; k++) {
@@ -777,17 +848,14 @@ __global__ void k_dest_bases(GridDev g, SpArgs sa) {
   S.in[D] = run;
 }
 
-// Sort, step 2: exclusive scan of arrivals into the new offsets (one
-// workgroup per species).
-__global__ void __launch_bounds__(1024) k_scan_offsets(GridDev g, SpArgs sa) {
-  const SpDev &S = sa.s[blockIdx.x];
-  __shared__ int64_t part[1024];
-  const int n = g.npatch;
+// Exclusive scan of n int64 values from `in` into out[0..n] (out[n] = total),
+// by one workgroup of 1024 threads.
+__device__ void block_scan_1024(const int64_t *in, int64_t *out, int n, int64_t *part) {
   const int per = (n + blockDim.x - 1) / blockDim.x;
   const int b = threadIdx.x * per;
   const int e = min(n, b + per);
   int64_t sum = 0;
-  for (int k = b; k < e; k++) sum += S.in[k];
+  for (int k = b; k < e; k++) sum += in[k];
   part[threadIdx.x] = sum;
   __syncthreads();
   for (int off = 1; off < (int)blockDim.x; off <<= 1) {
@@ -798,38 +866,46 @@ __global__ void __launch_bounds__(1024) k_scan_offsets(GridDev g, SpArgs sa) {
   }
   int64_t run = part[threadIdx.x] - sum;
   for (int k = b; k < e; k++) {
-    S.noff[k] = run;
-    run += S.in[k];
+    const int64_t v = in[k];
+    out[k] = run;
+    run += v;
   }
-  if (threadIdx.x == blockDim.x - 1) S.noff[n] = part[threadIdx.x];
+  if (threadIdx.x == blockDim.x - 1) out[n] = part[threadIdx.x];
+  __syncthreads();
+}
+
+// Sort, step 2: new patch offsets (one workgroup per species).
+__global__ void __launch_bounds__(1024) k_scan_offsets(GridDev g, SpArgs sa) {
+  const SpDev &S = sa.s[blockIdx.x];
+  __shared__ int64_t part[1024];
+  block_scan_1024(S.in, S.noff, g.npatch, part);
 }
 
 // Sort, step 3: move every particle of a source patch to its place:
-// destination start + start of (patch, code) inside it + earlier ranking
-// units' counts of that code + the particle's rank.
+// destination start + start of (patch, code) inside it + the code's count in
+// the patch's earlier segments + the particle's rank in its segment.
 __global__ void __launch_bounds__(256) k_scatter(GridDev g, SpArgs sa, int dim, int *err) {
   const int P = blockIdx.x;
   const SpDev &S = sa.s[blockIdx.y];
-  const int nc = g.nc, upp = g.upp;
-  __shared__ int64_t base[kWaveMax * 27];
-  if (threadIdx.x < (unsigned)(nc * upp)) {
-    const int w = threadIdx.x / nc, c = threadIdx.x - w * nc;
+  const int nc = g.nc;
+  __shared__ int64_t base[27];
+  if (threadIdx.x < (unsigned)nc) {
     int pc[3];
     patch_coords(g, P, pc);
-    const int D = dest_patch(g, pc, c);
-    int64_t b = S.noff[D] + S.rbase[(int64_t)P * nc + c];
-    for (int k = 0; k < w; k++) b += S.cnt[((int64_t)P * upp + k) * nc + c];
-    base[threadIdx.x] = b;
+    const int D = dest_patch(g, pc, threadIdx.x);
+    base[threadIdx.x] = S.noff[D] + S.rbase[(int64_t)P * nc + threadIdx.x];
   }
   __syncthreads();
   const int64_t beg = S.off[P], end = S.off[P + 1];
-  const int L = unit_len((int)(end - beg), upp);
+  const int sbase = S.sstart[P], nseg = S.sstart[P + 1] - sbase;
   int bad = 0;
   for (int64_t i = beg + threadIdx.x; i < end; i += blockDim.x) {
     const uint32_t tg = S.tag[i];
     const int c = (int)(tg >> 27);
-    const int w = (int)(i - beg) / L;
-    const int64_t dst = c < nc && w < upp ? base[w * nc + c] + (int64_t)(tg & ((1u << 27) - 1)) : S.n;
+    const int k = (int)((i - beg) / kSeg);
+    int64_t dst = S.n;
+    if (c < nc && k < nseg)
+      dst = base[c] + S.pre[(int64_t)(sbase + k) * nc + c] + (int64_t)(tg & ((1u << 27) - 1));
     if (dst >= S.n) {
       bad |= kErrPos;
       continue;
@@ -849,6 +925,43 @@ __global__ void k_copy_offsets(GridDev g, SpArgs sa) {
   const SpDev &S = sa.s[blockIdx.y];
   for (int k = blockIdx.x * blockDim.x + threadIdx.x; k <= g.npatch; k += gridDim.x * blockDim.x)
     S.off[k] = S.noff[k];
+}
+
+// Layout after any sort (one workgroup per species): segment starts from the
+// patch offsets; in persistent mode also each patch's work units
+// (ceil(segments / spc) of them) in patch order, their number in qctl[2s+1]
+// and a zero ticket in qctl[2s].  Uses the species' in/noff arrays as scratch.
+__global__ void __launch_bounds__(1024) k_layout(GridDev g, SpArgs sa, Unit *units, int *qctl) {
+  __shared__ int64_t part[1024];
+  const int s = blockIdx.x;
+  const SpDev &S = sa.s[s];
+  const int n = g.npatch;
+  for (int P = threadIdx.x; P < n; P += blockDim.x)
+    S.in[P] = (S.off[P + 1] - S.off[P] + kSeg - 1) / kSeg;
+  __syncthreads();
+  block_scan_1024(S.in, S.noff, n, part);
+  for (int P = threadIdx.x; P <= n; P += blockDim.x) S.sstart[P] = (int32_t)S.noff[P];
+  if (!units) return;
+  __syncthreads();
+  for (int P = threadIdx.x; P < n; P += blockDim.x) S.in[P] = (S.in[P] + g.spc - 1) / g.spc;
+  __syncthreads();
+  block_scan_1024(S.in, S.noff, n, part);
+  for (int P = threadIdx.x; P < n; P += blockDim.x) {
+    const int nseg = S.sstart[P + 1] - S.sstart[P];
+    int64_t at = S.ubase + S.noff[P];
+    for (int k0 = 0; k0 < nseg; k0 += g.spc, at++) {
+      Unit un;
+      un.s = s;
+      un.P = P;
+      un.k0 = k0;
+      un.k1 = k0 + g.spc < nseg ? k0 + g.spc : nseg;
+      units[at] = un;
+    }
+  }
+  if (threadIdx.x == 0) {
+    qctl[2 * s + 1] = (int)S.noff[n];
+    qctl[2 * s] = 0;
+  }
 }
 
 __global__ void k_zero(double *a, double *b, double *c, int64_t n) {
@@ -940,16 +1053,57 @@ hipError_t launch_tag(const GridDev &g, const SpArgs &sa, int *err, int wg, hipS
 }
 
 hipError_t launch_rebin(const GridDev &g, const SpArgs &sa, int *err, int wg, hipStream_t st) {
-  hipLaunchKernelGGL(k_dest_bases, dim3((g.npatch + 127) / 128, sa.nsp), dim3(128), 0, st, g, sa);
+  const int pc = g.npatch * g.nc;
+  hipLaunchKernelGGL(k_seg_prefix, dim3((pc + 255) / 256, sa.nsp), dim3(256), 0, st, g, sa);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_dest_bases, dim3((g.npatch + 127) / 128, sa.nsp), dim3(128), 0, st, g, sa);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
   hipLaunchKernelGGL(k_scan_offsets, dim3(sa.nsp), dim3(1024), 0, st, g, sa);
-  e = hipGetLastError();
-  if (e != hipSuccess) return e;
+  if ((e = hipGetLastError()) != hipSuccess) return e;
   hipLaunchKernelGGL(k_scatter, dim3(g.npatch, sa.nsp), dim3(wg), 0, st, g, sa, g.dim, err);
-  e = hipGetLastError();
-  if (e != hipSuccess) return e;
+  if ((e = hipGetLastError()) != hipSuccess) return e;
   hipLaunchKernelGGL(k_copy_offsets, dim3((g.npatch + 256) / 256, sa.nsp), dim3(256), 0, st, g, sa);
+  return hipGetLastError();
+}
+
+hipError_t launch_layout(const GridDev &g, const SpArgs &sa, Unit *units, int *qctl,
+                         hipStream_t st) {
+  hipLaunchKernelGGL(k_layout, dim3(sa.nsp), dim3(1024), 0, st, g, sa, units, qctl);
+  return hipGetLastError();
+}
+
+int persistent_grid(const GridDev &g, int wg) {
+  const size_t lds = lds_bytes_ipp(g);
+  int per_cu = 0;
+  hipError_t e;
+  if (g.dim == 2)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_ipp_persistent<2>, wg, lds);
+  else
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_ipp_persistent<3>, wg, lds);
+  int dev = 0, ncu = 0;
+  if (e != hipSuccess || per_cu < 1) per_cu = 1;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      ncu < 1)
+    ncu = 1;
+  return per_cu * ncu;
+}
+
+hipError_t launch_ipp_persistent(const GridDev &g, const SpArgs &sa, const double *const e[3],
+                                 const double *const b[3], double *const j[3], int *err,
+                                 const Unit *units, int *qctl, int grid, int wg, hipStream_t st) {
+  const Fields f = mkfields(e, b, j);
+  const size_t lds = lds_bytes_ipp(g);
+  if (g.dim == 2) {
+    hipLaunchKernelGGL(k_ipp_persistent<2>, dim3(grid), dim3(wg), lds, st, g, sa, f, err, units,
+                       qctl);
+  } else {
+    (void)hipFuncSetAttribute((const void *)k_ipp_persistent<3>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL(k_ipp_persistent<3>, dim3(grid), dim3(wg), lds, st, g, sa, f, err, units,
+                       qctl);
+  }
   return hipGetLastError();
 }
 

@@ -20,7 +20,7 @@ PIC_OK, PIC_ERR_ARG, PIC_ERR_HIP, PIC_ERR_CAPACITY, PIC_ERR_CFL, PIC_ERR_POS, PI
 STATUS_NAMES = {0: "PIC_OK", 1: "PIC_ERR_ARG", 2: "PIC_ERR_HIP", 3: "PIC_ERR_CAPACITY",
                 4: "PIC_ERR_CFL", 5: "PIC_ERR_POS", 6: "PIC_ERR_STATE"}
 MODE_PER_PATCH, MODE_PERSISTENT = 0, 1
-FLAG_CHECK = 1
+FLAG_CHECK, FLAG_GRAPH = 1, 2
 
 _DP = C.POINTER(C.c_double)
 _I64P = C.POINTER(C.c_int64)
@@ -204,9 +204,10 @@ class Context:
     """A library context (pic_init / pic_free)."""
 
     def __init__(self, wl, device: int = 0, mode=MODE_PER_PATCH, chunk=0, wg_size=0,
-                 check=False):
+                 check=False, graph=False):
         self.wl = wl
-        self.cfg = make_config(wl, mode, chunk, wg_size, FLAG_CHECK if check else 0)
+        flags = (FLAG_CHECK if check else 0) | (FLAG_GRAPH if graph else 0)
+        self.cfg = make_config(wl, mode, chunk, wg_size, flags)
         rc, msg = validate(self.cfg)
         if rc:
             raise PicError(rc, msg)

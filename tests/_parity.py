@@ -22,12 +22,14 @@ def run_oracle(wl, inp, steps, with_abs=True):
     return sps, J, A
 
 
-def run_gpu(wl, inp, steps, mode=0, chunk=0, wg_size=0, split=False, device="cuda:0"):
+def run_gpu(wl, inp, steps, mode=0, chunk=0, wg_size=0, split=False, device="cuda:0",
+            graph=False, step_sizes=None):
     import torch
 
     from paper_2204_12837_amd import pic
 
-    ctx = pic.Context(wl, device=0, mode=mode, chunk=chunk, wg_size=wg_size, check=True)
+    ctx = pic.Context(wl, device=0, mode=mode, chunk=chunk, wg_size=wg_size, check=True,
+                      graph=graph)
     sp = pic.upload(inp, device)
     E, B, J = pic.upload_fields(inp, device)
     ctx.bin(sp)
@@ -37,6 +39,11 @@ def run_gpu(wl, inp, steps, mode=0, chunk=0, wg_size=0, split=False, device="cud
             ctx.interp_push(sp, E, B)
             ctx.project(sp, J)
             ctx.bin(sp)
+    elif step_sizes:
+        assert sum(step_sizes) == steps
+        for k in step_sizes:
+            ctx.step(sp, E, B, J, nsteps=k)
+            torch.cuda.synchronize()
     else:
         ctx.step(sp, E, B, J, nsteps=steps)
     torch.cuda.synchronize()

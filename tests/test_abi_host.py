@@ -68,6 +68,7 @@ def test_valid_configs_pass():
     (dict(flags=0x80), "flag"),
     (dict(n=(64, 64, 2)), "2D"),
     (dict(chunk=-1), "chunk"),
+    (dict(chunk=300), "chunk"),
 ])
 def test_invalid_configs_rejected(over, frag):
     rc, msg = pic.validate(_cfg(**over))

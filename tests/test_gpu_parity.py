@@ -122,3 +122,51 @@ def test_zero_steps_and_zero_particles():
     g, Jg = run_gpu(wl, inp, 2)
     compare(osp, J, A, g, Jg)
     assert np.all(Jg == 0)
+
+
+PERSISTENT_CASES = [
+    # dim, n, patch, ppc, nspecies, sigma, steps, seed, chunk, wg
+    (2, (48, 24), (8, 8), 6, 1, 0.2, 4, 201, 256, 256),
+    (2, (48, 24), (8, 8), 6, 1, 0.2, 4, 202, 512, 128),
+    (2, (64, 32), (16, 16), 9, 2, 0.3, 3, 203, 1024, 256),
+    (3, (16, 16, 8), (8, 8, 8), 3, 2, 0.2, 3, 204, 256, 256),
+    (3, (24, 12, 12), (6, 6, 6), 2, 1, 0.4, 3, 205, 512, 192),
+]
+
+
+@pytest.mark.parametrize("case", PERSISTENT_CASES)
+def test_persistent_matches_oracle(case):
+    """The persistent work-queue launch (units of `chunk` particles) gives
+    the same particles, order and counts, and J within the bar."""
+    dim, n, patch, ppc, nsp, sigma, steps, seed, chunk, wg = case
+    wl = I.custom(dim, n, patch, ppc=ppc, seed=seed, sigma=sigma, n_species=nsp)
+    inp = I.generate(wl)
+    say(f"case persistent {case}")
+    osp, J, A = run_oracle(wl, inp, steps)
+    g, Jg = run_gpu(wl, inp, steps, mode=1, chunk=chunk, wg_size=wg)
+    compare(osp, J, A, g, Jg)
+
+
+def test_persistent_imbalanced_profile():
+    """Empty patches next to patches of several thousand particles."""
+    wl = I.custom(2, (96, 32), (16, 16), ppc=1, seed=210, sigma=0.2)
+    wl.species[0].ppc = lambda ix: np.where(ix < 48, 0, np.where(ix < 64, 24, 3)).astype(np.int64)
+    inp = I.generate(wl)
+    say("case persistent imbalanced")
+    osp, J, A = run_oracle(wl, inp, 4)
+    for chunk in (256, 2048):
+        g, Jg = run_gpu(wl, inp, 4, mode=1, chunk=chunk)
+        compare(osp, J, A, g, Jg)
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_graph_replay_matches_oracle(mode):
+    """Steps replayed from captured graphs (pairs of steps), interleaved
+    with eager odd steps and host synchronisations, agree with the oracle
+    after every call sequence."""
+    wl = I.custom(2, (48, 32), (8, 8), ppc=5, seed=300 + mode, sigma=0.2)
+    inp = I.generate(wl)
+    say(f"case graph mode={mode}")
+    osp, J, A = run_oracle(wl, inp, 11)
+    g, Jg = run_gpu(wl, inp, 11, mode=mode, chunk=512, graph=True, step_sizes=[4, 1, 2, 3, 1])
+    compare(osp, J, A, g, Jg)
