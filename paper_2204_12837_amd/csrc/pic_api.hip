@@ -24,6 +24,7 @@ struct SpScratch {
   int64_t maxseg = 0;   // ranking segments the count arrays hold
   uint32_t *tag = nullptr;
   int32_t *sstart = nullptr, *cnt = nullptr, *pre = nullptr, *tot = nullptr;
+  int32_t *seg2p = nullptr, *perm = nullptr;
   int64_t *rbase = nullptr, *in = nullptr, *noff = nullptr;
   int64_t x0cap = 0;
   double *x0[3] = {nullptr, nullptr, nullptr};
@@ -186,6 +187,9 @@ pic_status ensure_scratch(pic_ctx *c, const pic_species *sp, int32_t nsp, bool x
       const size_t np = (size_t)c->g.npatch, nc = (size_t)c->g.nc;
       const int64_t maxseg = (int64_t)np + cap / kSeg + 1;
       if ((e = realloc_dev(S.tag, (size_t)cap)) != hipSuccess) return hip_fail(c, e, "hipMalloc");
+      if ((e = realloc_dev(S.perm, (size_t)cap)) != hipSuccess) return hip_fail(c, e, "hipMalloc");
+      if ((e = realloc_dev(S.seg2p, (size_t)maxseg)) != hipSuccess)
+        return hip_fail(c, e, "hipMalloc");
       if ((e = realloc_dev(S.cnt, (size_t)maxseg * nc)) != hipSuccess)
         return hip_fail(c, e, "hipMalloc");
       if ((e = realloc_dev(S.pre, (size_t)maxseg * nc)) != hipSuccess)
@@ -230,6 +234,12 @@ pic_status ensure_scratch(pic_ctx *c, const pic_species *sp, int32_t nsp, bool x
   return PIC_OK;
 }
 
+int64_t max_segments(const pic_ctx *c, int32_t nsp) {
+  int64_t m = 1;
+  for (int s = 0; s < nsp; s++) m = std::max(m, c->sp[s].maxseg);
+  return m;
+}
+
 SpArgs make_args(pic_ctx *c, const pic_species *sp, int32_t nsp) {
   SpArgs a{};
   a.nsp = nsp;
@@ -260,6 +270,8 @@ SpArgs make_args(pic_ctx *c, const pic_species *sp, int32_t nsp) {
     d.rbase = c->sp[s].rbase;
     d.in = c->sp[s].in;
     d.ubase = (int32_t)c->sp[s].ubase;
+    d.seg2p = c->sp[s].seg2p;
+    d.perm = c->sp[s].perm;
   }
   return a;
 }
@@ -331,12 +343,17 @@ bool fields_ok(const pic_ctx *c, const pic_fields *f, bool eb, bool j) {
 }
 
 // Enqueue one whole step (J <- 0, fused kernel, sort, layout) on st for the
-// buffer assignment in sp; the caller swaps the buffers afterwards.
+// buffer assignment in sp.  gather: the fused kernel reads the particles
+// through the previous sort's permutation and writes the other buffer set.
+// materialize: the sort copies the particles into the other buffer set;
+// otherwise it only records the permutation.  The caller swaps the buffer
+// sets once per gather and once per materialize.
 hipError_t enqueue_step(pic_ctx *c, const pic_species *sp, int32_t nsp, const pic_fields *f,
-                        hipStream_t st) {
+                        hipStream_t st, bool gather, bool materialize) {
   int64_t ncell = 1;
   for (int a = 0; a < c->cfg.dim; a++) ncell *= c->cfg.n[a];
-  const SpArgs a = make_args(c, sp, nsp);
+  SpArgs a = make_args(c, sp, nsp);
+  a.gather = gather ? 1 : 0;
   const bool pers = c->cfg.mode == PIC_MODE_PERSISTENT;
   hipError_t e = timed(c, PIC_KERNEL_ZERO, st, [&] { return launch_zero(f->j, ncell, st); });
   if (e == hipSuccess)
@@ -345,13 +362,21 @@ hipError_t enqueue_step(pic_ctx *c, const pic_species *sp, int32_t nsp, const pi
                                           c->qctl, c->pgrid, c->wg, st)
                   : launch_ipp(c->g, a, f->e, f->b, f->j, c->err_dev, c->wg, st);
     });
-  if (e == hipSuccess)
-    e = timed(c, PIC_KERNEL_REBIN, st, [&] {
-      hipError_t r2 = launch_rebin(c->g, a, c->err_dev, c->wg, st);
-      if (r2 == hipSuccess) r2 = launch_layout(c->g, a, pers ? c->units : nullptr, c->qctl, st);
-      return r2;
-    });
-  return e;
+  if (e != hipSuccess) return e;
+  // the sort reads the particles where the fused kernel wrote them
+  SpArgs r = make_args(c, sp, nsp);
+  if (gather)
+    for (int s = 0; s < nsp; s++) {
+      std::swap(r.s[s].x, r.s[s].xa);
+      std::swap(r.s[s].u, r.s[s].ua);
+      std::swap(r.s[s].w, r.s[s].wa);
+      std::swap(r.s[s].id, r.s[s].ida);
+    }
+  return timed(c, PIC_KERNEL_REBIN, st, [&] {
+    hipError_t r2 = launch_rebin(c->g, r, c->err_dev, max_segments(c, nsp), !materialize, st);
+    if (r2 == hipSuccess) r2 = launch_layout(c->g, r, pers ? c->units : nullptr, c->qctl, st);
+    return r2;
+  });
 }
 
 // Everything a captured graph depends on.
@@ -390,8 +415,9 @@ std::vector<uintptr_t> graph_key(const pic_ctx *c, const pic_species *sp, int32_
   return k;
 }
 
-// Capture two steps (buffers A->B, then B->A) into a graph, unless one of
-// the two cached graphs was captured with the same pointers; returns it.
+// Capture two middle steps of a run (gathering fused kernel A->B with a
+// permutation-only sort, then B->A) into a graph, unless one of the two
+// cached graphs was captured with the same pointers; returns it.
 pic_status ensure_graph(pic_ctx *c, const pic_species *sp, int32_t nsp, const pic_fields *f,
                         hipGraphExec_t *out) {
   std::vector<uintptr_t> key = graph_key(c, sp, nsp, f);
@@ -415,7 +441,7 @@ pic_status ensure_graph(pic_ctx *c, const pic_species *sp, int32_t nsp, const pi
     return hip_fail(c, e, "hipStreamBeginCapture");
   hipError_t eq = hipSuccess;
   for (int k = 0; k < 2 && eq == hipSuccess; k++) {
-    eq = enqueue_step(c, tmp, nsp, f, c->cap_stream);
+    eq = enqueue_step(c, tmp, nsp, f, c->cap_stream, true, false);
     for (int s = 0; s < nsp; s++) swap_buffers(tmp[s]);
   }
   hipGraph_t g = nullptr;
@@ -569,6 +595,8 @@ void pic_free(pic_ctx *c) {
     SpScratch &S = c->sp[s];
     (void)hipFree(S.tag);
     (void)hipFree(S.cnt);
+    (void)hipFree(S.seg2p);
+    (void)hipFree(S.perm);
     (void)hipFree(S.pre);
     (void)hipFree(S.tot);
     (void)hipFree(S.sstart);
@@ -646,8 +674,9 @@ pic_status pic_bin(pic_ctx *c, pic_species *sp, int32_t nsp, void *stream) {
     hipError_t e =
         timed(c, PIC_KERNEL_TAG, st, [&] { return launch_tag(c->g, a, c->err_dev, c->wg, st); });
     if (e == hipSuccess)
-      e = timed(c, PIC_KERNEL_REBIN, st,
-                [&] { return launch_rebin(c->g, a, c->err_dev, c->wg, st); });
+      e = timed(c, PIC_KERNEL_REBIN, st, [&] {
+        return launch_rebin(c->g, a, c->err_dev, max_segments(c, nsp), false, st);
+      });
     if (e != hipSuccess) return hip_fail(c, e, "kernel launch");
   } else {
     if ((r = ensure_scratch(c, sp, nsp, false, st)) != PIC_OK) return r;
@@ -715,20 +744,33 @@ pic_status pic_step(pic_ctx *c, pic_species *sp, int32_t nsp, pic_fields *f, int
   hipStream_t st = (hipStream_t)stream;
   if (hipSetDevice(c->device) != hipSuccess) return fail(c, PIC_ERR_HIP, "hipSetDevice");
   if ((r = ensure_scratch(c, sp, nsp, false, st)) != PIC_OK) return r;
-  int k = 0;
-  if ((c->cfg.flags & PIC_FLAG_GRAPH) && !c->tm.on && nsteps >= 2) {
+  if (nsteps == 0) return finish(c, st);
+  // The first step updates the particles in place and records the sort as a
+  // permutation; middle steps gather through it into the other buffer set;
+  // the last step's sort copies the particles into their sorted places, so
+  // between calls the arrays are always sorted.
+  auto step = [&](bool gather, bool materialize) -> pic_status {
+    hipError_t e = enqueue_step(c, sp, nsp, f, st, gather, materialize);
+    if (e != hipSuccess) return hip_fail(c, e, "kernel launch");
+    for (int s = 0; s < nsp; s++) {
+      if (gather) swap_buffers(sp[s]);
+      if (materialize) swap_buffers(sp[s]);
+    }
+    return PIC_OK;
+  };
+  if ((r = step(false, nsteps == 1)) != PIC_OK) return r;
+  int middle = nsteps - 2;  // steps 1 .. nsteps-2
+  if ((c->cfg.flags & PIC_FLAG_GRAPH) && !c->tm.on && middle >= 2) {
     hipGraphExec_t x = nullptr;
     if ((r = ensure_graph(c, sp, nsp, f, &x)) != PIC_OK) return r;
-    for (; k + 2 <= nsteps; k += 2) {
+    for (; middle >= 2; middle -= 2) {
       hipError_t e = hipGraphLaunch(x, st);
       if (e != hipSuccess) return hip_fail(c, e, "hipGraphLaunch");
     }
   }
-  for (; k < nsteps; k++) {
-    hipError_t e = enqueue_step(c, sp, nsp, f, st);
-    if (e != hipSuccess) return hip_fail(c, e, "kernel launch");
-    for (int s = 0; s < nsp; s++) swap_buffers(sp[s]);
-  }
+  for (; middle > 0; middle--)
+    if ((r = step(true, false)) != PIC_OK) return r;
+  if (nsteps >= 2 && (r = step(true, true)) != PIC_OK) return r;
   return finish(c, st);
 }
 

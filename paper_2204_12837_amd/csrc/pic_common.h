@@ -47,6 +47,9 @@ struct SpDev {
   int64_t *rbase;   // [npatch * nc] start of (patch, code) inside its destination
   int64_t *in;      // [npatch] particles arriving in each destination patch
   double *x0[3];    // saved start-of-step positions (split path)
+  int32_t *seg2p;   // [max segments] patch of each ranking segment
+  int32_t *perm;    // [capacity] gather index: slot j of the next layout takes the
+                    // particle at perm[j] of the current one
   int32_t ubase;    // persistent mode: first work unit of this species
 };
 
@@ -57,6 +60,8 @@ struct Unit {
 
 struct SpArgs {
   int nsp;
+  int gather;  // fused kernel: read particle j from perm[j] of the other buffer set
+               // (the layout the previous sort computed) and write slot j
   SpDev s[kMaxSpecies];
 };
 
@@ -81,7 +86,12 @@ hipError_t launch_interp_push(const GridDev &g, const SpArgs &sa, const double *
 hipError_t launch_project(const GridDev &g, const SpArgs &sa, double *const j[3], int *err,
                           int wg, hipStream_t st);
 hipError_t launch_tag(const GridDev &g, const SpArgs &sa, int *err, int wg, hipStream_t st);
-hipError_t launch_rebin(const GridDev &g, const SpArgs &sa, int *err, int wg, hipStream_t st);
+// Counting sort from the tags: with to_perm the particles stay where they are
+// and perm[] records the new layout (applied by the next gathering fused
+// kernel); otherwise they are copied into the other buffer set.  maxseg
+// bounds the number of ranking segments of any species.
+hipError_t launch_rebin(const GridDev &g, const SpArgs &sa, int *err, int64_t maxseg, bool to_perm,
+                        hipStream_t st);
 
 // General sort (pic_sort.hip): wrap + key + stable sort of unsorted input.
 struct SortScratch {

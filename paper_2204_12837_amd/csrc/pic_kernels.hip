@@ -534,7 +534,7 @@ __device__ __forceinline__ bool in_patch(const TileGeom &t, const double xi[3]) 
 template <int DIM>
 __device__ __forceinline__ void ipp_segments(const GridDev &g, const SpDev &S, const TileGeom &t,
                                              const double *tEB, double *tJ, int P, int k0, int k1,
-                                             int &bad) {
+                                             bool gather, int &bad) {
   constexpr int NC = DIM == 2 ? 9 : 27;
   constexpr int CENTER = (NC - 1) / 2;
   const int64_t beg = S.off[P], end = S.off[P + 1];
@@ -550,19 +550,22 @@ __device__ __forceinline__ void ipp_segments(const GridDev &g, const SpDev &S, c
       const bool valid = i < se;
       int code = CENTER;
       if (valid) {
+        // particle slot i of the current layout: in place, or gathered from
+        // the other buffer set through the sort's permutation
+        const int64_t src = gather ? (int64_t)S.perm[i] : i;
         double x[3], xi[3], u[3], v[3], F[6];
 #pragma unroll
         for (int a = 0; a < DIM; a++) {
-          x[a] = S.x[a][i];
+          x[a] = S.x[a][src];
           xi[a] = x[a] * g.inv_d[a];
         }
+        u[0] = S.u[0][src];
+        u[1] = S.u[1][src];
+        u[2] = S.u[2][src];
+        const double w = S.w[src];
         if (!in_patch<DIM>(t, xi)) {
           bad |= kErrPos;
         } else {
-          u[0] = S.u[0][i];
-          u[1] = S.u[1][i];
-          u[2] = S.u[2][i];
-          const double w = S.w[i];
           const Shapes sh = shapes_at<DIM>(xi, t.org);
           interp6<DIM>(tEB, t.TE, t.Tx, t.Txy, sh, F);
           boris(alpha, F, u, v);
@@ -585,10 +588,18 @@ __device__ __forceinline__ void ipp_segments(const GridDev &g, const SpDev &S, c
             code = c;
           }
 #pragma unroll
-          for (int a = 0; a < DIM; a++) S.x[a][i] = x1[a];
-          S.u[0][i] = u[0];
-          S.u[1][i] = u[1];
-          S.u[2][i] = u[2];
+          for (int a = 0; a < DIM; a++) x[a] = x1[a];
+        }
+        double *const *xo = gather ? S.xa : S.x;
+        double *const *uo = gather ? S.ua : S.u;
+#pragma unroll
+        for (int a = 0; a < DIM; a++) xo[a][i] = x[a];
+        uo[0][i] = u[0];
+        uo[1][i] = u[1];
+        uo[2][i] = u[2];
+        if (gather) {
+          S.wa[i] = w;
+          S.ida[i] = S.id[src];
         }
       }
       const uint32_t rank = wave_rank(valid, code, lane, run);
@@ -611,7 +622,8 @@ __global__ void __launch_bounds__(256) k_ipp(GridDev g, SpArgs sa, Fields f, int
   zero_tile<DIM>(tJ, 3 * t.TJ);
   __syncthreads();
   int bad = 0;
-  ipp_segments<DIM>(g, S, t, tEB, tJ, P, 0, S.sstart[P + 1] - S.sstart[P], bad);
+  ipp_segments<DIM>(g, S, t, tEB, tJ, P, 0, S.sstart[P + 1] - S.sstart[P], sa.gather != 0,
+                    bad);
   if (bad) atomicOr(err, bad);
   __syncthreads();
   flush_j<DIM>(g, t, tJ, f.j);
@@ -654,7 +666,7 @@ __global__ void __launch_bounds__(256) k_ipp_persistent(GridDev g, SpArgs sa, Fi
         __syncthreads();
         curP = un.P;
       }
-      ipp_segments<DIM>(g, sa.s[s], t, tEB, tJ, un.P, un.k0, un.k1, bad);
+      ipp_segments<DIM>(g, sa.s[s], t, tEB, tJ, un.P, un.k0, un.k1, sa.gather != 0, bad);
       __syncthreads();  // this unit's deposits are done before any flush
     }
   }
@@ -881,43 +893,47 @@ __global__ void __launch_bounds__(1024) k_scan_offsets(GridDev g, SpArgs sa) {
   block_scan_1024(S.in, S.noff, g.npatch, part);
 }
 
-// Sort, step 3: move every particle of a source patch to its place:
-// destination start + start of (patch, code) inside it + the code's count in
-// the patch's earlier segments + the particle's rank in its segment.
-__global__ void __launch_bounds__(256) k_scatter(GridDev g, SpArgs sa, int dim, int *err) {
-  const int P = blockIdx.x;
+// Sort, step 3: the new slot of every particle of one ranking segment
+// (one workgroup of kSeg threads per segment): destination start + start of
+// (patch, code) inside it + the code's count in the patch's earlier segments
+// + the particle's rank in its segment.  TO_PERM records the slot's source in
+// perm[]; otherwise the particle is copied into the other buffer set.
+template <bool TO_PERM>
+__global__ void __launch_bounds__(kSeg) k_place(GridDev g, SpArgs sa, int *err) {
   const SpDev &S = sa.s[blockIdx.y];
+  const int seg = blockIdx.x;
+  if (seg >= S.sstart[g.npatch]) return;
   const int nc = g.nc;
+  const int P = S.seg2p[seg];
   __shared__ int64_t base[27];
   if (threadIdx.x < (unsigned)nc) {
     int pc[3];
     patch_coords(g, P, pc);
     const int D = dest_patch(g, pc, threadIdx.x);
-    base[threadIdx.x] = S.noff[D] + S.rbase[(int64_t)P * nc + threadIdx.x];
+    base[threadIdx.x] = S.noff[D] + S.rbase[(int64_t)P * nc + threadIdx.x] +
+                        S.pre[(int64_t)seg * nc + threadIdx.x];
   }
   __syncthreads();
-  const int64_t beg = S.off[P], end = S.off[P + 1];
-  const int sbase = S.sstart[P], nseg = S.sstart[P + 1] - sbase;
-  int bad = 0;
-  for (int64_t i = beg + threadIdx.x; i < end; i += blockDim.x) {
-    const uint32_t tg = S.tag[i];
-    const int c = (int)(tg >> 27);
-    const int k = (int)((i - beg) / kSeg);
-    int64_t dst = S.n;
-    if (c < nc && k < nseg)
-      dst = base[c] + S.pre[(int64_t)(sbase + k) * nc + c] + (int64_t)(tg & ((1u << 27) - 1));
-    if (dst >= S.n) {
-      bad |= kErrPos;
-      continue;
-    }
-    for (int a = 0; a < dim; a++) S.xa[a][dst] = S.x[a][i];
+  const int64_t i = S.off[P] + (int64_t)(seg - S.sstart[P]) * kSeg + threadIdx.x;
+  if (i >= S.off[P + 1]) return;
+  const uint32_t tg = S.tag[i];
+  const int c = (int)(tg >> 27);
+  int64_t dst = S.n;
+  if (c < nc) dst = base[c] + (int64_t)(tg & ((1u << 27) - 1));
+  if (dst >= S.n) {
+    atomicOr(err, kErrPos);
+    return;
+  }
+  if (TO_PERM) {
+    S.perm[dst] = (int32_t)i;
+  } else {
+    for (int a = 0; a < g.dim; a++) S.xa[a][dst] = S.x[a][i];
     S.ua[0][dst] = S.u[0][i];
     S.ua[1][dst] = S.u[1][i];
     S.ua[2][dst] = S.u[2][i];
     S.wa[dst] = S.w[i];
     S.ida[dst] = S.id[i];
   }
-  if (bad) atomicOr(err, bad);
 }
 
 // Sort, step 4: publish the new offsets.
@@ -941,6 +957,9 @@ __global__ void __launch_bounds__(1024) k_layout(GridDev g, SpArgs sa, Unit *uni
   __syncthreads();
   block_scan_1024(S.in, S.noff, n, part);
   for (int P = threadIdx.x; P <= n; P += blockDim.x) S.sstart[P] = (int32_t)S.noff[P];
+  __syncthreads();
+  for (int P = threadIdx.x; P < n; P += blockDim.x)
+    for (int k = S.sstart[P]; k < S.sstart[P + 1]; k++) S.seg2p[k] = P;
   if (!units) return;
   __syncthreads();
   for (int P = threadIdx.x; P < n; P += blockDim.x) S.in[P] = (S.in[P] + g.spc - 1) / g.spc;
@@ -1052,7 +1071,8 @@ hipError_t launch_tag(const GridDev &g, const SpArgs &sa, int *err, int wg, hipS
   return hipGetLastError();
 }
 
-hipError_t launch_rebin(const GridDev &g, const SpArgs &sa, int *err, int wg, hipStream_t st) {
+hipError_t launch_rebin(const GridDev &g, const SpArgs &sa, int *err, int64_t maxseg, bool to_perm,
+                        hipStream_t st) {
   const int pc = g.npatch * g.nc;
   hipLaunchKernelGGL(k_seg_prefix, dim3((pc + 255) / 256, sa.nsp), dim3(256), 0, st, g, sa);
   hipError_t e = hipGetLastError();
@@ -1061,7 +1081,11 @@ hipError_t launch_rebin(const GridDev &g, const SpArgs &sa, int *err, int wg, hi
   if ((e = hipGetLastError()) != hipSuccess) return e;
   hipLaunchKernelGGL(k_scan_offsets, dim3(sa.nsp), dim3(1024), 0, st, g, sa);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  hipLaunchKernelGGL(k_scatter, dim3(g.npatch, sa.nsp), dim3(wg), 0, st, g, sa, g.dim, err);
+  const dim3 grid((unsigned)maxseg, sa.nsp);
+  if (to_perm)
+    hipLaunchKernelGGL(k_place<true>, grid, dim3(kSeg), 0, st, g, sa, err);
+  else
+    hipLaunchKernelGGL(k_place<false>, grid, dim3(kSeg), 0, st, g, sa, err);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   hipLaunchKernelGGL(k_copy_offsets, dim3((g.npatch + 256) / 256, sa.nsp), dim3(256), 0, st, g, sa);
   return hipGetLastError();
