@@ -24,7 +24,8 @@ struct SpScratch {
   int64_t maxseg = 0;   // ranking segments the count arrays hold
   uint32_t *tag = nullptr;
   int32_t *sstart = nullptr, *cnt = nullptr, *pre = nullptr, *tot = nullptr;
-  int32_t *seg2p = nullptr, *perm = nullptr;
+  int32_t *snext = nullptr, *perm = nullptr;
+  int64_t *tmp = nullptr;
   int64_t *rbase = nullptr, *in = nullptr, *noff = nullptr;
   int64_t x0cap = 0;
   double *x0[3] = {nullptr, nullptr, nullptr};
@@ -188,14 +189,15 @@ pic_status ensure_scratch(pic_ctx *c, const pic_species *sp, int32_t nsp, bool x
       const int64_t maxseg = (int64_t)np + cap / kSeg + 1;
       if ((e = realloc_dev(S.tag, (size_t)cap)) != hipSuccess) return hip_fail(c, e, "hipMalloc");
       if ((e = realloc_dev(S.perm, (size_t)cap)) != hipSuccess) return hip_fail(c, e, "hipMalloc");
-      if ((e = realloc_dev(S.seg2p, (size_t)maxseg)) != hipSuccess)
-        return hip_fail(c, e, "hipMalloc");
+
       if ((e = realloc_dev(S.cnt, (size_t)maxseg * nc)) != hipSuccess)
         return hip_fail(c, e, "hipMalloc");
       if ((e = realloc_dev(S.pre, (size_t)maxseg * nc)) != hipSuccess)
         return hip_fail(c, e, "hipMalloc");
       if (!S.rbase) {
         if ((e = realloc_dev(S.sstart, np + 1)) != hipSuccess) return hip_fail(c, e, "hipMalloc");
+        if ((e = realloc_dev(S.snext, np + 1)) != hipSuccess) return hip_fail(c, e, "hipMalloc");
+        if ((e = realloc_dev(S.tmp, np + 1)) != hipSuccess) return hip_fail(c, e, "hipMalloc");
         if ((e = realloc_dev(S.tot, np * nc)) != hipSuccess) return hip_fail(c, e, "hipMalloc");
         if ((e = realloc_dev(S.rbase, np * nc)) != hipSuccess) return hip_fail(c, e, "hipMalloc");
         if ((e = realloc_dev(S.in, np)) != hipSuccess) return hip_fail(c, e, "hipMalloc");
@@ -270,7 +272,8 @@ SpArgs make_args(pic_ctx *c, const pic_species *sp, int32_t nsp) {
     d.rbase = c->sp[s].rbase;
     d.in = c->sp[s].in;
     d.ubase = (int32_t)c->sp[s].ubase;
-    d.seg2p = c->sp[s].seg2p;
+    d.snext = c->sp[s].snext;
+    d.tmp = c->sp[s].tmp;
     d.perm = c->sp[s].perm;
   }
   return a;
@@ -374,7 +377,7 @@ hipError_t enqueue_step(pic_ctx *c, const pic_species *sp, int32_t nsp, const pi
     }
   return timed(c, PIC_KERNEL_REBIN, st, [&] {
     hipError_t r2 = launch_rebin(c->g, r, c->err_dev, max_segments(c, nsp), !materialize, st);
-    if (r2 == hipSuccess) r2 = launch_layout(c->g, r, pers ? c->units : nullptr, c->qctl, st);
+    if (r2 == hipSuccess && pers) r2 = launch_layout(c->g, r, c->units, c->qctl, st);
     return r2;
   });
 }
@@ -595,7 +598,8 @@ void pic_free(pic_ctx *c) {
     SpScratch &S = c->sp[s];
     (void)hipFree(S.tag);
     (void)hipFree(S.cnt);
-    (void)hipFree(S.seg2p);
+    (void)hipFree(S.snext);
+    (void)hipFree(S.tmp);
     (void)hipFree(S.perm);
     (void)hipFree(S.pre);
     (void)hipFree(S.tot);

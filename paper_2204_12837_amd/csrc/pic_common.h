@@ -47,7 +47,8 @@ struct SpDev {
   int64_t *rbase;   // [npatch * nc] start of (patch, code) inside its destination
   int64_t *in;      // [npatch] particles arriving in each destination patch
   double *x0[3];    // saved start-of-step positions (split path)
-  int32_t *seg2p;   // [max segments] patch of each ranking segment
+  int32_t *snext;   // [npatch+1] segment starts of the layout after the sort
+  int64_t *tmp;     // [npatch+1] scan scratch
   int32_t *perm;    // [capacity] gather index: slot j of the next layout takes the
                     // particle at perm[j] of the current one
   int32_t ubase;    // persistent mode: first work unit of this species

@@ -241,6 +241,7 @@ __device__ __forceinline__ void boris(double alpha, const double F[6], double u[
 struct Win {
   double S0[4], DS[4], A[4];
   int it;
+  bool moved;  // m != 0: the fourth window node is live
 };
 
 __device__ __forceinline__ bool esk_win(const Sh &p0, double xi1, int i0, Win &w) {
@@ -263,6 +264,7 @@ __device__ __forceinline__ bool esk_win(const Sh &p0, double xi1, int i0, Win &w
     w.A[r] = __builtin_fma(0.5, w.DS[r], w.S0[r]);
   }
   w.it = p0.i + (lo ? 0 : 1);
+  w.moved = m != 0;
   return true;
 }
 
@@ -272,7 +274,8 @@ __device__ __forceinline__ bool esk_win(const Sh &p0, double xi1, int i0, Win &w
 //   3D  Wx = DSx (x) (Ay (x) Az + DSy (x) DSz / 12), y and z cyclic,
 // which equals Esirkepov's weights (expand A); J along a component's own axis
 // is the running sum of its W times -q w d/dt, so 3 of the 4 window nodes are
-// nonzero.  Adds per particle: 2D 12 + 12 + 16, 3D 3 x 48.
+// nonzero.  Adds per particle: 2D at most 12 + 12 + 16, 3D 3 x 48; 6 + 6 + 9
+// and 3 x 18 when the particle stays nearest to the same node.
 template <int DIM>
 __device__ __forceinline__ void deposit(const GridDev &g, double *tJ, int TJn, int TJx, int TJxy,
                                         double qw, const Win *w, double vz) {
@@ -295,14 +298,20 @@ __device__ __forceinline__ void deposit(const GridDev &g, double *tJ, int TJn, i
       Cx[k] *= cx;
       Cy[k] *= cy;
     }
+    // Without a node change along an axis (the common case) the window's
+    // last node carries zero weight and the running sum is exactly zero
+    // from the third node on; those adds are masked off per lane.
+    const bool mx = w[0].moved, my = w[1].moved;
 #pragma unroll
     for (int t = 0; t < 4; t++)
 #pragma unroll
-      for (int r = 0; r < 3; r++) lds_add(Jx + t * TJx + r, Cx[r] * w[1].A[t]);
+      for (int r = 0; r < 3; r++)
+        if ((t < 3 || my) && (r < 2 || mx)) lds_add(Jx + t * TJx + r, Cx[r] * w[1].A[t]);
 #pragma unroll
     for (int t = 0; t < 3; t++)
 #pragma unroll
-      for (int r = 0; r < 4; r++) lds_add(Jy + t * TJx + r, w[0].A[r] * Cy[t]);
+      for (int r = 0; r < 4; r++)
+        if ((r < 3 || mx) && (t < 2 || my)) lds_add(Jy + t * TJx + r, w[0].A[r] * Cy[t]);
     double az[4], dz[4];
 #pragma unroll
     for (int r = 0; r < 4; r++) {
@@ -313,7 +322,8 @@ __device__ __forceinline__ void deposit(const GridDev &g, double *tJ, int TJn, i
     for (int t = 0; t < 4; t++)
 #pragma unroll
       for (int r = 0; r < 4; r++)
-        lds_add(Jz + t * TJx + r, __builtin_fma(az[r], w[1].A[t], dz[r] * w[1].DS[t]));
+        if ((t < 3 || my) && (r < 3 || mx))
+          lds_add(Jz + t * TJx + r, __builtin_fma(az[r], w[1].A[t], dz[r] * w[1].DS[t]));
   } else {
     const int stride[3] = {1, TJx, TJxy};
     double *J0 = tJ + w[2].it * TJxy + w[1].it * TJx + w[0].it;
@@ -328,6 +338,7 @@ __device__ __forceinline__ void deposit(const GridDev &g, double *tJ, int TJn, i
 #pragma unroll
       for (int k = 0; k < 3; k++) C[k] *= ca;
       double *Ja = J0 + a * TJn;
+      const bool ma = w[a].moved, mb = w[b].moved, mc = w[c].moved;
 #pragma unroll
       for (int tb = 0; tb < 4; tb++) {
         const double db12 = w[b].DS[tb] * (1.0 / 12.0);
@@ -336,7 +347,9 @@ __device__ __forceinline__ void deposit(const GridDev &g, double *tJ, int TJn, i
           const double f = __builtin_fma(w[b].A[tb], w[c].A[tc], db12 * w[c].DS[tc]);
           double *line = Ja + tb * stride[b] + tc * stride[c];
 #pragma unroll
-          for (int ta = 0; ta < 3; ta++) lds_add(line + ta * stride[a], C[ta] * f);
+          for (int ta = 0; ta < 3; ta++)
+            if ((tb < 3 || mb) && (tc < 3 || mc) && (ta < 2 || ma))
+              lds_add(line + ta * stride[a], C[ta] * f);
         }
       }
     }
@@ -886,61 +899,95 @@ __device__ void block_scan_1024(const int64_t *in, int64_t *out, int n, int64_t 
   __syncthreads();
 }
 
-// Sort, step 2: new patch offsets (one workgroup per species).
+// Sort, step 2: new patch offsets and the new layout's ranking-segment
+// starts (one workgroup per species).
 __global__ void __launch_bounds__(1024) k_scan_offsets(GridDev g, SpArgs sa) {
   const SpDev &S = sa.s[blockIdx.x];
   __shared__ int64_t part[1024];
-  block_scan_1024(S.in, S.noff, g.npatch, part);
+  const int n = g.npatch;
+  block_scan_1024(S.in, S.noff, n, part);
+  for (int P = threadIdx.x; P < n; P += blockDim.x) S.in[P] = (S.in[P] + kSeg - 1) / kSeg;
+  __syncthreads();
+  block_scan_1024(S.in, S.tmp, n, part);
+  for (int P = threadIdx.x; P <= n; P += blockDim.x) S.snext[P] = (int32_t)S.tmp[P];
 }
 
-// Sort, step 3: the new slot of every particle of one ranking segment
-// (one workgroup of kSeg threads per segment): destination start + start of
-// (patch, code) inside it + the code's count in the patch's earlier segments
-// + the particle's rank in its segment.  TO_PERM records the slot's source in
-// perm[]; otherwise the particle is copied into the other buffer set.
+// Sort, step 3: the new slot of every particle: destination start + start
+// of (patch, code) inside it + the code's count in the patch's earlier
+// segments + the particle's rank in its segment.  A workgroup of kSeg threads
+// takes kPlaceSegs consecutive ranking segments (their patches found by
+// binary search in the segment starts).  TO_PERM records the slot's source
+// in perm[]; otherwise the particle is copied into the other buffer set.
+constexpr int kPlaceSegs = 4;
+
 template <bool TO_PERM>
 __global__ void __launch_bounds__(kSeg) k_place(GridDev g, SpArgs sa, int *err) {
   const SpDev &S = sa.s[blockIdx.y];
-  const int seg = blockIdx.x;
-  if (seg >= S.sstart[g.npatch]) return;
+  const int nseg = S.sstart[g.npatch];
+  const int seg0 = blockIdx.x * kPlaceSegs;
+  if (seg0 >= nseg) return;
   const int nc = g.nc;
-  const int P = S.seg2p[seg];
-  __shared__ int64_t base[27];
-  if (threadIdx.x < (unsigned)nc) {
-    int pc[3];
-    patch_coords(g, P, pc);
-    const int D = dest_patch(g, pc, threadIdx.x);
-    base[threadIdx.x] = S.noff[D] + S.rbase[(int64_t)P * nc + threadIdx.x] +
-                        S.pre[(int64_t)seg * nc + threadIdx.x];
+  __shared__ int s_patch[kPlaceSegs];
+  __shared__ int64_t base[kPlaceSegs][27];
+  if (threadIdx.x < kPlaceSegs) {
+    const int seg = seg0 + threadIdx.x;
+    int lo = 0, hi = g.npatch;  // largest P with sstart[P] <= seg
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (S.sstart[mid] <= seg)
+        lo = mid;
+      else
+        hi = mid;
+    }
+    s_patch[threadIdx.x] = seg < nseg ? lo : -1;
   }
   __syncthreads();
-  const int64_t i = S.off[P] + (int64_t)(seg - S.sstart[P]) * kSeg + threadIdx.x;
-  if (i >= S.off[P + 1]) return;
-  const uint32_t tg = S.tag[i];
-  const int c = (int)(tg >> 27);
-  int64_t dst = S.n;
-  if (c < nc) dst = base[c] + (int64_t)(tg & ((1u << 27) - 1));
-  if (dst >= S.n) {
-    atomicOr(err, kErrPos);
-    return;
+  if (threadIdx.x < (unsigned)(kPlaceSegs * nc)) {
+    const int k = threadIdx.x / nc, c = threadIdx.x - k * nc;
+    const int P = s_patch[k];
+    if (P >= 0) {
+      int pc[3];
+      patch_coords(g, P, pc);
+      const int D = dest_patch(g, pc, c);
+      base[k][c] = S.noff[D] + S.rbase[(int64_t)P * nc + c] + S.pre[(int64_t)(seg0 + k) * nc + c];
+    }
   }
-  if (TO_PERM) {
-    S.perm[dst] = (int32_t)i;
-  } else {
-    for (int a = 0; a < g.dim; a++) S.xa[a][dst] = S.x[a][i];
-    S.ua[0][dst] = S.u[0][i];
-    S.ua[1][dst] = S.u[1][i];
-    S.ua[2][dst] = S.u[2][i];
-    S.wa[dst] = S.w[i];
-    S.ida[dst] = S.id[i];
+  __syncthreads();
+  int bad = 0;
+  for (int k = 0; k < kPlaceSegs; k++) {
+    const int P = s_patch[k];
+    if (P < 0) break;
+    const int64_t i = S.off[P] + (int64_t)(seg0 + k - S.sstart[P]) * kSeg + threadIdx.x;
+    if (i >= S.off[P + 1]) continue;
+    const uint32_t tg = S.tag[i];
+    const int c = (int)(tg >> 27);
+    int64_t dst = S.n;
+    if (c < nc) dst = base[k][c] + (int64_t)(tg & ((1u << 27) - 1));
+    if (dst >= S.n) {
+      bad |= kErrPos;
+      continue;
+    }
+    if (TO_PERM) {
+      S.perm[dst] = (int32_t)i;
+    } else {
+      for (int a = 0; a < g.dim; a++) S.xa[a][dst] = S.x[a][i];
+      S.ua[0][dst] = S.u[0][i];
+      S.ua[1][dst] = S.u[1][i];
+      S.ua[2][dst] = S.u[2][i];
+      S.wa[dst] = S.w[i];
+      S.ida[dst] = S.id[i];
+    }
   }
+  if (bad) atomicOr(err, bad);
 }
 
-// Sort, step 4: publish the new offsets.
+// Sort, step 4: publish the new offsets and segment starts.
 __global__ void k_copy_offsets(GridDev g, SpArgs sa) {
   const SpDev &S = sa.s[blockIdx.y];
-  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k <= g.npatch; k += gridDim.x * blockDim.x)
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k <= g.npatch; k += gridDim.x * blockDim.x) {
     S.off[k] = S.noff[k];
+    S.sstart[k] = S.snext[k];
+  }
 }
 
 // Layout after any sort (one workgroup per species): segment starts from the
@@ -957,9 +1004,6 @@ __global__ void __launch_bounds__(1024) k_layout(GridDev g, SpArgs sa, Unit *uni
   __syncthreads();
   block_scan_1024(S.in, S.noff, n, part);
   for (int P = threadIdx.x; P <= n; P += blockDim.x) S.sstart[P] = (int32_t)S.noff[P];
-  __syncthreads();
-  for (int P = threadIdx.x; P < n; P += blockDim.x)
-    for (int k = S.sstart[P]; k < S.sstart[P + 1]; k++) S.seg2p[k] = P;
   if (!units) return;
   __syncthreads();
   for (int P = threadIdx.x; P < n; P += blockDim.x) S.in[P] = (S.in[P] + g.spc - 1) / g.spc;
@@ -1081,7 +1125,7 @@ hipError_t launch_rebin(const GridDev &g, const SpArgs &sa, int *err, int64_t ma
   if ((e = hipGetLastError()) != hipSuccess) return e;
   hipLaunchKernelGGL(k_scan_offsets, dim3(sa.nsp), dim3(1024), 0, st, g, sa);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  const dim3 grid((unsigned)maxseg, sa.nsp);
+  const dim3 grid((unsigned)((maxseg + kPlaceSegs - 1) / kPlaceSegs), sa.nsp);
   if (to_perm)
     hipLaunchKernelGGL(k_place<true>, grid, dim3(kSeg), 0, st, g, sa, err);
   else
