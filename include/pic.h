@@ -160,6 +160,34 @@ pic_status pic_project(pic_ctx *ctx, const pic_species *sp, int32_t nsp, pic_fie
 pic_status pic_step(pic_ctx *ctx, pic_species *sp, int32_t nsp, pic_fields *f, int32_t nsteps,
                     void *stream);
 
+/* Cotangents of one species' particle state, indexed by particle id. */
+typedef struct {
+  double *x[3]; /* d L / d position (x[2] unused in 2D) */
+  double *u[3]; /* d L / d momentum */
+  int64_t n;    /* length of every array; particle ids must lie in [0, n) */
+} pic_cotangent;
+
+/* Reverse-mode derivative of a segment of nsteps (1..8) 2D3V steps, for a
+ * loss L = sum Jbar . J_final that depends on the current deposited by the
+ * last step (fields static, J rebuilt every step, so only the final deposit
+ * enters L and particles do not interact).  The gradient of the Boris push,
+ * the quadratic-shape interpolation and Esirkepov's deposit, written by hand.
+ *   ckpt      particle state at the segment start (any order; ids index the
+ *             cotangents).  Not modified.
+ *   f         E and B (read); f->j unused.
+ *   with_deposit  1: the segment's last step is the final step, its deposit
+ *             contracted with jbar seeds the cotangents; 0: cot holds, on
+ *             entry, the cotangents of the state after the segment.
+ *   cot       on return: cotangents of the state at the segment start.
+ *   ebar,bbar d L / d E and d L / d B, accumulated (+=).
+ * The segment is recomputed from ckpt with the forward kernels' operation
+ * sequence (checkpointing: the caller keeps states every few steps and calls
+ * this for each segment from the last to the first).  2D only. */
+pic_status pic_adjoint(pic_ctx *ctx, const pic_species *ckpt, int32_t nsp, const pic_fields *f,
+                       const double *const jbar[3], int32_t nsteps, int32_t with_deposit,
+                       pic_cotangent *cot, double *const ebar[3], double *const bbar[3],
+                       void *stream);
+
 /* Kernel classes whose launches the context can time. */
 enum {
   PIC_KERNEL_ZERO = 0,        /* J <- 0 */
@@ -169,7 +197,8 @@ enum {
   PIC_KERNEL_PROJECT = 4,     /* split path: Projection */
   PIC_KERNEL_TAG = 5,         /* split path: pre-BC codes and ranks */
   PIC_KERNEL_SORT = 6,        /* general sort of unsorted input */
-  PIC_KERNEL_COUNT = 7
+  PIC_KERNEL_ADJOINT = 7,     /* adjoint segment */
+  PIC_KERNEL_COUNT = 8
 };
 
 /* Observability: when on, every later launch of a kernel class is bracketed

@@ -778,4 +778,56 @@ pic_status pic_step(pic_ctx *c, pic_species *sp, int32_t nsp, pic_fields *f, int
   return finish(c, st);
 }
 
+pic_status pic_adjoint(pic_ctx *c, const pic_species *ck, int32_t nsp, const pic_fields *f,
+                       const double *const jbar[3], int32_t nsteps, int32_t with_deposit,
+                       pic_cotangent *cot, double *const ebar[3], double *const bbar[3],
+                       void *stream) {
+  if (!c) return PIC_ERR_ARG;
+  if (c->poisoned) return fail(c, PIC_ERR_STATE, "context unusable after a device error");
+  if (c->cfg.dim != 2) return fail(c, PIC_ERR_ARG, "pic_adjoint supports 2D3V only");
+  if (!ck || nsp < 1 || nsp > kMaxSpecies || !cot)
+    return fail(c, PIC_ERR_ARG, "bad species or cotangent arguments");
+  if (nsteps < 1 || nsteps > kAdjMaxSteps)
+    return fail(c, PIC_ERR_ARG, "nsteps must be in [1, %d]", kAdjMaxSteps);
+  if (!fields_ok(c, f, true, false)) return fail(c, PIC_ERR_ARG, "null field pointer");
+  if (!ebar || !bbar) return fail(c, PIC_ERR_ARG, "null field cotangent");
+  for (int k = 0; k < 3; k++)
+    if (!ebar[k] || !bbar[k]) return fail(c, PIC_ERR_ARG, "null field cotangent");
+  if (with_deposit && (!jbar || !jbar[0] || !jbar[1] || !jbar[2]))
+    return fail(c, PIC_ERR_ARG, "with_deposit needs jbar");
+  AdjArgs a{};
+  a.nsp = nsp;
+  for (int s = 0; s < nsp; s++) {
+    const pic_species &p = ck[s];
+    const pic_cotangent &q = cot[s];
+    if (p.n < 0 || p.n > p.capacity) return fail(c, PIC_ERR_CAPACITY, "species %d: bad n", s);
+    if (!(p.m > 0) || !std::isfinite(p.q)) return fail(c, PIC_ERR_ARG, "species %d: q, m", s);
+    if (!p.x[0] || !p.x[1] || !p.u[0] || !p.u[1] || !p.u[2] || !p.w || !p.id)
+      return fail(c, PIC_ERR_ARG, "species %d: null particle array", s);
+    if (q.n < 0 || !q.x[0] || !q.x[1] || !q.u[0] || !q.u[1] || !q.u[2])
+      return fail(c, PIC_ERR_ARG, "species %d: null cotangent array", s);
+    AdjSp &d = a.s[s];
+    d.alpha = (p.q / p.m) * (0.5 * c->cfg.dt);
+    d.q = p.q;
+    d.n = p.n;
+    d.nid = q.n;
+    for (int k = 0; k < 3; k++) {
+      d.x[k] = k < 2 ? p.x[k] : nullptr;
+      d.u[k] = p.u[k];
+      d.xb[k] = k < 2 ? q.x[k] : nullptr;
+      d.ub[k] = q.u[k];
+    }
+    d.w = p.w;
+    d.id = p.id;
+  }
+  hipStream_t st = (hipStream_t)stream;
+  if (hipSetDevice(c->device) != hipSuccess) return fail(c, PIC_ERR_HIP, "hipSetDevice");
+  hipError_t e = timed(c, PIC_KERNEL_ADJOINT, st, [&] {
+    return launch_adjoint(c->g, a, f->e, f->b, with_deposit ? jbar : nullptr, ebar, bbar, nsteps,
+                          with_deposit ? 1 : 0, c->err_dev, st);
+  });
+  if (e != hipSuccess) return hip_fail(c, e, "kernel launch");
+  return finish(c, st);
+}
+
 }  // extern "C"

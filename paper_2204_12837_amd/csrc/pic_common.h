@@ -54,6 +54,28 @@ struct SpDev {
   int32_t ubase;    // persistent mode: first work unit of this species
 };
 
+// Adjoint (reverse-mode derivative) of a segment of 2D steps.
+constexpr int kAdjMaxSteps = 8;  // steps per recomputed segment
+
+struct AdjSp {
+  double alpha, q;
+  int64_t n;        // particles in the checkpoint arrays
+  int64_t nid;      // length of the cotangent arrays (ids lie in [0, nid))
+  const double *x[3], *u[3], *w;
+  const int64_t *id;
+  double *xb[3], *ub[3];  // cotangents of the state, indexed by id
+};
+
+struct AdjArgs {
+  int nsp;
+  AdjSp s[kMaxSpecies];
+};
+
+hipError_t launch_adjoint(const GridDev &g, const AdjArgs &aa, const double *const e[3],
+                          const double *const b[3], const double *const jb[3],
+                          double *const eb[3], double *const bb[3], int nsteps, int with_dep,
+                          int *err, hipStream_t st);
+
 // A persistent-mode work unit: ranking segments [k0, k1) of patch P of species s.
 struct Unit {
   int32_t s, P, k0, k1;

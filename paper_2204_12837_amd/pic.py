@@ -49,10 +49,15 @@ class FieldsC(C.Structure):
     _fields_ = [("e", C.c_void_p * 3), ("b", C.c_void_p * 3), ("j", C.c_void_p * 3)]
 
 
+class CotangentC(C.Structure):
+    _fields_ = [("x", C.c_void_p * 3), ("u", C.c_void_p * 3), ("n", C.c_int64)]
+
+
 ENTRY_POINTS = ("pic_validate_config", "pic_num_patches", "pic_init", "pic_free", "pic_bin",
                 "pic_interp_push", "pic_project", "pic_step", "pic_check", "pic_last_error",
-                "pic_timing_enable", "pic_timing_read")
-KERNELS = {"zero": 0, "ipp": 1, "rebin": 2, "interp_push": 3, "project": 4, "tag": 5, "sort": 6}
+                "pic_timing_enable", "pic_timing_read", "pic_adjoint")
+KERNELS = {"zero": 0, "ipp": 1, "rebin": 2, "interp_push": 3, "project": 4, "tag": 5, "sort": 6,
+           "adjoint": 7}
 
 _lib_handle = None
 
@@ -91,6 +96,10 @@ def lib():
         L.pic_timing_read.argtypes = [C.c_void_p, C.c_int32, C.POINTER(C.c_double),
                                       C.POINTER(C.c_int64)]
         L.pic_timing_read.restype = C.c_int
+        L.pic_adjoint.argtypes = [C.c_void_p, C.POINTER(SpeciesC), C.c_int32, C.POINTER(FieldsC),
+                                  C.c_void_p * 3, C.c_int32, C.c_int32, C.POINTER(CotangentC),
+                                  C.c_void_p * 3, C.c_void_p * 3, C.c_void_p]
+        L.pic_adjoint.restype = C.c_int
         L.pic_last_error.argtypes = [C.c_void_p]
         L.pic_last_error.restype = C.c_char_p
         _lib_handle = L
@@ -187,6 +196,23 @@ class Species:
         return self.id[:self.n]
 
 
+class Cotangent:
+    """Cotangents of one species' positions and momenta, indexed by particle id."""
+
+    def __init__(self, n_ids: int, dim: int = 2, device="cuda"):
+        self.x = torch.zeros((dim, max(n_ids, 1)), dtype=torch.float64, device=device)
+        self.u = torch.zeros((3, max(n_ids, 1)), dtype=torch.float64, device=device)
+        self.n = n_ids
+
+    def cstruct(self) -> CotangentC:
+        c = CotangentC()
+        for a in range(3):
+            c.x[a] = self.x[a].data_ptr() if a < self.x.shape[0] else None
+            c.u[a] = self.u[a].data_ptr()
+        c.n = self.n
+        return c
+
+
 def fields_struct(E=None, B=None, J=None) -> FieldsC:
     f = FieldsC()
     for c in range(3):
@@ -254,6 +280,20 @@ class Context:
 
     def check(self):
         self._raise(lib().pic_check(self._h, _stream()))
+
+    def adjoint(self, ckpt: Sequence["Species"], E, B, Jbar, nsteps: int, with_deposit: bool,
+                cot: Sequence["Cotangent"], Ebar, Bbar):
+        """pic_adjoint on one segment (see include/pic.h)."""
+        arr = (SpeciesC * len(ckpt))(*[s.cstruct() for s in ckpt])
+        f = fields_struct(E, B, None)
+        jb = (C.c_void_p * 3)(*[Jbar[c].data_ptr() for c in range(3)]) if Jbar is not None \
+            else (C.c_void_p * 3)()
+        cs = (CotangentC * len(cot))(*[c.cstruct() for c in cot])
+        eb = (C.c_void_p * 3)(*[Ebar[c].data_ptr() for c in range(3)])
+        bb = (C.c_void_p * 3)(*[Bbar[c].data_ptr() for c in range(3)])
+        rc = lib().pic_adjoint(self._h, arr, len(ckpt), C.byref(f), jb, int(nsteps),
+                               1 if with_deposit else 0, cs, eb, bb, _stream())
+        self._raise(rc)
 
     def timing(self, on: bool = True):
         self._raise(lib().pic_timing_enable(self._h, 1 if on else 0))

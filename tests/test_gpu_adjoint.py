@@ -1,0 +1,143 @@
+"""The HIP adjoint (reverse mode, hand-written) against the oracle's
+forward-mode derivative and extended-precision finite differences.
+
+L = sum W . J_final; gradients with respect to the initial momenta u0 and the
+static fields E, B, through torch.autograd (PicSteps) with step
+checkpointing."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_2204_12837_amd import adjoint as ADJ
+from paper_2204_12837_amd import inputs as I
+
+from _parity import say
+
+pytestmark = pytest.mark.gpu
+
+
+def _setup(wl, inp):
+    s = inp.species[0]
+    L = np.array([wl.n[0] * wl.d[0], wl.n[1] * wl.d[1]])
+    x = np.mod(s.x, L[:, None])
+    x = np.where(x >= L[:, None], 0.0, x)
+    return s, x
+
+
+def _gpu_grads(wl, inp, x, every):
+    s = inp.species[0]
+    dev = "cuda:0"
+    run = ADJ.StepRun(wl, torch.from_numpy(x).to(dev), torch.from_numpy(s.wt).to(dev),
+                      torch.from_numpy(s.id).to(dev), s.q, s.m, wl.steps, every)
+    u0 = torch.from_numpy(s.u).to(dev).requires_grad_(True)
+    E = torch.from_numpy(inp.E).to(dev).requires_grad_(True)
+    B = torch.from_numpy(inp.B).to(dev).requires_grad_(True)
+    W = torch.from_numpy(inp.W).to(dev)
+    J = ADJ.PicSteps.apply(u0, E, B, run)
+    L = (W * J).sum()
+    L.backward()
+    torch.cuda.synchronize()
+    run.ctx.check()
+    return (J.detach().cpu().numpy(), u0.grad.cpu().numpy(), E.grad.cpu().numpy(),
+            B.grad.cpu().numpy())
+
+
+def _dot(g, v):
+    return math.fsum((g * v).ravel()), math.fsum(np.abs(g * v).ravel())
+
+
+@pytest.mark.parametrize("every", [3, 5])
+def test_adjoint_matches_oracle_jvp(every):
+    wl = I.custom(2, (32, 32), (8, 8), ppc=4, seed=401, sigma=0.05, bz0=1.0, steps=7)
+    inp = I.generate(wl, with_W=True)
+    s, x = _setup(wl, inp)
+    say(f"case adjoint small every={every}")
+    J, gu, gE, gB = _gpu_grads(wl, inp, x, every)
+    rng = np.random.default_rng(402)
+    for kind in ("u", "E", "B", "all"):
+        du = rng.normal(size=s.u.shape) if kind in ("u", "all") else None
+        dE = rng.normal(size=inp.E.shape) if kind in ("E", "all") else None
+        dB = rng.normal(size=inp.B.shape) if kind in ("B", "all") else None
+        Jo, dJ = O.jvp(wl, s.q, s.m, x, s.u, s.wt, inp.E, inp.B, du, dE, dB)
+        ref = math.fsum((inp.W * dJ).ravel())
+        got, scale = 0.0, 0.0
+        for g, v in ((gu, du), (gE, dE), (gB, dB)):
+            if v is not None:
+                a, b = _dot(g, v)
+                got += a
+                scale += b
+        assert abs(got - ref) <= 1e-11 * scale, (kind, got, ref, scale)
+    # the forward J is the oracle's
+    assert np.max(np.abs(J - Jo)) <= 1e-12 * np.abs(Jo).max()
+
+
+def test_adjoint_matches_extended_precision_fd():
+    """The criterion of the adjoint: central differences (h = 1e-6) of the
+    loss computed in x87 extended precision, relative error <= 1e-7."""
+    wl = I.custom(2, (64, 64), (16, 16), ppc=8, seed=403, sigma=0.01, bz0=1.0, steps=20)
+    inp = I.generate(wl, with_W=True)
+    s, x = _setup(wl, inp)
+    say("case adjoint fd 64x64 20 steps every 5")
+    J, gu, gE, gB = _gpu_grads(wl, inp, x, 5)
+    rng = np.random.default_rng(404)
+    for kind in ("u", "EB"):
+        du = rng.normal(size=s.u.shape) if kind == "u" else None
+        dE = rng.normal(size=inp.E.shape) * 0.01 if kind == "EB" else None
+        dB = rng.normal(size=inp.B.shape) * 0.01 if kind == "EB" else None
+        fd, _ = O.fd(wl, s.q, s.m, x, s.u, s.wt, inp.E, inp.B, inp.W, du, dE, dB, h=1e-6)
+        got = 0.0
+        for g, v in ((gu, du), (gE, dE), (gB, dB)):
+            if v is not None:
+                got += _dot(g, v)[0]
+        assert abs(got - fd) <= 1e-7 * abs(fd), (kind, got, fd)
+
+
+def test_adjoint_full_size_sampled():
+    """The adjoint workload at full size (256x256 cells, 16 ppc = 1,048,576
+    particles, 20 steps, checkpoint every 5): per-particle momentum
+    gradients of sampled particles, each from the oracle's derivative of that
+    particle alone (particles do not interact), and one direction over all
+    momenta and fields from the oracle's forward-mode derivative."""
+    wl = I.workload("adjoint256")
+    inp = I.generate(wl)
+    s, x = _setup(wl, inp)
+    say("case adjoint256 full size")
+    J, gu, gE, gB = _gpu_grads(wl, inp, x, wl.ckpt)
+    rng = np.random.default_rng(405)
+    scale = np.abs(gu).max()
+    for p in rng.choice(s.u.shape[1], 12, replace=False):
+        xs = np.ascontiguousarray(x[:, p:p + 1])
+        us = np.ascontiguousarray(s.u[:, p:p + 1])
+        ws = np.ascontiguousarray(s.wt[p:p + 1])
+        for c in range(3):
+            du = np.zeros((3, 1))
+            du[c, 0] = 1.0
+            _, dJ = O.jvp(wl, s.q, s.m, xs, us, ws, inp.E, inp.B, du, None, None)
+            ref = math.fsum((inp.W * dJ).ravel())
+            assert abs(gu[c, p] - ref) <= 1e-10 * scale + 1e-11 * abs(ref), (p, c, gu[c, p], ref)
+    du = rng.normal(size=s.u.shape)
+    dE = rng.normal(size=inp.E.shape) * 0.01
+    dB = rng.normal(size=inp.B.shape) * 0.01
+    _, dJ = O.jvp(wl, s.q, s.m, x, s.u, s.wt, inp.E, inp.B, du, dE, dB)
+    ref = math.fsum((inp.W * dJ).ravel())
+    got, sc = 0.0, 0.0
+    for g, v in ((gu, du), (gE, dE), (gB, dB)):
+        a, b = _dot(g, v)
+        got += a
+        sc += b
+    assert abs(got - ref) <= 1e-11 * sc, (got, ref, sc)
+
+
+def test_checkpoint_interval_does_not_change_gradients():
+    wl = I.custom(2, (32, 32), (8, 8), ppc=4, seed=406, sigma=0.05, bz0=1.0, steps=8)
+    inp = I.generate(wl, with_W=True)
+    s, x = _setup(wl, inp)
+    say("case adjoint checkpoint intervals")
+    ref = _gpu_grads(wl, inp, x, 8)
+    for every in (1, 2, 3):
+        got = _gpu_grads(wl, inp, x, every)
+        for a, b in zip(ref[1:], got[1:]):
+            assert np.max(np.abs(a - b)) <= 1e-12 * np.abs(a).max()
