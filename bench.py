@@ -125,6 +125,66 @@ def tune_persistent(wl, inp):
     return res
 
 
+def run_expansion3d(steps: int, warmup: int):
+    """The 3D two-species workload: per-patch launch and the persistent
+    launch with an autotuned chunk."""
+    from paper_2204_12837_amd import inputs as I
+
+    wl = I.workload("expansion3d")
+    inp = I.generate(wl)
+    n = sum(s.x.shape[1] for s in inp.species)
+    n_pp, s_pp, t_pp = run_gpu(wl, steps, warmup, inp=inp)
+    tuned = tune_persistent(wl, inp)
+    n_pe, s_pe, t_pe = run_gpu(wl, steps, warmup, mode=1, chunk=tuned["chunk"], wg=tuned["wg"],
+                               inp=inp)
+    ipp_pp = t_pp["ipp"][0] / t_pp["ipp"][1]
+    ipp_pe = t_pe["ipp"][0] / t_pe["ipp"][1]
+    abytes = algorithmic_bytes(wl, n)
+    return {"workload": "expansion3d", "particles": n, "species": 2, "steps": steps,
+            "per_patch": {"ns_per_particle_step": s_pp / (n * steps) * 1e9, "ipp_ms": ipp_pp},
+            "persistent": {"ns_per_particle_step": s_pe / (n * steps) * 1e9, "ipp_ms": ipp_pe,
+                           "chunk": tuned["chunk"], "wg": tuned["wg"]},
+            "ipp_hbm_frac_best": abytes / (min(ipp_pp, ipp_pe) * 1e-3) / 1e9 / HBM_PEAK_GBS}
+
+
+def run_adjoint(every: int = 5):
+    """Forward (with checkpoints) and backward of the adjoint workload:
+    L = sum W.J after 20 steps of 256^2 cells x 16 ppc, gradients with
+    respect to the initial momenta and the fields."""
+    import torch
+
+    from paper_2204_12837_amd import adjoint as ADJ
+    from paper_2204_12837_amd import inputs as I
+
+    wl = I.workload("adjoint256")
+    inp = I.generate(wl)
+    s = inp.species[0]
+    dev = "cuda:0"
+    times = []
+    for rep in range(3):
+        run = ADJ.StepRun(wl, torch.from_numpy(s.x).to(dev), torch.from_numpy(s.wt).to(dev),
+                          torch.from_numpy(s.id).to(dev), s.q, s.m, wl.steps, every)
+        u0 = torch.from_numpy(s.u).to(dev).requires_grad_(True)
+        E = torch.from_numpy(inp.E).to(dev).requires_grad_(True)
+        B = torch.from_numpy(inp.B).to(dev).requires_grad_(True)
+        W = torch.from_numpy(inp.W).to(dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        J = ADJ.PicSteps.apply(u0, E, B, run)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        (W * J).sum().backward()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        run.ctx.check()
+        times.append((t1 - t0, t2 - t1))
+    fw, bw = min(times, key=lambda t: t[0] + t[1])
+    n = s.x.shape[1]
+    return {"workload": "adjoint256", "particles": n, "steps": wl.steps, "checkpoint_every": every,
+            "forward_ms": fw * 1e3, "backward_ms": bw * 1e3,
+            "gradient_particle_steps_per_s": n * wl.steps / (fw + bw)}
+
+
 def cpu_baseline(sample_steps: int):
     """The CPU oracle (serial, one core) on a strip of the uniform workload:
     1024 x 64 cells with the same density, momenta and fields, periodic."""
@@ -175,6 +235,8 @@ def main(argv=None) -> int:
     ap.add_argument("--workload", default="uniform1024")
     ap.add_argument("--no-imbalanced", action="store_true", help="skip the imbalanced workload")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-3d", action="store_true", help="skip the 3D two-species workload")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint workload")
     ap.add_argument("--cpu-steps", type=int, default=8)
     ap.add_argument("--copy-calibration", type=float, default=0.0, metavar="GIB",
                     help="only run a plain device copy of this many GiB (5 times), to scale "
@@ -249,6 +311,10 @@ def main(argv=None) -> int:
             "step_ratio_persistent_vs_uniform": (sp_ / ni) / (secs / n),
             "step_speedup_persistent_vs_per_patch": si / sp_,
         }
+    if not args.no_3d:
+        out["expansion3d"] = run_expansion3d(min(args.steps, 50), args.warmup)
+    if not args.no_adjoint:
+        out["adjoint"] = run_adjoint()
     out["cpu_baseline"] = None if args.no_cpu_baseline else cpu_baseline(args.cpu_steps)
     print(json.dumps(out), flush=True)
     return 0

@@ -84,7 +84,8 @@ typedef struct {
                           (patch, species, chunk) units from a device queue */
   int32_t chunk;       /* persistent mode: particles per work unit, a multiple
                           of 256 (0 = auto: 2048) */
-  int32_t wg_size;     /* threads per workgroup: 64, 128, 192 or 256 (0 = auto) */
+  int32_t wg_size;     /* threads per workgroup, a multiple of 64 up to 256 in
+                          2D and 512 in 3D (0 = auto: 256 in 2D, 512 in 3D) */
   uint32_t flags;      /* PIC_FLAG_* */
 } pic_config;
 

@@ -22,6 +22,7 @@ from . import pic
 
 CHUNKS = (512, 1024, 2048, 4096, 8192)
 WGS = (128, 256)
+WGS_3D = (256, 512)
 
 
 def cache_path() -> str:
@@ -75,6 +76,8 @@ def tune(wl, species: Sequence[pic.Species], E, B, J, steps: int = 3,
         out["cached"] = True
         return out
     trials: List[Tuple[float, int, int]] = []
+    if wl.dim == 3 and tuple(wgs) == WGS:
+        wgs = WGS_3D
     for wg in wgs:
         for chunk in chunks:
             ctx = pic.Context(wl, mode=pic.MODE_PERSISTENT, chunk=chunk, wg_size=wg)

@@ -533,8 +533,9 @@ pic_status pic_validate_config(const pic_config *c, char *msg, size_t len) {
     set_msg(msg, len, "chunk must be 0 (auto) or a positive multiple of %d", kSeg);
     return PIC_ERR_ARG;
   }
-  if (c->wg_size != 0 && (c->wg_size < 64 || c->wg_size > 256 || c->wg_size % 64)) {
-    set_msg(msg, len, "wg_size must be 0 or a multiple of 64 in [64, 256]");
+  const int wg_max = c->dim == 2 ? 256 : 512;
+  if (c->wg_size != 0 && (c->wg_size < 64 || c->wg_size > wg_max || c->wg_size % 64)) {
+    set_msg(msg, len, "wg_size must be 0 or a multiple of 64 in [64, %d]", wg_max);
     return PIC_ERR_ARG;
   }
   if (c->flags & ~(uint32_t)(PIC_FLAG_CHECK | PIC_FLAG_GRAPH)) {
@@ -573,7 +574,7 @@ pic_status pic_init(const pic_config *cfg, int32_t device, pic_ctx **out) {
   }
   c->g = make_grid(&c->cfg);
   c->device = device;
-  c->wg = cfg->wg_size ? cfg->wg_size : 256;
+  c->wg = cfg->wg_size ? cfg->wg_size : (c->cfg.dim == 2 ? 256 : 512);
   const int chunk = cfg->chunk ? cfg->chunk : 2048;
   c->g.spc = std::max(1, chunk / kSeg);
   if (hipMalloc(&c->err_dev, sizeof(int)) != hipSuccess ||

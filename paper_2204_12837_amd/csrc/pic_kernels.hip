@@ -36,6 +36,15 @@ namespace pic {
 
 namespace {
 
+// Largest workgroup per dimension: 3D tiles take most of a CU's LDS, so a
+// 3D workgroup runs alone on its CU and needs more waves to hide latency.
+template <int DIM>
+constexpr int kMaxWg = DIM == 2 ? 256 : 512;
+// Waves per SIMD the register allocation must allow: four in 2D (a 2D
+// workgroup's tiles take ~28 KB, so LDS admits several per CU), two in 3D.
+template <int DIM>
+constexpr int kMinWaves = DIM == 2 ? 4 : 2;
+
 __device__ __forceinline__ int wrap_near(int k, int n) {
   // k is within one period of [0, n)
   return k < 0 ? k + n : (k >= n ? k - n : k);
@@ -624,7 +633,7 @@ __device__ __forceinline__ void ipp_segments(const GridDev &g, const SpDev &S, c
 
 // Per-patch launch: one workgroup per (patch, species), all its segments.
 template <int DIM>
-__global__ void __launch_bounds__(256) k_ipp(GridDev g, SpArgs sa, Fields f, int *err) {
+__global__ void __launch_bounds__(kMaxWg<DIM>, kMinWaves<DIM>) k_ipp(GridDev g, SpArgs sa, Fields f, int *err) {
   extern __shared__ __align__(16) double lds[];
   const int P = blockIdx.x;
   const SpDev &S = sa.s[blockIdx.y];
@@ -649,7 +658,7 @@ __global__ void __launch_bounds__(256) k_ipp(GridDev g, SpArgs sa, Fields f, int
 // between a workgroup's consecutive units (E/B and J do not depend on the
 // species).
 template <int DIM>
-__global__ void __launch_bounds__(256) k_ipp_persistent(GridDev g, SpArgs sa, Fields f, int *err,
+__global__ void __launch_bounds__(kMaxWg<DIM>, kMinWaves<DIM>) k_ipp_persistent(GridDev g, SpArgs sa, Fields f, int *err,
                                                         const Unit *units, int *qctl) {
   extern __shared__ __align__(16) double lds[];
   __shared__ int s_unit;
@@ -689,7 +698,7 @@ __global__ void __launch_bounds__(256) k_ipp_persistent(GridDev g, SpArgs sa, Fi
 
 // Split path, first half: Interpolation + Push; saves the start positions.
 template <int DIM>
-__global__ void __launch_bounds__(256) k_interp_push(GridDev g, SpArgs sa, Fields f, int *err) {
+__global__ void __launch_bounds__(kMaxWg<DIM>) k_interp_push(GridDev g, SpArgs sa, Fields f, int *err) {
   extern __shared__ __align__(16) double lds[];
   const int P = blockIdx.x;
   const SpDev &S = sa.s[blockIdx.y];
@@ -727,7 +736,7 @@ __global__ void __launch_bounds__(256) k_interp_push(GridDev g, SpArgs sa, Field
 
 // Split path, second half: Projection from the saved start positions.
 template <int DIM>
-__global__ void __launch_bounds__(256) k_project(GridDev g, SpArgs sa, Fields f, int *err) {
+__global__ void __launch_bounds__(kMaxWg<DIM>) k_project(GridDev g, SpArgs sa, Fields f, int *err) {
   extern __shared__ __align__(16) double lds[];
   const int P = blockIdx.x;
   const SpDev &S = sa.s[blockIdx.y];
@@ -770,7 +779,7 @@ __global__ void __launch_bounds__(256) k_project(GridDev g, SpArgs sa, Fields f,
 // segment, as in the fused kernel) of particles that moved at most one cell
 // since the last sort.
 template <int DIM>
-__global__ void __launch_bounds__(256) k_tag(GridDev g, SpArgs sa, int *err) {
+__global__ void __launch_bounds__(kMaxWg<DIM>) k_tag(GridDev g, SpArgs sa, int *err) {
   constexpr int NC = DIM == 2 ? 9 : 27;
   constexpr int CENTER = (NC - 1) / 2;
   const int P = blockIdx.x;
