@@ -483,24 +483,63 @@ __device__ __forceinline__ TileGeom tile_geom(const GridDev &g, int P) {
   return t;
 }
 
+// Walks a (component, z, y, x) tile in flat order with stride blockDim
+// without per-element divisions: the start index and the stride are split
+// into coordinates once, then advanced with at most one carry per axis.
+struct TileWalk {
+  int c, k, j, i;      // current coordinates
+  int dc, dk, dj, di;  // the stride in coordinates
+  int nx, ny, nz;
+
+  __device__ TileWalk(int start, int stride, int nx_, int ny_, int nz_)
+      : nx(nx_), ny(ny_), nz(nz_) {
+    split(start, c, k, j, i);
+    split(stride, dc, dk, dj, di);
+  }
+  __device__ void split(int v, int &c_, int &k_, int &j_, int &i_) const {
+    const int plane = nx * ny, vol = plane * nz;
+    c_ = v / vol;
+    v -= c_ * vol;
+    k_ = v / plane;
+    v -= k_ * plane;
+    j_ = v / nx;
+    i_ = v - j_ * nx;
+  }
+  __device__ void next() {
+    i += di;
+    if (i >= nx) {
+      i -= nx;
+      j++;
+    }
+    j += dj;
+    if (j >= ny) {
+      j -= ny;
+      k++;
+    }
+    k += dk;
+    if (k >= nz) {
+      k -= nz;
+      c++;
+    }
+    c += dc;
+  }
+};
+
 template <int DIM>
 __device__ void stage_eb(const GridDev &g, const TileGeom &t, const Fields &f, double *tile) {
-  for (int idx = threadIdx.x; idx < 6 * t.TE; idx += blockDim.x) {
-    const int c = idx / t.TE;
-    const int r = idx - c * t.TE;
-    const int kk = r / t.Txy;
-    const int r2 = r - kk * t.Txy;
-    const int jj = r2 / t.Tx;
-    const int ii = r2 - jj * t.Tx;
-    const int gx = wrap_near(t.org[0] + ii, g.n[0]);
-    const int gy = wrap_near(t.org[1] + jj, g.n[1]);
-    const int gz = DIM == 3 ? wrap_near(t.org[2] + kk, g.n[2]) : 0;
-    const double *F = c < 3 ? f.e[c] : f.b[c - 3];
+  const int Ty = t.Txy / t.Tx, Tz = t.TE / t.Txy;
+  TileWalk w(threadIdx.x, blockDim.x, t.Tx, Ty, Tz);
+  for (int idx = threadIdx.x; idx < 6 * t.TE; idx += blockDim.x, w.next()) {
+    const int r = idx - w.c * t.TE;
+    const int gx = wrap_near(t.org[0] + w.i, g.n[0]);
+    const int gy = wrap_near(t.org[1] + w.j, g.n[1]);
+    const int gz = DIM == 3 ? wrap_near(t.org[2] + w.k, g.n[2]) : 0;
+    const double *F = w.c < 3 ? f.e[w.c] : f.b[w.c - 3];
     const double v = F[((int64_t)gz * g.n[1] + gy) * g.n[0] + gx];
     if constexpr (DIM == 2) {
       // Ex -> pair 0 .x, By -> pair 0 .y, Ey -> pair 1 .x, Bx -> pair 1 .y
       int at;
-      switch (c) {
+      switch (w.c) {
         case 0: at = 2 * r; break;
         case 4: at = 2 * r + 1; break;
         case 1: at = 2 * t.TE + 2 * r; break;
@@ -522,19 +561,15 @@ __device__ void zero_tile(double *tJ, int n) {
 
 template <int DIM>
 __device__ void flush_j(const GridDev &g, const TileGeom &t, const double *tJ, double *const j[3]) {
-  for (int idx = threadIdx.x; idx < 3 * t.TJ; idx += blockDim.x) {
+  const int Jy = t.Jxy / t.Jx, Jz = t.TJ / t.Jxy;
+  TileWalk w(threadIdx.x, blockDim.x, t.Jx, Jy, Jz);
+  for (int idx = threadIdx.x; idx < 3 * t.TJ; idx += blockDim.x, w.next()) {
     const double v = tJ[idx];
     if (v == 0.0) continue;
-    const int c = idx / t.TJ;
-    const int r = idx - c * t.TJ;
-    const int kk = r / t.Jxy;
-    const int r2 = r - kk * t.Jxy;
-    const int jj = r2 / t.Jx;
-    const int ii = r2 - jj * t.Jx;
-    const int gx = wrap_near(t.org2[0] + ii, g.n[0]);
-    const int gy = wrap_near(t.org2[1] + jj, g.n[1]);
-    const int gz = DIM == 3 ? wrap_near(t.org2[2] + kk, g.n[2]) : 0;
-    glb_add(j[c] + ((int64_t)gz * g.n[1] + gy) * g.n[0] + gx, v);
+    const int gx = wrap_near(t.org2[0] + w.i, g.n[0]);
+    const int gy = wrap_near(t.org2[1] + w.j, g.n[1]);
+    const int gz = DIM == 3 ? wrap_near(t.org2[2] + w.k, g.n[2]) : 0;
+    glb_add(j[w.c] + ((int64_t)gz * g.n[1] + gy) * g.n[0] + gx, v);
   }
 }
 
@@ -1000,9 +1035,12 @@ __global__ void k_copy_offsets(GridDev g, SpArgs sa) {
 }
 
 // Layout after any sort (one workgroup per species): segment starts from the
-// patch offsets; in persistent mode also each patch's work units
-// (ceil(segments / spc) of them) in patch order, their number in qctl[2s+1]
-// and a zero ticket in qctl[2s].  Uses the species' in/noff arrays as scratch.
+// patch offsets; in persistent mode also the work units: every patch's full
+// units (spc segments each) first, in patch order, then the patches'
+// remainder units (fewer segments), so the queue ends with the small units
+// and the last workgroups to finish wait less.  Their number goes to
+// qctl[2s+1] and a zero ticket to qctl[2s].  Uses the species' in, noff and
+// tmp arrays as scratch.
 __global__ void __launch_bounds__(1024) k_layout(GridDev g, SpArgs sa, Unit *units, int *qctl) {
   __shared__ int64_t part[1024];
   const int s = blockIdx.x;
@@ -1015,23 +1053,39 @@ __global__ void __launch_bounds__(1024) k_layout(GridDev g, SpArgs sa, Unit *uni
   for (int P = threadIdx.x; P <= n; P += blockDim.x) S.sstart[P] = (int32_t)S.noff[P];
   if (!units) return;
   __syncthreads();
-  for (int P = threadIdx.x; P < n; P += blockDim.x) S.in[P] = (S.in[P] + g.spc - 1) / g.spc;
+  // full units per patch -> noff (scan); remainder flags -> tmp (scan)
+  for (int P = threadIdx.x; P < n; P += blockDim.x) {
+    const int nseg = S.sstart[P + 1] - S.sstart[P];
+    S.in[P] = nseg / g.spc;
+  }
   __syncthreads();
   block_scan_1024(S.in, S.noff, n, part);
   for (int P = threadIdx.x; P < n; P += blockDim.x) {
     const int nseg = S.sstart[P + 1] - S.sstart[P];
-    int64_t at = S.ubase + S.noff[P];
-    for (int k0 = 0; k0 < nseg; k0 += g.spc, at++) {
-      Unit un;
-      un.s = s;
-      un.P = P;
-      un.k0 = k0;
-      un.k1 = k0 + g.spc < nseg ? k0 + g.spc : nseg;
-      units[at] = un;
+    S.in[P] = nseg % g.spc != 0;
+  }
+  __syncthreads();
+  block_scan_1024(S.in, S.tmp, n, part);
+  const int64_t nfull = S.noff[n];
+  for (int P = threadIdx.x; P < n; P += blockDim.x) {
+    const int nseg = S.sstart[P + 1] - S.sstart[P];
+    const int nf = nseg / g.spc;
+    Unit un;
+    un.s = s;
+    un.P = P;
+    for (int j = 0; j < nf; j++) {
+      un.k0 = j * g.spc;
+      un.k1 = un.k0 + g.spc;
+      units[S.ubase + S.noff[P] + j] = un;
+    }
+    if (nseg % g.spc) {
+      un.k0 = nf * g.spc;
+      un.k1 = nseg;
+      units[S.ubase + nfull + S.tmp[P]] = un;
     }
   }
   if (threadIdx.x == 0) {
-    qctl[2 * s + 1] = (int)S.noff[n];
+    qctl[2 * s + 1] = (int)(nfull + S.tmp[n]);
     qctl[2 * s] = 0;
   }
 }
