@@ -91,7 +91,8 @@ typedef struct {
 
 typedef struct {
   double q, m;         /* charge, mass */
-  int64_t n;           /* particles in the arrays */
+  int64_t n;           /* particles in the arrays, below 2^29 (element offsets
+                          of every array fit in 32 bits as byte offsets) */
   int64_t capacity;    /* length of every particle array */
   double *x[3];        /* positions (x[2] = NULL in 2D) */
   double *u[3];        /* momenta u^{n-1/2} */

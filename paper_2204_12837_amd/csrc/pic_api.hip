@@ -143,8 +143,8 @@ pic_status check_species(pic_ctx *c, const pic_species *sp, int32_t nsp, bool ne
     if (p.n > p.capacity)
       return fail(c, PIC_ERR_CAPACITY, "species %d: n=%lld above capacity=%lld", s,
                   (long long)p.n, (long long)p.capacity);
-    if (p.n >= (int64_t)1 << 31)
-      return fail(c, PIC_ERR_CAPACITY, "species %d: n must stay below 2^31", s);
+    if (p.n >= (int64_t)1 << 29)
+      return fail(c, PIC_ERR_CAPACITY, "species %d: n must stay below 2^29", s);
     if (!(p.m > 0) || !std::isfinite(p.m) || !std::isfinite(p.q))
       return fail(c, PIC_ERR_ARG, "species %d: bad charge or mass", s);
     for (int a = 0; a < c->cfg.dim; a++)
@@ -190,7 +190,7 @@ pic_status ensure_scratch(pic_ctx *c, const pic_species *sp, int32_t nsp, bool x
       if ((e = realloc_dev(S.tag, (size_t)cap)) != hipSuccess) return hip_fail(c, e, "hipMalloc");
       if ((e = realloc_dev(S.perm, (size_t)cap)) != hipSuccess) return hip_fail(c, e, "hipMalloc");
 
-      if ((e = realloc_dev(S.cnt, (size_t)maxseg * nc)) != hipSuccess)
+      if ((e = realloc_dev(S.cnt, (size_t)maxseg * kCntRow)) != hipSuccess)
         return hip_fail(c, e, "hipMalloc");
       if ((e = realloc_dev(S.pre, (size_t)maxseg * nc)) != hipSuccess)
         return hip_fail(c, e, "hipMalloc");

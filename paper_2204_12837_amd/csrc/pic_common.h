@@ -9,6 +9,7 @@ namespace pic {
 
 constexpr int kMaxSpecies = 8;
 constexpr int kSeg = 256;   // particles per ranking segment (multiple of 64)
+constexpr int kCntRow = 64; // row length of the per-segment code counts (one per lane)
 constexpr int kErrCFL = 1;  // device error bits
 constexpr int kErrPos = 2;
 
@@ -41,7 +42,7 @@ struct SpDev {
   int64_t *noff;    // [npatch+1] scratch: offsets after the sort
   uint32_t *tag;    // [capacity] neighbour code << 27 | rank inside (segment, code)
   int32_t *sstart;  // [npatch+1] first ranking segment of each patch (kSeg particles each)
-  int32_t *cnt;     // [max segments * nc] particles per (segment, code)
+  int32_t *cnt;     // [max segments * kCntRow] particles per (segment, code)
   int32_t *pre;     // [max segments * nc] earlier segments' count of the code, same patch
   int32_t *tot;     // [npatch * nc] particles per (patch, code)
   int64_t *rbase;   // [npatch * nc] start of (patch, code) inside its destination

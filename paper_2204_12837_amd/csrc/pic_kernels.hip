@@ -582,92 +582,215 @@ __device__ __forceinline__ bool in_patch(const TileGeom &t, const double xi[3]) 
   return ok;
 }
 
+// Element k of a particle array through a 32-bit byte offset (k < 2^29):
+// loads and stores then take the array's base from scalar registers and one
+// vector register for the offset, shared by every array.
+template <typename T>
+__device__ __forceinline__ T &at(T *p, uint32_t k) {
+  return *reinterpret_cast<T *>(reinterpret_cast<char *>(p) + (k * (uint32_t)sizeof(T)));
+}
+template <typename T>
+__device__ __forceinline__ const T &at(const T *p, uint32_t k) {
+  return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(p) + (k * (uint32_t)sizeof(T)));
+}
+
+// State of one particle as read at the start of a step (with its id when
+// the particle moves to another slot).
+template <int DIM, bool ID>
+struct Part {
+  double x[DIM], u[3], w;
+  int64_t id;
+};
+
+template <int DIM, bool ID>
+__device__ __forceinline__ void load_part(const SpDev &S, uint32_t src, Part<DIM, ID> &p) {
+#pragma unroll
+  for (int a = 0; a < DIM; a++) p.x[a] = at(S.x[a], src);
+  p.u[0] = at(S.u[0], src);
+  p.u[1] = at(S.u[1], src);
+  p.u[2] = at(S.u[2], src);
+  p.w = at(S.w, src);
+  if (ID) p.id = at(S.id, src);
+}
+
+// The 64-particle blocks one wave processes: sub-blocks of ranking segments
+// k = k0 + wv, k0 + wv + nw, ... below k1 (segments hold kSeg consecutive
+// particles of the patch; only the patch's last one can be short, so only
+// the wave's last block can be partial).  All fields are wave-uniform.  A
+// step past the wave's last block leaves the block where it is, marked dead.
+struct Blk {
+  int k;          // ranking segment inside the patch
+  uint32_t base;  // first particle of the block
+  uint32_t se;    // end of the segment
+  bool dead;
+  __device__ void start(int k_, uint32_t beg, uint32_t end) {
+    k = k_;
+    base = beg + (uint32_t)k * kSeg;
+    se = base + kSeg < end ? base + kSeg : end;
+    dead = false;
+  }
+  __device__ void next(int nw, int k1, uint32_t beg, uint32_t end) {
+    if (dead) return;
+    if (base + 64 < se) {
+      base += 64;
+    } else if (k + nw < k1) {
+      start(k + nw, beg, end);
+    } else {
+      dead = true;
+    }
+  }
+  __device__ bool full() const { return base + 64 <= se; }
+  // lane's slot, clamped into the block (always a valid particle)
+  __device__ uint32_t slot(int lane) const {
+    const uint32_t i = base + (uint32_t)lane;
+    return i < se ? i : se - 1;
+  }
+};
+
+// Interpolation, Push, Projection and pre-BC of one particle: advances x
+// (wrapped) and u in place and returns its neighbour code (CENTER when the
+// particle is rejected, with the error bit set).
+template <int DIM>
+__device__ __forceinline__ int step_particle(const GridDev &g, const TileGeom &t, const double *tEB,
+                                             double *tJ, double q, double alpha, double w,
+                                             double x[3], double u[3], int &bad) {
+  constexpr int CENTER = DIM == 2 ? 4 : 13;
+  double xi[3], v[3], F[6];
+#pragma unroll
+  for (int a = 0; a < DIM; a++) xi[a] = x[a] * g.inv_d[a];
+  if (!in_patch<DIM>(t, xi)) {
+    bad |= kErrPos;
+    return CENTER;
+  }
+  const Shapes sh = shapes_at<DIM>(xi, t.org);
+  interp6<DIM>(tEB, t.TE, t.Tx, t.Txy, sh, F);
+  boris(alpha, F, u, v);
+  double x1[3];
+  Win win[DIM];
+  bool ok = true;
+#pragma unroll
+  for (int a = 0; a < DIM; a++) {
+    x1[a] = x[a] + g.dt * v[a];
+    ok = ok && esk_win(sh.p[a], x1[a] * g.inv_d[a], sh.p[a].i + 1 + t.org[a], win[a]);
+  }
+  if (ok)
+    deposit<DIM>(g, tJ, t.TJ, t.Jx, t.Jxy, q * w, win, v[2]);
+  else
+    bad |= kErrCFL;
+  const int c = dest_code<DIM>(g, t.lo, x1);
+#pragma unroll
+  for (int a = 0; a < DIM; a++) x[a] = x1[a];
+  if (c < 0) {
+    bad |= kErrPos;
+    return CENTER;
+  }
+  return c;
+}
+
 // ---------------------------------------------------------------------------
 // Fused step: Interpolation, Push, pre-BC and Projection of ranking segments
 // [k0, k1) of patch P (each segment kSeg consecutive particles; the waves of
-// the workgroup take segments in turn, 64 particles per iteration, and rank
-// each segment on their own, so the loop has no barrier).  The E/B tile of P
-// is in tEB, the J tile tJ accumulates.
-template <int DIM>
+// the workgroup take segments in turn, 64 particles per block, and rank each
+// segment on their own, so the loop has no barrier).  The E/B tile of P is in
+// tEB, the J tile tJ accumulates.  GATHER: slot i of the patch takes the
+// particle at perm[i] of the other buffer set (the previous sort's layout)
+// and is written to this set; otherwise particles are updated in place.
+//
+// Each wave runs a software pipeline over its blocks: while block n is
+// computed, the particles of block n+1 are being loaded and the permutation
+// entries of block n+2 as well, so the dependent global loads (permutation,
+// then particle) do not stall the wave.  Every global access of a full block
+// is issued unconditionally (prefetches past the wave's end reload its last
+// block), which keeps the memory-counter waits exact; only a partial last
+// block runs masked.
+template <int DIM, bool GATHER>
 __device__ __forceinline__ void ipp_segments(const GridDev &g, const SpDev &S, const TileGeom &t,
                                              const double *tEB, double *tJ, int P, int k0, int k1,
-                                             bool gather, int &bad) {
-  constexpr int NC = DIM == 2 ? 9 : 27;
-  constexpr int CENTER = (NC - 1) / 2;
-  const int64_t beg = S.off[P], end = S.off[P + 1];
-  const int nw = blockDim.x >> 6, wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+                                             int &bad) {
+  const uint32_t beg = (uint32_t)S.off[P], end = (uint32_t)S.off[P + 1];
+  const int nw = blockDim.x >> 6, lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   const int sbase = S.sstart[P];
   const double q = S.q, alpha = S.alpha;
-  for (int k = k0 + wv; k < k1; k += nw) {
-    const int64_t sb = beg + (int64_t)k * kSeg;
-    const int64_t se = sb + kSeg < end ? sb + kSeg : end;
-    int run = 0;
-    for (int64_t base = sb; base < se; base += 64) {
-      const int64_t i = base + lane;
-      const bool valid = i < se;
-      int code = CENTER;
-      if (valid) {
-        // particle slot i of the current layout: in place, or gathered from
-        // the other buffer set through the sort's permutation
-        const int64_t src = gather ? (int64_t)S.perm[i] : i;
-        double x[3], xi[3], u[3], v[3], F[6];
+  Blk cur;
+  cur.start(k0 + wv, beg, end);
+  if (cur.k >= k1) return;
+  Blk nxt = cur;
+  nxt.next(nw, k1, beg, end);
+  auto src_of = [&](const Blk &b) -> uint32_t {
+    const uint32_t i = b.slot(lane);
+    return GATHER ? (uint32_t)at(S.perm, i) : i;
+  };
+  Part<DIM, GATHER> pc, pn;
+  load_part<DIM, GATHER>(S, src_of(cur), pc);
+  uint32_t srcn = src_of(nxt);
+  double *const *xo = GATHER ? S.xa : S.x;
+  double *const *uo = GATHER ? S.ua : S.u;
+  int run = 0;
+  // full blocks
+  while (!cur.dead && cur.full()) {
+    Blk nn = nxt;
+    nn.next(nw, k1, beg, end);
+    load_part<DIM, GATHER>(S, srcn, pn);
+    const uint32_t srcnn = src_of(nn);
+    const uint32_t i = cur.base + lane;
+    double x[3], u[3];
 #pragma unroll
-        for (int a = 0; a < DIM; a++) {
-          x[a] = S.x[a][src];
-          xi[a] = x[a] * g.inv_d[a];
-        }
-        u[0] = S.u[0][src];
-        u[1] = S.u[1][src];
-        u[2] = S.u[2][src];
-        const double w = S.w[src];
-        if (!in_patch<DIM>(t, xi)) {
-          bad |= kErrPos;
-        } else {
-          const Shapes sh = shapes_at<DIM>(xi, t.org);
-          interp6<DIM>(tEB, t.TE, t.Tx, t.Txy, sh, F);
-          boris(alpha, F, u, v);
-          double x1[3];
-          Win win[DIM];
-          bool ok = true;
+    for (int a = 0; a < DIM; a++) x[a] = pc.x[a];
+    u[0] = pc.u[0];
+    u[1] = pc.u[1];
+    u[2] = pc.u[2];
+    const int code = step_particle<DIM>(g, t, tEB, tJ, q, alpha, pc.w, x, u, bad);
 #pragma unroll
-          for (int a = 0; a < DIM; a++) {
-            x1[a] = x[a] + g.dt * v[a];
-            ok = ok && esk_win(sh.p[a], x1[a] * g.inv_d[a], sh.p[a].i + 1 + t.org[a], win[a]);
-          }
-          if (ok)
-            deposit<DIM>(g, tJ, t.TJ, t.Jx, t.Jxy, q * w, win, v[2]);
-          else
-            bad |= kErrCFL;
-          const int c = dest_code<DIM>(g, t.lo, x1);
-          if (c < 0) {
-            bad |= kErrPos;
-          } else {
-            code = c;
-          }
-#pragma unroll
-          for (int a = 0; a < DIM; a++) x[a] = x1[a];
-        }
-        double *const *xo = gather ? S.xa : S.x;
-        double *const *uo = gather ? S.ua : S.u;
-#pragma unroll
-        for (int a = 0; a < DIM; a++) xo[a][i] = x[a];
-        uo[0][i] = u[0];
-        uo[1][i] = u[1];
-        uo[2][i] = u[2];
-        if (gather) {
-          S.wa[i] = w;
-          S.ida[i] = S.id[src];
-        }
-      }
-      const uint32_t rank = wave_rank(valid, code, lane, run);
-      if (valid) S.tag[i] = ((uint32_t)code << 27) | rank;
+    for (int a = 0; a < DIM; a++) at(xo[a], i) = x[a];
+    at(uo[0], i) = u[0];
+    at(uo[1], i) = u[1];
+    at(uo[2], i) = u[2];
+    if (GATHER) {
+      at(S.wa, i) = pc.w;
+      at(S.ida, i) = pc.id;
     }
-    if (lane < NC) S.cnt[(int64_t)(sbase + k) * NC + lane] = run;
+    const uint32_t rank = wave_rank(true, code, lane, run);
+    at(S.tag, i) = ((uint32_t)code << 27) | rank;
+    // lanes >= 3^dim hold zero: the row is kCntRow wide
+    S.cnt[(int64_t)(sbase + cur.k) * kCntRow + lane] = run;
+    if (cur.base + 64 >= cur.se) run = 0;
+    cur = nxt;
+    nxt = nn;
+    pc = pn;
+    srcn = srcnn;
+  }
+  // partial last block
+  if (!cur.dead) {
+    const uint32_t i = cur.base + lane;
+    const bool valid = i < cur.se;
+    int code = DIM == 2 ? 4 : 13;
+    if (valid) {
+      double x[3], u[3];
+#pragma unroll
+      for (int a = 0; a < DIM; a++) x[a] = pc.x[a];
+      u[0] = pc.u[0];
+      u[1] = pc.u[1];
+      u[2] = pc.u[2];
+      code = step_particle<DIM>(g, t, tEB, tJ, q, alpha, pc.w, x, u, bad);
+#pragma unroll
+      for (int a = 0; a < DIM; a++) at(xo[a], i) = x[a];
+      at(uo[0], i) = u[0];
+      at(uo[1], i) = u[1];
+      at(uo[2], i) = u[2];
+      if (GATHER) {
+        at(S.wa, i) = pc.w;
+        at(S.ida, i) = pc.id;
+      }
+    }
+    const uint32_t rank = wave_rank(valid, code, lane, run);
+    if (valid) at(S.tag, i) = ((uint32_t)code << 27) | rank;
+    S.cnt[(int64_t)(sbase + cur.k) * kCntRow + lane] = run;
   }
 }
 
 // Per-patch launch: one workgroup per (patch, species), all its segments.
-template <int DIM>
+template <int DIM, bool GATHER>
 __global__ void __launch_bounds__(kMaxWg<DIM>, kMinWaves<DIM>) k_ipp(GridDev g, SpArgs sa, Fields f, int *err) {
   extern __shared__ __align__(16) double lds[];
   const int P = blockIdx.x;
@@ -679,8 +802,7 @@ __global__ void __launch_bounds__(kMaxWg<DIM>, kMinWaves<DIM>) k_ipp(GridDev g, 
   zero_tile<DIM>(tJ, 3 * t.TJ);
   __syncthreads();
   int bad = 0;
-  ipp_segments<DIM>(g, S, t, tEB, tJ, P, 0, S.sstart[P + 1] - S.sstart[P], sa.gather != 0,
-                    bad);
+  ipp_segments<DIM, GATHER>(g, S, t, tEB, tJ, P, 0, S.sstart[P + 1] - S.sstart[P], bad);
   if (bad) atomicOr(err, bad);
   __syncthreads();
   flush_j<DIM>(g, t, tJ, f.j);
@@ -692,7 +814,7 @@ __global__ void __launch_bounds__(kMaxWg<DIM>, kMinWaves<DIM>) k_ipp(GridDev g, 
 // The E/B tile is restaged and the J tile flushed only when the patch changes
 // between a workgroup's consecutive units (E/B and J do not depend on the
 // species).
-template <int DIM>
+template <int DIM, bool GATHER>
 __global__ void __launch_bounds__(kMaxWg<DIM>, kMinWaves<DIM>) k_ipp_persistent(GridDev g, SpArgs sa, Fields f, int *err,
                                                         const Unit *units, int *qctl) {
   extern __shared__ __align__(16) double lds[];
@@ -708,7 +830,7 @@ __global__ void __launch_bounds__(kMaxWg<DIM>, kMinWaves<DIM>) k_ipp_persistent(
     for (;;) {
       if (threadIdx.x == 0) s_unit = atomicAdd(&qctl[2 * s], 1);
       __syncthreads();
-      const int u = s_unit;
+      const int u = __builtin_amdgcn_readfirstlane(s_unit);  // wave-uniform
       __syncthreads();  // every thread has read s_unit before the next pop
       if (u >= n_units) break;
       const Unit un = ul[u];
@@ -723,7 +845,7 @@ __global__ void __launch_bounds__(kMaxWg<DIM>, kMinWaves<DIM>) k_ipp_persistent(
         __syncthreads();
         curP = un.P;
       }
-      ipp_segments<DIM>(g, sa.s[s], t, tEB, tJ, un.P, un.k0, un.k1, sa.gather != 0, bad);
+      ipp_segments<DIM, GATHER>(g, sa.s[s], t, tEB, tJ, un.P, un.k0, un.k1, bad);
       __syncthreads();  // this unit's deposits are done before any flush
     }
   }
@@ -848,7 +970,7 @@ __global__ void __launch_bounds__(kMaxWg<DIM>) k_tag(GridDev g, SpArgs sa, int *
       const uint32_t rank = wave_rank(valid, code, lane, run);
       if (valid) S.tag[i] = ((uint32_t)code << 27) | rank;
     }
-    if (lane < NC) S.cnt[(int64_t)(sbase + k) * NC + lane] = run;
+    if (lane < NC) S.cnt[(int64_t)(sbase + k) * kCntRow + lane] = run;
   }
   if (bad) atomicOr(err, bad);
 }
@@ -865,7 +987,7 @@ __global__ void k_seg_prefix(GridDev g, SpArgs sa) {
   int run = 0;
   for (int k = s0; k < s1; k++) {
     const int64_t at = (int64_t)k * nc + c;
-    const int v = S.cnt[at];
+    const int v = S.cnt[(int64_t)k * kCntRow + c];
     S.pre[at] = run;
     run += v;
   }
@@ -1012,7 +1134,7 @@ __global__ void __launch_bounds__(kSeg) k_place(GridDev g, SpArgs sa, int *err) 
       continue;
     }
     if (TO_PERM) {
-      S.perm[dst] = (int32_t)i;
+      S.perm[dst] = (int32_t)i;  // the particle moves at the next fused kernel
     } else {
       for (int a = 0; a < g.dim; a++) S.xa[a][dst] = S.x[a][i];
       S.ua[0][dst] = S.u[0][i];
@@ -1131,19 +1253,27 @@ hipError_t launch_zero(double *const j[3], int64_t ncell, hipStream_t st) {
   return hipGetLastError();
 }
 
+template <int DIM, bool GATHER>
+void launch_ipp_t(const GridDev &g, const SpArgs &sa, const Fields &f, int *err, int wg,
+                  size_t lds, hipStream_t st) {
+  if (DIM == 3)
+    (void)hipFuncSetAttribute((const void *)k_ipp<DIM, GATHER>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  hipLaunchKernelGGL((k_ipp<DIM, GATHER>), dim3(g.npatch, sa.nsp), dim3(wg), lds, st, g, sa, f,
+                     err);
+}
+
 hipError_t launch_ipp(const GridDev &g, const SpArgs &sa, const double *const e[3],
                       const double *const b[3], double *const j[3], int *err, int wg,
                       hipStream_t st) {
   const Fields f = mkfields(e, b, j);
   const size_t lds = lds_bytes_ipp(g);
-  const dim3 grid(g.npatch, sa.nsp);
-  if (g.dim == 2) {
-    hipLaunchKernelGGL(k_ipp<2>, grid, dim3(wg), lds, st, g, sa, f, err);
-  } else {
-    (void)hipFuncSetAttribute((const void *)k_ipp<3>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)lds);
-    hipLaunchKernelGGL(k_ipp<3>, grid, dim3(wg), lds, st, g, sa, f, err);
-  }
+  if (g.dim == 2)
+    sa.gather ? launch_ipp_t<2, true>(g, sa, f, err, wg, lds, st)
+              : launch_ipp_t<2, false>(g, sa, f, err, wg, lds, st);
+  else
+    sa.gather ? launch_ipp_t<3, true>(g, sa, f, err, wg, lds, st)
+              : launch_ipp_t<3, false>(g, sa, f, err, wg, lds, st);
   return hipGetLastError();
 }
 
@@ -1204,16 +1334,24 @@ hipError_t launch_layout(const GridDev &g, const SpArgs &sa, Unit *units, int *q
   return hipGetLastError();
 }
 
+template <int DIM, bool GATHER>
+int blocks_per_cu(int wg, size_t lds) {
+  if (DIM == 3)
+    (void)hipFuncSetAttribute((const void *)k_ipp_persistent<DIM, GATHER>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  int n = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_ipp_persistent<DIM, GATHER>, wg, lds) !=
+      hipSuccess)
+    return 1;
+  return n;
+}
+
 int persistent_grid(const GridDev &g, int wg) {
   const size_t lds = lds_bytes_ipp(g);
-  int per_cu = 0;
-  hipError_t e;
-  if (g.dim == 2)
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_ipp_persistent<2>, wg, lds);
-  else
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_ipp_persistent<3>, wg, lds);
+  int per_cu = g.dim == 2 ? std::min(blocks_per_cu<2, true>(wg, lds), blocks_per_cu<2, false>(wg, lds))
+                          : std::min(blocks_per_cu<3, true>(wg, lds), blocks_per_cu<3, false>(wg, lds));
   int dev = 0, ncu = 0;
-  if (e != hipSuccess || per_cu < 1) per_cu = 1;
+  if (per_cu < 1) per_cu = 1;
   if (hipGetDevice(&dev) != hipSuccess ||
       hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
       ncu < 1)
@@ -1221,20 +1359,27 @@ int persistent_grid(const GridDev &g, int wg) {
   return per_cu * ncu;
 }
 
+template <int DIM, bool GATHER>
+void launch_pers_t(const GridDev &g, const SpArgs &sa, const Fields &f, int *err,
+                   const Unit *units, int *qctl, int grid, int wg, size_t lds, hipStream_t st) {
+  if (DIM == 3)
+    (void)hipFuncSetAttribute((const void *)k_ipp_persistent<DIM, GATHER>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  hipLaunchKernelGGL((k_ipp_persistent<DIM, GATHER>), dim3(grid), dim3(wg), lds, st, g, sa, f,
+                     err, units, qctl);
+}
+
 hipError_t launch_ipp_persistent(const GridDev &g, const SpArgs &sa, const double *const e[3],
                                  const double *const b[3], double *const j[3], int *err,
                                  const Unit *units, int *qctl, int grid, int wg, hipStream_t st) {
   const Fields f = mkfields(e, b, j);
   const size_t lds = lds_bytes_ipp(g);
-  if (g.dim == 2) {
-    hipLaunchKernelGGL(k_ipp_persistent<2>, dim3(grid), dim3(wg), lds, st, g, sa, f, err, units,
-                       qctl);
-  } else {
-    (void)hipFuncSetAttribute((const void *)k_ipp_persistent<3>,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL(k_ipp_persistent<3>, dim3(grid), dim3(wg), lds, st, g, sa, f, err, units,
-                       qctl);
-  }
+  if (g.dim == 2)
+    sa.gather ? launch_pers_t<2, true>(g, sa, f, err, units, qctl, grid, wg, lds, st)
+              : launch_pers_t<2, false>(g, sa, f, err, units, qctl, grid, wg, lds, st);
+  else
+    sa.gather ? launch_pers_t<3, true>(g, sa, f, err, units, qctl, grid, wg, lds, st)
+              : launch_pers_t<3, false>(g, sa, f, err, units, qctl, grid, wg, lds, st);
   return hipGetLastError();
 }
 
