@@ -200,7 +200,9 @@ enum {
   PIC_KERNEL_TAG = 5,         /* split path: pre-BC codes and ranks */
   PIC_KERNEL_SORT = 6,        /* general sort of unsorted input */
   PIC_KERNEL_ADJOINT = 7,     /* adjoint segment */
-  PIC_KERNEL_COUNT = 8
+  PIC_KERNEL_EXCHANGE = 8,    /* slab layout: departures, arrivals, counts, work units */
+  PIC_KERNEL_SLAB = 9,        /* slab layout: dense -> slabs and back, once per call */
+  PIC_KERNEL_COUNT = 10
 };
 
 /* Observability: when on, every later launch of a kernel class is bracketed

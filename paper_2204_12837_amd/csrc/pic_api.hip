@@ -32,6 +32,20 @@ struct SpScratch {
   int64_t ubase = 0, maxunits = 0;  // persistent mode: place in the unit list
 };
 
+// Slab-layout scratch of one species (the per-patch arrays, the outbox and
+// the control words; the code and hole lists reuse the sort's tag and
+// permutation arrays).
+struct SlabScratch {
+  int64_t cap = 0;  // particle capacity the outbox was sized for
+  int64_t *sb = nullptr, *sb2 = nullptr;
+  int32_t *room = nullptr, *room2 = nullptr, *cnt = nullptr, *cnt2 = nullptr;
+  int32_t *arr = nullptr, *arr2 = nullptr, *dep = nullptr, *ctl = nullptr;
+  double *ox[3] = {nullptr, nullptr, nullptr}, *ou[3] = {nullptr, nullptr, nullptr};
+  double *ow = nullptr;
+  int64_t *oid = nullptr;
+  int32_t *odest = nullptr;
+};
+
 constexpr size_t kStaticLds = 2 * 4 * 27 * 4 + 27 * 4 + 64;  // ranking scratch + slack
 
 }  // namespace
@@ -73,6 +87,9 @@ struct pic_ctx {
   int64_t units_cap = 0;
   int *qctl = nullptr;    // per species: ticket, number of units
   int pgrid = 0;          // persistent grid size
+  SlabScratch slab[kMaxSpecies];
+  GraphCache slab_gc;     // one captured slab-layout step
+  int pgrid_slab = 0;     // persistent grid size of the slab-layout kernel
 };
 
 namespace {
@@ -465,6 +482,217 @@ pic_status ensure_graph(pic_ctx *c, const pic_species *sp, int32_t nsp, const pi
   return PIC_OK;
 }
 
+// The slab layout fits when every species' buffers hold its particles plus
+// the room the plan adds (n/8 + 79 per patch, see slab_room) and stay below
+// 2^29 elements (32-bit byte offsets in the kernels).
+bool slab_fits(const pic_ctx *c, const pic_species *sp, int32_t nsp) {
+  const int64_t np = c->g.npatch;
+  for (int s = 0; s < nsp; s++) {
+    const int64_t n = sp[s].n, cap = sp[s].capacity;
+    if (cap >= ((int64_t)1 << 29)) return false;
+    if (cap < n + n / 8 + 80 * np) return false;
+  }
+  return true;
+}
+
+pic_status ensure_slab(pic_ctx *c, const pic_species *sp, int32_t nsp, hipStream_t st) {
+  const size_t np = (size_t)c->g.npatch;
+  bool synced = false;
+  auto sync = [&]() -> hipError_t {
+    if (synced) return hipSuccess;
+    synced = true;
+    return hipStreamSynchronize(st);
+  };
+  for (int s = 0; s < nsp; s++) {
+    SlabScratch &L = c->slab[s];
+    hipError_t e = hipSuccess;
+    if (!L.sb) {
+      if ((e = sync()) != hipSuccess) return hip_fail(c, e, "hipStreamSynchronize");
+      if ((e = realloc_dev(L.sb, np + 1)) != hipSuccess ||
+          (e = realloc_dev(L.sb2, np + 1)) != hipSuccess ||
+          (e = realloc_dev(L.room, np)) != hipSuccess ||
+          (e = realloc_dev(L.room2, np)) != hipSuccess ||
+          (e = realloc_dev(L.cnt, np)) != hipSuccess ||
+          (e = realloc_dev(L.cnt2, np)) != hipSuccess ||
+          (e = realloc_dev(L.arr, np)) != hipSuccess ||
+          (e = realloc_dev(L.arr2, np)) != hipSuccess || (e = realloc_dev(L.dep, np)) != hipSuccess ||
+          (e = realloc_dev(L.ctl, 2)) != hipSuccess)
+        return hip_fail(c, e, "hipMalloc");
+    }
+    const int64_t cap = sp[s].capacity;
+    if (cap > L.cap) {
+      if ((e = sync()) != hipSuccess) return hip_fail(c, e, "hipStreamSynchronize");
+      for (int a = 0; a < 3; a++) {
+        if (a < c->cfg.dim && (e = realloc_dev(L.ox[a], (size_t)cap)) != hipSuccess)
+          return hip_fail(c, e, "hipMalloc");
+        if ((e = realloc_dev(L.ou[a], (size_t)cap)) != hipSuccess) return hip_fail(c, e, "hipMalloc");
+      }
+      if ((e = realloc_dev(L.ow, (size_t)cap)) != hipSuccess ||
+          (e = realloc_dev(L.oid, (size_t)cap)) != hipSuccess ||
+          (e = realloc_dev(L.odest, (size_t)cap)) != hipSuccess)
+        return hip_fail(c, e, "hipMalloc");
+      L.cap = cap;
+    }
+  }
+  return PIC_OK;
+}
+
+SlabArgs make_slab_args(pic_ctx *c, const pic_species *sp, int32_t nsp) {
+  SlabArgs a{};
+  a.nsp = nsp;
+  for (int s = 0; s < nsp; s++) {
+    const pic_species &p = sp[s];
+    const SlabScratch &L = c->slab[s];
+    SlabDev &d = a.s[s];
+    d.alpha = (p.q / p.m) * (0.5 * c->cfg.dt);
+    d.q = p.q;
+    d.capacity = p.capacity;
+    for (int k = 0; k < 3; k++) {
+      const bool on = k < c->cfg.dim;
+      d.x[k] = on ? p.x[k] : nullptr;
+      d.xs[k] = on ? p.x_alt[k] : nullptr;
+      d.ox[k] = on ? L.ox[k] : nullptr;
+      d.u[k] = p.u[k];
+      d.us[k] = p.u_alt[k];
+      d.ou[k] = L.ou[k];
+    }
+    d.w = p.w;
+    d.ws = p.w_alt;
+    d.ow = L.ow;
+    d.id = p.id;
+    d.ids = p.id_alt;
+    d.oid = L.oid;
+    d.odest = L.odest;
+    d.off = p.offset;
+    d.sb = L.sb;
+    d.sb2 = L.sb2;
+    d.cap = L.room;
+    d.cap2 = L.room2;
+    d.cnt = L.cnt;
+    d.cnt2 = L.cnt2;
+    d.arr = L.arr;
+    d.arr2 = L.arr2;
+    d.dep = L.dep;
+    d.ctl = L.ctl;
+    d.code = reinterpret_cast<uint8_t *>(c->sp[s].tag);
+    d.hole = c->sp[s].perm;
+    d.tmp = c->sp[s].tmp;
+    d.ubase = (int32_t)c->sp[s].ubase;
+  }
+  return a;
+}
+
+// One step in the slab layout: J <- 0, the in-place fused kernel, the
+// exchange of the particles that changed patch.
+hipError_t enqueue_slab_step(pic_ctx *c, const SlabArgs &a, const pic_fields *f, hipStream_t st) {
+  int64_t ncell = 1;
+  for (int d = 0; d < c->cfg.dim; d++) ncell *= c->cfg.n[d];
+  const bool pers = c->cfg.mode == PIC_MODE_PERSISTENT;
+  hipError_t e = timed(c, PIC_KERNEL_ZERO, st, [&] { return launch_zero(f->j, ncell, st); });
+  if (e == hipSuccess)
+    e = timed(c, PIC_KERNEL_IPP, st, [&] {
+      return pers ? launch_ipp_slab_persistent(c->g, a, f->e, f->b, f->j, c->err_dev, c->units,
+                                               c->qctl, c->pgrid_slab, c->wg, st)
+                  : launch_ipp_slab(c->g, a, f->e, f->b, f->j, c->err_dev, c->wg, st);
+    });
+  if (e == hipSuccess)
+    e = timed(c, PIC_KERNEL_EXCHANGE, st, [&] {
+      return launch_exchange(c->g, a, c->err_dev, pers ? c->units : nullptr, c->qctl,
+                             c->g.spc * kSeg, st);
+    });
+  return e;
+}
+
+// The captured slab step for these arguments (captured anew when any
+// pointer, count or field differs from the cached one).
+pic_status ensure_slab_graph(pic_ctx *c, const SlabArgs &a, const pic_fields *f,
+                             hipGraphExec_t *out) {
+  std::vector<uintptr_t> key((sizeof(SlabArgs) + sizeof(uintptr_t) - 1) / sizeof(uintptr_t), 0);
+  std::memcpy(key.data(), &a, sizeof(SlabArgs));
+  for (int k = 0; k < 3; k++) {
+    key.push_back((uintptr_t)f->e[k]);
+    key.push_back((uintptr_t)f->b[k]);
+    key.push_back((uintptr_t)f->j[k]);
+  }
+  key.push_back((uintptr_t)c->units);
+  key.push_back((uintptr_t)c->pgrid_slab);
+  GraphCache &gc = c->slab_gc;
+  if (gc.exec && key == gc.key) {
+    *out = gc.exec;
+    return PIC_OK;
+  }
+  if (gc.exec) (void)hipGraphExecDestroy(gc.exec);
+  if (gc.graph) (void)hipGraphDestroy(gc.graph);
+  gc = GraphCache{};
+  hipError_t e;
+  if (!c->cap_stream && (e = hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking)) !=
+                            hipSuccess)
+    return hip_fail(c, e, "hipStreamCreate");
+  if ((e = hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal)) != hipSuccess)
+    return hip_fail(c, e, "hipStreamBeginCapture");
+  const hipError_t eq = enqueue_slab_step(c, a, f, c->cap_stream);
+  hipGraph_t g = nullptr;
+  e = hipStreamEndCapture(c->cap_stream, &g);
+  if (eq != hipSuccess || e != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    return hip_fail(c, eq != hipSuccess ? eq : e, "graph capture");
+  }
+  hipGraphExec_t x = nullptr;
+  if ((e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0)) != hipSuccess) {
+    (void)hipGraphDestroy(g);
+    return hip_fail(c, e, "hipGraphInstantiate");
+  }
+  gc.graph = g;
+  gc.exec = x;
+  gc.key = std::move(key);
+  *out = x;
+  return PIC_OK;
+}
+
+// pic_step in the slab layout: dense -> slabs, nsteps slab steps, slabs ->
+// dense (new offsets); the caller's first buffer set holds the result.
+pic_status step_slab(pic_ctx *c, pic_species *sp, int32_t nsp, pic_fields *f, int32_t nsteps,
+                     hipStream_t st) {
+  pic_status r = ensure_slab(c, sp, nsp, st);
+  if (r != PIC_OK) return r;
+  const bool pers = c->cfg.mode == PIC_MODE_PERSISTENT;
+  if (pers && !c->pgrid_slab) {
+    int dev = 0, ncu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        ncu < 1)
+      ncu = 1;
+    c->pgrid_slab = slab_persistent_blocks_per_cu(c->g, c->wg) * ncu;
+  }
+  const SlabArgs a = make_slab_args(c, sp, nsp);
+  hipError_t e = timed(c, PIC_KERNEL_SLAB, st,
+                       [&] { return launch_slab_begin(c->g, a, c->err_dev, st); });
+  if (e == hipSuccess && pers)
+    e = timed(c, PIC_KERNEL_EXCHANGE, st, [&] {
+      return launch_slab_units(c->g, a, c->g.spc * kSeg, c->units, c->qctl, st);
+    });
+  if (e != hipSuccess) return hip_fail(c, e, "kernel launch");
+  if ((c->cfg.flags & PIC_FLAG_GRAPH) && !c->tm.on) {
+    hipGraphExec_t x = nullptr;
+    if ((r = ensure_slab_graph(c, a, f, &x)) != PIC_OK) return r;
+    for (int k = 0; k < nsteps; k++)
+      if ((e = hipGraphLaunch(x, st)) != hipSuccess) return hip_fail(c, e, "hipGraphLaunch");
+  } else {
+    for (int k = 0; k < nsteps; k++)
+      if ((e = enqueue_slab_step(c, a, f, st)) != hipSuccess) return hip_fail(c, e, "kernel launch");
+  }
+  e = timed(c, PIC_KERNEL_SLAB, st, [&] {
+    hipError_t r2 = launch_slab_end(c->g, a, st);
+    // the dense layout's segment starts (and persistent work units) for
+    // whatever runs next on these particles
+    if (r2 == hipSuccess)
+      r2 = launch_layout(c->g, make_args(c, sp, nsp), pers ? c->units : nullptr, c->qctl, st);
+    return r2;
+  });
+  if (e != hipSuccess) return hip_fail(c, e, "kernel launch");
+  return finish(c, st);
+}
+
 }  // namespace
 
 extern "C" {
@@ -610,7 +838,18 @@ void pic_free(pic_ctx *c) {
     (void)hipFree(S.noff);
     for (int a = 0; a < 3; a++) (void)hipFree(S.x0[a]);
     free_sort_scratch(c->sort[s]);
+    SlabScratch &L = c->slab[s];
+    for (void *p : {(void *)L.sb, (void *)L.sb2, (void *)L.room, (void *)L.room2, (void *)L.cnt,
+                    (void *)L.cnt2, (void *)L.arr, (void *)L.arr2, (void *)L.dep, (void *)L.ctl, (void *)L.ow,
+                    (void *)L.oid, (void *)L.odest})
+      (void)hipFree(p);
+    for (int a = 0; a < 3; a++) {
+      (void)hipFree(L.ox[a]);
+      (void)hipFree(L.ou[a]);
+    }
   }
+  if (c->slab_gc.exec) (void)hipGraphExecDestroy(c->slab_gc.exec);
+  if (c->slab_gc.graph) (void)hipGraphDestroy(c->slab_gc.graph);
   for (hipEvent_t e : c->tm.pool) (void)hipEventDestroy(e);
   for (GraphCache &gc : c->gc) {
     if (gc.exec) (void)hipGraphExecDestroy(gc.exec);
@@ -656,6 +895,8 @@ pic_status pic_check(pic_ctx *c, void *stream) {
     c->poisoned = true;
     if (h & kErrCFL)
       return fail(c, PIC_ERR_CFL, "a particle moved more than one cell in one step");
+    if (h & kErrCap)
+      return fail(c, PIC_ERR_CAPACITY, "the per-patch slabs outgrew the particle buffers");
     return fail(c, PIC_ERR_POS,
                 "a particle lies outside its patch or more than one period outside the box");
   }
@@ -750,6 +991,7 @@ pic_status pic_step(pic_ctx *c, pic_species *sp, int32_t nsp, pic_fields *f, int
   if (hipSetDevice(c->device) != hipSuccess) return fail(c, PIC_ERR_HIP, "hipSetDevice");
   if ((r = ensure_scratch(c, sp, nsp, false, st)) != PIC_OK) return r;
   if (nsteps == 0) return finish(c, st);
+  if (nsteps >= 3 && slab_fits(c, sp, nsp)) return step_slab(c, sp, nsp, f, nsteps, st);
   // The first step updates the particles in place and records the sort as a
   // permutation; middle steps gather through it into the other buffer set;
   // the last step's sort copies the particles into their sorted places, so

@@ -12,6 +12,7 @@ constexpr int kSeg = 256;   // particles per ranking segment (multiple of 64)
 constexpr int kCntRow = 64; // row length of the per-segment code counts (one per lane)
 constexpr int kErrCFL = 1;  // device error bits
 constexpr int kErrPos = 2;
+constexpr int kErrCap = 4;  // the slab layout does not fit the particle buffers
 
 // Grid geometry as the kernels see it.  All derived values (inverse cell
 // sizes, box lengths, Esirkepov factors) are computed once on the host.
@@ -55,6 +56,62 @@ struct SpDev {
   int32_t ubase;    // persistent mode: first work unit of this species
 };
 
+// A persistent-mode work unit of species s and patch P: ranking segments
+// [k0, k1) in the dense layout, particles [k0, k1) of the slab in the slab
+// layout.
+struct Unit {
+  int32_t s, P, k0, k1;
+};
+
+// One species in the slab layout of a pic_step call: patch P owns slots
+// [sb[P], sb[P] + cap[P]) of the second buffer set, cnt[P] of them live.
+struct SlabDev {
+  double alpha, q;
+  int64_t capacity;
+  double *x[3], *u[3], *w;      // dense layout (first buffer set): the call's input and
+  int64_t *id;                  // output, and scratch of a new slab plan
+  double *xs[3], *us[3], *ws;   // slabs (second buffer set)
+  int64_t *ids;
+  int64_t *off;                 // [npatch+1] dense patch offsets
+  int64_t *sb, *sb2;            // [npatch+1] slab starts (current, new plan)
+  int32_t *cap, *cap2;          // [npatch] slab room (current, new plan)
+  int32_t *cnt, *cnt2;          // [npatch] live particles (after the step, after departures)
+  int32_t *arr, *arr2;          // [npatch] arrivals of the step, arrivals of a new plan
+  int32_t *dep;                 // [npatch] departures of the step
+  uint8_t *code;                // [capacity] neighbour code of each slab slot
+  int32_t *hole;                // [capacity] hole lists (patch P's at sb[P])
+  double *ox[3], *ou[3], *ow;   // outbox of departures [capacity], patch P's
+  int64_t *oid;                 // from sb[P]
+  int32_t *odest;               // destination patch of each outbox entry
+  int32_t *ctl;                 // [2] unused, overflow state (0 none, 1 new plan, 2 fatal)
+  int64_t *tmp;                 // [npatch+1] scan scratch
+  int32_t ubase;                // persistent mode: first work unit of this species
+};
+
+struct SlabArgs {
+  int nsp;
+  SlabDev s[kMaxSpecies];
+};
+static_assert(sizeof(SlabArgs) <= 4096, "kernel argument block too large");
+
+// Slab-layout launchers (pic_slab.hip).
+hipError_t launch_slab_begin(const GridDev &g, const SlabArgs &sa, int *err, hipStream_t st);
+hipError_t launch_ipp_slab(const GridDev &g, const SlabArgs &sa, const double *const e[3],
+                           const double *const b[3], double *const j[3], int *err, int wg,
+                           hipStream_t st);
+hipError_t launch_ipp_slab_persistent(const GridDev &g, const SlabArgs &sa,
+                                      const double *const e[3], const double *const b[3],
+                                      double *const j[3], int *err, const Unit *units,
+                                      int *qctl, int grid, int wg, hipStream_t st);
+int slab_persistent_blocks_per_cu(const GridDev &g, int wg);
+// Departures, arrivals, counts (and, on an overflow, a new slab plan); with
+// units != nullptr also the next step's work units of chunk particles.
+hipError_t launch_exchange(const GridDev &g, const SlabArgs &sa, int *err, Unit *units,
+                           int *qctl, int chunk, hipStream_t st);
+hipError_t launch_slab_units(const GridDev &g, const SlabArgs &sa, int chunk, Unit *units,
+                             int *qctl, hipStream_t st);
+hipError_t launch_slab_end(const GridDev &g, const SlabArgs &sa, hipStream_t st);
+
 // Adjoint (reverse-mode derivative) of a segment of 2D steps.
 constexpr int kAdjMaxSteps = 8;  // steps per recomputed segment
 
@@ -77,10 +134,6 @@ hipError_t launch_adjoint(const GridDev &g, const AdjArgs &aa, const double *con
                           double *const eb[3], double *const bb[3], int nsteps, int with_dep,
                           int *err, hipStream_t st);
 
-// A persistent-mode work unit: ranking segments [k0, k1) of patch P of species s.
-struct Unit {
-  int32_t s, P, k0, k1;
-};
 
 struct SpArgs {
   int nsp;

@@ -1,0 +1,686 @@
+// Slab layout of the particles inside a pic_step call (gfx950).
+//
+// Between calls the particles of a species are dense and sorted by patch (the
+// layout the C ABI documents).  Inside a call of several steps they live in
+// the species' second buffer set in per-patch slabs: patch P owns slots
+// [sb[P], sb[P] + cap[P]), of which the first cnt[P] hold its particles and
+// the rest is room for arrivals.  A step then
+//   * updates every particle in place (Interpolation, Push, pre-BC,
+//     Projection: the fused kernel reads and writes each particle once and
+//     records its neighbour code in one byte);
+//   * moves only the particles that changed patch (the paper's exchange of
+//     particles between patches in the synchronisation phase): departures
+//     are copied to an outbox and their slots refilled from the slab's tail,
+//     then arrivals are appended to their destination slab.
+// After this the particles of each patch are again contiguous, as after the
+// paper's per-patch sort; their order inside a patch is arbitrary.  A slab
+// that runs out of room triggers, on the device, a new slab plan and a copy
+// through the first buffer set.  The last step of a call copies the slabs
+// back into the dense sorted layout.
+#include <hip/hip_runtime.h>
+
+#include "pic_common.h"
+#include "pic_device.h"
+
+namespace pic {
+
+namespace {
+
+constexpr int32_t kUnplaced = 1 << 30;  // outbox entry waiting for a new slab plan
+
+// Room of a slab holding c particles: c + c/8 + 64, rounded up to 16 slots
+// (128 bytes), so every slab starts on a cache-line boundary.
+__device__ __forceinline__ int64_t slab_room(int64_t c) {
+  return (c + (c >> 3) + 64 + 15) & ~(int64_t)15;
+}
+
+template <int DIM>
+__device__ __forceinline__ void copy_particle(double *const dx[3], double *const du[3], double *dw,
+                                              int64_t *did, int64_t d, const double *const sx[3],
+                                              const double *const su[3], const double *sw,
+                                              const int64_t *sid, int64_t s) {
+#pragma unroll
+  for (int a = 0; a < DIM; a++) dx[a][d] = sx[a][s];
+  du[0][d] = su[0][s];
+  du[1][d] = su[1][s];
+  du[2][d] = su[2][s];
+  dw[d] = sw[s];
+  did[d] = sid[s];
+}
+
+// Slab plan from the dense offsets (one workgroup of 1024 per species).
+__global__ void __launch_bounds__(1024) k_slab_plan(GridDev g, SlabArgs sa, int *err) {
+  __shared__ int64_t part[1024];
+  const SlabDev &S = sa.s[blockIdx.x];
+  const int n = g.npatch;
+  for (int P = threadIdx.x; P < n; P += blockDim.x) {
+    const int64_t c = S.off[P + 1] - S.off[P];
+    S.cnt[P] = (int32_t)c;
+    S.cap[P] = (int32_t)slab_room(c);
+    S.tmp[P] = slab_room(c);
+    S.arr[P] = 0;
+  }
+  __syncthreads();
+  block_scan_1024(S.tmp, S.sb, n, part);
+  if (threadIdx.x == 0) {
+    S.ctl[1] = 0;
+    if (S.sb[n] > S.capacity) {
+      S.ctl[1] = 2;  // does not fit: every later kernel of the call stands still
+      atomicOr(err, kErrCap);
+    }
+  }
+}
+
+// Dense -> slabs (grid: patches x species).
+template <int DIM>
+__global__ void __launch_bounds__(256) k_slab_in(GridDev g, SlabArgs sa) {
+  const SlabDev &S = sa.s[blockIdx.y];
+  if (S.ctl[1] == 2) return;
+  const int P = blockIdx.x;
+  const int64_t b = S.off[P], c = S.off[P + 1] - b, d = S.sb[P];
+  for (int64_t j = threadIdx.x; j < c; j += blockDim.x)
+    copy_particle<DIM>(S.xs, S.us, S.ws, S.ids, d + j, S.x, S.u, S.w, S.id, b + j);
+}
+
+// Fused step on particles [r0, r1) of the slab of patch P, in place: each
+// wave takes 64-particle blocks r0 + 64 (wv + j nw) and prefetches the next
+// block's particles while it computes the current one; every global access
+// of a full block is unconditional (a prefetch past the range reloads its
+// last particle), so the memory-counter waits stay exact.  The neighbour code
+// of each particle goes to code[].
+template <int DIM>
+__device__ __forceinline__ void ipp_slab(const GridDev &g, const SlabDev &S, const TileGeom &t,
+                                         const double *tEB, double *tJ, int P, uint32_t r0,
+                                         uint32_t r1, int &bad) {
+  const int nw = blockDim.x >> 6, lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const uint32_t sbP = (uint32_t)S.sb[P];
+  const double q = S.q, alpha = S.alpha;
+  uint32_t base = r0 + 64u * (uint32_t)wv;
+  if (base >= r1) return;
+  const uint32_t step = 64u * (uint32_t)nw;
+  auto slot = [&](uint32_t b) -> uint32_t {
+    const uint32_t i = b + (uint32_t)lane;
+    return sbP + (i < r1 ? i : r1 - 1);
+  };
+  struct PartS {
+    double x[DIM], u[3], w;
+  };
+  auto load = [&](uint32_t k, PartS &p) {
+#pragma unroll
+    for (int a = 0; a < DIM; a++) p.x[a] = at(S.xs[a], k);
+    p.u[0] = at(S.us[0], k);
+    p.u[1] = at(S.us[1], k);
+    p.u[2] = at(S.us[2], k);
+    p.w = at(S.ws, k);
+  };
+  PartS pc, pn;
+  load(slot(base), pc);
+  while (base + 64 <= r1) {
+    const uint32_t nb = base + step;
+    load(slot(nb), pn);
+    const uint32_t i = sbP + base + (uint32_t)lane;
+    double x[3], u[3];
+#pragma unroll
+    for (int a = 0; a < DIM; a++) x[a] = pc.x[a];
+    u[0] = pc.u[0];
+    u[1] = pc.u[1];
+    u[2] = pc.u[2];
+    const int code = step_particle<DIM>(g, t, tEB, tJ, q, alpha, pc.w, x, u, bad);
+#pragma unroll
+    for (int a = 0; a < DIM; a++) at(S.xs[a], i) = x[a];
+    at(S.us[0], i) = u[0];
+    at(S.us[1], i) = u[1];
+    at(S.us[2], i) = u[2];
+    at(S.code, i) = (uint8_t)code;
+    base = nb;
+    pc = pn;
+  }
+  if (base < r1) {  // partial last block
+    const uint32_t i = sbP + base + (uint32_t)lane;
+    if (base + (uint32_t)lane < r1) {
+      double x[3], u[3];
+#pragma unroll
+      for (int a = 0; a < DIM; a++) x[a] = pc.x[a];
+      u[0] = pc.u[0];
+      u[1] = pc.u[1];
+      u[2] = pc.u[2];
+      const int code = step_particle<DIM>(g, t, tEB, tJ, q, alpha, pc.w, x, u, bad);
+#pragma unroll
+      for (int a = 0; a < DIM; a++) at(S.xs[a], i) = x[a];
+      at(S.us[0], i) = u[0];
+      at(S.us[1], i) = u[1];
+      at(S.us[2], i) = u[2];
+      at(S.code, i) = (uint8_t)code;
+    }
+  }
+}
+
+// Per-patch launch: one workgroup per (patch, species).
+template <int DIM>
+__global__ void __launch_bounds__(kMaxWg<DIM>, kMinWaves<DIM>) k_ipp_slab(GridDev g, SlabArgs sa, Fields f, int *err) {
+  extern __shared__ __align__(16) double lds[];
+  const int P = blockIdx.x;
+  const SlabDev &S = sa.s[blockIdx.y];
+  if (S.ctl[1] == 2) return;
+  const TileGeom t = tile_geom<DIM>(g, P);
+  double *tEB = lds;
+  double *tJ = lds + 6 * t.TE;
+  stage_eb<DIM>(g, t, f, tEB);
+  zero_tile<DIM>(tJ, 3 * t.TJ);
+  __syncthreads();
+  int bad = 0;
+  ipp_slab<DIM>(g, S, t, tEB, tJ, P, 0u, (uint32_t)S.cnt[P], bad);
+  if (bad) atomicOr(err, bad);
+  __syncthreads();
+  flush_j<DIM>(g, t, tJ, f.j);
+}
+
+// Persistent launch: workgroups pop (patch, particle range) units of each
+// species in turn (ticket qctl[2s], count qctl[2s+1], list at units +
+// ubase); E/B is restaged and J flushed only when the patch changes.
+template <int DIM>
+__global__ void __launch_bounds__(kMaxWg<DIM>, kMinWaves<DIM>) k_ipp_slab_persistent(GridDev g, SlabArgs sa, Fields f, int *err,
+                                                                    const Unit *units, int *qctl) {
+  extern __shared__ __align__(16) double lds[];
+  __shared__ int s_unit;
+  int curP = -1;
+  TileGeom t = tile_geom<DIM>(g, 0);
+  double *tEB = lds;
+  double *tJ = lds + 6 * t.TE;
+  int bad = 0;
+  for (int s = 0; s < sa.nsp; s++) {
+    const SlabDev &S = sa.s[s];
+    if (S.ctl[1] == 2) continue;
+    const int n_units = qctl[2 * s + 1];
+    const Unit *ul = units + S.ubase;
+    for (;;) {
+      if (threadIdx.x == 0) s_unit = atomicAdd(&qctl[2 * s], 1);
+      __syncthreads();
+      const int u = __builtin_amdgcn_readfirstlane(s_unit);
+      __syncthreads();  // every thread has read s_unit before the next pop
+      if (u >= n_units) break;
+      const Unit un = ul[u];
+      if (un.P != curP) {
+        if (curP >= 0) {
+          flush_j<DIM>(g, t, tJ, f.j);
+          __syncthreads();  // flush has read the J tile before it is zeroed
+        }
+        t = tile_geom<DIM>(g, un.P);
+        stage_eb<DIM>(g, t, f, tEB);
+        zero_tile<DIM>(tJ, 3 * t.TJ);
+        __syncthreads();
+        curP = un.P;
+      }
+      ipp_slab<DIM>(g, S, t, tEB, tJ, un.P, (uint32_t)un.k0, (uint32_t)un.k1, bad);
+      __syncthreads();  // this unit's deposits are done before any flush
+    }
+  }
+  if (curP >= 0) flush_j<DIM>(g, t, tJ, f.j);
+  if (bad) atomicOr(err, bad);
+}
+
+// Exclusive prefix sum of v over a workgroup of 256 threads; total in tot.
+// Uses the 4-entry shared array w4.
+__device__ __forceinline__ int excl_sum_256(int v, int &tot, int *w4) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  int x = v;  // inclusive scan inside the wave
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  __syncthreads();
+  if (lane == 63) w4[wv] = x;
+  __syncthreads();
+  int base = 0;
+  for (int k = 0; k < wv; k++) base += w4[k];
+  tot = w4[0] + w4[1] + w4[2] + w4[3];
+  return base + x - v;
+}
+
+constexpr int kExchPer = 64;                 // slab slots per thread (fast path)
+constexpr int kExchTile = 256 * kExchPer;    // largest patch of the fast path
+constexpr int kDepList = 2048;               // most departures of the fast path
+
+// The 64 codes of this thread's slots j0 .. j0+63 as 16 words; slots at or
+// past c read as CENTER.  Slabs start on 16-slot boundaries and j0 is a
+// multiple of 64, so the 16-byte loads are aligned.
+template <int CENTER>
+__device__ __forceinline__ void load_codes(const uint8_t *code, int64_t sbP, int j0, int c,
+                                           uint32_t w[16]) {
+  if (j0 + kExchPer <= c) {
+    const uint4 *p = reinterpret_cast<const uint4 *>(code + sbP + j0);
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+      const uint4 v = p[k];
+      w[4 * k] = v.x;
+      w[4 * k + 1] = v.y;
+      w[4 * k + 2] = v.z;
+      w[4 * k + 3] = v.w;
+    }
+  } else {
+    constexpr uint32_t kC = CENTER * 0x01010101u;
+#pragma unroll
+    for (int k = 0; k < 16; k++) w[k] = kC;
+    for (int j = j0; j < c && j < j0 + kExchPer; j++) {
+      const int k = j - j0;
+      w[k >> 2] = (w[k >> 2] & ~(0xffu << (8 * (k & 3)))) | ((uint32_t)code[sbP + j] << (8 * (k & 3)));
+    }
+  }
+}
+
+__device__ __forceinline__ int code_at(const uint32_t w[16], int k) {
+  return (int)((w[k >> 2] >> (8 * (k & 3))) & 0xffu);
+}
+
+// Departures of patch P (grid: patches x species, 256 threads): the
+// particles whose code leaves the patch are copied to the patch's outbox
+// region (from sb[P]) with their destination patch; the stayers in the
+// slab's tail [c2, c) then fill the holes the departures left below
+// c2 = c - departures.  Fast path (up to 16384 particles and 2048
+// departures): every thread holds the codes of 64 consecutive slots, the
+// departures and the movers are listed in LDS and copied by all threads at
+// once, three dependent memory round trips in all.  Larger cases run each
+// thread's copies in turn.
+template <int DIM>
+__global__ void __launch_bounds__(256) k_exch_out(GridDev g, SlabArgs sa) {
+  constexpr int CENTER = DIM == 2 ? 4 : 13;
+  const SlabDev &S = sa.s[blockIdx.y];
+  const int P = blockIdx.x;
+  __shared__ int w4[4];
+  __shared__ uint32_t deps[kDepList];   // departure slot | code << 24, in slot order
+  __shared__ int movers[kDepList];      // mover slots, in slot order
+  if (S.ctl[1] == 2) return;
+  if (P == 0 && threadIdx.x == 0) S.ctl[1] = 0;  // the previous step's overflow is resolved
+  const int c = S.cnt[P];
+  const int64_t sbP = S.sb[P];
+  int pc[3];
+  patch_coords(g, P, pc);
+  uint32_t w[16];
+  int tot = 0;
+  if (c <= kExchTile) {
+    const int j0 = kExchPer * (int)threadIdx.x;
+    load_codes<CENTER>(S.code, sbP, j0, c, w);
+    int k = 0;
+#pragma unroll
+    for (int i = 0; i < kExchPer; i++) k += code_at(w, i) != CENTER;
+    int r = excl_sum_256(k, tot, w4);
+    const int m = tot;
+    if (threadIdx.x == 0) S.dep[P] = m;
+    if (m == 0) {
+      if (threadIdx.x == 0) S.cnt2[P] = c;
+      return;
+    }
+    const int c2 = c - m;
+    if (m <= kDepList) {
+      for (int i = 0; i < kExchPer && k > 0; i++) {
+        const int cd = code_at(w, i);
+        if (cd != CENTER) {
+          deps[r++] = (uint32_t)(j0 + i) | ((uint32_t)cd << 24);
+          k--;
+        }
+      }
+      int kk = 0;
+#pragma unroll
+      for (int i = 0; i < kExchPer; i++)
+        kk += j0 + i >= c2 && j0 + i < c && code_at(w, i) == CENTER;
+      int r2 = excl_sum_256(kk, tot, w4);  // also orders the deps writes before the reads
+      for (int i = 0; i < kExchPer && kk > 0; i++) {
+        const int j = j0 + i;
+        if (j >= c2 && j < c && code_at(w, i) == CENTER) {
+          movers[r2++] = j;
+          kk--;
+        }
+      }
+      __syncthreads();
+      for (int q = threadIdx.x; q < m; q += blockDim.x) {
+        const int j = (int)(deps[q] & 0xffffffu);
+        const int64_t o = sbP + q;
+        copy_particle<DIM>(S.ox, S.ou, S.ow, S.oid, o, S.xs, S.us, S.ws, S.ids, sbP + j);
+        S.odest[o] = dest_patch(g, pc, (int)(deps[q] >> 24));
+      }
+      __syncthreads();  // departures read before movers overwrite their slots
+      // the q-th mover fills the q-th departure (those below c2 come first)
+      for (int q = threadIdx.x; q < tot; q += blockDim.x) {
+        const int h = (int)(deps[q] & 0xffffffu);
+        copy_particle<DIM>(S.xs, S.us, S.ws, S.ids, sbP + h, S.xs, S.us, S.ws, S.ids,
+                           sbP + movers[q]);
+      }
+      if (threadIdx.x == 0) S.cnt2[P] = c2;
+      return;
+    }
+  }
+  // Large case: tiles of 16384 slots; each thread copies its own departures
+  // and movers in slot order.
+  int m = 0;
+  for (int t0 = 0; t0 < c; t0 += kExchTile) {
+    load_codes<CENTER>(S.code, sbP, t0 + kExchPer * (int)threadIdx.x, c, w);
+    int k = 0;
+#pragma unroll
+    for (int i = 0; i < kExchPer; i++) k += code_at(w, i) != CENTER;
+    (void)excl_sum_256(k, tot, w4);
+    m += tot;
+  }
+  if (threadIdx.x == 0) S.dep[P] = m;
+  if (m == 0) {
+    if (threadIdx.x == 0) S.cnt2[P] = c;
+    return;
+  }
+  const int c2 = c - m;
+  int run = 0;
+  for (int t0 = 0; t0 < c; t0 += kExchTile) {
+    const int j0 = t0 + kExchPer * (int)threadIdx.x;
+    load_codes<CENTER>(S.code, sbP, j0, c, w);
+    int k = 0;
+#pragma unroll
+    for (int i = 0; i < kExchPer; i++) k += code_at(w, i) != CENTER;
+    int r = run + excl_sum_256(k, tot, w4);
+    run += tot;
+    for (int i = 0; i < kExchPer && k > 0; i++) {
+      const int cd = code_at(w, i);
+      if (cd == CENTER) continue;
+      const int j = j0 + i;
+      const int64_t o = sbP + r;
+      copy_particle<DIM>(S.ox, S.ou, S.ow, S.oid, o, S.xs, S.us, S.ws, S.ids, sbP + j);
+      S.odest[o] = dest_patch(g, pc, cd);
+      if (j < c2) S.hole[sbP + r] = j;  // departures in slot order: the first lie below c2
+      r++;
+      k--;
+    }
+  }
+  __threadfence_block();
+  __syncthreads();  // departures copied and holes listed before the tail moves in
+  run = 0;
+  for (int t0 = c2 / kExchTile * kExchTile; t0 < c; t0 += kExchTile) {
+    const int j0 = t0 + kExchPer * (int)threadIdx.x;
+    load_codes<CENTER>(S.code, sbP, j0, c, w);
+    int k = 0;
+#pragma unroll
+    for (int i = 0; i < kExchPer; i++) k += j0 + i >= c2 && j0 + i < c && code_at(w, i) == CENTER;
+    int r = run + excl_sum_256(k, tot, w4);
+    run += tot;
+    for (int i = 0; i < kExchPer && k > 0; i++) {
+      const int j = j0 + i;
+      if (j < c2 || j >= c || code_at(w, i) != CENTER) continue;
+      const int h = S.hole[sbP + r];
+      copy_particle<DIM>(S.xs, S.us, S.ws, S.ids, sbP + h, S.xs, S.us, S.ws, S.ids, sbP + j);
+      r++;
+      k--;
+    }
+  }
+  if (threadIdx.x == 0) S.cnt2[P] = c2;
+}
+
+// Arrivals (grid: source patches x species): each departure of patch Q
+// takes the next free slot of its destination slab; one that finds the slab
+// full stays in the outbox, marked, and raises the overflow flag.
+template <int DIM>
+__global__ void __launch_bounds__(256) k_exch_in(GridDev g, SlabArgs sa) {
+  const SlabDev &S = sa.s[blockIdx.y];
+  if (S.ctl[1] == 2) return;
+  const int Q = blockIdx.x;
+  const int m = S.dep[Q];
+  const int64_t ob = S.sb[Q];
+  for (int r = threadIdx.x; r < m; r += blockDim.x) {
+    const int64_t e = ob + r;
+    const int D = S.odest[e];
+    const int pos = S.cnt2[D] + atomicAdd(&S.arr[D], 1);
+    if (pos < S.cap[D]) {
+      copy_particle<DIM>(S.xs, S.us, S.ws, S.ids, S.sb[D] + pos, S.ox, S.ou, S.ow, S.oid, e);
+    } else {
+      S.odest[e] = D | kUnplaced;
+      atomicOr(&S.ctl[1], 1);
+    }
+  }
+}
+
+// End of the exchange (one workgroup of 1024 per species): new counts; on
+// an overflow, a new slab plan for the counts every patch needs.
+__global__ void __launch_bounds__(1024) k_exch_fin(GridDev g, SlabArgs sa, int *err) {
+  __shared__ int64_t part[1024];
+  const SlabDev &S = sa.s[blockIdx.x];
+  const int n = g.npatch;
+  const int flag = S.ctl[1];
+  if (flag == 2) return;
+  if (flag == 0) {
+    for (int P = threadIdx.x; P < n; P += blockDim.x) {
+      S.cnt[P] = S.cnt2[P] + S.arr[P];
+      S.arr[P] = 0;
+    }
+    return;
+  }
+  for (int P = threadIdx.x; P < n; P += blockDim.x) {
+    const int64_t need = (int64_t)S.cnt2[P] + S.arr[P];
+    S.cap2[P] = (int32_t)slab_room(need);
+    S.tmp[P] = slab_room(need);
+    S.arr2[P] = 0;
+  }
+  __syncthreads();
+  block_scan_1024(S.tmp, S.sb2, n, part);
+  if (threadIdx.x == 0 && S.sb2[n] > S.capacity) {
+    S.ctl[1] = 2;  // no room for a new plan: the species stands still
+    atomicOr(err, kErrCap);
+  }
+}
+
+// Overflow, part 1 (grid: 2 x patches, x species): every
+// particle goes to its place in the new plan, inside the first buffer set.
+template <int DIM>
+__global__ void __launch_bounds__(256) k_reslab_move(GridDev g, SlabArgs sa) {
+  const SlabDev &S = sa.s[blockIdx.y];
+  if (S.ctl[1] != 1) return;
+  const int n = g.npatch;
+  if ((int)blockIdx.x < n) {
+    const int P = blockIdx.x;
+    const int placed = min(S.arr[P], S.cap[P] - S.cnt2[P]);
+    const int64_t c = (int64_t)S.cnt2[P] + placed, s0 = S.sb[P], d0 = S.sb2[P];
+    for (int64_t j = threadIdx.x; j < c; j += blockDim.x)
+      copy_particle<DIM>(S.x, S.u, S.w, S.id, d0 + j, S.xs, S.us, S.ws, S.ids, s0 + j);
+    return;
+  }
+  const int Q = blockIdx.x - n;  // the outbox of patch Q
+  const int m = S.dep[Q];
+  const int64_t ob = S.sb[Q];
+  for (int r = threadIdx.x; r < m; r += blockDim.x) {
+    const int64_t e = ob + r;
+    const int dv = S.odest[e];
+    if (!(dv & kUnplaced)) continue;
+    const int D = dv & ~kUnplaced;
+    const int placed = min(S.arr[D], S.cap[D] - S.cnt2[D]);
+    const int64_t pos = (int64_t)S.cnt2[D] + placed + atomicAdd(&S.arr2[D], 1);
+    copy_particle<DIM>(S.x, S.u, S.w, S.id, S.sb2[D] + pos, S.ox, S.ou, S.ow, S.oid, e);
+  }
+}
+
+// Overflow, part 2 (grid: patches x species): back into the slab buffers at
+// the new plan's places; the plan becomes current.
+template <int DIM>
+__global__ void __launch_bounds__(256) k_reslab_back(GridDev g, SlabArgs sa) {
+  const SlabDev &S = sa.s[blockIdx.y];
+  if (S.ctl[1] != 1) return;
+  const int P = blockIdx.x;
+  const int64_t c = (int64_t)S.cnt2[P] + S.arr[P], d0 = S.sb2[P];
+  for (int64_t j = threadIdx.x; j < c; j += blockDim.x)
+    copy_particle<DIM>(S.xs, S.us, S.ws, S.ids, d0 + j, S.x, S.u, S.w, S.id, d0 + j);
+  __syncthreads();  // every thread has read arr[P] before it is cleared
+  if (threadIdx.x == 0) {
+    S.cnt[P] = (int32_t)c;
+    S.cap[P] = S.cap2[P];
+    S.sb[P] = d0;
+    S.arr[P] = 0;
+    if (P == 0) S.sb[g.npatch] = S.sb2[g.npatch];
+  }
+}
+
+// Persistent mode: work units of chunk particles from the slab counts,
+// every species' full units first, then the remainders (one workgroup of
+// 1024 per species).
+__global__ void __launch_bounds__(1024) k_slab_units(GridDev g, SlabArgs sa, int chunk,
+                                                     Unit *units, int *qctl) {
+  __shared__ int64_t part[1024];
+  const int s = blockIdx.x;
+  const SlabDev &S = sa.s[s];
+  const int n = g.npatch;
+  for (int P = threadIdx.x; P < n; P += blockDim.x) S.tmp[P] = S.cnt[P] / chunk;
+  __syncthreads();
+  block_scan_1024(S.tmp, S.sb2, n, part);  // sb2 is free outside an overflow
+  const int64_t nfull = S.sb2[n];
+  for (int P = threadIdx.x; P < n; P += blockDim.x) {
+    const int c = S.cnt[P];
+    Unit un;
+    un.s = s;
+    un.P = P;
+    for (int j = 0; j < c / chunk; j++) {
+      un.k0 = j * chunk;
+      un.k1 = un.k0 + chunk;
+      units[S.ubase + S.sb2[P] + j] = un;
+    }
+  }
+  __syncthreads();
+  for (int P = threadIdx.x; P < n; P += blockDim.x) S.tmp[P] = S.cnt[P] % chunk != 0;
+  __syncthreads();
+  block_scan_1024(S.tmp, S.sb2, n, part);
+  for (int P = threadIdx.x; P < n; P += blockDim.x) {
+    const int c = S.cnt[P];
+    if (c % chunk) {
+      Unit un;
+      un.s = s;
+      un.P = P;
+      un.k0 = c / chunk * chunk;
+      un.k1 = c;
+      units[S.ubase + nfull + S.sb2[P]] = un;
+    }
+  }
+  if (threadIdx.x == 0) {
+    qctl[2 * s + 1] = S.ctl[1] == 2 ? 0 : (int)(nfull + S.sb2[n]);
+    qctl[2 * s] = 0;
+  }
+}
+
+// End of a call: dense offsets from the slab counts (one workgroup of 1024
+// per species) ...
+__global__ void __launch_bounds__(1024) k_slab_offsets(GridDev g, SlabArgs sa) {
+  __shared__ int64_t part[1024];
+  const SlabDev &S = sa.s[blockIdx.x];
+  if (S.ctl[1] == 2) return;
+  const int n = g.npatch;
+  for (int P = threadIdx.x; P < n; P += blockDim.x) S.tmp[P] = S.cnt[P];
+  __syncthreads();
+  block_scan_1024(S.tmp, S.off, n, part);
+}
+
+// ... and slabs -> dense (grid: patches x species).
+template <int DIM>
+__global__ void __launch_bounds__(256) k_slab_out(GridDev g, SlabArgs sa) {
+  const SlabDev &S = sa.s[blockIdx.y];
+  if (S.ctl[1] == 2) return;
+  const int P = blockIdx.x;
+  const int64_t d = S.off[P], c = S.cnt[P], b = S.sb[P];
+  for (int64_t j = threadIdx.x; j < c; j += blockDim.x)
+    copy_particle<DIM>(S.x, S.u, S.w, S.id, d + j, S.xs, S.us, S.ws, S.ids, b + j);
+}
+
+}  // namespace
+
+hipError_t launch_slab_begin(const GridDev &g, const SlabArgs &sa, int *err, hipStream_t st) {
+  hipLaunchKernelGGL(k_slab_plan, dim3(sa.nsp), dim3(1024), 0, st, g, sa, err);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (g.dim == 2)
+    hipLaunchKernelGGL(k_slab_in<2>, dim3(g.npatch, sa.nsp), dim3(256), 0, st, g, sa);
+  else
+    hipLaunchKernelGGL(k_slab_in<3>, dim3(g.npatch, sa.nsp), dim3(256), 0, st, g, sa);
+  return hipGetLastError();
+}
+
+hipError_t launch_ipp_slab(const GridDev &g, const SlabArgs &sa, const double *const e[3],
+                           const double *const b[3], double *const j[3], int *err, int wg,
+                           hipStream_t st) {
+  const Fields f = mkfields(e, b, j);
+  const size_t lds = lds_bytes_ipp(g);
+  if (g.dim == 2) {
+    hipLaunchKernelGGL(k_ipp_slab<2>, dim3(g.npatch, sa.nsp), dim3(wg), lds, st, g, sa, f, err);
+  } else {
+    (void)hipFuncSetAttribute((const void *)k_ipp_slab<3>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL(k_ipp_slab<3>, dim3(g.npatch, sa.nsp), dim3(wg), lds, st, g, sa, f, err);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_ipp_slab_persistent(const GridDev &g, const SlabArgs &sa,
+                                      const double *const e[3], const double *const b[3],
+                                      double *const j[3], int *err, const Unit *units, int *qctl,
+                                      int grid, int wg, hipStream_t st) {
+  const Fields f = mkfields(e, b, j);
+  const size_t lds = lds_bytes_ipp(g);
+  if (g.dim == 2) {
+    hipLaunchKernelGGL(k_ipp_slab_persistent<2>, dim3(grid), dim3(wg), lds, st, g, sa, f, err,
+                       units, qctl);
+  } else {
+    (void)hipFuncSetAttribute((const void *)k_ipp_slab_persistent<3>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL(k_ipp_slab_persistent<3>, dim3(grid), dim3(wg), lds, st, g, sa, f, err,
+                       units, qctl);
+  }
+  return hipGetLastError();
+}
+
+int slab_persistent_blocks_per_cu(const GridDev &g, int wg) {
+  const size_t lds = lds_bytes_ipp(g);
+  int n = 0;
+  hipError_t e;
+  if (g.dim == 2) {
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_ipp_slab_persistent<2>, wg, lds);
+  } else {
+    (void)hipFuncSetAttribute((const void *)k_ipp_slab_persistent<3>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_ipp_slab_persistent<3>, wg, lds);
+  }
+  return e == hipSuccess && n > 0 ? n : 1;
+}
+
+hipError_t launch_exchange(const GridDev &g, const SlabArgs &sa, int *err, Unit *units, int *qctl,
+                           int chunk, hipStream_t st) {
+  const dim3 pg(g.npatch, sa.nsp);
+  if (g.dim == 2) {
+    hipLaunchKernelGGL(k_exch_out<2>, pg, dim3(256), 0, st, g, sa);
+    hipLaunchKernelGGL(k_exch_in<2>, pg, dim3(256), 0, st, g, sa);
+  } else {
+    hipLaunchKernelGGL(k_exch_out<3>, pg, dim3(256), 0, st, g, sa);
+    hipLaunchKernelGGL(k_exch_in<3>, pg, dim3(256), 0, st, g, sa);
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_exch_fin, dim3(sa.nsp), dim3(1024), 0, st, g, sa, err);
+  const dim3 mg(2 * g.npatch, sa.nsp);
+  if (g.dim == 2) {
+    hipLaunchKernelGGL(k_reslab_move<2>, mg, dim3(256), 0, st, g, sa);
+    hipLaunchKernelGGL(k_reslab_back<2>, pg, dim3(256), 0, st, g, sa);
+  } else {
+    hipLaunchKernelGGL(k_reslab_move<3>, mg, dim3(256), 0, st, g, sa);
+    hipLaunchKernelGGL(k_reslab_back<3>, pg, dim3(256), 0, st, g, sa);
+  }
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if (units)
+    hipLaunchKernelGGL(k_slab_units, dim3(sa.nsp), dim3(1024), 0, st, g, sa, chunk, units, qctl);
+  return hipGetLastError();
+}
+
+hipError_t launch_slab_units(const GridDev &g, const SlabArgs &sa, int chunk, Unit *units,
+                             int *qctl, hipStream_t st) {
+  hipLaunchKernelGGL(k_slab_units, dim3(sa.nsp), dim3(1024), 0, st, g, sa, chunk, units, qctl);
+  return hipGetLastError();
+}
+
+hipError_t launch_slab_end(const GridDev &g, const SlabArgs &sa, hipStream_t st) {
+  hipLaunchKernelGGL(k_slab_offsets, dim3(sa.nsp), dim3(1024), 0, st, g, sa);
+  if (g.dim == 2)
+    hipLaunchKernelGGL(k_slab_out<2>, dim3(g.npatch, sa.nsp), dim3(256), 0, st, g, sa);
+  else
+    hipLaunchKernelGGL(k_slab_out<3>, dim3(g.npatch, sa.nsp), dim3(256), 0, st, g, sa);
+  return hipGetLastError();
+}
+
+}  // namespace pic

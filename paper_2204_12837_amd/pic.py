@@ -57,7 +57,7 @@ ENTRY_POINTS = ("pic_validate_config", "pic_num_patches", "pic_init", "pic_free"
                 "pic_interp_push", "pic_project", "pic_step", "pic_check", "pic_last_error",
                 "pic_timing_enable", "pic_timing_read", "pic_adjoint")
 KERNELS = {"zero": 0, "ipp": 1, "rebin": 2, "interp_push": 3, "project": 4, "tag": 5, "sort": 6,
-           "adjoint": 7}
+           "adjoint": 7, "exchange": 8, "slab": 9}
 
 _lib_handle = None
 
@@ -130,15 +130,22 @@ def _ptr(t: Optional[torch.Tensor]):
     return t.data_ptr() if t is not None else None
 
 
+def slab_capacity(n: int, n_patches: int) -> int:
+    """Buffer length with which pic_step keeps every patch's particles in a
+    slab with room for arrivals: n + n/8 + 80 per patch."""
+    return n + n // 8 + 80 * n_patches
+
+
 class Species:
     """One species' device arrays: two buffer sets (the sort ping-pongs
-    between them) and the patch offsets."""
+    between them; pic_step keeps its per-patch slabs in the second) and the
+    patch offsets.  The default capacity is slab_capacity(n, n_patches)."""
 
     def __init__(self, q: float, m: float, x: torch.Tensor, u: torch.Tensor, w: torch.Tensor,
                  pid: torch.Tensor, n_patches: int, capacity: Optional[int] = None):
         dev = x.device
         n = x.shape[1]
-        cap = max(n if capacity is None else int(capacity), 1)
+        cap = max(slab_capacity(n, n_patches) if capacity is None else int(capacity), 1)
         self.q, self.m, self.n, self.capacity = float(q), float(m), n, cap
         self.dim = x.shape[0]
         f64 = dict(dtype=torch.float64, device=dev)
@@ -308,13 +315,15 @@ class Context:
         return out
 
 
-def upload(inputs, device="cuda", capacity_factor: float = 1.0) -> List[Species]:
-    """Device species from generated inputs (a list of ParticleSet)."""
+def upload(inputs, device="cuda", capacity_factor: Optional[float] = None) -> List[Species]:
+    """Device species from generated inputs (a list of ParticleSet); buffers
+    of capacity_factor * n particles, or slab_capacity(n, n_patches)."""
     out = []
     npch = inputs.wl.n_patches
     for s in inputs.species:
         t = lambda a: torch.from_numpy(a).to(device)
-        cap = int(s.x.shape[1] * capacity_factor)
+        n = s.x.shape[1]
+        cap = slab_capacity(n, npch) if capacity_factor is None else int(n * capacity_factor)
         out.append(Species(s.q, s.m, t(s.x), t(s.u), t(s.wt), t(s.id), npch, capacity=cap))
     return out
 

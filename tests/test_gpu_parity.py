@@ -1,9 +1,16 @@
 """Parity of the HIP library with the CPU oracle (needs an MI355X).
 
-The bar: per-patch counts and particle order exact; particle positions and
-momenta bit for bit (the kernels repeat the oracle's operation sequence);
-J within 1e-12 of the sum of absolute contributions at each node (the only
-difference is the order of the float64 atomic additions)."""
+The bar: per-patch counts exact; the same particles in every patch, in the
+oracle's (stable) order in the dense layout and by id in the slab layout,
+where the order inside a patch is arbitrary; particle positions and momenta
+bit for bit (the kernels repeat the oracle's operation sequence); J within
+1e-12 of the sum of absolute contributions at each node (the only difference
+is the order of the float64 atomic additions).
+
+Layouts: calls of three steps or more keep the particles in per-patch slabs
+when the buffers have room for them (the default capacity); with buffers of
+exactly n particles (capacity factor 1) every call uses the dense layout and
+the permutation sort."""
 import numpy as np
 import pytest
 
@@ -13,14 +20,24 @@ from _parity import compare, run_gpu, run_oracle, say
 
 pytestmark = pytest.mark.gpu
 
+LAYOUTS = {"slab": dict(capacity_factor=None, exact_order=False),
+           "dense": dict(capacity_factor=1.0, exact_order=True)}
 
-def test_uniform64_ten_steps():
+
+def run_cmp(wl, inp, steps, layout, osp, J, A, **kw):
+    lay = LAYOUTS[layout]
+    g, Jg = run_gpu(wl, inp, steps, capacity_factor=lay["capacity_factor"], **kw)
+    compare(osp, J, A, g, Jg, exact_order=lay["exact_order"])
+    return g, Jg
+
+
+@pytest.mark.parametrize("layout", list(LAYOUTS))
+def test_uniform64_ten_steps(layout):
     wl = I.workload("uniform64")
     inp = I.generate(wl)
-    say("case uniform64, 10 steps, fused")
+    say(f"case uniform64, 10 steps, fused, {layout}")
     osp, J, A = run_oracle(wl, inp, 10)
-    g, Jg = run_gpu(wl, inp, 10)
-    compare(osp, J, A, g, Jg)
+    run_cmp(wl, inp, 10, layout, osp, J, A)
 
 
 def test_split_path_equals_oracle():
@@ -29,7 +46,7 @@ def test_split_path_equals_oracle():
     say("case uniform64, 3 steps, split interp_push / project / bin")
     osp, J, A = run_oracle(wl, inp, 3)
     g, Jg = run_gpu(wl, inp, 3, split=True)
-    compare(osp, J, A, g, Jg)
+    compare(osp, J, A, g, Jg, exact_order=True)
 
 
 @pytest.mark.parametrize("wg", [64, 128, 192])
@@ -54,15 +71,15 @@ CASES = [
 ]
 
 
+@pytest.mark.parametrize("layout", list(LAYOUTS))
 @pytest.mark.parametrize("case", CASES)
-def test_random_small_configs(case):
+def test_random_small_configs(case, layout):
     dim, n, patch, ppc, nsp, sigma, steps, seed = case
     wl = I.custom(dim, n, patch, ppc=ppc, seed=seed, sigma=sigma, n_species=nsp)
     inp = I.generate(wl)
-    say(f"case {case}")
+    say(f"case {case} {layout}")
     osp, J, A = run_oracle(wl, inp, steps)
-    g, Jg = run_gpu(wl, inp, steps)
-    compare(osp, J, A, g, Jg)
+    run_cmp(wl, inp, steps, layout, osp, J, A)
 
 
 def test_general_sort_from_any_order():
@@ -77,7 +94,7 @@ def test_general_sort_from_any_order():
     say("case unsorted bin")
     osp, _, _ = run_oracle(wl, inp, 0)
     g, _ = run_gpu(wl, inp, 0)
-    compare(osp, None, None, g, None)
+    compare(osp, None, None, g, None, exact_order=True)
 
 
 def test_edge_positions():
@@ -98,8 +115,8 @@ def test_edge_positions():
     s.u[:, :k] = 0.0  # stay on the boundary in a zero-momentum start
     say("case edges")
     osp, J, A = run_oracle(wl, inp, 4)
-    g, Jg = run_gpu(wl, inp, 4)
-    compare(osp, J, A, g, Jg)
+    for layout in LAYOUTS:
+        run_cmp(wl, inp, 4, layout, osp, J, A)
 
 
 def test_empty_and_crowded_patches():
@@ -110,18 +127,19 @@ def test_empty_and_crowded_patches():
     inp = I.generate(wl)
     say("case empty/crowded patches")
     osp, J, A = run_oracle(wl, inp, 5)
-    g, Jg = run_gpu(wl, inp, 5)
-    compare(osp, J, A, g, Jg)
+    for layout in LAYOUTS:
+        run_cmp(wl, inp, 5, layout, osp, J, A)
 
 
 def test_zero_steps_and_zero_particles():
     wl = I.custom(2, (16, 16), (8, 8), ppc=0, seed=140)
     inp = I.generate(wl)
     say("case no particles")
-    osp, J, A = run_oracle(wl, inp, 2)
-    g, Jg = run_gpu(wl, inp, 2)
-    compare(osp, J, A, g, Jg)
-    assert np.all(Jg == 0)
+    for steps in (2, 4):
+        osp, J, A = run_oracle(wl, inp, steps)
+        g, Jg = run_gpu(wl, inp, steps)
+        compare(osp, J, A, g, Jg)
+        assert np.all(Jg == 0)
 
 
 PERSISTENT_CASES = [
@@ -134,17 +152,17 @@ PERSISTENT_CASES = [
 ]
 
 
+@pytest.mark.parametrize("layout", list(LAYOUTS))
 @pytest.mark.parametrize("case", PERSISTENT_CASES)
-def test_persistent_matches_oracle(case):
+def test_persistent_matches_oracle(case, layout):
     """The persistent work-queue launch (units of `chunk` particles) gives
-    the same particles, order and counts, and J within the bar."""
+    the same particles and counts, and J within the bar."""
     dim, n, patch, ppc, nsp, sigma, steps, seed, chunk, wg = case
     wl = I.custom(dim, n, patch, ppc=ppc, seed=seed, sigma=sigma, n_species=nsp)
     inp = I.generate(wl)
-    say(f"case persistent {case}")
+    say(f"case persistent {case} {layout}")
     osp, J, A = run_oracle(wl, inp, steps)
-    g, Jg = run_gpu(wl, inp, steps, mode=1, chunk=chunk, wg_size=wg)
-    compare(osp, J, A, g, Jg)
+    run_cmp(wl, inp, steps, layout, osp, J, A, mode=1, chunk=chunk, wg_size=wg)
 
 
 def test_persistent_imbalanced_profile():
@@ -155,18 +173,39 @@ def test_persistent_imbalanced_profile():
     say("case persistent imbalanced")
     osp, J, A = run_oracle(wl, inp, 4)
     for chunk in (256, 2048):
-        g, Jg = run_gpu(wl, inp, 4, mode=1, chunk=chunk)
-        compare(osp, J, A, g, Jg)
+        for layout in LAYOUTS:
+            run_cmp(wl, inp, 4, layout, osp, J, A, mode=1, chunk=chunk)
+
+
+@pytest.mark.parametrize("layout", list(LAYOUTS))
+@pytest.mark.parametrize("mode", [0, 1])
+def test_graph_replay_matches_oracle(mode, layout):
+    """Steps replayed from captured graphs (slab steps, or pairs of dense
+    steps), interleaved with eager steps and host synchronisations, agree
+    with the oracle after every call sequence."""
+    wl = I.custom(2, (48, 32), (8, 8), ppc=5, seed=300 + mode, sigma=0.2)
+    inp = I.generate(wl)
+    say(f"case graph mode={mode} {layout}")
+    osp, J, A = run_oracle(wl, inp, 11)
+    run_cmp(wl, inp, 11, layout, osp, J, A, mode=mode, chunk=512, graph=True,
+            step_sizes=[4, 1, 2, 3, 1])
 
 
 @pytest.mark.parametrize("mode", [0, 1])
-def test_graph_replay_matches_oracle(mode):
-    """Steps replayed from captured graphs (pairs of steps), interleaved
-    with eager odd steps and host synchronisations, agree with the oracle
-    after every call sequence."""
-    wl = I.custom(2, (48, 32), (8, 8), ppc=5, seed=300 + mode, sigma=0.2)
+def test_slab_overflow_replans(mode):
+    """A drifting half-box beam floods initially empty patches faster than
+    their slab room (64 slots) allows: the device re-plans the slabs inside
+    the call and no particle is lost or misplaced."""
+    wl = I.custom(2, (64, 32), (8, 8), ppc=1, seed=310 + mode, sigma=0.05, bz0=0.0)
+    wl.species[0].ppc = lambda ix: np.where(ix < 32, 16, 0).astype(np.int64)
     inp = I.generate(wl)
-    say(f"case graph mode={mode}")
-    osp, J, A = run_oracle(wl, inp, 11)
-    g, Jg = run_gpu(wl, inp, 11, mode=mode, chunk=512, graph=True, step_sizes=[4, 1, 2, 3, 1])
-    compare(osp, J, A, g, Jg)
+    inp.species[0].u[0] += 0.7
+    steps = 6
+    osp, J, A = run_oracle(wl, inp, steps)
+    counts = np.diff(osp[0].off)
+    say(f"case slab overflow mode={mode}: max patch count {counts.max()}")
+    # patches of the empty half that now hold more than an empty slab's room
+    npx = wl.n[0] // wl.patch[0]
+    px = np.arange(counts.size) % npx
+    assert counts[px >= npx // 2].max() > 64
+    run_cmp(wl, inp, steps, "slab", osp, J, A, mode=mode, chunk=256)
