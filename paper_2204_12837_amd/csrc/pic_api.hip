@@ -46,7 +46,9 @@ struct SlabScratch {
   int32_t *odest = nullptr;
 };
 
-constexpr size_t kStaticLds = 2 * 4 * 27 * 4 + 27 * 4 + 64;  // ranking scratch + slack
+// Static LDS of the fused kernels beside the tiles: the slab-layout kernel's
+// departure bitmap and prefix (2 x 2048 words) plus control words and slack.
+constexpr size_t kStaticLds = 2 * 2048 * 4 + 256;
 
 }  // namespace
 

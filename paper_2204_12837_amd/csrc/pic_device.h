@@ -458,73 +458,65 @@ __device__ __forceinline__ TileGeom tile_geom(const GridDev &g, int P) {
   return t;
 }
 
-// Walks a (component, z, y, x) tile in flat order with stride blockDim
-// without per-element divisions: the start index and the stride are split
-// into coordinates once, then advanced with at most one carry per axis.
-struct TileWalk {
-  int c, k, j, i;      // current coordinates
-  int dc, dk, dj, di;  // the stride in coordinates
-  int nx, ny, nz;
+// Global index of node r of a tile of extents tx, ty (x fastest) whose first
+// node sits at org (periodic wrap into the grid).
+template <int DIM>
+__device__ __forceinline__ int64_t tile_node(const GridDev &g, const int org[3], int r, int tx,
+                                             int ty) {
+  const int txy = tx * ty;
+  const int k = DIM == 3 ? r / txy : 0;
+  const int rr = r - k * txy;
+  const int j = rr / tx;
+  const int i = rr - j * tx;
+  const int gx = wrap_near(org[0] + i, g.n[0]);
+  const int gy = wrap_near(org[1] + j, g.n[1]);
+  const int gz = DIM == 3 ? wrap_near(org[2] + k, g.n[2]) : 0;
+  return ((int64_t)gz * g.n[1] + gy) * g.n[0] + gx;
+}
 
-  __device__ TileWalk(int start, int stride, int nx_, int ny_, int nz_)
-      : nx(nx_), ny(ny_), nz(nz_) {
-    split(start, c, k, j, i);
-    split(stride, dc, dk, dj, di);
-  }
-  __device__ void split(int v, int &c_, int &k_, int &j_, int &i_) const {
-    const int plane = nx * ny, vol = plane * nz;
-    c_ = v / vol;
-    v -= c_ * vol;
-    k_ = v / plane;
-    v -= k_ * plane;
-    j_ = v / nx;
-    i_ = v - j_ * nx;
-  }
-  __device__ void next() {
-    i += di;
-    if (i >= nx) {
-      i -= nx;
-      j++;
-    }
-    j += dj;
-    if (j >= ny) {
-      j -= ny;
-      k++;
-    }
-    k += dk;
-    if (k >= nz) {
-      k -= nz;
-      c++;
-    }
-    c += dc;
-  }
-};
+// Stage the E/B tile: each thread takes up to kStageNodes nodes at a time
+// and issues the loads of all six components before any LDS store, so the
+// staging costs one memory round trip per batch (the component loop is
+// uniform: the field pointers stay in scalar registers).
+constexpr int kStageNodes = 4;
 
 template <int DIM>
 __device__ void stage_eb(const GridDev &g, const TileGeom &t, const Fields &f, double *tile) {
-  const int Ty = t.Txy / t.Tx, Tz = t.TE / t.Txy;
-  TileWalk w(threadIdx.x, blockDim.x, t.Tx, Ty, Tz);
-  for (int idx = threadIdx.x; idx < 6 * t.TE; idx += blockDim.x, w.next()) {
-    const int r = idx - w.c * t.TE;
-    const int gx = wrap_near(t.org[0] + w.i, g.n[0]);
-    const int gy = wrap_near(t.org[1] + w.j, g.n[1]);
-    const int gz = DIM == 3 ? wrap_near(t.org[2] + w.k, g.n[2]) : 0;
-    const double *F = w.c < 3 ? f.e[w.c] : f.b[w.c - 3];
-    const double v = F[((int64_t)gz * g.n[1] + gy) * g.n[0] + gx];
-    if constexpr (DIM == 2) {
-      // Ex -> pair 0 .x, By -> pair 0 .y, Ey -> pair 1 .x, Bx -> pair 1 .y
-      int at;
-      switch (w.c) {
-        case 0: at = 2 * r; break;
-        case 4: at = 2 * r + 1; break;
-        case 1: at = 2 * t.TE + 2 * r; break;
-        case 3: at = 2 * t.TE + 2 * r + 1; break;
-        case 2: at = 4 * t.TE + r; break;
-        default: at = 5 * t.TE + r; break;
+  const int Ty = t.Txy / t.Tx;
+  const int nt = blockDim.x;
+  for (int b0 = 0; b0 < t.TE; b0 += kStageNodes * nt) {
+    int64_t gi[kStageNodes];
+    int rr[kStageNodes];
+#pragma unroll
+    for (int k = 0; k < kStageNodes; k++) {
+      rr[k] = b0 + (int)threadIdx.x + k * nt;
+      gi[k] = rr[k] < t.TE ? tile_node<DIM>(g, t.org, rr[k], t.Tx, Ty) : 0;
+    }
+    double v[6][kStageNodes];
+#pragma unroll
+    for (int c = 0; c < 6; c++) {
+      const double *F = c < 3 ? f.e[c] : f.b[c - 3];
+      // unconditional loads (a node past the tile reads grid node 0), so
+      // the memory-counter waits need not assume a skipped load
+#pragma unroll
+      for (int k = 0; k < kStageNodes; k++) v[c][k] = F[gi[k]];
+    }
+#pragma unroll
+    for (int k = 0; k < kStageNodes; k++) {
+      const int r = rr[k];
+      if (r >= t.TE) continue;
+      if constexpr (DIM == 2) {
+        // (Ex, By) pairs, (Ey, Bx) pairs, Ez, Bz
+        tile[2 * r] = v[0][k];
+        tile[2 * r + 1] = v[4][k];
+        tile[2 * t.TE + 2 * r] = v[1][k];
+        tile[2 * t.TE + 2 * r + 1] = v[3][k];
+        tile[4 * t.TE + r] = v[2][k];
+        tile[5 * t.TE + r] = v[5][k];
+      } else {
+#pragma unroll
+        for (int c = 0; c < 6; c++) tile[c * t.TE + r] = v[c][k];
       }
-      tile[at] = v;
-    } else {
-      tile[idx] = v;
     }
   }
 }
@@ -534,17 +526,22 @@ __device__ void zero_tile(double *tJ, int n) {
   for (int idx = threadIdx.x; idx < n; idx += blockDim.x) tJ[idx] = 0.0;
 }
 
+// Add the J tile into the grid with one global atomic per nonzero entry;
+// the component loop is uniform, so the grid pointers stay in scalar
+// registers and no global load precedes the atomics.
 template <int DIM>
 __device__ void flush_j(const GridDev &g, const TileGeom &t, const double *tJ, double *const j[3]) {
-  const int Jy = t.Jxy / t.Jx, Jz = t.TJ / t.Jxy;
-  TileWalk w(threadIdx.x, blockDim.x, t.Jx, Jy, Jz);
-  for (int idx = threadIdx.x; idx < 3 * t.TJ; idx += blockDim.x, w.next()) {
-    const double v = tJ[idx];
-    if (v == 0.0) continue;
-    const int gx = wrap_near(t.org2[0] + w.i, g.n[0]);
-    const int gy = wrap_near(t.org2[1] + w.j, g.n[1]);
-    const int gz = DIM == 3 ? wrap_near(t.org2[2] + w.k, g.n[2]) : 0;
-    glb_add(j[w.c] + ((int64_t)gz * g.n[1] + gy) * g.n[0] + gx, v);
+  const int Jy = t.Jxy / t.Jx;
+  const int nt = blockDim.x;
+#pragma unroll
+  for (int c = 0; c < 3; c++) {
+    double *J = j[c];
+    const double *T = tJ + c * t.TJ;
+    for (int r = threadIdx.x; r < t.TJ; r += nt) {
+      const double v = T[r];
+      if (v == 0.0) continue;
+      glb_add(J + tile_node<DIM>(g, t.org2, r, t.Jx, Jy), v);
+    }
   }
 }
 

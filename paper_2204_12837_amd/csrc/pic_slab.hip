@@ -91,7 +91,8 @@ __global__ void __launch_bounds__(256) k_slab_in(GridDev g, SlabArgs sa) {
 template <int DIM>
 __device__ __forceinline__ void ipp_slab(const GridDev &g, const SlabDev &S, const TileGeom &t,
                                          const double *tEB, double *tJ, int P, uint32_t r0,
-                                         uint32_t r1, int &bad) {
+                                         uint32_t r1, int &bad, uint32_t *bits) {
+  constexpr int CENTER = DIM == 2 ? 4 : 13;
   const int nw = blockDim.x >> 6, lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   const uint32_t sbP = (uint32_t)S.sb[P];
@@ -133,6 +134,10 @@ __device__ __forceinline__ void ipp_slab(const GridDev &g, const SlabDev &S, con
     at(S.us[1], i) = u[1];
     at(S.us[2], i) = u[2];
     at(S.code, i) = (uint8_t)code;
+    if (bits && __ballot(code != CENTER)) {  // mark departures (slab-relative slot)
+      const uint32_t j = base + (uint32_t)lane;
+      if (code != CENTER) atomicOr(&bits[j >> 5], 1u << (j & 31));
+    }
     base = nb;
     pc = pn;
   }
@@ -152,28 +157,140 @@ __device__ __forceinline__ void ipp_slab(const GridDev &g, const SlabDev &S, con
       at(S.us[1], i) = u[1];
       at(S.us[2], i) = u[2];
       at(S.code, i) = (uint8_t)code;
+      if (bits && code != CENTER) {
+        const uint32_t j = base + (uint32_t)lane;
+        atomicOr(&bits[j >> 5], 1u << (j & 31));
+      }
     }
   }
 }
 
+constexpr int kBitSlots = 16384;           // largest patch whose departures the fused
+constexpr int kBitWords = kBitSlots / 32;  // kernel handles itself
+
+// Exclusive prefix sum of v over the workgroup (any size up to 1024, a
+// multiple of 64); total in tot.  wtot: 16 shared ints.
+__device__ __forceinline__ int block_excl_sum(int v, int &tot, int *wtot) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  int x = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  __syncthreads();
+  if (lane == 63) wtot[wv] = x;
+  __syncthreads();
+  int base = 0, all = 0;
+  for (int k = 0; k < nw; k++) {
+    const int t = wtot[k];
+    if (k < wv) base += t;
+    all += t;
+  }
+  tot = all;
+  return base + x - v;
+}
+
+// Departures of patch P handled by the fused kernel's workgroup after its
+// particle loop: `bits` marks the departing slots, `pre` receives the
+// departures before each bitmap word.  Copies the departures to the outbox
+// region (in slot order) and refills the holes below c2 = c - departures
+// with the stayers of [c2, c): the q-th stayer of the tail takes the slot of
+// the q-th departure.
+template <int DIM>
+__device__ void depart_in_kernel(const GridDev &g, const SlabDev &S, int P, int c,
+                                 const uint32_t *bits, int *pre, int *wtot) {
+  const int64_t sbP = S.sb[P];
+  const int nt = blockDim.x;
+  const int W = (c + 31) >> 5;
+  const int per = (W + nt - 1) / nt;
+  const int w0 = min(W, (int)threadIdx.x * per), w1 = min(W, w0 + per);
+  int k = 0;
+  for (int i = w0; i < w1; i++) k += __popc(bits[i]);
+  int m = 0;
+  int r = block_excl_sum(k, m, wtot);
+  for (int i = w0; i < w1; i++) {
+    pre[i] = r;
+    r += __popc(bits[i]);
+  }
+  if (threadIdx.x == 0) S.dep[P] = m;
+  if (m == 0) {
+    if (threadIdx.x == 0) S.cnt2[P] = c;
+    return;
+  }
+  const int c2 = c - m;
+  int pc[3];
+  patch_coords(g, P, pc);
+  for (int i = w0; i < w1; i++) {
+    uint32_t b = bits[i];
+    int rr = pre[i];
+    while (b) {
+      const int j = 32 * i + __ffs(b) - 1;
+      b &= b - 1;
+      const int64_t o = sbP + rr++;
+      copy_particle<DIM>(S.ox, S.ou, S.ow, S.oid, o, S.xs, S.us, S.ws, S.ids, sbP + j);
+      S.odest[o] = dest_patch(g, pc, (int)S.code[sbP + j]);
+    }
+  }
+  __syncthreads();  // pre[] complete, departures read before the holes are refilled
+  int qrun = 0, tot = 0;
+  for (int j0 = c2; j0 < c; j0 += nt) {
+    const int j = j0 + (int)threadIdx.x;
+    const bool stay = j < c && !((bits[j >> 5] >> (j & 31)) & 1u);
+    const int q = qrun + block_excl_sum(stay ? 1 : 0, tot, wtot);
+    qrun += tot;
+    if (stay) {
+      // the q-th departure: word i with pre[i] <= q < pre[i + 1], then its bit
+      int lo = 0, hi = W - 1;
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (pre[mid] <= q)
+          lo = mid;
+        else
+          hi = mid - 1;
+      }
+      uint32_t b = bits[lo];
+      for (int d = q - pre[lo]; d > 0; d--) b &= b - 1;
+      const int h = 32 * lo + __ffs(b) - 1;
+      copy_particle<DIM>(S.xs, S.us, S.ws, S.ids, sbP + h, S.xs, S.us, S.ws, S.ids, sbP + j);
+    }
+  }
+  if (threadIdx.x == 0) S.cnt2[P] = c2;
+}
+
+// Waves per SIMD the per-patch kernel's registers allow (four in 2D: five,
+// at 96 registers, measured slower).
+template <int DIM>
+constexpr int kSlabMinWaves = DIM == 2 ? 4 : 2;
+
 // Per-patch launch: one workgroup per (patch, species).
 template <int DIM>
-__global__ void __launch_bounds__(kMaxWg<DIM>, kMinWaves<DIM>) k_ipp_slab(GridDev g, SlabArgs sa, Fields f, int *err) {
+__global__ void __launch_bounds__(kMaxWg<DIM>, kSlabMinWaves<DIM>) k_ipp_slab(GridDev g, SlabArgs sa, Fields f, int *err) {
   extern __shared__ __align__(16) double lds[];
+  __shared__ uint32_t bits[kBitWords];
+  __shared__ int pre[kBitWords];
+  __shared__ int wtot[16];
   const int P = blockIdx.x;
   const SlabDev &S = sa.s[blockIdx.y];
   if (S.ctl[1] == 2) return;
   const TileGeom t = tile_geom<DIM>(g, P);
   double *tEB = lds;
   double *tJ = lds + 6 * t.TE;
+  const int c = S.cnt[P];
+  const bool mark = c <= kBitSlots;
   stage_eb<DIM>(g, t, f, tEB);
   zero_tile<DIM>(tJ, 3 * t.TJ);
+  for (int k = threadIdx.x; k < kBitWords; k += blockDim.x) bits[k] = 0u;
   __syncthreads();
   int bad = 0;
-  ipp_slab<DIM>(g, S, t, tEB, tJ, P, 0u, (uint32_t)S.cnt[P], bad);
+  ipp_slab<DIM>(g, S, t, tEB, tJ, P, 0u, (uint32_t)c, bad, mark ? bits : nullptr);
   if (bad) atomicOr(err, bad);
   __syncthreads();
   flush_j<DIM>(g, t, tJ, f.j);
+  if (mark)
+    depart_in_kernel<DIM>(g, S, P, c, bits, pre, wtot);
+  else if (threadIdx.x == 0)
+    S.dep[P] = -1;  // left to the departures kernel
 }
 
 // Persistent launch: workgroups pop (patch, particle range) units of each
@@ -212,7 +329,7 @@ __global__ void __launch_bounds__(kMaxWg<DIM>, kMinWaves<DIM>) k_ipp_slab_persis
         __syncthreads();
         curP = un.P;
       }
-      ipp_slab<DIM>(g, S, t, tEB, tJ, un.P, (uint32_t)un.k0, (uint32_t)un.k1, bad);
+      ipp_slab<DIM>(g, S, t, tEB, tJ, un.P, (uint32_t)un.k0, (uint32_t)un.k1, bad, nullptr);
       __syncthreads();  // this unit's deposits are done before any flush
     }
   }
@@ -274,7 +391,8 @@ __device__ __forceinline__ int code_at(const uint32_t w[16], int k) {
   return (int)((w[k >> 2] >> (8 * (k & 3))) & 0xffu);
 }
 
-// Departures of patch P (grid: patches x species, 256 threads): the
+// Departures of patch P (grid: patches x species, 256 threads; with
+// only_marked, only the patches the fused kernel left, dep[P] < 0): the
 // particles whose code leaves the patch are copied to the patch's outbox
 // region (from sb[P]) with their destination patch; the stayers in the
 // slab's tail [c2, c) then fill the holes the departures left below
@@ -284,7 +402,7 @@ __device__ __forceinline__ int code_at(const uint32_t w[16], int k) {
 // once, three dependent memory round trips in all.  Larger cases run each
 // thread's copies in turn.
 template <int DIM>
-__global__ void __launch_bounds__(256) k_exch_out(GridDev g, SlabArgs sa) {
+__global__ void __launch_bounds__(256) k_exch_out(GridDev g, SlabArgs sa, int only_marked) {
   constexpr int CENTER = DIM == 2 ? 4 : 13;
   const SlabDev &S = sa.s[blockIdx.y];
   const int P = blockIdx.x;
@@ -293,6 +411,7 @@ __global__ void __launch_bounds__(256) k_exch_out(GridDev g, SlabArgs sa) {
   __shared__ int movers[kDepList];      // mover slots, in slot order
   if (S.ctl[1] == 2) return;
   if (P == 0 && threadIdx.x == 0) S.ctl[1] = 0;  // the previous step's overflow is resolved
+  if (only_marked && S.dep[P] >= 0) return;     // done by the fused kernel
   const int c = S.cnt[P];
   const int64_t sbP = S.sb[P];
   int pc[3];
@@ -644,11 +763,12 @@ int slab_persistent_blocks_per_cu(const GridDev &g, int wg) {
 hipError_t launch_exchange(const GridDev &g, const SlabArgs &sa, int *err, Unit *units, int *qctl,
                            int chunk, hipStream_t st) {
   const dim3 pg(g.npatch, sa.nsp);
+  const int only_marked = units ? 0 : 1;  // the per-patch fused kernel did the departures
   if (g.dim == 2) {
-    hipLaunchKernelGGL(k_exch_out<2>, pg, dim3(256), 0, st, g, sa);
+    hipLaunchKernelGGL(k_exch_out<2>, pg, dim3(256), 0, st, g, sa, only_marked);
     hipLaunchKernelGGL(k_exch_in<2>, pg, dim3(256), 0, st, g, sa);
   } else {
-    hipLaunchKernelGGL(k_exch_out<3>, pg, dim3(256), 0, st, g, sa);
+    hipLaunchKernelGGL(k_exch_out<3>, pg, dim3(256), 0, st, g, sa, only_marked);
     hipLaunchKernelGGL(k_exch_in<3>, pg, dim3(256), 0, st, g, sa);
   }
   hipError_t e = hipGetLastError();
