@@ -2,14 +2,16 @@
 """Throughput of the PIC macro-particle step on one MI355X.
 
 One step = J <- 0, the fused Interpolation + Push + pre-BC + Projection of
-every particle, and the sort by patch (the synchronisation phase), i.e. one
-`pic_step`.  Inputs are generated (seeded, synthetic) and resident in HBM
-before the timed region starts.
+every particle (in place, in per-patch slabs), and the exchange of the
+particles that changed patch (the synchronisation phase); the timed
+`pic_step` call of `--steps` steps also includes its one-off copies from the
+dense sorted layout into the slabs and back.  Inputs are generated (seeded,
+synthetic) and resident in HBM before the timed region starts.
 
-Prints one JSON line: particle-steps/s of the whole step, the roofline of
-the dominant kernel (the fused step kernel, HBM-bound), the imbalanced
-workload next to the uniform one, and the CPU oracle timed on a bounded
-sample on the host.
+Prints one JSON line: particle-steps/s of the whole call, the roofline of
+the dominant kernel (the fused step kernel, HBM-bound by its bytes), the
+imbalanced workload next to the uniform one, the 3D two-species and adjoint
+workloads, and the CPU oracle timed on a bounded sample on the host.
 """
 from __future__ import annotations
 
@@ -38,9 +40,12 @@ def algorithmic_bytes(wl, n_particles: int) -> int:
     return per_particle * n_particles + per_cell * wl.n_cells
 
 
+FUSED_KERNEL = "k_ipp_slab"  # the fused step kernel of a pic_step call of several steps
+
+
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("pic_kernels.hip", "pic_common.h"):
+    for f in ("pic_slab.hip", "pic_device.h", "pic_common.h"):
         with open(os.path.join(ROOT, "paper_2204_12837_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -49,7 +54,7 @@ def kernel_source_hash() -> str:
 def measured_traffic(workload: str):
     """HBM bytes per launch of the fused kernel from the committed rocprofv3
     counter summary, if it was taken on the current kernel source."""
-    path = os.path.join(ROOT, "profiles", f"k_ipp_{workload}_traffic.json")
+    path = os.path.join(ROOT, "profiles", f"{FUSED_KERNEL}_{workload}_traffic.json")
     try:
         with open(path) as fh:
             t = json.load(fh)
@@ -275,10 +280,10 @@ def main(argv=None) -> int:
         "data": "synthetic",
         "config": {"workload": args.workload, "dim": wl.dim, "cells": list(wl.n[:wl.dim]),
                    "patch": list(wl.patch[:wl.dim]), "particles": n,
-                   "species": len(wl.species), "mode": "per_patch"},
+                   "species": len(wl.species), "mode": "per_patch", "layout": "slab"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "k_ipp", "algorithmic_bytes": abytes, "avg_ms": ipp_avg},
+                     "kernel": FUSED_KERNEL, "algorithmic_bytes": abytes, "avg_ms": ipp_avg},
         "kernel_ms": per_kernel,
         "interp_push_project_rate": n / (ipp_avg * 1e-3),
     }
