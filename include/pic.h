@@ -66,9 +66,11 @@ enum { PIC_MODE_PER_PATCH = 0, PIC_MODE_PERSISTENT = 1 };
 
 enum {
   PIC_FLAG_CHECK = 1, /* every call waits for its stream and reports device errors */
-  PIC_FLAG_GRAPH = 2  /* pic_step replays a captured HIP graph of two steps (the
-                         buffer swap makes two steps the period); the graph is
-                         recaptured when any array pointer or count changes */
+  PIC_FLAG_GRAPH = 2  /* pic_step replays a captured HIP graph of its steps
+                         (one step in the slab layout, two in the dense one,
+                         whose buffer swap makes two steps the period); the
+                         graph is recaptured when any array pointer or count
+                         changes */
 };
 
 typedef struct {
@@ -150,15 +152,28 @@ pic_status pic_interp_push(pic_ctx *ctx, pic_species *sp, int32_t nsp, const pic
 pic_status pic_project(pic_ctx *ctx, const pic_species *sp, int32_t nsp, pic_fields *f,
                        void *stream);
 
-/* nsteps whole steps: J <- 0, then the fused Interpolation, Push, pre-BC
- * and Projection of every species (J accumulated in on-chip tiles per patch
- * and added to the grid), then the sort.  Equals the sequence {zero J;
- * pic_interp_push; pic_project; pic_bin} per step.  J holds the last
- * step's current.  Particles must be sorted (offset[] valid, e.g. by
- * pic_bin on this context).  In persistent mode the fused kernel runs on a
- * fixed grid that pulls (patch, chunk) units from a device queue built by the
- * sort.  With PIC_FLAG_GRAPH (and timing off) pairs of steps replay a
- * captured HIP graph. */
+/* nsteps whole steps (paper, section "Parallelization without tasks": the
+ * per-patch operators, then the synchronisation phase): J <- 0, then the
+ * fused Interpolation, Push, pre-BC and Projection of every species (J
+ * accumulated in on-chip tiles per patch and added to the grid), then the
+ * particles regrouped by patch.  Equals the sequence {zero J;
+ * pic_interp_push; pic_project; pic_bin} per step, up to the order of the
+ * particles inside a patch.  J holds the last step's current.  Particles
+ * must be sorted (offset[] valid, e.g. by pic_bin on this context); on
+ * return they are sorted again, in the first buffer set or the second
+ * (follow the pointers in sp).
+ *
+ * Layout: with nsteps >= 3 and, for every species, capacity >=
+ * n + n/8 + 80 * (number of patches) and capacity < 2^29, the call keeps the
+ * particles in per-patch slabs of the second buffer set, updates them in
+ * place and moves only those that change patch; the order inside a patch is
+ * then arbitrary and the result is in the first set.  Otherwise every step
+ * sorts by neighbour code (stable: the order inside a patch is the previous
+ * order).  In persistent mode the fused kernel runs on a fixed grid that pulls
+ * (patch, particle range) units from a device queue.  With PIC_FLAG_GRAPH
+ * (and timing off) the steps replay a captured HIP graph (one step in the
+ * slab layout, two otherwise).  The context owns an outbox of capacity
+ * particles per species for the slab layout. */
 pic_status pic_step(pic_ctx *ctx, pic_species *sp, int32_t nsp, pic_fields *f, int32_t nsteps,
                     void *stream);
 
