@@ -166,9 +166,10 @@ def run_adjoint(every: int = 5):
     s = inp.species[0]
     dev = "cuda:0"
     times = []
+    ctx = None  # one context for every repetition: its scratch and graphs stay warm
     for rep in range(3):
         run = ADJ.StepRun(wl, torch.from_numpy(s.x).to(dev), torch.from_numpy(s.wt).to(dev),
-                          torch.from_numpy(s.id).to(dev), s.q, s.m, wl.steps, every)
+                          torch.from_numpy(s.id).to(dev), s.q, s.m, wl.steps, every, ctx=ctx)
         u0 = torch.from_numpy(s.u).to(dev).requires_grad_(True)
         E = torch.from_numpy(inp.E).to(dev).requires_grad_(True)
         B = torch.from_numpy(inp.B).to(dev).requires_grad_(True)
@@ -182,6 +183,7 @@ def run_adjoint(every: int = 5):
         torch.cuda.synchronize()
         t2 = time.perf_counter()
         run.ctx.check()
+        ctx = run.ctx
         times.append((t1 - t0, t2 - t1))
     fw, bw = min(times, key=lambda t: t[0] + t[1])
     n = s.x.shape[1]

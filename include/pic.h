@@ -87,7 +87,8 @@ typedef struct {
   int32_t chunk;       /* persistent mode: particles per work unit, a multiple
                           of 256 (0 = auto: 2048) */
   int32_t wg_size;     /* threads per workgroup, a multiple of 64 up to 256 in
-                          2D and 512 in 3D (0 = auto: 256 in 2D, 512 in 3D) */
+                          2D and 1024 in 3D (0 = auto: 256 in 2D, 1024 in 3D);
+                          the dense-layout kernels use at most 512 in 3D */
   uint32_t flags;      /* PIC_FLAG_* */
 } pic_config;
 

@@ -33,16 +33,17 @@ class StepRun:
 
 
 def _clone_live(s: pic.Species) -> pic.Species:
-    """A checkpoint: an independent copy of the live particles."""
-    c = pic.Species(s.q, s.m, s.xs.clone(), s.us.clone(), s.ws.clone(), s.ids.clone(),
-                    s.offset.numel() - 1)
+    """A checkpoint: an independent copy of the live particles (buffers of
+    exactly n particles: pic_adjoint only reads them)."""
+    c = pic.Species(s.q, s.m, s.xs, s.us, s.ws, s.ids, s.offset.numel() - 1, capacity=s.n)
+    c.offset.copy_(s.offset)
     return c
 
 
 def forward(run: StepRun, u0: torch.Tensor, E: torch.Tensor, B: torch.Tensor):
     """nsteps steps from (x0, u0); returns (J_final, checkpoints) where the
     checkpoints are the particle states at steps 0, every, 2*every, ..."""
-    ctx = run.ctx or pic.Context(run.wl, mode=run.mode)
+    ctx = run.ctx or pic.Context(run.wl, mode=run.mode, graph=True)
     run.ctx = ctx
     sp = pic.Species(run.q, run.m, run.x0, u0.detach(), run.w, run.ids,
                      ctx.n_patches)

@@ -22,7 +22,7 @@ from . import pic
 
 CHUNKS = (512, 1024, 2048, 4096, 8192)
 WGS = (128, 256)
-WGS_3D = (256, 512)
+WGS_3D = (512, 1024)
 
 
 def cache_path() -> str:

@@ -451,6 +451,246 @@ __global__ void __launch_bounds__(128) k_adjoint(GridDev g, AdjArgs aa, AdjField
   S.ub[2][id] = ub[2];
 }
 
+// ---------------------------------------------------------------------------
+// Tiled variant: one workgroup per (patch, species) of a checkpoint sorted
+// by patch.  The fields and their cotangents live in LDS tiles covering the
+// patch plus everything a particle starting in it can reach in the segment
+// (nsteps cells, the Courant limit, plus the stencil), so the interpolation,
+// its adjoint and the scatter of the field cotangents stay on chip; the
+// cotangent tile is added to the grid once at the end.  A stencil that does
+// not lie inside the tile (a particle outside its patch) falls back to the
+// global arrays, so the result never depends on the sort.
+struct ATile {
+  int org[2];   // first tile node (unwrapped grid index)
+  int T;        // tile extent per axis
+  const double *F;  // 6 component tiles
+  double *Fb;       // 6 cotangent tiles
+};
+
+// Tile offset of grid node i along axis a (periodic), or -1 if outside.
+__device__ __forceinline__ int tile_off(const GridDev &g, const ATile &t, int a, int i) {
+  int d = i - t.org[a];
+  if (d < 0) d += g.n[a];
+  if (d >= g.n[a]) d -= g.n[a];
+  return d < t.T ? d : -1;
+}
+
+__device__ __forceinline__ double gather_t(const GridDev &g, const ATile &t, int c,
+                                           const double *Fg, const Ax &ax, const Ax &ay) {
+  const int dx = tile_off(g, t, 0, ax.i0), dy = tile_off(g, t, 1, ay.i0);
+  if (dx < 0 || dy < 0 || dx + 2 >= t.T || dy + 2 >= t.T) return gather_g(g, Fg, ax, ay);
+  const double *r = t.F + c * t.T * t.T + dy * t.T + dx;
+  double rr[3];
+#pragma unroll
+  for (int b = 0; b < 3; b++) {
+    double v = ax.S[0] * r[0];
+    v = v + ax.S[1] * r[1];
+    v = v + ax.S[2] * r[2];
+    rr[b] = v;
+    r += t.T;
+  }
+  double v = ay.S[0] * rr[0];
+  v = v + ay.S[1] * rr[1];
+  v = v + ay.S[2] * rr[2];
+  return v;
+}
+
+__device__ __forceinline__ void interp_t(const GridDev &g, const ATile &t, const AdjFields &f,
+                                         const double x[2], double F[6]) {
+  const double xi = x[0] * g.inv_d[0], yi = x[1] * g.inv_d[1];
+  const Ax x0 = axis_at(xi, 0), x1 = axis_at(xi, 1), y0 = axis_at(yi, 0), y1 = axis_at(yi, 1);
+#pragma unroll
+  for (int c = 0; c < 6; c++)
+    F[c] = gather_t(g, t, c, f.f[c], kStagX[c] ? x1 : x0, kStagY[c] ? y1 : y0);
+}
+
+__device__ __forceinline__ void interp_adj_t(const GridDev &g, const ATile &t, const AdjFields &f,
+                                             const double x[2], const double Fb[6],
+                                             double xb[2]) {
+  const double xi = x[0] * g.inv_d[0], yi = x[1] * g.inv_d[1];
+  const Ax x0 = axis_at(xi, 0), x1 = axis_at(xi, 1), y0 = axis_at(yi, 0), y1 = axis_at(yi, 1);
+  double gx = 0.0, gy = 0.0;
+#pragma unroll
+  for (int c = 0; c < 6; c++) {
+    const Ax &ax = kStagX[c] ? x1 : x0;
+    const Ax &ay = kStagY[c] ? y1 : y0;
+    const double fb = Fb[c];
+    const int dx = tile_off(g, t, 0, ax.i0), dy = tile_off(g, t, 1, ay.i0);
+    if (dx < 0 || dy < 0 || dx + 2 >= t.T || dy + 2 >= t.T) {
+      // outside the tile: global reads and atomics (one component)
+      const double *F = f.f[c];
+      double *Fbg = f.fb[c];
+#pragma unroll
+      for (int b = 0; b < 3; b++) {
+        const int row = wrap_near_a(ay.i0 + b, g.n[1]) * g.n[0];
+#pragma unroll
+        for (int a = 0; a < 3; a++) {
+          const int at = row + wrap_near_a(ax.i0 + a, g.n[0]);
+          const double v = F[at];
+          gx += fb * ax.D[a] * ay.S[b] * v;
+          gy += fb * ax.S[a] * ay.D[b] * v;
+          if (fb != 0.0) glb_add_a(Fbg + at, fb * ax.S[a] * ay.S[b]);
+        }
+      }
+      continue;
+    }
+    const int base = c * t.T * t.T + dy * t.T + dx;
+#pragma unroll
+    for (int b = 0; b < 3; b++) {
+#pragma unroll
+      for (int a = 0; a < 3; a++) {
+        const int at = base + b * t.T + a;
+        const double v = t.F[at];
+        gx += fb * ax.D[a] * ay.S[b] * v;
+        gy += fb * ax.S[a] * ay.D[b] * v;
+        if (fb != 0.0)
+          __hip_atomic_fetch_add(t.Fb + at, fb * ax.S[a] * ay.S[b], __ATOMIC_RELAXED,
+                                 __HIP_MEMORY_SCOPE_WORKGROUP);
+      }
+    }
+  }
+  xb[0] += gx * g.inv_d[0];
+  xb[1] += gy * g.inv_d[1];
+}
+
+// Tile extent for a segment of nsteps steps: the patch, nsteps cells each
+// side (Courant limit), the stencil's reach (one node below, two above).
+__host__ __device__ constexpr int adj_tile_extent(int p, int nsteps) { return p + 2 * nsteps + 5; }
+
+template <int NS>
+__global__ void __launch_bounds__(256) k_adjoint_tiled(GridDev g, AdjArgs aa, AdjFields f,
+                                                       int with_dep, int *err) {
+  extern __shared__ __align__(16) double lds[];
+  const AdjSp &S = aa.s[blockIdx.y];
+  const int P = blockIdx.x;
+  const int px = P % g.np[0], py = P / g.np[0];
+  ATile t;
+  t.T = adj_tile_extent(g.patch[0], NS);  // square patches checked on the host
+  t.org[0] = px * g.patch[0] - NS - 2;
+  t.org[1] = py * g.patch[1] - NS - 2;
+  const int TT = t.T * t.T;
+  double *tf = lds, *tb = lds + 6 * TT;
+  t.F = tf;
+  t.Fb = tb;
+  for (int r = threadIdx.x; r < TT; r += blockDim.x) {
+    const int j = r / t.T, i = r - j * t.T;
+    int gx = t.org[0] + i, gy = t.org[1] + j;
+    gx = ((gx % g.n[0]) + g.n[0]) % g.n[0];
+    gy = ((gy % g.n[1]) + g.n[1]) % g.n[1];
+    const int64_t at = (int64_t)gy * g.n[0] + gx;
+#pragma unroll
+    for (int c = 0; c < 6; c++) {
+      tf[c * TT + r] = f.f[c][at];
+      tb[c * TT + r] = 0.0;
+    }
+  }
+  __syncthreads();
+  const int64_t beg = S.off[P], end = S.off[P + 1];
+  int bad = 0;
+  for (int64_t p = beg + threadIdx.x; p < end; p += blockDim.x) {
+    const int64_t id = S.id[p];
+    if (id < 0 || id >= S.nid) {
+      bad |= kErrPos;
+      continue;
+    }
+    double xs[NS][2], us[NS][3];
+    double x[2] = {S.x[0][p], S.x[1][p]};
+    double u[3] = {S.u[0][p], S.u[1][p], S.u[2][p]};
+    double xlast[2] = {0, 0}, xend[2] = {0, 0}, vend[3] = {0, 0, 0};
+#pragma unroll
+    for (int k = 0; k < NS; k++) {
+      xs[k][0] = x[0];
+      xs[k][1] = x[1];
+      us[k][0] = u[0];
+      us[k][1] = u[1];
+      us[k][2] = u[2];
+      double F[6], v[3];
+      interp_t(g, t, f, x, F);
+      boris_f(S.alpha, F, u, v);
+      double x1[2] = {x[0] + g.dt * v[0], x[1] + g.dt * v[1]};
+      if (k == NS - 1) {
+        xlast[0] = x[0];
+        xlast[1] = x[1];
+        xend[0] = x1[0];
+        xend[1] = x1[1];
+        vend[0] = v[0];
+        vend[1] = v[1];
+        vend[2] = v[2];
+      }
+      wrap2(g, x1);
+      x[0] = x1[0];
+      x[1] = x1[1];
+    }
+    double xb[2], ub[3], vzb = 0.0;
+    if (with_dep) {
+      double x0b[2] = {0, 0}, x1b[2] = {0, 0};
+      if (!deposit_adj(g, f, S.q * S.w[p], xlast, xend, vend[2], x0b, x1b, vzb)) {
+        bad |= kErrCFL;
+        continue;
+      }
+      xb[0] = x1b[0];
+      xb[1] = x1b[1];
+      ub[0] = ub[1] = ub[2] = 0.0;
+      x[0] = x0b[0];
+      x[1] = x0b[1];
+    } else {
+      xb[0] = S.xb[0][id];
+      xb[1] = S.xb[1][id];
+      ub[0] = S.ub[0][id];
+      ub[1] = S.ub[1][id];
+      ub[2] = S.ub[2][id];
+      x[0] = x[1] = 0.0;
+    }
+#pragma unroll
+    for (int k = NS - 1; k >= 0; k--) {
+      double F[6];
+      interp_t(g, t, f, xs[k], F);
+      double vb[3] = {g.dt * xb[0], g.dt * xb[1], 0.0};
+      if (with_dep && k == NS - 1) vb[2] += vzb;
+      double Fb[6];
+      boris_adj(S.alpha, F, us[k], ub, vb, Fb);
+      double xprev[2] = {xb[0], xb[1]};
+      if (with_dep && k == NS - 1) {
+        xprev[0] += x[0];
+        xprev[1] += x[1];
+      }
+      interp_adj_t(g, t, f, xs[k], Fb, xprev);
+      xb[0] = xprev[0];
+      xb[1] = xprev[1];
+    }
+    S.xb[0][id] = xb[0];
+    S.xb[1][id] = xb[1];
+    S.ub[0][id] = ub[0];
+    S.ub[1][id] = ub[1];
+    S.ub[2][id] = ub[2];
+  }
+  if (bad) atomicOr(err, bad);
+  __syncthreads();
+  for (int r = threadIdx.x; r < TT; r += blockDim.x) {
+    const int j = r / t.T, i = r - j * t.T;
+    int gx = t.org[0] + i, gy = t.org[1] + j;
+    gx = ((gx % g.n[0]) + g.n[0]) % g.n[0];
+    gy = ((gy % g.n[1]) + g.n[1]) % g.n[1];
+    const int64_t at = (int64_t)gy * g.n[0] + gx;
+#pragma unroll
+    for (int c = 0; c < 6; c++) {
+      const double v = tb[c * TT + r];
+      if (v != 0.0) glb_add_a(f.fb[c] + at, v);
+    }
+  }
+}
+
+template <int NS>
+void launch_tiled(const GridDev &g, const AdjArgs &aa, const AdjFields &f, int with_dep, int *err,
+                  hipStream_t st) {
+  const int T = adj_tile_extent(g.patch[0], NS);
+  const size_t lds = (size_t)12 * T * T * sizeof(double);
+  (void)hipFuncSetAttribute((const void *)k_adjoint_tiled<NS>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  hipLaunchKernelGGL(k_adjoint_tiled<NS>, dim3(g.npatch, aa.nsp), dim3(256), lds, st, g, aa, f,
+                     with_dep, err);
+}
+
 }  // namespace
 
 hipError_t launch_adjoint(const GridDev &g, const AdjArgs &aa, const double *const e[3],
@@ -464,6 +704,26 @@ hipError_t launch_adjoint(const GridDev &g, const AdjArgs &aa, const double *con
     f.jb[c] = jb ? jb[c] : nullptr;
     f.fb[c] = eb[c];
     f.fb[3 + c] = bb[c];
+  }
+  // tiled when every species brings its patch offsets, patches are square
+  // and the two tiles fit in LDS with the grid at least a tile wide
+  bool tiled = g.dim == 2 && g.patch[0] == g.patch[1];
+  for (int s = 0; s < aa.nsp; s++) tiled = tiled && aa.s[s].off != nullptr;
+  const int T = adj_tile_extent(g.patch[0], nsteps);
+  tiled = tiled && (size_t)12 * T * T * sizeof(double) <= 150 * 1024 && g.n[0] >= T &&
+          g.n[1] >= T;
+  if (tiled) {
+    switch (nsteps) {
+      case 1: launch_tiled<1>(g, aa, f, with_dep, err, st); break;
+      case 2: launch_tiled<2>(g, aa, f, with_dep, err, st); break;
+      case 3: launch_tiled<3>(g, aa, f, with_dep, err, st); break;
+      case 4: launch_tiled<4>(g, aa, f, with_dep, err, st); break;
+      case 5: launch_tiled<5>(g, aa, f, with_dep, err, st); break;
+      case 6: launch_tiled<6>(g, aa, f, with_dep, err, st); break;
+      case 7: launch_tiled<7>(g, aa, f, with_dep, err, st); break;
+      default: launch_tiled<8>(g, aa, f, with_dep, err, st); break;
+    }
+    return hipGetLastError();
   }
   int64_t nmax = 1;
   for (int s = 0; s < aa.nsp; s++) nmax = std::max<int64_t>(nmax, aa.s[s].n);

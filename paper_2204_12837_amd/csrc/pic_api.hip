@@ -77,7 +77,8 @@ struct pic_ctx {
   hipStream_t cap_stream = nullptr;  // stream used only to capture graphs
   GridDev g;
   int device = 0;
-  int wg = 256;
+  int wg = 256;           // threads per workgroup of the slab-layout kernels
+  int wgd = 256;          // ... of the dense-layout kernels (at most 512 in 3D)
   int *err_dev = nullptr;
   bool poisoned = false;
   bool moved = false;   // pic_interp_push ran since the last sort
@@ -381,8 +382,8 @@ hipError_t enqueue_step(pic_ctx *c, const pic_species *sp, int32_t nsp, const pi
   if (e == hipSuccess)
     e = timed(c, PIC_KERNEL_IPP, st, [&] {
       return pers ? launch_ipp_persistent(c->g, a, f->e, f->b, f->j, c->err_dev, c->units,
-                                          c->qctl, c->pgrid, c->wg, st)
-                  : launch_ipp(c->g, a, f->e, f->b, f->j, c->err_dev, c->wg, st);
+                                          c->qctl, c->pgrid, c->wgd, st)
+                  : launch_ipp(c->g, a, f->e, f->b, f->j, c->err_dev, c->wgd, st);
     });
   if (e != hipSuccess) return e;
   // the sort reads the particles where the fused kernel wrote them
@@ -763,7 +764,7 @@ pic_status pic_validate_config(const pic_config *c, char *msg, size_t len) {
     set_msg(msg, len, "chunk must be 0 (auto) or a positive multiple of %d", kSeg);
     return PIC_ERR_ARG;
   }
-  const int wg_max = c->dim == 2 ? 256 : 512;
+  const int wg_max = c->dim == 2 ? 256 : 1024;
   if (c->wg_size != 0 && (c->wg_size < 64 || c->wg_size > wg_max || c->wg_size % 64)) {
     set_msg(msg, len, "wg_size must be 0 or a multiple of 64 in [64, %d]", wg_max);
     return PIC_ERR_ARG;
@@ -804,7 +805,8 @@ pic_status pic_init(const pic_config *cfg, int32_t device, pic_ctx **out) {
   }
   c->g = make_grid(&c->cfg);
   c->device = device;
-  c->wg = cfg->wg_size ? cfg->wg_size : (c->cfg.dim == 2 ? 256 : 512);
+  c->wg = cfg->wg_size ? cfg->wg_size : (c->cfg.dim == 2 ? 256 : 1024);
+  c->wgd = std::min(c->wg, c->cfg.dim == 2 ? 256 : 512);
   const int chunk = cfg->chunk ? cfg->chunk : 2048;
   c->g.spc = std::max(1, chunk / kSeg);
   if (hipMalloc(&c->err_dev, sizeof(int)) != hipSuccess ||
@@ -816,7 +818,7 @@ pic_status pic_init(const pic_config *cfg, int32_t device, pic_ctx **out) {
     delete c;
     return PIC_ERR_HIP;
   }
-  if (c->cfg.mode == PIC_MODE_PERSISTENT) c->pgrid = persistent_grid(c->g, c->wg);
+  if (c->cfg.mode == PIC_MODE_PERSISTENT) c->pgrid = persistent_grid(c->g, c->wgd);
   *out = c;
   return PIC_OK;
 }
@@ -920,7 +922,7 @@ pic_status pic_bin(pic_ctx *c, pic_species *sp, int32_t nsp, void *stream) {
     if ((r = ensure_scratch(c, sp, nsp, false, st)) != PIC_OK) return r;
     const SpArgs a = make_args(c, sp, nsp);
     hipError_t e =
-        timed(c, PIC_KERNEL_TAG, st, [&] { return launch_tag(c->g, a, c->err_dev, c->wg, st); });
+        timed(c, PIC_KERNEL_TAG, st, [&] { return launch_tag(c->g, a, c->err_dev, c->wgd, st); });
     if (e == hipSuccess)
       e = timed(c, PIC_KERNEL_REBIN, st, [&] {
         return launch_rebin(c->g, a, c->err_dev, max_segments(c, nsp), false, st);
@@ -958,7 +960,7 @@ pic_status pic_interp_push(pic_ctx *c, pic_species *sp, int32_t nsp, const pic_f
   if ((r = ensure_scratch(c, sp, nsp, true, st)) != PIC_OK) return r;
   const SpArgs a = make_args(c, sp, nsp);
   hipError_t e = timed(c, PIC_KERNEL_INTERP_PUSH, st, [&] {
-    return launch_interp_push(c->g, a, f->e, f->b, c->err_dev, c->wg, st);
+    return launch_interp_push(c->g, a, f->e, f->b, c->err_dev, c->wgd, st);
   });
   if (e != hipSuccess) return hip_fail(c, e, "kernel launch");
   c->moved = true;
@@ -977,7 +979,7 @@ pic_status pic_project(pic_ctx *c, const pic_species *sp, int32_t nsp, pic_field
   if (hipSetDevice(c->device) != hipSuccess) return fail(c, PIC_ERR_HIP, "hipSetDevice");
   const SpArgs a = make_args(c, sp, nsp);
   hipError_t e = timed(c, PIC_KERNEL_PROJECT, st,
-                       [&] { return launch_project(c->g, a, f->j, c->err_dev, c->wg, st); });
+                       [&] { return launch_project(c->g, a, f->j, c->err_dev, c->wgd, st); });
   if (e != hipSuccess) return hip_fail(c, e, "kernel launch");
   return finish(c, st);
 }
@@ -1064,6 +1066,7 @@ pic_status pic_adjoint(pic_ctx *c, const pic_species *ck, int32_t nsp, const pic
     }
     d.w = p.w;
     d.id = p.id;
+    d.off = p.offset;
   }
   hipStream_t st = (hipStream_t)stream;
   if (hipSetDevice(c->device) != hipSuccess) return fail(c, PIC_ERR_HIP, "hipSetDevice");

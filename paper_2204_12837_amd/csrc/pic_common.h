@@ -121,6 +121,7 @@ struct AdjSp {
   int64_t nid;      // length of the cotangent arrays (ids lie in [0, nid))
   const double *x[3], *u[3], *w;
   const int64_t *id;
+  const int64_t *off;     // [npatch+1] patch offsets if the checkpoint is sorted, else null
   double *xb[3], *ub[3];  // cotangents of the state, indexed by id
 };
 

@@ -265,7 +265,7 @@ constexpr int kSlabMinWaves = DIM == 2 ? 4 : 2;
 
 // Per-patch launch: one workgroup per (patch, species).
 template <int DIM>
-__global__ void __launch_bounds__(kMaxWg<DIM>, kSlabMinWaves<DIM>) k_ipp_slab(GridDev g, SlabArgs sa, Fields f, int *err) {
+__global__ void __launch_bounds__(kMaxWgSlab<DIM>, kSlabMinWaves<DIM>) k_ipp_slab(GridDev g, SlabArgs sa, Fields f, int *err) {
   extern __shared__ __align__(16) double lds[];
   __shared__ uint32_t bits[kBitWords];
   __shared__ int pre[kBitWords];
@@ -297,7 +297,7 @@ __global__ void __launch_bounds__(kMaxWg<DIM>, kSlabMinWaves<DIM>) k_ipp_slab(Gr
 // species in turn (ticket qctl[2s], count qctl[2s+1], list at units +
 // ubase); E/B is restaged and J flushed only when the patch changes.
 template <int DIM>
-__global__ void __launch_bounds__(kMaxWg<DIM>, kMinWaves<DIM>) k_ipp_slab_persistent(GridDev g, SlabArgs sa, Fields f, int *err,
+__global__ void __launch_bounds__(kMaxWgSlab<DIM>, kSlabMinWaves<DIM>) k_ipp_slab_persistent(GridDev g, SlabArgs sa, Fields f, int *err,
                                                                     const Unit *units, int *qctl) {
   extern __shared__ __align__(16) double lds[];
   __shared__ int s_unit;

@@ -54,6 +54,14 @@ def test_valid_configs_pass():
     assert pic.lib().pic_num_patches(C.byref(pic.make_config(I.workload("expansion3d")))) == 8192
 
 
+def test_workgroup_limits_per_dimension():
+    """Up to 256 threads in 2D, 1024 in 3D (multiples of 64)."""
+    wl3 = I.custom(3, (16, 16, 16), (8, 8, 8), ppc=1)
+    for wg, ok in ((1024, True), (576, True), (1088, False), (1000, False)):
+        rc, msg = pic.validate(pic.make_config(wl3, wg_size=wg))
+        assert (rc == pic.PIC_OK) == ok, (wg, msg)
+
+
 @pytest.mark.parametrize("over,frag", [
     (dict(dim=4), "dim"),
     (dict(shape_order=1), "shape_order"),
