@@ -141,3 +141,31 @@ def test_checkpoint_interval_does_not_change_gradients():
         got = _gpu_grads(wl, inp, x, every)
         for a, b in zip(ref[1:], got[1:]):
             assert np.max(np.abs(a - b)) <= 1e-12 * np.abs(a).max()
+
+
+def test_tiled_adjoint_falls_back_outside_its_tile():
+    """The tiled backward kernel keeps every stencil that leaves its patch's
+    tile on the global path: with checkpoint offsets that put every particle
+    in patch 0, almost all stencils lie outside patch 0's tile, and the
+    gradients still equal the ones of the correctly sorted checkpoints."""
+    wl = I.custom(2, (48, 48), (8, 8), ppc=3, seed=420, sigma=0.05, bz0=1.0, steps=6)
+    inp = I.generate(wl, with_W=True)
+    s, x = _setup(wl, inp)
+    dev = "cuda:0"
+    run = ADJ.StepRun(wl, torch.from_numpy(x).to(dev), torch.from_numpy(s.wt).to(dev),
+                      torch.from_numpy(s.id).to(dev), s.q, s.m, wl.steps, 3)
+    u0 = torch.from_numpy(s.u).to(dev)
+    E = torch.from_numpy(inp.E).to(dev).contiguous()
+    B = torch.from_numpy(inp.B).to(dev).contiguous()
+    W = torch.from_numpy(inp.W).to(dev).contiguous()
+    J, ckpts = ADJ.forward(run, u0, E, B)
+    say("case tiled adjoint fallback")
+    du, dE, dB = ADJ.backward(run, ckpts, E, B, W)
+    for c in ckpts:
+        c.offset[1:] = c.n  # every particle claimed by patch 0
+    du2, dE2, dB2 = ADJ.backward(run, ckpts, E, B, W)
+    torch.cuda.synchronize()
+    run.ctx.check()
+    for a, b in ((du, du2), (dE, dE2), (dB, dB2)):
+        a, b = a.cpu().numpy(), b.cpu().numpy()
+        assert np.max(np.abs(a - b)) <= 1e-12 * max(np.abs(a).max(), 1e-300)
