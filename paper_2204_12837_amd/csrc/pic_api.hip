@@ -844,8 +844,8 @@ void pic_free(pic_ctx *c) {
     free_sort_scratch(c->sort[s]);
     SlabScratch &L = c->slab[s];
     for (void *p : {(void *)L.sb, (void *)L.sb2, (void *)L.room, (void *)L.room2, (void *)L.cnt,
-                    (void *)L.cnt2, (void *)L.arr, (void *)L.arr2, (void *)L.dep, (void *)L.ctl, (void *)L.ow,
-                    (void *)L.oid, (void *)L.odest})
+                    (void *)L.cnt2, (void *)L.arr, (void *)L.arr2, (void *)L.dep,
+                    (void *)L.ctl, (void *)L.ow, (void *)L.oid, (void *)L.odest})
       (void)hipFree(p);
     for (int a = 0; a < 3; a++) {
       (void)hipFree(L.ox[a]);

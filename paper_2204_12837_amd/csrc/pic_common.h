@@ -104,8 +104,9 @@ hipError_t launch_ipp_slab_persistent(const GridDev &g, const SlabArgs &sa,
                                       double *const j[3], int *err, const Unit *units,
                                       int *qctl, int grid, int wg, hipStream_t st);
 int slab_persistent_blocks_per_cu(const GridDev &g, int wg);
-// Departures, arrivals, counts (and, on an overflow, a new slab plan); with
-// units != nullptr also the next step's work units of chunk particles.
+// Departures left by the fused kernel, arrivals, counts (and, on an
+// overflow, a new slab plan); with units != nullptr (persistent mode) also
+// the next step's work units of chunk particles.
 hipError_t launch_exchange(const GridDev &g, const SlabArgs &sa, int *err, Unit *units,
                            int *qctl, int chunk, hipStream_t st);
 hipError_t launch_slab_units(const GridDev &g, const SlabArgs &sa, int chunk, Unit *units,

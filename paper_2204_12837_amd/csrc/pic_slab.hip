@@ -48,6 +48,47 @@ __device__ __forceinline__ void copy_particle(double *const dx[3], double *const
   did[d] = sid[s];
 }
 
+// Copies particles src + j -> dst + j for j in [0, c), four per thread at a
+// time (all loads of a batch before its stores).
+template <int DIM>
+__device__ __forceinline__ void copy_run(double *const dx[3], double *const du[3], double *dw,
+                                         int64_t *did, int64_t d0, const double *const sx[3],
+                                         const double *const su[3], const double *sw,
+                                         const int64_t *sid, int64_t s0, int64_t c) {
+  constexpr int kB = 4;
+  const int64_t nt = blockDim.x;
+  for (int64_t j0 = threadIdx.x; j0 < c; j0 += kB * nt) {
+    double x[kB][DIM], u[kB][3], w[kB];
+    int64_t id[kB];
+#pragma unroll
+    for (int b = 0; b < kB; b++) {
+      const int64_t j = j0 + b * nt;
+      if (j < c) {
+#pragma unroll
+        for (int a = 0; a < DIM; a++) x[b][a] = sx[a][s0 + j];
+        u[b][0] = su[0][s0 + j];
+        u[b][1] = su[1][s0 + j];
+        u[b][2] = su[2][s0 + j];
+        w[b] = sw[s0 + j];
+        id[b] = sid[s0 + j];
+      }
+    }
+#pragma unroll
+    for (int b = 0; b < kB; b++) {
+      const int64_t j = j0 + b * nt;
+      if (j < c) {
+#pragma unroll
+        for (int a = 0; a < DIM; a++) dx[a][d0 + j] = x[b][a];
+        du[0][d0 + j] = u[b][0];
+        du[1][d0 + j] = u[b][1];
+        du[2][d0 + j] = u[b][2];
+        dw[d0 + j] = w[b];
+        did[d0 + j] = id[b];
+      }
+    }
+  }
+}
+
 // Slab plan from the dense offsets (one workgroup of 1024 per species).
 __global__ void __launch_bounds__(1024) k_slab_plan(GridDev g, SlabArgs sa, int *err) {
   __shared__ int64_t part[1024];
@@ -77,9 +118,8 @@ __global__ void __launch_bounds__(256) k_slab_in(GridDev g, SlabArgs sa) {
   const SlabDev &S = sa.s[blockIdx.y];
   if (S.ctl[1] == 2) return;
   const int P = blockIdx.x;
-  const int64_t b = S.off[P], c = S.off[P + 1] - b, d = S.sb[P];
-  for (int64_t j = threadIdx.x; j < c; j += blockDim.x)
-    copy_particle<DIM>(S.xs, S.us, S.ws, S.ids, d + j, S.x, S.u, S.w, S.id, b + j);
+  const int64_t b = S.off[P], c = S.off[P + 1] - b;
+  copy_run<DIM>(S.xs, S.us, S.ws, S.ids, S.sb[P], S.x, S.u, S.w, S.id, b, c);
 }
 
 // Fused step on particles [r0, r1) of the slab of patch P, in place: each
@@ -167,6 +207,8 @@ __device__ __forceinline__ void ipp_slab(const GridDev &g, const SlabDev &S, con
 
 constexpr int kBitSlots = 16384;           // largest patch whose departures the fused
 constexpr int kBitWords = kBitSlots / 32;  // kernel handles itself
+constexpr int kExchBitSlots = 65536;       // the departures kernel's bitmap path
+constexpr int kExchBitWords = kExchBitSlots / 32;
 
 // Exclusive prefix sum of v over the workgroup (any size up to 1024, a
 // multiple of 64); total in tot.  wtot: 16 shared ints.
@@ -356,9 +398,8 @@ __device__ __forceinline__ int excl_sum_256(int v, int &tot, int *w4) {
   return base + x - v;
 }
 
-constexpr int kExchPer = 64;                 // slab slots per thread (fast path)
-constexpr int kExchTile = 256 * kExchPer;    // largest patch of the fast path
-constexpr int kDepList = 2048;               // most departures of the fast path
+constexpr int kExchPer = 64;               // slab slots per thread and tile
+constexpr int kExchTile = 256 * kExchPer;  // slots per tile of the large-patch path
 
 // The 64 codes of this thread's slots j0 .. j0+63 as 16 words; slots at or
 // past c read as CENTER.  Slabs start on 16-slot boundaries and j0 is a
@@ -391,85 +432,62 @@ __device__ __forceinline__ int code_at(const uint32_t w[16], int k) {
   return (int)((w[k >> 2] >> (8 * (k & 3))) & 0xffu);
 }
 
+// Departure bitmap of a slab of c <= kExchBitSlots particles from its code
+// bytes: bit j of word j/32 set if slot j leaves the patch.  Slabs start on
+// 16-slot boundaries, so the 16-byte loads are aligned; the last word's
+// loads stay inside the slab's room (at least c + 64 slots).
+template <int CENTER>
+__device__ __forceinline__ void code_bits(const uint8_t *code, int c, uint32_t *bits) {
+  constexpr uint32_t kC = CENTER * 0x01010101u;
+  const int W = (c + 31) >> 5;
+  for (int i = threadIdx.x; i < W; i += blockDim.x) {
+    const uint4 *p = reinterpret_cast<const uint4 *>(code) + 2 * i;
+    const uint4 a = p[0], b = p[1];
+    const uint32_t v[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+    uint32_t m = 0;
+#pragma unroll
+    for (int k = 0; k < 8; k++) {
+      const uint32_t d = v[k] ^ kC;  // zero byte: code CENTER
+#pragma unroll
+      for (int y = 0; y < 4; y++) m |= (uint32_t)(((d >> (8 * y)) & 0xffu) != 0u) << (4 * k + y);
+    }
+    const int valid = c - 32 * i;
+    bits[i] = valid >= 32 ? m : m & ((1u << valid) - 1u);
+  }
+}
+
 // Departures of patch P (grid: patches x species, 256 threads; with
 // only_marked, only the patches the fused kernel left, dep[P] < 0): the
 // particles whose code leaves the patch are copied to the patch's outbox
 // region (from sb[P]) with their destination patch; the stayers in the
 // slab's tail [c2, c) then fill the holes the departures left below
-// c2 = c - departures.  Fast path (up to 16384 particles and 2048
-// departures): every thread holds the codes of 64 consecutive slots, the
-// departures and the movers are listed in LDS and copied by all threads at
-// once, three dependent memory round trips in all.  Larger cases run each
-// thread's copies in turn.
+// c2 = c - departures.  Up to kExchBitSlots particles: the departure
+// bitmap in LDS and the fused kernel's epilogue.  Larger patches: tiles of
+// 16384 slots, each thread copying its own departures and movers in turn.
 template <int DIM>
 __global__ void __launch_bounds__(256) k_exch_out(GridDev g, SlabArgs sa, int only_marked) {
   constexpr int CENTER = DIM == 2 ? 4 : 13;
   const SlabDev &S = sa.s[blockIdx.y];
   const int P = blockIdx.x;
   __shared__ int w4[4];
-  __shared__ uint32_t deps[kDepList];   // departure slot | code << 24, in slot order
-  __shared__ int movers[kDepList];      // mover slots, in slot order
+  __shared__ uint32_t bits[kExchBitWords];
+  __shared__ int pre[kExchBitWords];
+  __shared__ int wtot[16];
   if (S.ctl[1] == 2) return;
   if (P == 0 && threadIdx.x == 0) S.ctl[1] = 0;  // the previous step's overflow is resolved
   if (only_marked && S.dep[P] >= 0) return;     // done by the fused kernel
   const int c = S.cnt[P];
   const int64_t sbP = S.sb[P];
+  if (c <= kExchBitSlots) {
+    code_bits<CENTER>(S.code + sbP, c, bits);
+    __syncthreads();
+    depart_in_kernel<DIM>(g, S, P, c, bits, pre, wtot);
+    return;
+  }
   int pc[3];
   patch_coords(g, P, pc);
   uint32_t w[16];
   int tot = 0;
-  if (c <= kExchTile) {
-    const int j0 = kExchPer * (int)threadIdx.x;
-    load_codes<CENTER>(S.code, sbP, j0, c, w);
-    int k = 0;
-#pragma unroll
-    for (int i = 0; i < kExchPer; i++) k += code_at(w, i) != CENTER;
-    int r = excl_sum_256(k, tot, w4);
-    const int m = tot;
-    if (threadIdx.x == 0) S.dep[P] = m;
-    if (m == 0) {
-      if (threadIdx.x == 0) S.cnt2[P] = c;
-      return;
-    }
-    const int c2 = c - m;
-    if (m <= kDepList) {
-      for (int i = 0; i < kExchPer && k > 0; i++) {
-        const int cd = code_at(w, i);
-        if (cd != CENTER) {
-          deps[r++] = (uint32_t)(j0 + i) | ((uint32_t)cd << 24);
-          k--;
-        }
-      }
-      int kk = 0;
-#pragma unroll
-      for (int i = 0; i < kExchPer; i++)
-        kk += j0 + i >= c2 && j0 + i < c && code_at(w, i) == CENTER;
-      int r2 = excl_sum_256(kk, tot, w4);  // also orders the deps writes before the reads
-      for (int i = 0; i < kExchPer && kk > 0; i++) {
-        const int j = j0 + i;
-        if (j >= c2 && j < c && code_at(w, i) == CENTER) {
-          movers[r2++] = j;
-          kk--;
-        }
-      }
-      __syncthreads();
-      for (int q = threadIdx.x; q < m; q += blockDim.x) {
-        const int j = (int)(deps[q] & 0xffffffu);
-        const int64_t o = sbP + q;
-        copy_particle<DIM>(S.ox, S.ou, S.ow, S.oid, o, S.xs, S.us, S.ws, S.ids, sbP + j);
-        S.odest[o] = dest_patch(g, pc, (int)(deps[q] >> 24));
-      }
-      __syncthreads();  // departures read before movers overwrite their slots
-      // the q-th mover fills the q-th departure (those below c2 come first)
-      for (int q = threadIdx.x; q < tot; q += blockDim.x) {
-        const int h = (int)(deps[q] & 0xffffffu);
-        copy_particle<DIM>(S.xs, S.us, S.ws, S.ids, sbP + h, S.xs, S.us, S.ws, S.ids,
-                           sbP + movers[q]);
-      }
-      if (threadIdx.x == 0) S.cnt2[P] = c2;
-      return;
-    }
-  }
   // Large case: tiles of 16384 slots; each thread copies its own departures
   // and movers in slot order.
   int m = 0;
@@ -554,11 +572,57 @@ __global__ void __launch_bounds__(256) k_exch_in(GridDev g, SlabArgs sa) {
   }
 }
 
+// Persistent mode: work units of chunk particles for the counts count(P),
+// every full unit first, then the remainders (one workgroup per species,
+// each thread a contiguous run of patches).  count must not change during
+// the call; the list goes to units + ubase, its length to qctl[2s+1] (0 if
+// the species stands still) and a zero ticket to qctl[2s].
+template <class Count>
+__device__ void make_units(const SlabDev &S, int s, int n, int chunk, bool still, Count count,
+                           Unit *units, int *qctl, int *wtot) {
+  const int per = (n + blockDim.x - 1) / blockDim.x;
+  const int p0 = min(n, (int)threadIdx.x * per), p1 = min(n, p0 + per);
+  int nf = 0, nr = 0;
+  for (int P = p0; P < p1; P++) {
+    const int c = count(P);
+    nf += c / chunk;
+    nr += c % chunk != 0;
+  }
+  int tf = 0, tr = 0;
+  int rf = block_excl_sum(nf, tf, wtot);
+  int rr = tf + block_excl_sum(nr, tr, wtot);
+  Unit *ul = units + S.ubase;
+  for (int P = p0; P < p1; P++) {
+    const int c = count(P);
+    Unit un;
+    un.s = s;
+    un.P = P;
+    for (int j = 0; j < c / chunk; j++) {
+      un.k0 = j * chunk;
+      un.k1 = un.k0 + chunk;
+      ul[rf++] = un;
+    }
+    if (c % chunk) {
+      un.k0 = c / chunk * chunk;
+      un.k1 = c;
+      ul[rr++] = un;
+    }
+  }
+  if (threadIdx.x == 0) {
+    qctl[2 * s + 1] = still ? 0 : tf + tr;
+    qctl[2 * s] = 0;
+  }
+}
+
 // End of the exchange (one workgroup of 1024 per species): new counts; on
-// an overflow, a new slab plan for the counts every patch needs.
-__global__ void __launch_bounds__(1024) k_exch_fin(GridDev g, SlabArgs sa, int *err) {
+// an overflow, a new slab plan for the counts every patch needs.  With
+// units (persistent mode), also the next step's work units.
+__global__ void __launch_bounds__(1024) k_exch_fin(GridDev g, SlabArgs sa, int *err, Unit *units,
+                                                   int *qctl, int chunk) {
   __shared__ int64_t part[1024];
-  const SlabDev &S = sa.s[blockIdx.x];
+  __shared__ int wtot[16];
+  const int s = blockIdx.x;
+  const SlabDev &S = sa.s[s];
   const int n = g.npatch;
   const int flag = S.ctl[1];
   if (flag == 2) return;
@@ -566,6 +630,10 @@ __global__ void __launch_bounds__(1024) k_exch_fin(GridDev g, SlabArgs sa, int *
     for (int P = threadIdx.x; P < n; P += blockDim.x) {
       S.cnt[P] = S.cnt2[P] + S.arr[P];
       S.arr[P] = 0;
+    }
+    if (units) {
+      __syncthreads();  // counts written before other threads read them
+      make_units(S, s, n, chunk, false, [&](int P) { return S.cnt[P]; }, units, qctl, wtot);
     }
     return;
   }
@@ -577,14 +645,18 @@ __global__ void __launch_bounds__(1024) k_exch_fin(GridDev g, SlabArgs sa, int *
   }
   __syncthreads();
   block_scan_1024(S.tmp, S.sb2, n, part);
-  if (threadIdx.x == 0 && S.sb2[n] > S.capacity) {
+  const bool still = S.sb2[n] > S.capacity;
+  if (threadIdx.x == 0 && still) {
     S.ctl[1] = 2;  // no room for a new plan: the species stands still
     atomicOr(err, kErrCap);
   }
+  if (units)  // the counts the new plan's copies will set
+    make_units(S, s, n, chunk, still, [&](int P) { return S.cnt2[P] + S.arr[P]; }, units, qctl,
+               wtot);
 }
 
-// Overflow, part 1 (grid: 2 x patches, x species): every
-// particle goes to its place in the new plan, inside the first buffer set.
+// Overflow, part 1 (grid: 2 x patches, x species): every particle goes to
+// its place in the new plan, inside the first buffer set.
 template <int DIM>
 __global__ void __launch_bounds__(256) k_reslab_move(GridDev g, SlabArgs sa) {
   const SlabDev &S = sa.s[blockIdx.y];
@@ -593,9 +665,8 @@ __global__ void __launch_bounds__(256) k_reslab_move(GridDev g, SlabArgs sa) {
   if ((int)blockIdx.x < n) {
     const int P = blockIdx.x;
     const int placed = min(S.arr[P], S.cap[P] - S.cnt2[P]);
-    const int64_t c = (int64_t)S.cnt2[P] + placed, s0 = S.sb[P], d0 = S.sb2[P];
-    for (int64_t j = threadIdx.x; j < c; j += blockDim.x)
-      copy_particle<DIM>(S.x, S.u, S.w, S.id, d0 + j, S.xs, S.us, S.ws, S.ids, s0 + j);
+    const int64_t c = (int64_t)S.cnt2[P] + placed;
+    copy_run<DIM>(S.x, S.u, S.w, S.id, S.sb2[P], S.xs, S.us, S.ws, S.ids, S.sb[P], c);
     return;
   }
   const int Q = blockIdx.x - n;  // the outbox of patch Q
@@ -620,8 +691,7 @@ __global__ void __launch_bounds__(256) k_reslab_back(GridDev g, SlabArgs sa) {
   if (S.ctl[1] != 1) return;
   const int P = blockIdx.x;
   const int64_t c = (int64_t)S.cnt2[P] + S.arr[P], d0 = S.sb2[P];
-  for (int64_t j = threadIdx.x; j < c; j += blockDim.x)
-    copy_particle<DIM>(S.xs, S.us, S.ws, S.ids, d0 + j, S.x, S.u, S.w, S.id, d0 + j);
+  copy_run<DIM>(S.xs, S.us, S.ws, S.ids, d0, S.x, S.u, S.w, S.id, d0, c);
   __syncthreads();  // every thread has read arr[P] before it is cleared
   if (threadIdx.x == 0) {
     S.cnt[P] = (int32_t)c;
@@ -632,49 +702,15 @@ __global__ void __launch_bounds__(256) k_reslab_back(GridDev g, SlabArgs sa) {
   }
 }
 
-// Persistent mode: work units of chunk particles from the slab counts,
-// every species' full units first, then the remainders (one workgroup of
-// 1024 per species).
+// Persistent mode, start of a call: work units from the slab counts (one
+// workgroup of 1024 per species).
 __global__ void __launch_bounds__(1024) k_slab_units(GridDev g, SlabArgs sa, int chunk,
                                                      Unit *units, int *qctl) {
-  __shared__ int64_t part[1024];
+  __shared__ int wtot[16];
   const int s = blockIdx.x;
   const SlabDev &S = sa.s[s];
-  const int n = g.npatch;
-  for (int P = threadIdx.x; P < n; P += blockDim.x) S.tmp[P] = S.cnt[P] / chunk;
-  __syncthreads();
-  block_scan_1024(S.tmp, S.sb2, n, part);  // sb2 is free outside an overflow
-  const int64_t nfull = S.sb2[n];
-  for (int P = threadIdx.x; P < n; P += blockDim.x) {
-    const int c = S.cnt[P];
-    Unit un;
-    un.s = s;
-    un.P = P;
-    for (int j = 0; j < c / chunk; j++) {
-      un.k0 = j * chunk;
-      un.k1 = un.k0 + chunk;
-      units[S.ubase + S.sb2[P] + j] = un;
-    }
-  }
-  __syncthreads();
-  for (int P = threadIdx.x; P < n; P += blockDim.x) S.tmp[P] = S.cnt[P] % chunk != 0;
-  __syncthreads();
-  block_scan_1024(S.tmp, S.sb2, n, part);
-  for (int P = threadIdx.x; P < n; P += blockDim.x) {
-    const int c = S.cnt[P];
-    if (c % chunk) {
-      Unit un;
-      un.s = s;
-      un.P = P;
-      un.k0 = c / chunk * chunk;
-      un.k1 = c;
-      units[S.ubase + nfull + S.sb2[P]] = un;
-    }
-  }
-  if (threadIdx.x == 0) {
-    qctl[2 * s + 1] = S.ctl[1] == 2 ? 0 : (int)(nfull + S.sb2[n]);
-    qctl[2 * s] = 0;
-  }
+  make_units(S, s, g.npatch, chunk, S.ctl[1] == 2, [&](int P) { return S.cnt[P]; }, units, qctl,
+             wtot);
 }
 
 // End of a call: dense offsets from the slab counts (one workgroup of 1024
@@ -695,9 +731,7 @@ __global__ void __launch_bounds__(256) k_slab_out(GridDev g, SlabArgs sa) {
   const SlabDev &S = sa.s[blockIdx.y];
   if (S.ctl[1] == 2) return;
   const int P = blockIdx.x;
-  const int64_t d = S.off[P], c = S.cnt[P], b = S.sb[P];
-  for (int64_t j = threadIdx.x; j < c; j += blockDim.x)
-    copy_particle<DIM>(S.x, S.u, S.w, S.id, d + j, S.xs, S.us, S.ws, S.ids, b + j);
+  copy_run<DIM>(S.x, S.u, S.w, S.id, S.off[P], S.xs, S.us, S.ws, S.ids, S.sb[P], S.cnt[P]);
 }
 
 }  // namespace
@@ -773,7 +807,7 @@ hipError_t launch_exchange(const GridDev &g, const SlabArgs &sa, int *err, Unit 
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_exch_fin, dim3(sa.nsp), dim3(1024), 0, st, g, sa, err);
+  hipLaunchKernelGGL(k_exch_fin, dim3(sa.nsp), dim3(1024), 0, st, g, sa, err, units, qctl, chunk);
   const dim3 mg(2 * g.npatch, sa.nsp);
   if (g.dim == 2) {
     hipLaunchKernelGGL(k_reslab_move<2>, mg, dim3(256), 0, st, g, sa);
@@ -782,9 +816,6 @@ hipError_t launch_exchange(const GridDev &g, const SlabArgs &sa, int *err, Unit 
     hipLaunchKernelGGL(k_reslab_move<3>, mg, dim3(256), 0, st, g, sa);
     hipLaunchKernelGGL(k_reslab_back<3>, pg, dim3(256), 0, st, g, sa);
   }
-  if ((e = hipGetLastError()) != hipSuccess) return e;
-  if (units)
-    hipLaunchKernelGGL(k_slab_units, dim3(sa.nsp), dim3(1024), 0, st, g, sa, chunk, units, qctl);
   return hipGetLastError();
 }
 

@@ -209,3 +209,20 @@ def test_slab_overflow_replans(mode):
     px = np.arange(counts.size) % npx
     assert counts[px >= npx // 2].max() > 64
     run_cmp(wl, inp, steps, "slab", osp, J, A, mode=mode, chunk=256)
+
+
+@pytest.mark.parametrize("ppc", [72, 280])
+@pytest.mark.parametrize("mode", [0, 1])
+def test_patch_beyond_the_departure_bitmap(mode, ppc):
+    """Patches of more than 16384 particles, whose departures the fused
+    kernel leaves to the departures kernel: with 72 ppc its bitmap path,
+    with 280 ppc (more than 65536 particles) its tiled large-patch path."""
+    wl = I.custom(2, (32, 32), (16, 16), ppc=2, seed=320 + mode, sigma=0.2)
+    wl.species[0].ppc = lambda ix: np.where(ix < 16, ppc, 2).astype(np.int64)
+    inp = I.generate(wl)
+    steps = 4
+    osp, J, A = run_oracle(wl, inp, steps)
+    counts = np.diff(osp[0].off)
+    say(f"case large patches mode={mode} ppc={ppc}: max patch count {counts.max()}")
+    assert counts.max() > (16384 if ppc < 100 else 65536)
+    run_cmp(wl, inp, steps, "slab", osp, J, A, mode=mode, chunk=2048)

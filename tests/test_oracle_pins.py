@@ -605,3 +605,44 @@ def test_step_rejects_unsorted_offsets():
     sp = O.species_from(inp)[0]  # offsets never computed
     with pytest.raises(O.OracleError):
         O.step(wl, [sp], inp.E, inp.B)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_window_of_particles_reproduces_the_full_run(dim):
+    """Finite propagation: the particles within the margin of a window of
+    patches give the full run's counts, particles and J inside it (the
+    reduction the full-size GPU parity tests rely on).  Fast particles
+    (sigma 0.4) and a window across the periodic corner."""
+    import _window as Wn
+
+    if dim == 2:
+        wl = I.custom(2, (64, 48), (8, 8), ppc=3, seed=150, sigma=0.4)
+        a0, npw, steps = [-8, -8, 0], [3, 2, 1], 6
+    else:
+        wl = I.custom(3, (24, 24, 24), (4, 4, 4), ppc=1, seed=151, sigma=0.4, n_species=2)
+        a0, npw, steps = [-4, 4, -4], [2, 2, 2], 3
+    inp = I.generate(wl)
+    full = O.species_from(inp)
+    for s in full:
+        O.bin(wl, s)
+    for _ in range(steps):
+        J, A = O.step(wl, full, inp.E, inp.B, with_abs=True)
+    margin = Wn.margin_cells(wl, steps)
+    sub, Js, _ = Wn.oracle_window(wl, inp, steps, a0, npw, margin)
+    assert sum(s.n for s in sub) < sum(s.n for s in full)
+    patches = Wn.window_patches(wl, a0, npw)
+    for f, s in zip(full, sub):
+        assert np.array_equal(np.diff(f.off)[patches], np.diff(s.off)[patches])
+        for P in patches:
+            fi, si = np.arange(f.off[P], f.off[P + 1]), np.arange(s.off[P], s.off[P + 1])
+            assert np.array_equal(f.id[fi], s.id[si])  # stable sort keeps the order
+            assert np.array_equal(f.x[:, fi], s.x[:, si])
+            assert np.array_equal(f.u[:, fi], s.u[:, si])
+    nodes = Wn.window_nodes(wl, a0, npw)
+    for c in range(3):
+        assert np.all(np.abs(J[c][nodes] - Js[c][nodes]) <= 1e-12 * A[c][nodes])
+    # the margin is needed: without it the window's particle sets differ
+    sub0, _, _ = Wn.oracle_window(wl, inp, steps, a0, npw, 0)
+    ids = lambda sps: [np.sort(np.concatenate([s.id[s.off[P]:s.off[P + 1]] for P in patches]))
+                       for s in sps]
+    assert any(not np.array_equal(a, b) for a, b in zip(ids(sub0), ids(full)))
