@@ -22,7 +22,8 @@
  *             Px + NPx (Py + NPy Pz); particles are stored sorted by patch:
  *             patch P owns entries [offset[P], offset[P+1]) of every particle
  *             array.  Inside a patch the order is that of the previous step
- *             (the sort is stable).
+ *             (the sort is stable), except where pic_step (slab layout) or
+ *             x-bins (pic_config.bin_x) state otherwise.
  *   Particles structure of arrays per species, float64 x/u/w and int64 id,
  *             all on the context's device, each of `capacity` elements.
  *   Memory    the caller owns every particle, field and offset array and
@@ -90,6 +91,20 @@ typedef struct {
                           2D and 1024 in 3D (0 = auto: 256 in 2D, 1024 in 3D);
                           the dense-layout kernels use at most 512 in 3D */
   uint32_t flags;      /* PIC_FLAG_* */
+  int32_t bin_x;       /* x-bins: width in cells of the bins a patch is cut
+                          into along x (paper, sections "Parallelization
+                          without tasks" and "Parallelization with OpenMP
+                          task": bins of bin_x_size cells, each with its own
+                          local sub-grid whose current is added to the grid
+                          with a shift of a multiple of bin_x_size).  The
+                          kernels stage fields and accumulate J per bin, so a
+                          patch whose tiles do not fit in the 160 KB of LDS
+                          can still be used.  Must divide patch[0].  0 = auto:
+                          patch[0] if its tiles fit, else the widest divisor
+                          of patch[0] whose tiles fit.  With more than one
+                          bin per patch, the particles inside a patch are
+                          ordered by bin, and pic_step and pic_interp_push
+                          first sort them by bin (one general sort per call). */
 } pic_config;
 
 typedef struct {
@@ -121,6 +136,11 @@ pic_status pic_validate_config(const pic_config *cfg, char *msg, size_t len);
 
 /* Number of patches of a valid configuration (0 if invalid).  Pure host. */
 int64_t pic_num_patches(const pic_config *cfg);
+
+/* Width in cells of the x-bins a valid configuration uses (bin_x, or the
+ * automatic choice when bin_x = 0); 0 if the configuration is invalid.
+ * Pure host. */
+int32_t pic_bin_width(const pic_config *cfg);
 
 /* Create a context on HIP device `device`: validates cfg, allocates the
  * context's scratch.  *out is NULL on failure. */
@@ -165,8 +185,9 @@ pic_status pic_project(pic_ctx *ctx, const pic_species *sp, int32_t nsp, pic_fie
  * (follow the pointers in sp).
  *
  * Layout: with nsteps >= 3 and, for every species, capacity >=
- * n + n/8 + 80 * (number of patches) and capacity < 2^29, the call keeps the
- * particles in per-patch slabs of the second buffer set, updates them in
+ * n + n/8 + 80 * (number of x-bins: patches times patch[0] / bin width) and
+ * capacity < 2^29, the call keeps the
+ * particles in per-bin slabs of the second buffer set, updates them in
  * place and moves only those that change patch; the order inside a patch is
  * then arbitrary and the result is in the first set.  Otherwise every step
  * sorts by neighbour code (stable: the order inside a patch is the previous

@@ -93,6 +93,12 @@ struct pic_ctx {
   SlabScratch slab[kMaxSpecies];
   GraphCache slab_gc;     // one captured slab-layout step
   int pgrid_slab = 0;     // persistent grid size of the slab-layout kernel
+  // x-bins: the kernels' "patches" (GridDev) are the bins; with more than one
+  // bin per patch the bin offsets live here and the caller's offset arrays
+  // receive every nb-th entry.
+  int nb = 1;                           // bins per patch
+  int64_t npatch_api = 0;               // patches of the configuration
+  int64_t *boff[kMaxSpecies] = {};      // [bins + 1] per species
 };
 
 namespace {
@@ -121,16 +127,41 @@ pic_status hip_fail(pic_ctx *c, hipError_t e, const char *what) {
 
 int axes(const pic_config *c) { return c->dim == 3 ? 3 : 2; }
 
-// Derived geometry; cfg must be valid.
+size_t tiles_bytes(const pic_config *c, int bx) {
+  size_t te = 1, tj = 1;
+  for (int a = 0; a < axes(c); a++) {
+    const int p = a == 0 ? bx : c->patch[a];
+    te *= (size_t)(p + 3);
+    tj *= (size_t)(p + 5);
+  }
+  return (6 * te + 3 * tj) * sizeof(double);
+}
+
+constexpr size_t kLdsMax = 160 * 1024;  // LDS of one CU
+
+bool tiles_fit(const pic_config *c, int bx) { return tiles_bytes(c, bx) + kStaticLds <= kLdsMax; }
+
+// Width of the x-bins: bin_x if set, else patch[0] or its widest divisor
+// whose tiles fit (0 if none does).
+int choose_bin(const pic_config *c) {
+  if (c->bin_x > 0) return c->bin_x;
+  for (int b = c->patch[0]; b >= 1; b--)
+    if (c->patch[0] % b == 0 && tiles_fit(c, b)) return b;
+  return 0;
+}
+
+// Derived geometry of the kernels, whose patches are the x-bins; cfg must
+// be valid.
 GridDev make_grid(const pic_config *c) {
   GridDev g{};
   g.dim = c->dim;
   g.npatch = 1;
   g.nc = c->dim == 3 ? 27 : 9;
+  const int bx = choose_bin(c);
   for (int a = 0; a < 3; a++) {
     const bool on = a < c->dim;
     g.n[a] = on ? c->n[a] : 1;
-    g.patch[a] = on ? c->patch[a] : 1;
+    g.patch[a] = on ? (a == 0 ? bx : c->patch[a]) : 1;
     g.np[a] = g.n[a] / g.patch[a];
     g.npatch *= g.np[a];
     const double d = on ? c->d[a] : 1.0;
@@ -140,15 +171,6 @@ GridDev make_grid(const pic_config *c) {
   }
   g.dt = c->dt;
   return g;
-}
-
-size_t tiles_bytes(const pic_config *c) {
-  size_t te = 1, tj = 1;
-  for (int a = 0; a < axes(c); a++) {
-    te *= (size_t)(c->patch[a] + 3);
-    tj *= (size_t)(c->patch[a] + 5);
-  }
-  return (6 * te + 3 * tj) * sizeof(double);
 }
 
 pic_status check_species(pic_ctx *c, const pic_species *sp, int32_t nsp, bool need_sorted) {
@@ -282,7 +304,7 @@ SpArgs make_args(pic_ctx *c, const pic_species *sp, int32_t nsp) {
     d.wa = p.w_alt;
     d.id = p.id;
     d.ida = p.id_alt;
-    d.off = p.offset;
+    d.off = c->nb > 1 ? c->boff[s] : p.offset;
     d.noff = c->sp[s].noff;
     d.tag = c->sp[s].tag;
     d.sstart = c->sp[s].sstart;
@@ -566,7 +588,7 @@ SlabArgs make_slab_args(pic_ctx *c, const pic_species *sp, int32_t nsp) {
     d.ids = p.id_alt;
     d.oid = L.oid;
     d.odest = L.odest;
-    d.off = p.offset;
+    d.off = c->nb > 1 ? c->boff[s] : p.offset;
     d.sb = L.sb;
     d.sb2 = L.sb2;
     d.cap = L.room;
@@ -654,6 +676,7 @@ pic_status ensure_slab_graph(pic_ctx *c, const SlabArgs &a, const pic_fields *f,
 
 // pic_step in the slab layout: dense -> slabs, nsteps slab steps, slabs ->
 // dense (new offsets); the caller's first buffer set holds the result.
+// Enqueues only (the caller finishes the call).
 pic_status step_slab(pic_ctx *c, pic_species *sp, int32_t nsp, pic_fields *f, int32_t nsteps,
                      hipStream_t st) {
   pic_status r = ensure_slab(c, sp, nsp, st);
@@ -693,7 +716,68 @@ pic_status step_slab(pic_ctx *c, pic_species *sp, int32_t nsp, pic_fields *f, in
     return r2;
   });
   if (e != hipSuccess) return hip_fail(c, e, "kernel launch");
-  return finish(c, st);
+  return PIC_OK;
+}
+
+// x-bins: the bin offsets of each species, allocated on first use.
+pic_status ensure_boff(pic_ctx *c, int32_t nsp) {
+  if (c->nb == 1) return PIC_OK;
+  for (int s = 0; s < nsp; s++)
+    if (!c->boff[s]) {
+      hipError_t e = realloc_dev(c->boff[s], (size_t)c->g.npatch + 1);
+      if (e != hipSuccess) return hip_fail(c, e, "hipMalloc");
+    }
+  return PIC_OK;
+}
+
+// x-bins: the caller's patch offsets (every nb-th bin offset).
+hipError_t api_offsets(pic_ctx *c, const pic_species *sp, int32_t nsp, hipStream_t st) {
+  if (c->nb == 1) return hipSuccess;
+  for (int s = 0; s < nsp; s++) {
+    const hipError_t e = launch_api_offsets(c->boff[s], sp[s].offset, c->npatch_api, c->nb, st);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+// The synchronisation-phase sort of pic_bin: with general, wrap + key +
+// stable sort of particles in any order; otherwise the neighbour-code sort
+// after pic_interp_push.  Then segment starts (and work units), the buffer
+// swap and, with x-bins, the caller's patch offsets.
+pic_status sort_species(pic_ctx *c, pic_species *sp, int32_t nsp, bool general, hipStream_t st) {
+  pic_status r;
+  if ((r = ensure_scratch(c, sp, nsp, false, st)) != PIC_OK) return r;
+  if ((r = ensure_boff(c, nsp)) != PIC_OK) return r;
+  if (!general) {
+    // particles moved at most one cell since the last sort: neighbour-code sort
+    const SpArgs a = make_args(c, sp, nsp);
+    hipError_t e =
+        timed(c, PIC_KERNEL_TAG, st, [&] { return launch_tag(c->g, a, c->err_dev, c->wgd, st); });
+    if (e == hipSuccess)
+      e = timed(c, PIC_KERNEL_REBIN, st, [&] {
+        return launch_rebin(c->g, a, c->err_dev, max_segments(c, nsp), false, st);
+      });
+    if (e != hipSuccess) return hip_fail(c, e, "kernel launch");
+  } else {
+    for (int s = 0; s < nsp; s++) {
+      const SpArgs a = make_args(c, sp + s, 1);
+      SpDev d = a.s[0];
+      d.off = c->nb > 1 ? c->boff[s] : sp[s].offset;
+      hipError_t e = timed(c, PIC_KERNEL_SORT, st,
+                           [&] { return general_sort(c->g, d, c->sort[s], c->err_dev, st); });
+      if (e != hipSuccess) return hip_fail(c, e, "general sort");
+    }
+  }
+  {
+    const SpArgs a = make_args(c, sp, nsp);
+    hipError_t e = launch_layout(c->g, a, c->cfg.mode == PIC_MODE_PERSISTENT ? c->units : nullptr,
+                                 c->qctl, st);
+    if (e == hipSuccess) e = api_offsets(c, sp, nsp, st);
+    if (e != hipSuccess) return hip_fail(c, e, "kernel launch");
+  }
+  for (int s = 0; s < nsp; s++) swap_buffers(sp[s]);
+  c->moved = false;
+  return PIC_OK;
 }
 
 }  // namespace
@@ -773,9 +857,17 @@ pic_status pic_validate_config(const pic_config *c, char *msg, size_t len) {
     set_msg(msg, len, "unknown flag bits 0x%x", c->flags);
     return PIC_ERR_ARG;
   }
-  const size_t lds = tiles_bytes(c) + kStaticLds;
-  if (lds > 160 * 1024) {
-    set_msg(msg, len, "patch too large: E/B and J tiles need %zu bytes of LDS (max 163840)", lds);
+  if (c->bin_x < 0 || (c->bin_x > 0 && c->patch[0] % c->bin_x)) {
+    set_msg(msg, len, "bin_x=%d must be 0 (auto) or divide patch[0]=%d", c->bin_x, c->patch[0]);
+    return PIC_ERR_ARG;
+  }
+  const int bx = choose_bin(c);
+  if (bx == 0 || !tiles_fit(c, bx)) {
+    const int b = bx ? bx : 1;
+    set_msg(msg, len,
+            "patch too large: E/B and J tiles of x-bins of %d cells need %zu bytes of LDS "
+            "(max %zu)",
+            b, tiles_bytes(c, b) + kStaticLds, kLdsMax);
     return PIC_ERR_ARG;
   }
   return PIC_OK;
@@ -786,6 +878,11 @@ int64_t pic_num_patches(const pic_config *c) {
   int64_t n = 1;
   for (int a = 0; a < c->dim; a++) n *= c->n[a] / c->patch[a];
   return n;
+}
+
+int32_t pic_bin_width(const pic_config *c) {
+  if (pic_validate_config(c, nullptr, 0) != PIC_OK) return 0;
+  return choose_bin(c);
 }
 
 pic_status pic_init(const pic_config *cfg, int32_t device, pic_ctx **out) {
@@ -804,6 +901,8 @@ pic_status pic_init(const pic_config *cfg, int32_t device, pic_ctx **out) {
     c->cfg.d[2] = 1.0;
   }
   c->g = make_grid(&c->cfg);
+  c->nb = c->cfg.patch[0] / c->g.patch[0];
+  c->npatch_api = c->g.npatch / c->nb;
   c->device = device;
   c->wg = cfg->wg_size ? cfg->wg_size : (c->cfg.dim == 2 ? 256 : 1024);
   c->wgd = std::min(c->wg, c->cfg.dim == 2 ? 256 : 512);
@@ -842,6 +941,7 @@ void pic_free(pic_ctx *c) {
     (void)hipFree(S.noff);
     for (int a = 0; a < 3; a++) (void)hipFree(S.x0[a]);
     free_sort_scratch(c->sort[s]);
+    (void)hipFree(c->boff[s]);
     SlabScratch &L = c->slab[s];
     for (void *p : {(void *)L.sb, (void *)L.sb2, (void *)L.room, (void *)L.room2, (void *)L.cnt,
                     (void *)L.cnt2, (void *)L.arr, (void *)L.arr2, (void *)L.dep,
@@ -917,35 +1017,7 @@ pic_status pic_bin(pic_ctx *c, pic_species *sp, int32_t nsp, void *stream) {
   if (hipSetDevice(c->device) != hipSuccess) return fail(c, PIC_ERR_HIP, "hipSetDevice");
   if (c->moved && nsp != c->moved_nsp)
     return fail(c, PIC_ERR_STATE, "pic_bin after pic_interp_push needs the same species");
-  if (c->moved) {
-    // particles moved at most one cell since the last sort: neighbour-code sort
-    if ((r = ensure_scratch(c, sp, nsp, false, st)) != PIC_OK) return r;
-    const SpArgs a = make_args(c, sp, nsp);
-    hipError_t e =
-        timed(c, PIC_KERNEL_TAG, st, [&] { return launch_tag(c->g, a, c->err_dev, c->wgd, st); });
-    if (e == hipSuccess)
-      e = timed(c, PIC_KERNEL_REBIN, st, [&] {
-        return launch_rebin(c->g, a, c->err_dev, max_segments(c, nsp), false, st);
-      });
-    if (e != hipSuccess) return hip_fail(c, e, "kernel launch");
-  } else {
-    if ((r = ensure_scratch(c, sp, nsp, false, st)) != PIC_OK) return r;
-    for (int s = 0; s < nsp; s++) {
-      const SpArgs a = make_args(c, sp + s, 1);
-      SpDev d = a.s[0];
-      hipError_t e = timed(c, PIC_KERNEL_SORT, st,
-                           [&] { return general_sort(c->g, d, c->sort[s], c->err_dev, st); });
-      if (e != hipSuccess) return hip_fail(c, e, "general sort");
-    }
-  }
-  {
-    const SpArgs a = make_args(c, sp, nsp);
-    hipError_t e = launch_layout(c->g, a, c->cfg.mode == PIC_MODE_PERSISTENT ? c->units : nullptr,
-                                 c->qctl, st);
-    if (e != hipSuccess) return hip_fail(c, e, "kernel launch");
-  }
-  for (int s = 0; s < nsp; s++) swap_buffers(sp[s]);
-  c->moved = false;
+  if ((r = sort_species(c, sp, nsp, !c->moved, st)) != PIC_OK) return r;
   return finish(c, st);
 }
 
@@ -958,6 +1030,8 @@ pic_status pic_interp_push(pic_ctx *c, pic_species *sp, int32_t nsp, const pic_f
   hipStream_t st = (hipStream_t)stream;
   if (hipSetDevice(c->device) != hipSuccess) return fail(c, PIC_ERR_HIP, "hipSetDevice");
   if ((r = ensure_scratch(c, sp, nsp, true, st)) != PIC_OK) return r;
+  // x-bins: the particles arrive sorted by patch; the kernels need them by bin
+  if (c->nb > 1 && (r = sort_species(c, sp, nsp, true, st)) != PIC_OK) return r;
   const SpArgs a = make_args(c, sp, nsp);
   hipError_t e = timed(c, PIC_KERNEL_INTERP_PUSH, st, [&] {
     return launch_interp_push(c->g, a, f->e, f->b, c->err_dev, c->wgd, st);
@@ -995,33 +1069,40 @@ pic_status pic_step(pic_ctx *c, pic_species *sp, int32_t nsp, pic_fields *f, int
   if (hipSetDevice(c->device) != hipSuccess) return fail(c, PIC_ERR_HIP, "hipSetDevice");
   if ((r = ensure_scratch(c, sp, nsp, false, st)) != PIC_OK) return r;
   if (nsteps == 0) return finish(c, st);
-  if (nsteps >= 3 && slab_fits(c, sp, nsp)) return step_slab(c, sp, nsp, f, nsteps, st);
-  // The first step updates the particles in place and records the sort as a
-  // permutation; middle steps gather through it into the other buffer set;
-  // the last step's sort copies the particles into their sorted places, so
-  // between calls the arrays are always sorted.
-  auto step = [&](bool gather, bool materialize) -> pic_status {
-    hipError_t e = enqueue_step(c, sp, nsp, f, st, gather, materialize);
-    if (e != hipSuccess) return hip_fail(c, e, "kernel launch");
-    for (int s = 0; s < nsp; s++) {
-      if (gather) swap_buffers(sp[s]);
-      if (materialize) swap_buffers(sp[s]);
+  // x-bins: the particles arrive sorted by patch; the kernels need them by bin
+  if (c->nb > 1 && (r = sort_species(c, sp, nsp, true, st)) != PIC_OK) return r;
+  if (nsteps >= 3 && slab_fits(c, sp, nsp)) {
+    if ((r = step_slab(c, sp, nsp, f, nsteps, st)) != PIC_OK) return r;
+  } else {
+    // The first step updates the particles in place and records the sort as
+    // a permutation; middle steps gather through it into the other buffer
+    // set; the last step's sort copies the particles into their sorted
+    // places, so between calls the arrays are always sorted.
+    auto step = [&](bool gather, bool materialize) -> pic_status {
+      hipError_t e = enqueue_step(c, sp, nsp, f, st, gather, materialize);
+      if (e != hipSuccess) return hip_fail(c, e, "kernel launch");
+      for (int s = 0; s < nsp; s++) {
+        if (gather) swap_buffers(sp[s]);
+        if (materialize) swap_buffers(sp[s]);
+      }
+      return PIC_OK;
+    };
+    if ((r = step(false, nsteps == 1)) != PIC_OK) return r;
+    int middle = nsteps - 2;  // steps 1 .. nsteps-2
+    if ((c->cfg.flags & PIC_FLAG_GRAPH) && !c->tm.on && middle >= 2) {
+      hipGraphExec_t x = nullptr;
+      if ((r = ensure_graph(c, sp, nsp, f, &x)) != PIC_OK) return r;
+      for (; middle >= 2; middle -= 2) {
+        hipError_t e = hipGraphLaunch(x, st);
+        if (e != hipSuccess) return hip_fail(c, e, "hipGraphLaunch");
+      }
     }
-    return PIC_OK;
-  };
-  if ((r = step(false, nsteps == 1)) != PIC_OK) return r;
-  int middle = nsteps - 2;  // steps 1 .. nsteps-2
-  if ((c->cfg.flags & PIC_FLAG_GRAPH) && !c->tm.on && middle >= 2) {
-    hipGraphExec_t x = nullptr;
-    if ((r = ensure_graph(c, sp, nsp, f, &x)) != PIC_OK) return r;
-    for (; middle >= 2; middle -= 2) {
-      hipError_t e = hipGraphLaunch(x, st);
-      if (e != hipSuccess) return hip_fail(c, e, "hipGraphLaunch");
-    }
+    for (; middle > 0; middle--)
+      if ((r = step(true, false)) != PIC_OK) return r;
+    if (nsteps >= 2 && (r = step(true, true)) != PIC_OK) return r;
   }
-  for (; middle > 0; middle--)
-    if ((r = step(true, false)) != PIC_OK) return r;
-  if (nsteps >= 2 && (r = step(true, true)) != PIC_OK) return r;
+  const hipError_t e = api_offsets(c, sp, nsp, st);
+  if (e != hipSuccess) return hip_fail(c, e, "kernel launch");
   return finish(c, st);
 }
 
@@ -1066,7 +1147,7 @@ pic_status pic_adjoint(pic_ctx *c, const pic_species *ck, int32_t nsp, const pic
     }
     d.w = p.w;
     d.id = p.id;
-    d.off = p.offset;
+    d.off = c->nb > 1 ? nullptr : p.offset;  // x-bins: the untiled kernel
   }
   hipStream_t st = (hipStream_t)stream;
   if (hipSetDevice(c->device) != hipSuccess) return fail(c, PIC_ERR_HIP, "hipSetDevice");

@@ -160,6 +160,10 @@ int persistent_grid(const GridDev &g, int wg);
 // qctl[1] and a zero ticket in qctl[0]) from the current patch offsets.
 hipError_t launch_layout(const GridDev &g, const SpArgs &sa, Unit *units, int *qctl,
                          hipStream_t st);
+// x-bins: off[P] = boff[nb * P] for P in [0, npatch] (the offsets of the
+// patches, each made of nb consecutive bins).
+hipError_t launch_api_offsets(const int64_t *boff, int64_t *off, int64_t npatch, int nb,
+                              hipStream_t st);
 hipError_t launch_interp_push(const GridDev &g, const SpArgs &sa, const double *const e[3],
                               const double *const b[3], int *err, int wg, hipStream_t st);
 hipError_t launch_project(const GridDev &g, const SpArgs &sa, double *const j[3], int *err,

@@ -544,6 +544,13 @@ __global__ void k_zero(double *a, double *b, double *c, int64_t n) {
   }
 }
 
+// x-bins: patch offsets from bin offsets.
+__global__ void __launch_bounds__(256) k_api_offsets(const int64_t *boff, int64_t *off, int64_t n,
+                                                     int nb) {
+  const int64_t P = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (P < n) off[P] = boff[P * nb];
+}
+
 }  // namespace
 
 size_t lds_bytes_ipp(const GridDev &g) { return tile_eb_bytes(g) + tile_j_bytes(g); }
@@ -626,6 +633,14 @@ hipError_t launch_rebin(const GridDev &g, const SpArgs &sa, int *err, int64_t ma
     hipLaunchKernelGGL(k_place<false>, grid, dim3(kSeg), 0, st, g, sa, err);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   hipLaunchKernelGGL(k_copy_offsets, dim3((g.npatch + 256) / 256, sa.nsp), dim3(256), 0, st, g, sa);
+  return hipGetLastError();
+}
+
+hipError_t launch_api_offsets(const int64_t *boff, int64_t *off, int64_t npatch, int nb,
+                              hipStream_t st) {
+  const int64_t n = npatch + 1;
+  hipLaunchKernelGGL(k_api_offsets, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, boff, off,
+                     n, nb);
   return hipGetLastError();
 }
 

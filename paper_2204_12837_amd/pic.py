@@ -35,7 +35,8 @@ class PicError(RuntimeError):
 class ConfigC(C.Structure):
     _fields_ = [("dim", C.c_int32), ("n", C.c_int32 * 3), ("d", C.c_double * 3), ("dt", C.c_double),
                 ("patch", C.c_int32 * 3), ("shape_order", C.c_int32), ("mode", C.c_int32),
-                ("chunk", C.c_int32), ("wg_size", C.c_int32), ("flags", C.c_uint32)]
+                ("chunk", C.c_int32), ("wg_size", C.c_int32), ("flags", C.c_uint32),
+                ("bin_x", C.c_int32)]
 
 
 class SpeciesC(C.Structure):
@@ -53,7 +54,8 @@ class CotangentC(C.Structure):
     _fields_ = [("x", C.c_void_p * 3), ("u", C.c_void_p * 3), ("n", C.c_int64)]
 
 
-ENTRY_POINTS = ("pic_validate_config", "pic_num_patches", "pic_init", "pic_free", "pic_bin",
+ENTRY_POINTS = ("pic_validate_config", "pic_num_patches", "pic_bin_width", "pic_init", "pic_free",
+                "pic_bin",
                 "pic_interp_push", "pic_project", "pic_step", "pic_check", "pic_last_error",
                 "pic_timing_enable", "pic_timing_read", "pic_adjoint")
 KERNELS = {"zero": 0, "ipp": 1, "rebin": 2, "interp_push": 3, "project": 4, "tag": 5, "sort": 6,
@@ -74,6 +76,8 @@ def lib():
         L.pic_validate_config.restype = C.c_int
         L.pic_num_patches.argtypes = [C.POINTER(ConfigC)]
         L.pic_num_patches.restype = C.c_int64
+        L.pic_bin_width.argtypes = [C.POINTER(ConfigC)]
+        L.pic_bin_width.restype = C.c_int32
         L.pic_init.argtypes = [C.POINTER(ConfigC), C.c_int32, C.POINTER(C.c_void_p)]
         L.pic_init.restype = C.c_int
         L.pic_free.argtypes = [C.c_void_p]
@@ -106,8 +110,9 @@ def lib():
     return _lib_handle
 
 
-def make_config(wl, mode=MODE_PER_PATCH, chunk=0, wg_size=0, flags=0) -> ConfigC:
-    """Config struct from a workload description (dim, n, d, dt, patch)."""
+def make_config(wl, mode=MODE_PER_PATCH, chunk=0, wg_size=0, flags=0, bin_x=0) -> ConfigC:
+    """Config struct from a workload description (dim, n, d, dt, patch);
+    bin_x = 0 lets the library choose the x-bin width."""
     c = ConfigC()
     c.dim = wl.dim
     for a in range(3):
@@ -117,6 +122,7 @@ def make_config(wl, mode=MODE_PER_PATCH, chunk=0, wg_size=0, flags=0) -> ConfigC
     c.dt = float(wl.dt)
     c.shape_order = 2
     c.mode, c.chunk, c.wg_size, c.flags = mode, chunk, wg_size, flags
+    c.bin_x = bin_x
     return c
 
 
@@ -237,14 +243,17 @@ class Context:
     """A library context (pic_init / pic_free)."""
 
     def __init__(self, wl, device: int = 0, mode=MODE_PER_PATCH, chunk=0, wg_size=0,
-                 check=False, graph=False):
+                 check=False, graph=False, bin_x=0):
         self.wl = wl
         flags = (FLAG_CHECK if check else 0) | (FLAG_GRAPH if graph else 0)
-        self.cfg = make_config(wl, mode, chunk, wg_size, flags)
+        self.cfg = make_config(wl, mode, chunk, wg_size, flags, bin_x)
         rc, msg = validate(self.cfg)
         if rc:
             raise PicError(rc, msg)
         self.n_patches = int(lib().pic_num_patches(C.byref(self.cfg)))
+        self.bin_width = int(lib().pic_bin_width(C.byref(self.cfg)))
+        # slabs of pic_step's slab layout: one per x-bin
+        self.n_slabs = self.n_patches * (int(self.cfg.patch[0]) // self.bin_width)
         h = C.c_void_p()
         rc = lib().pic_init(C.byref(self.cfg), device, C.byref(h))
         if rc:
@@ -315,15 +324,18 @@ class Context:
         return out
 
 
-def upload(inputs, device="cuda", capacity_factor: Optional[float] = None) -> List[Species]:
+def upload(inputs, device="cuda", capacity_factor: Optional[float] = None,
+           n_slabs: Optional[int] = None) -> List[Species]:
     """Device species from generated inputs (a list of ParticleSet); buffers
-    of capacity_factor * n particles, or slab_capacity(n, n_patches)."""
+    of capacity_factor * n particles, or slab_capacity(n, n_slabs) (n_slabs:
+    Context.n_slabs, by default the number of patches)."""
     out = []
     npch = inputs.wl.n_patches
+    ns = npch if n_slabs is None else int(n_slabs)
     for s in inputs.species:
         t = lambda a: torch.from_numpy(a).to(device)
         n = s.x.shape[1]
-        cap = slab_capacity(n, npch) if capacity_factor is None else int(n * capacity_factor)
+        cap = slab_capacity(n, ns) if capacity_factor is None else int(n * capacity_factor)
         out.append(Species(s.q, s.m, t(s.x), t(s.u), t(s.wt), t(s.id), npch, capacity=cap))
     return out
 

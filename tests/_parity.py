@@ -23,7 +23,7 @@ def run_oracle(wl, inp, steps, with_abs=True):
 
 
 def run_gpu(wl, inp, steps, mode=0, chunk=0, wg_size=0, split=False, device="cuda:0",
-            graph=False, step_sizes=None, capacity_factor=None):
+            graph=False, step_sizes=None, capacity_factor=None, bin_x=0):
     """capacity_factor None gives the buffers room for pic_step's slab
     layout (used for calls of three steps or more); 1.0 keeps the dense
     layout with the permutation sort."""
@@ -32,8 +32,8 @@ def run_gpu(wl, inp, steps, mode=0, chunk=0, wg_size=0, split=False, device="cud
     from paper_2204_12837_amd import pic
 
     ctx = pic.Context(wl, device=0, mode=mode, chunk=chunk, wg_size=wg_size, check=True,
-                      graph=graph)
-    sp = pic.upload(inp, device, capacity_factor=capacity_factor)
+                      graph=graph, bin_x=bin_x)
+    sp = pic.upload(inp, device, capacity_factor=capacity_factor, n_slabs=ctx.n_slabs)
     E, B, J = pic.upload_fields(inp, device)
     ctx.bin(sp)
     if split:

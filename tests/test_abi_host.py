@@ -62,6 +62,32 @@ def test_workgroup_limits_per_dimension():
         assert (rc == pic.PIC_OK) == ok, (wg, msg)
 
 
+def test_x_bins_of_large_patches():
+    """A patch whose E/B and J tiles exceed the LDS is cut into x-bins: the
+    widest divisor of patch[0] whose tiles fit (auto), or bin_x when given;
+    bin_x must divide patch[0], and a patch that fits keeps one bin."""
+    bw = lambda wl, bx=0: pic.lib().pic_bin_width(C.byref(pic.make_config(wl, bin_x=bx)))
+    small = I.workload("uniform1024")
+    assert bw(small) == 16 and bw(small, 8) == 8
+    big = I.workload("uniform1024", patch=(64, 128, 1))  # tiles of 64 x 128 cells: 0.63 MB
+    assert pic.lib().pic_num_patches(C.byref(pic.make_config(big))) == 128
+    b = bw(big)
+    # 8 cells: (8+3)(128+3) x 6 + (8+5)(128+5) x 3 doubles = 110 KB
+    assert b == 8, b
+    assert bw(big, 4) == 4
+    rc, msg = pic.validate(pic.make_config(big, bin_x=16))  # 186 KB of tiles
+    assert rc == pic.PIC_ERR_ARG and "LDS" in msg, msg
+    rc, msg = pic.validate(pic.make_config(big, bin_x=6))
+    assert rc == pic.PIC_ERR_ARG and "bin_x" in msg, msg
+    rc, msg = pic.validate(pic.make_config(small, bin_x=-2))
+    assert rc == pic.PIC_ERR_ARG and "bin_x" in msg, msg
+    big3 = I.custom(3, (24, 24, 24), (12, 12, 12), ppc=1)
+    assert bw(big3) == 4  # 12-, 6-cell bins do not fit; (4+3)(15)(15) x 6 + (9)(17)(17) x 3
+    huge3 = I.custom(3, (32, 32, 32), (32, 32, 32), ppc=1)
+    rc, msg = pic.validate(pic.make_config(huge3))
+    assert rc == pic.PIC_ERR_ARG and "LDS" in msg, msg
+
+
 @pytest.mark.parametrize("over,frag", [
     (dict(dim=4), "dim"),
     (dict(shape_order=1), "shape_order"),
@@ -85,12 +111,16 @@ def test_invalid_configs_rejected(over, frag):
 
 
 def test_patch_too_large_for_lds():
+    """Tiles of one bin spanning the whole patch do not fit: rejected when
+    bin_x asks for that, accepted with narrower automatic x-bins."""
     wl = I.custom(2, (128, 128), (64, 64), ppc=1)
-    rc, msg = pic.validate(pic.make_config(wl))
+    rc, msg = pic.validate(pic.make_config(wl, bin_x=64))
     assert rc == pic.PIC_ERR_ARG and "LDS" in msg
+    assert pic.validate(pic.make_config(wl))[0] == pic.PIC_OK
     wl3 = I.custom(3, (32, 32, 32), (16, 16, 16), ppc=1)
-    rc, msg = pic.validate(pic.make_config(wl3))
+    rc, msg = pic.validate(pic.make_config(wl3, bin_x=16))
     assert rc == pic.PIC_ERR_ARG and "LDS" in msg
+    assert pic.lib().pic_bin_width(C.byref(pic.make_config(wl3))) == 1
 
 
 def test_null_arguments():

@@ -27,13 +27,13 @@ from _window import margin_cells, oracle_window, window_nodes, window_patches
 pytestmark = pytest.mark.gpu
 
 
-def _gpu_run(wl, inp, steps, mode, chunk, wg):
+def _gpu_run(wl, inp, steps, mode, chunk, wg, bin_x=0):
     import torch
 
     from paper_2204_12837_amd import pic
 
-    ctx = pic.Context(wl, device=0, mode=mode, chunk=chunk, wg_size=wg, check=True)
-    sp = pic.upload(inp, "cuda:0")
+    ctx = pic.Context(wl, device=0, mode=mode, chunk=chunk, wg_size=wg, check=True, bin_x=bin_x)
+    sp = pic.upload(inp, "cuda:0", n_slabs=ctx.n_slabs)
     E, B, J = pic.upload_fields(inp, "cuda:0")
     ctx.bin(sp)
     ctx.step(sp, E, B, J, nsteps=steps)
@@ -87,8 +87,8 @@ def _check_window(wl, inp, steps, sp_gpu, Jg, a0, npw):
     return total
 
 
-def _run(name, steps, mode, chunk, wg, windows):
-    wl = I.workload(name)
+def _run(name, steps, mode, chunk, wg, windows, **over):
+    wl = I.workload(name, **over)
     inp = I.generate(wl)
     n = sum(s.id.size for s in inp.species)
     say(f"case {name} full size ({n} particles), {steps} steps, mode={mode} chunk={chunk} wg={wg}")
@@ -119,3 +119,10 @@ def test_imbalanced(mode):
 def test_expansion3d_persistent():
     """3D, two species, persistent launch (chunk 4096, 512 threads)."""
     _run("expansion3d", 5, 1, 4096, 512, [((120, 56, 56), (2, 2, 2)), ((248, 120, 0), (2, 2, 1))])
+
+
+def test_uniform1024_large_patches():
+    """Patches of 64 x 128 cells (automatic 8-cell x-bins), per-patch launch:
+    one window across the periodic corner."""
+    _run("uniform1024", 10, 0, 0, 0, [((-64, -128), (1, 1)), ((448, 384), (2, 1))],
+         patch=(64, 128, 1))

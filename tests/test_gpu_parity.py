@@ -226,3 +226,41 @@ def test_patch_beyond_the_departure_bitmap(mode, ppc):
     say(f"case large patches mode={mode} ppc={ppc}: max patch count {counts.max()}")
     assert counts.max() > (16384 if ppc < 100 else 65536)
     run_cmp(wl, inp, steps, "slab", osp, J, A, mode=mode, chunk=2048)
+
+
+BIN_CASES = [
+    # dim, n, patch, bin_x, ppc, nspecies, sigma, steps, seed
+    (2, (128, 64), (64, 64), 0, 2, 1, 0.3, 4, 501),        # automatic 16-cell bins
+    (2, (96, 48), (48, 24), 8, 3, 2, 0.3, 3, 502),         # bins asked for: 8 cells
+    (3, (24, 24, 24), (12, 12, 12), 0, 1, 2, 0.3, 3, 503),  # automatic 4-cell bins
+]
+
+
+@pytest.mark.parametrize("layout", list(LAYOUTS))
+@pytest.mark.parametrize("mode", [0, 1])
+@pytest.mark.parametrize("case", BIN_CASES)
+def test_x_bins(case, mode, layout):
+    """Patches cut into x-bins: same per-patch counts, particle sets and
+    values, and J as the oracle's patch-level run; inside a patch the
+    particles are ordered by bin."""
+    dim, n, patch, bx, ppc, nsp, sigma, steps, seed = case
+    wl = I.custom(dim, n, patch, ppc=ppc, seed=seed, sigma=sigma, n_species=nsp)
+    inp = I.generate(wl)
+    say(f"case x-bins {case} mode={mode} {layout}")
+    osp, J, A = run_oracle(wl, inp, steps)
+    g, Jg = run_gpu(wl, inp, steps, mode=mode, chunk=512, bin_x=bx,
+                    capacity_factor=LAYOUTS[layout]["capacity_factor"])
+    compare(osp, J, A, g, Jg, exact_order=False)
+
+
+def test_x_bins_split_path_and_general_sort():
+    """The split sequence and pic_bin on unsorted input with x-bins."""
+    wl = I.custom(2, (128, 64), (64, 64), ppc=2, seed=510, sigma=0.3)
+    inp = I.generate(wl)
+    say("case x-bins split path")
+    osp, J, A = run_oracle(wl, inp, 3)
+    g, Jg = run_gpu(wl, inp, 3, split=True)
+    compare(osp, J, A, g, Jg, exact_order=False)
+    osp, _, _ = run_oracle(wl, inp, 0)
+    g, _ = run_gpu(wl, inp, 0)
+    compare(osp, None, None, g, None, exact_order=False)
