@@ -10,8 +10,9 @@ synthetic) and resident in HBM before the timed region starts.
 
 Prints one JSON line: particle-steps/s of the whole call, the roofline of
 the dominant kernel (the fused step kernel, HBM-bound by its bytes), the
-imbalanced workload next to the uniform one, the 3D two-species and adjoint
-workloads, and the CPU oracle timed on a bounded sample on the host.
+imbalanced workload next to the uniform one, the 3D two-species workload,
+the uniform plasma with patches too large for the LDS (x-bins), the adjoint
+workload, and the CPU oracle timed on a bounded sample on the host.
 """
 from __future__ import annotations
 
@@ -77,7 +78,7 @@ def cpu_model() -> str:
 
 
 def run_gpu(wl, steps: int, warmup: int, mode: int = 0, chunk: int = 0, wg: int = 0,
-            inp=None, graph: bool = False):
+            inp=None, graph: bool = False, bin_x: int = 0):
     """Timed pic_step on fresh device copies of the generated inputs.  With
     graph=False the library times each kernel class with HIP events on the
     launch stream; with graph=True steps replay captured graphs (no per-kernel
@@ -89,8 +90,8 @@ def run_gpu(wl, steps: int, warmup: int, mode: int = 0, chunk: int = 0, wg: int 
 
     inp = I.generate(wl) if inp is None else inp
     n = sum(s.x.shape[1] for s in inp.species)
-    ctx = pic.Context(wl, device=0, mode=mode, chunk=chunk, wg_size=wg, graph=graph)
-    sp = pic.upload(inp, "cuda:0")
+    ctx = pic.Context(wl, device=0, mode=mode, chunk=chunk, wg_size=wg, graph=graph, bin_x=bin_x)
+    sp = pic.upload(inp, "cuda:0", n_slabs=ctx.n_slabs)
     E, B, J = pic.upload_fields(inp, "cuda:0")
     ctx.bin(sp)
     if warmup:
@@ -150,6 +151,25 @@ def run_expansion3d(steps: int, warmup: int):
             "persistent": {"ns_per_particle_step": s_pe / (n * steps) * 1e9, "ipp_ms": ipp_pe,
                            "chunk": tuned["chunk"], "wg": tuned["wg"]},
             "ipp_hbm_frac_best": abytes / (min(ipp_pp, ipp_pe) * 1e-3) / 1e9 / HBM_PEAK_GBS}
+
+
+def run_large_patches(steps: int, warmup: int):
+    """The uniform plasma with patches of 64 x 128 cells, whose E/B and J
+    tiles exceed the LDS: the library cuts them into x-bins (per-patch
+    launch, automatic bin width)."""
+    import ctypes
+
+    from paper_2204_12837_amd import inputs as I
+    from paper_2204_12837_amd import pic
+
+    wl = I.workload("uniform1024", patch=(64, 128, 1))
+    n, secs, tim = run_gpu(wl, steps, warmup)
+    ipp = tim["ipp"][0] / tim["ipp"][1]
+    bx = int(pic.lib().pic_bin_width(ctypes.byref(pic.make_config(wl))))
+    return {"workload": "uniform1024", "patch": [64, 128], "bin_x": bx, "particles": n,
+            "steps": steps, "ns_per_particle_step": secs / (n * steps) * 1e9, "ipp_ms": ipp,
+            "ipp_hbm_frac": algorithmic_bytes(wl, n) / (ipp * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "kernel_ms": {k: round(v[0] / max(v[1], 1), 4) for k, v in tim.items() if v[1]}}
 
 
 def run_adjoint(every: int = 5):
@@ -244,6 +264,8 @@ def main(argv=None) -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-3d", action="store_true", help="skip the 3D two-species workload")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint workload")
+    ap.add_argument("--no-large-patches", action="store_true",
+                    help="skip the 64x128-cell patches (x-bins) workload")
     ap.add_argument("--cpu-steps", type=int, default=8)
     ap.add_argument("--copy-calibration", type=float, default=0.0, metavar="GIB",
                     help="only run a plain device copy of this many GiB (5 times), to scale "
@@ -320,6 +342,8 @@ def main(argv=None) -> int:
         }
     if not args.no_3d:
         out["expansion3d"] = run_expansion3d(min(args.steps, 50), args.warmup)
+    if not args.no_large_patches:
+        out["large_patches"] = run_large_patches(min(args.steps, 50), args.warmup)
     if not args.no_adjoint:
         out["adjoint"] = run_adjoint()
     out["cpu_baseline"] = None if args.no_cpu_baseline else cpu_baseline(args.cpu_steps)

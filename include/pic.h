@@ -87,9 +87,12 @@ typedef struct {
                           (patch, species, chunk) units from a device queue */
   int32_t chunk;       /* persistent mode: particles per work unit, a multiple
                           of 256 (0 = auto: 2048) */
-  int32_t wg_size;     /* threads per workgroup, a multiple of 64 up to 256 in
-                          2D and 1024 in 3D (0 = auto: 256 in 2D, 1024 in 3D);
-                          the dense-layout kernels use at most 512 in 3D */
+  int32_t wg_size;     /* threads per workgroup, a multiple of 64 up to 1024
+                          (0 = auto: 1024 in 3D; in 2D 256, or up to 1024 when
+                          the LDS tiles admit fewer than four workgroups per
+                          CU, as with x-bins of tall patches); the
+                          dense-layout kernels use at most 256 in 2D and 512
+                          in 3D */
   uint32_t flags;      /* PIC_FLAG_* */
   int32_t bin_x;       /* x-bins: width in cells of the bins a patch is cut
                           into along x (paper, sections "Parallelization

@@ -150,6 +150,18 @@ int choose_bin(const pic_config *c) {
   return 0;
 }
 
+// Default threads per workgroup of the slab-layout kernels: 1024 in 3D; in
+// 2D 256 when the LDS admits three or more workgroups per CU, else enough
+// threads for 16 waves per CU (the 128-register budget): 512 for two, 1024
+// for one.  The per-patch fused kernel's static LDS (departure bitmap and
+// prefix) is about 4 KB.
+int default_wg(const pic_config *c) {
+  if (c->dim == 3) return 1024;
+  const size_t per_wg = tiles_bytes(c, choose_bin(c)) + 4352;
+  const size_t per_cu = kLdsMax / per_wg;
+  return per_cu >= 3 ? 256 : per_cu == 2 ? 512 : 1024;
+}
+
 // Derived geometry of the kernels, whose patches are the x-bins; cfg must
 // be valid.
 GridDev make_grid(const pic_config *c) {
@@ -848,9 +860,8 @@ pic_status pic_validate_config(const pic_config *c, char *msg, size_t len) {
     set_msg(msg, len, "chunk must be 0 (auto) or a positive multiple of %d", kSeg);
     return PIC_ERR_ARG;
   }
-  const int wg_max = c->dim == 2 ? 256 : 1024;
-  if (c->wg_size != 0 && (c->wg_size < 64 || c->wg_size > wg_max || c->wg_size % 64)) {
-    set_msg(msg, len, "wg_size must be 0 or a multiple of 64 in [64, %d]", wg_max);
+  if (c->wg_size != 0 && (c->wg_size < 64 || c->wg_size > 1024 || c->wg_size % 64)) {
+    set_msg(msg, len, "wg_size must be 0 or a multiple of 64 in [64, 1024]");
     return PIC_ERR_ARG;
   }
   if (c->flags & ~(uint32_t)(PIC_FLAG_CHECK | PIC_FLAG_GRAPH)) {
@@ -904,7 +915,7 @@ pic_status pic_init(const pic_config *cfg, int32_t device, pic_ctx **out) {
   c->nb = c->cfg.patch[0] / c->g.patch[0];
   c->npatch_api = c->g.npatch / c->nb;
   c->device = device;
-  c->wg = cfg->wg_size ? cfg->wg_size : (c->cfg.dim == 2 ? 256 : 1024);
+  c->wg = cfg->wg_size ? cfg->wg_size : default_wg(&c->cfg);
   c->wgd = std::min(c->wg, c->cfg.dim == 2 ? 256 : 512);
   const int chunk = cfg->chunk ? cfg->chunk : 2048;
   c->g.spc = std::max(1, chunk / kSeg);

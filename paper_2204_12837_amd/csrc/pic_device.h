@@ -13,14 +13,15 @@ namespace pic {
 namespace {
 
 
-// Largest workgroup per dimension: 3D tiles take most of a CU's LDS, so a
-// 3D workgroup runs alone on its CU and needs more waves to hide latency.
-// The slab-layout kernels fit 128 registers and take 1024 threads in 3D
-// (four waves per SIMD on one tile); the dense-layout ones stop at 512.
+// Largest workgroup per dimension: 3D tiles (and 2D x-bins of tall
+// patches) take most of a CU's LDS, so such a workgroup runs alone on its CU
+// and needs more waves to hide latency.  The slab-layout kernels fit 128
+// registers and take 1024 threads (four waves per SIMD on one tile); the
+// dense-layout ones stop at 256 in 2D and 512 in 3D.
 template <int DIM>
 constexpr int kMaxWg = DIM == 2 ? 256 : 512;
 template <int DIM>
-constexpr int kMaxWgSlab = DIM == 2 ? 256 : 1024;
+constexpr int kMaxWgSlab = 1024;
 // Waves per SIMD the register allocation must allow: four in 2D (a 2D
 // workgroup's tiles take ~28 KB, so LDS admits several per CU), two in 3D.
 template <int DIM>

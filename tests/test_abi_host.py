@@ -54,12 +54,13 @@ def test_valid_configs_pass():
     assert pic.lib().pic_num_patches(C.byref(pic.make_config(I.workload("expansion3d")))) == 8192
 
 
-def test_workgroup_limits_per_dimension():
-    """Up to 256 threads in 2D, 1024 in 3D (multiples of 64)."""
-    wl3 = I.custom(3, (16, 16, 16), (8, 8, 8), ppc=1)
-    for wg, ok in ((1024, True), (576, True), (1088, False), (1000, False)):
-        rc, msg = pic.validate(pic.make_config(wl3, wg_size=wg))
-        assert (rc == pic.PIC_OK) == ok, (wg, msg)
+def test_workgroup_limits():
+    """Multiples of 64 up to 1024 threads, in 2D and 3D."""
+    for wl in (I.custom(3, (16, 16, 16), (8, 8, 8), ppc=1), I.custom(2, (32, 32), (8, 8), ppc=1)):
+        for wg, ok in ((1024, True), (576, True), (64, True), (1088, False), (1000, False),
+                       (0, True), (32, False)):
+            rc, msg = pic.validate(pic.make_config(wl, wg_size=wg))
+            assert (rc == pic.PIC_OK) == ok, (wg, msg)
 
 
 def test_x_bins_of_large_patches():
@@ -98,7 +99,7 @@ def test_x_bins_of_large_patches():
     (dict(d=(0.0, 0.1, 0.1)), "positive"),
     (dict(mode=7), "mode"),
     (dict(wg_size=100), "wg_size"),
-    (dict(wg_size=512), "wg_size"),
+    (dict(wg_size=1280), "wg_size"),
     (dict(flags=0x80), "flag"),
     (dict(n=(64, 64, 2)), "2D"),
     (dict(chunk=-1), "chunk"),

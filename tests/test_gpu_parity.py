@@ -49,7 +49,7 @@ def test_split_path_equals_oracle():
     compare(osp, J, A, g, Jg, exact_order=True)
 
 
-@pytest.mark.parametrize("wg", [64, 128, 192])
+@pytest.mark.parametrize("wg", [64, 128, 192, 512, 1024])
 def test_workgroup_sizes(wg):
     wl = I.custom(2, (48, 32), (8, 8), ppc=5, seed=40 + wg, sigma=0.1)
     inp = I.generate(wl)
