@@ -53,6 +53,8 @@ def _lib(name: str = "liborc.so"):
         lib.orc_fd.argtypes = [C.POINTER(Grid), C.c_double, C.c_double, C.c_int64, _DP * 3,
                                _DP * 3, _DP, _DP * 3, _DP * 3, _DP * 3, C.c_void_p, C.c_void_p,
                                C.c_void_p, C.c_int64, C.c_double, _DP, _DP]
+        lib.orc_maxwell.argtypes = [C.POINTER(Grid), _DP * 3, _DP * 3, _DP * 3, C.c_int64]
+        lib.orc_maxwell.restype = None
         lib.orc_real_size.restype = C.c_int32
         _libs[name] = lib
     return _libs[name]
@@ -203,6 +205,17 @@ def rho(wl, q, x, w) -> np.ndarray:
     _lib().orc_rho(C.byref(grid(wl)), q, x.shape[1], _arr3([x[a] for a in range(x.shape[0])]),
                    _p(w), _p(r.reshape(-1)))
     return r
+
+
+def maxwell(wl, E, B, J, nsteps: int = 1, lib="liborc.so"):
+    """nsteps Yee updates (Ampere, then Faraday) of copies of E and B with the
+    current J; returns the new (E, B), each (3, nz, ny, nx)."""
+    E = np.array(E, dtype=np.float64, order="C", copy=True)
+    B = np.array(B, dtype=np.float64, order="C", copy=True)
+    Jc = np.ascontiguousarray(J, dtype=np.float64)
+    Ef, Bf, Jf = E.reshape(3, -1), B.reshape(3, -1), Jc.reshape(3, -1)
+    _lib(lib).orc_maxwell(C.byref(grid(wl)), _arr3(Ef), _arr3(Bf), _arr3(Jf), int(nsteps))
+    return E, B
 
 
 def _opt3(a: Optional[np.ndarray], keep: list):

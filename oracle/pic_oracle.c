@@ -596,6 +596,67 @@ void orc_rho(const orc_grid *gi, double q, int64_t n, const double *const x[3], 
 }
 
 /* ---------------------------------------------------------------------- */
+/* Yee field solver: Ampere for every node, then Faraday with the new E. */
+void orc_maxwell(const orc_grid *gi, double *const E[3], double *const B[3],
+                 const double *const J[3], int64_t nsteps) {
+  G g;
+  mk_grid(gi, &g);
+  const int three = g.dim == 3;
+  const real dt = g.dt;
+  const real cx = dt / g.d[0], cy = dt / g.d[1], cz = three ? dt / g.d[2] : (real)0;
+  for (int64_t s = 0; s < nsteps; s++) {
+    for (int64_t k = 0; k < g.n[2]; k++)
+      for (int64_t j = 0; j < g.n[1]; j++)
+        for (int64_t i = 0; i < g.n[0]; i++) {
+          const int64_t o = node(&g, i, j, k);
+          const int64_t xm = node(&g, i - 1, j, k), ym = node(&g, i, j - 1, k);
+          const real dyBz = (real)B[2][o] - (real)B[2][ym];
+          const real dxBz = (real)B[2][o] - (real)B[2][xm];
+          const real dxBy = (real)B[1][o] - (real)B[1][xm];
+          const real dyBx = (real)B[0][o] - (real)B[0][ym];
+          real ex = (real)E[0][o] + cy * dyBz;
+          real ey = (real)E[1][o];
+          if (three) {
+            const int64_t zm = node(&g, i, j, k - 1);
+            const real dzBy = (real)B[1][o] - (real)B[1][zm];
+            const real dzBx = (real)B[0][o] - (real)B[0][zm];
+            ex = ex - cz * dzBy;
+            ey = ey + cz * dzBx;
+          }
+          ey = ey - cx * dxBz;
+          real ez = ((real)E[2][o] + cx * dxBy) - cy * dyBx;
+          E[0][o] = (double)(ex - dt * (real)J[0][o]);
+          E[1][o] = (double)(ey - dt * (real)J[1][o]);
+          E[2][o] = (double)(ez - dt * (real)J[2][o]);
+        }
+    for (int64_t k = 0; k < g.n[2]; k++)
+      for (int64_t j = 0; j < g.n[1]; j++)
+        for (int64_t i = 0; i < g.n[0]; i++) {
+          const int64_t o = node(&g, i, j, k);
+          const int64_t xp = node(&g, i + 1, j, k), yp = node(&g, i, j + 1, k);
+          const real dyEz = (real)E[2][yp] - (real)E[2][o];
+          const real dxEz = (real)E[2][xp] - (real)E[2][o];
+          const real dxEy = (real)E[1][xp] - (real)E[1][o];
+          const real dyEx = (real)E[0][yp] - (real)E[0][o];
+          real bx = (real)B[0][o] - cy * dyEz;
+          real by = (real)B[1][o];
+          if (three) {
+            const int64_t zp = node(&g, i, j, k + 1);
+            const real dzEy = (real)E[1][zp] - (real)E[1][o];
+            const real dzEx = (real)E[0][zp] - (real)E[0][o];
+            bx = bx + cz * dzEy;
+            by = by - cz * dzEx;
+          }
+          by = by + cx * dxEz;
+          const real bz = ((real)B[2][o] - cx * dxEy) + cy * dyEx;
+          B[0][o] = (double)bx;
+          B[1][o] = (double)by;
+          B[2][o] = (double)bz;
+        }
+  }
+}
+
+/* ---------------------------------------------------------------------- */
 /* Derivatives of L = sum W . J_final (2D3V).  Fields are static and J is
  * rebuilt from zero at every step, so only the last step's deposit reaches
  * L, and every particle can be advanced on its own; the sort is a

@@ -107,6 +107,26 @@ int orc_fd(const orc_grid *g, double q, double m, int64_t n, const double *const
            const double *const dE[3], const double *const dB[3], int64_t nsteps, double h,
            double *fd, double *L0);
 
+/* Field solver of the PIC loop (the paper's loop solves Maxwell's equations
+ * on the grid with the projected current as source, section "Parallelization
+ * without tasks"; the scheme is Yee's finite-difference time-domain method,
+ * normalised units c = 1): nsteps times, with the same J,
+ *   E <- E + dt (curl B - J)    (Ampere; B at the half step),
+ *   B <- B - dt curl E          (Faraday; with the new E),
+ * the curls as differences of neighbouring staggered values over the cell
+ * size, periodic.  With c_a = dt / d_a, per component and in this order:
+ *   Ex <- ((Ex + c_y dy Bz) - c_z dz By) - dt Jx     dy Bz = Bz(j) - Bz(j-1) ...
+ *   Ey <- ((Ey + c_z dz Bx) - c_x dx Bz) - dt Jy
+ *   Ez <- ((Ez + c_x dx By) - c_y dy Bx) - dt Jz
+ *   Bx <- (Bx - c_y dy Ez) + c_z dz Ey               dy Ez = Ez(j+1) - Ez(j) ...
+ *   By <- (By - c_z dz Ex) + c_x dx Ez
+ *   Bz <- (Bz - c_x dx Ey) + c_y dy Ex
+ * (backward differences of B, forward differences of E, as the staggering
+ * puts them); in 2D the z differences are absent and their terms dropped.
+ * Arrays are updated in place. */
+void orc_maxwell(const orc_grid *g, double *const E[3], double *const B[3],
+                 const double *const J[3], int64_t nsteps);
+
 /* sizeof(real) of this build */
 int32_t orc_real_size(void);
 

@@ -44,7 +44,7 @@ class _G:
     def __init__(self, dim, n, d=0.1, patch=None, dt=None):
         self.dim = dim
         self.n = tuple(n) + (1,) * (3 - len(n))
-        self.d = (d, d, d)
+        self.d = tuple(d) if isinstance(d, tuple) else (d, d, d)
         self.patch = tuple(patch or self.n[:dim]) + (1,) * (3 - dim)
         self.dt = dt if dt is not None else I.cfl_dt(self.d, dim)
 
@@ -646,3 +646,136 @@ def test_window_of_particles_reproduces_the_full_run(dim):
     ids = lambda sps: [np.sort(np.concatenate([s.id[s.off[P]:s.off[P + 1]] for P in patches]))
                        for s in sps]
     assert any(not np.array_equal(a, b) for a, b in zip(ids(sub0), ids(full)))
+
+
+# --------------------------------------------------------------------------
+# field solver (Yee): pins from the Fourier symbol of the staggered
+# differences, the vector identities div curl = 0, the continuity of the
+# deposit, and energy conservation of the leapfrog
+
+E_STAG = ((1, 0, 0), (0, 1, 0), (0, 0, 1))
+B_STAG = ((0, 1, 1), (1, 0, 1), (1, 1, 0))
+
+
+def _phase(g, st, k):
+    """k . x at every entry of a component with stagger bits st."""
+    nz, ny, nx = field_shape(g)
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    ph = k[0] * (x + st[0] / 2) * g.d[0] + k[1] * (y + st[1] / 2) * g.d[1]
+    if g.dim == 3:
+        ph = ph + k[2] * (z + st[2] / 2) * g.d[2]
+    return ph
+
+
+def _mode(g, amp, stag, k, t_phase):
+    return np.stack([np.real(amp[c] * np.exp(1j * (_phase(g, stag[c], k) - t_phase)))
+                     for c in range(3)])
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_maxwell_plane_wave_follows_the_yee_dispersion(dim):
+    """A Fourier mode of the staggered grid evolves exactly as the Yee
+    scheme's symbol says: the differences act as i kappa with
+    kappa_a = 2 sin(k_a d_a / 2) / d_a, and the leapfrog turns |kappa| into
+    the frequency omega with sin(omega dt / 2) = dt |kappa| / 2.  Two
+    polarisations, unequal cell sizes, 40 steps."""
+    n = (24, 20, 16)[:dim]
+    d = (0.1, 0.13, 0.08)
+    dt = 0.9 * I.cfl_dt(d, dim)
+    g = _G(dim, n, d=d, dt=dt)
+    m = (3, -2, 1)
+    k = np.array([2 * np.pi * m[a] / (g.n[a] * d[a]) if a < dim else 0.0 for a in range(3)])
+    kap = np.array([2 * np.sin(k[a] * d[a] / 2) / d[a] if a < dim else 0.0 for a in range(3)])
+    om_t = np.linalg.norm(kap)
+    omega = 2 / dt * np.arcsin(dt * om_t / 2)
+    a1 = np.cross(kap, [0.3, -0.2, 1.0])
+    a1 /= np.linalg.norm(a1)
+    a2 = np.cross(kap, a1) / om_t
+    N = 40
+    for A in (a1, a2):
+        A = A * np.exp(0.7j)
+        Bh = np.cross(kap, A) / om_t
+        E0 = _mode(g, A, E_STAG, k, 0.0)
+        B0 = _mode(g, Bh, B_STAG, k, omega * dt / 2)
+        E1, B1 = O.maxwell(g, E0, B0, np.zeros_like(E0), N)
+        Ee = _mode(g, A, E_STAG, k, omega * N * dt)
+        Be = _mode(g, Bh, B_STAG, k, omega * (N + 0.5) * dt)
+        assert np.abs(E1 - Ee).max() <= 1e-11, np.abs(E1 - Ee).max()
+        assert np.abs(B1 - Be).max() <= 1e-11, np.abs(B1 - Be).max()
+        assert np.abs(E1 - E0).max() > 0.1  # the wave moved
+
+
+def _divB(g, B):
+    out = np.zeros(B.shape[1:])
+    for a in range(g.dim):
+        ax = 2 - a
+        out += (np.roll(B[a], -1, axis=ax) - B[a]) / g.d[a]
+    return out
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_maxwell_keeps_div_b(dim):
+    """div B at cell centres is unchanged by any number of steps (the
+    discrete divergence of a discrete curl vanishes), whatever E, B and J."""
+    g = _G(dim, (10, 12, 8)[:dim], d=(0.1, 0.12, 0.09))
+    rng = np.random.default_rng(31)
+    shp = (3,) + field_shape(g)
+    E, B, J = rng.standard_normal(shp), rng.standard_normal(shp), rng.standard_normal(shp)
+    E1, B1 = O.maxwell(g, E, B, J, 5)
+    assert np.abs(B1 - B).max() > 0.1
+    assert np.abs(_divB(g, B1) - _divB(g, B)).max() <= 1e-12 / min(g.d[:dim])
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_maxwell_keeps_gauss_law_with_the_deposited_current(dim):
+    """With the current of a particle step, div E changes by exactly the
+    change of the charge density: Gauss's law is preserved (Yee's Ampere
+    update plus the deposit's discrete continuity)."""
+    if dim == 2:
+        wl = I.workload("uniform64")
+    else:
+        wl = I.custom(3, (16, 16, 16), (8, 8, 8), ppc=2, seed=15, n_species=2, sigma=0.05)
+    inp = I.generate(wl)
+    sps = O.species_from(inp)
+    for s in sps:
+        O.bin(wl, s)
+    rho0 = sum(O.rho(wl, s.q, s.x, s.w) for s in sps)
+    J = O.step(wl, sps, inp.E, inp.B)
+    rho1 = sum(O.rho(wl, s.q, s.x, s.w) for s in sps)
+    E1, _ = O.maxwell(wl, inp.E, inp.B, J, 1)
+    res = _div(wl, E1) - _div(wl, inp.E) - (rho1 - rho0)
+    scale = max(np.abs(rho0).max(), np.abs(inp.E).max() / min(wl.d[:dim]))
+    assert np.abs(res).max() <= 1e-12 * scale
+    assert np.abs(rho1 - rho0).max() > 1e-6 * np.abs(rho0).max()  # charges moved
+
+
+def test_maxwell_conserves_the_leapfrog_energy():
+    """Without current, sum |E^n|^2 + B^(n-1/2) . B^(n+1/2) is conserved by the
+    Yee leapfrog (to rounding) while the fields change."""
+    g = _G(2, (16, 14), d=(0.1, 0.11, 1.0))
+    rng = np.random.default_rng(32)
+    shp = (3,) + field_shape(g)
+    E, B = rng.standard_normal(shp), rng.standard_normal(shp)
+    E_init = E.copy()
+    Z = np.zeros(shp)
+    W = []
+    for _ in range(50):
+        E1, B1 = O.maxwell(g, E, B, Z, 1)
+        W.append((E1 * E1).sum() + (B * B1).sum())
+        E, B = E1, B1
+    W = np.array(W)
+    assert np.abs(W - W[0]).max() <= 1e-12 * W[0]
+    assert np.abs(E - E_init).max() > 0.1
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_maxwell_uniform_fields_and_current(dim):
+    """Uniform fields have no curl: B stays, E changes by -dt J exactly."""
+    g = _G(dim, (8, 6, 4)[:dim])
+    shp = (3,) + field_shape(g)
+    E = np.ones(shp) * np.array([0.3, -0.7, 1.1])[:, None, None, None]
+    B = np.ones(shp) * np.array([-0.2, 0.5, 0.9])[:, None, None, None]
+    J = np.ones(shp) * np.array([0.01, 0.02, -0.03])[:, None, None, None]
+    E1, B1 = O.maxwell(g, E, B, J, 1)
+    assert np.array_equal(B1, B)
+    assert np.array_equal(E1, E - g.dt * J)
