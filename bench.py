@@ -11,8 +11,9 @@ synthetic) and resident in HBM before the timed region starts.
 Prints one JSON line: particle-steps/s of the whole call, the roofline of
 the dominant kernel (the fused step kernel, HBM-bound by its bytes), the
 imbalanced workload next to the uniform one, the 3D two-species workload,
-the uniform plasma with patches too large for the LDS (x-bins), the adjoint
-workload, and the CPU oracle timed on a bounded sample on the host.
+the uniform plasma with patches too large for the LDS (x-bins), the field
+solver on the 2D and 3D grids, the adjoint workload, and the CPU oracle
+timed on a bounded sample on the host.
 """
 from __future__ import annotations
 
@@ -172,6 +173,44 @@ def run_large_patches(steps: int, warmup: int):
             "kernel_ms": {k: round(v[0] / max(v[1], 1), 4) for k, v in tim.items() if v[1]}}
 
 
+def run_maxwell(steps: int = 50):
+    """The field solver (pic_maxwell) on the 2D benchmark grid (1024^2) and
+    the 3D one (256x128x128): ms per Yee step and GB/s of its algorithmic
+    bytes (96 B per node for Ampere + 72 B for Faraday)."""
+    import numpy as np
+    import torch
+
+    from paper_2204_12837_amd import inputs as I
+    from paper_2204_12837_amd import pic
+
+    out = {}
+    for name in ("uniform1024", "expansion3d"):
+        wl = I.workload(name)
+        rng = np.random.default_rng(7)
+        shp = (3, wl.n[2] if wl.dim == 3 else 1, wl.n[1], wl.n[0])
+        E, B, J = (torch.from_numpy(rng.standard_normal(shp) * 1e-3).to("cuda:0")
+                   for _ in range(3))
+        ctx = pic.Context(wl)
+        ctx.maxwell(E, B, J, 2)
+        torch.cuda.synchronize()
+        ctx.timing(True)
+        t0 = time.perf_counter()
+        ctx.maxwell(E, B, J, steps)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        ms, n = ctx.timing_read()["maxwell"]
+        ctx.timing(False)
+        ctx.check()
+        ctx.close()
+        cells = wl.n_cells
+        kern = ms / n
+        gbs = 168.0 * cells / (kern * 1e-3) / 1e9
+        out[name] = {"cells": cells, "steps": steps, "ms_per_step": (t1 - t0) / steps * 1e3,
+                     "kernel_ms_per_step": kern, "algorithmic_GBs": gbs,
+                     "hbm_frac": gbs / HBM_PEAK_GBS}
+    return out
+
+
 def run_adjoint(every: int = 5):
     """Forward (with checkpoints) and backward of the adjoint workload:
     L = sum W.J after 20 steps of 256^2 cells x 16 ppc, gradients with
@@ -264,6 +303,7 @@ def main(argv=None) -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-3d", action="store_true", help="skip the 3D two-species workload")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint workload")
+    ap.add_argument("--no-maxwell", action="store_true", help="skip the field solver")
     ap.add_argument("--no-large-patches", action="store_true",
                     help="skip the 64x128-cell patches (x-bins) workload")
     ap.add_argument("--cpu-steps", type=int, default=8)
@@ -344,6 +384,8 @@ def main(argv=None) -> int:
         out["expansion3d"] = run_expansion3d(min(args.steps, 50), args.warmup)
     if not args.no_large_patches:
         out["large_patches"] = run_large_patches(min(args.steps, 50), args.warmup)
+    if not args.no_maxwell:
+        out["maxwell"] = run_maxwell()
     if not args.no_adjoint:
         out["adjoint"] = run_adjoint()
     out["cpu_baseline"] = None if args.no_cpu_baseline else cpu_baseline(args.cpu_steps)

@@ -202,6 +202,29 @@ pic_status pic_project(pic_ctx *ctx, const pic_species *sp, int32_t nsp, pic_fie
 pic_status pic_step(pic_ctx *ctx, pic_species *sp, int32_t nsp, pic_fields *f, int32_t nsteps,
                     void *stream);
 
+/* Field solver of the PIC loop (the paper's loop solves Maxwell's equations
+ * on the grid with the current densities of the Projection as sources,
+ * section "Parallelization without tasks"): nsteps steps of Yee's
+ * finite-difference time-domain scheme, normalised units (c = 1), periodic,
+ * with the same current j in every step:
+ *   E <- E + dt (curl B - j)   (Ampere: B is at the half step),
+ *   B <- B - dt curl E         (Faraday: with the new E).
+ * Curls are differences of neighbouring staggered values divided by the
+ * cell size (backward differences of B at E's positions, forward
+ * differences of E at B's positions); with c_a = dt / d_a every component
+ * is evaluated in one fixed order without contraction:
+ *   Ex <- ((Ex + c_y dyBz) - c_z dzBy) - dt Jx, Ey <- ((Ey + c_z dzBx) -
+ *   c_x dxBz) - dt Jy, Ez <- ((Ez + c_x dxBy) - c_y dyBx) - dt Jz,
+ *   Bx <- (Bx - c_y dyEz) + c_z dzEy, By <- (By - c_z dzEx) + c_x dxEz,
+ *   Bz <- (Bz - c_x dxEy) + c_y dyEx
+ * (no z terms in 2D).  e and b (device, prod(n) values per component, x
+ * fastest, the staggering of the file header) are updated in place; j is
+ * read.  With the current of a pic_step step (Esirkepov's charge-conserving
+ * deposit) the update keeps Gauss's law.  At most 65535 cells along y and
+ * along z.  Timed as PIC_KERNEL_MAXWELL. */
+pic_status pic_maxwell(pic_ctx *ctx, double *const e[3], double *const b[3],
+                       const double *const j[3], int32_t nsteps, void *stream);
+
 /* Cotangents of one species' particle state, indexed by particle id. */
 typedef struct {
   double *x[3]; /* d L / d position (x[2] unused in 2D) */
@@ -242,7 +265,8 @@ enum {
   PIC_KERNEL_ADJOINT = 7,     /* adjoint segment */
   PIC_KERNEL_EXCHANGE = 8,    /* slab layout: departures, arrivals, counts, work units */
   PIC_KERNEL_SLAB = 9,        /* slab layout: dense -> slabs and back, once per call */
-  PIC_KERNEL_COUNT = 10
+  PIC_KERNEL_MAXWELL = 10,    /* field solver step (Ampere and Faraday) */
+  PIC_KERNEL_COUNT = 11
 };
 
 /* Observability: when on, every later launch of a kernel class is bracketed

@@ -57,9 +57,9 @@ class CotangentC(C.Structure):
 ENTRY_POINTS = ("pic_validate_config", "pic_num_patches", "pic_bin_width", "pic_init", "pic_free",
                 "pic_bin",
                 "pic_interp_push", "pic_project", "pic_step", "pic_check", "pic_last_error",
-                "pic_timing_enable", "pic_timing_read", "pic_adjoint")
+                "pic_timing_enable", "pic_timing_read", "pic_adjoint", "pic_maxwell")
 KERNELS = {"zero": 0, "ipp": 1, "rebin": 2, "interp_push": 3, "project": 4, "tag": 5, "sort": 6,
-           "adjoint": 7, "exchange": 8, "slab": 9}
+           "adjoint": 7, "exchange": 8, "slab": 9, "maxwell": 10}
 
 _lib_handle = None
 
@@ -104,6 +104,9 @@ def lib():
                                   C.c_void_p * 3, C.c_int32, C.c_int32, C.POINTER(CotangentC),
                                   C.c_void_p * 3, C.c_void_p * 3, C.c_void_p]
         L.pic_adjoint.restype = C.c_int
+        L.pic_maxwell.argtypes = [C.c_void_p, C.c_void_p * 3, C.c_void_p * 3, C.c_void_p * 3,
+                                  C.c_int32, C.c_void_p]
+        L.pic_maxwell.restype = C.c_int
         L.pic_last_error.argtypes = [C.c_void_p]
         L.pic_last_error.restype = C.c_char_p
         _lib_handle = L
@@ -296,6 +299,15 @@ class Context:
 
     def check(self):
         self._raise(lib().pic_check(self._h, _stream()))
+
+    def maxwell(self, E, B, J, nsteps: int = 1):
+        """pic_maxwell: nsteps Yee updates of E and B (in place) with current J
+        (tensors of shape (3, nz, ny, nx), float64, contiguous, on the device)."""
+        for t in (E, B, J):
+            if t.dtype != torch.float64 or not t.is_contiguous() or t.device != self.device:
+                raise PicError(PIC_ERR_ARG, "fields must be contiguous float64 on the device")
+        ptr = lambda t: (C.c_void_p * 3)(*[t[c].data_ptr() for c in range(3)])
+        self._raise(lib().pic_maxwell(self._h, ptr(E), ptr(B), ptr(J), int(nsteps), _stream()))
 
     def adjoint(self, ckpt: Sequence["Species"], E, B, Jbar, nsteps: int, with_deposit: bool,
                 cot: Sequence["Cotangent"], Ebar, Bbar):
