@@ -55,6 +55,8 @@ def _lib(name: str = "liborc.so"):
                                C.c_void_p, C.c_int64, C.c_double, _DP, _DP]
         lib.orc_maxwell.argtypes = [C.POINTER(Grid), _DP * 3, _DP * 3, _DP * 3, C.c_int64]
         lib.orc_maxwell.restype = None
+        lib.orc_maxwell_adjoint.argtypes = [C.POINTER(Grid), _DP * 3, _DP * 3, _DP * 3, C.c_int64]
+        lib.orc_maxwell_adjoint.restype = None
         lib.orc_real_size.restype = C.c_int32
         _libs[name] = lib
     return _libs[name]
@@ -216,6 +218,18 @@ def maxwell(wl, E, B, J, nsteps: int = 1, lib="liborc.so"):
     Ef, Bf, Jf = E.reshape(3, -1), B.reshape(3, -1), Jc.reshape(3, -1)
     _lib(lib).orc_maxwell(C.byref(grid(wl)), _arr3(Ef), _arr3(Bf), _arr3(Jf), int(nsteps))
     return E, B
+
+
+def maxwell_adjoint(wl, Eb, Bb, nsteps: int = 1, Jb=None, lib="liborc.so"):
+    """Reverse mode of maxwell(): cotangents (Eb, Bb) of the fields after
+    nsteps steps -> cotangents of the fields before and of the current
+    (added to Jb, zeros if None).  Returns (Eb, Bb, Jb) as new arrays."""
+    Eb = np.array(Eb, dtype=np.float64, order="C", copy=True)
+    Bb = np.array(Bb, dtype=np.float64, order="C", copy=True)
+    Jb = np.zeros_like(Eb) if Jb is None else np.array(Jb, dtype=np.float64, order="C", copy=True)
+    _lib(lib).orc_maxwell_adjoint(C.byref(grid(wl)), _arr3(Eb.reshape(3, -1)),
+                                  _arr3(Bb.reshape(3, -1)), _arr3(Jb.reshape(3, -1)), int(nsteps))
+    return Eb, Bb, Jb
 
 
 def _opt3(a: Optional[np.ndarray], keep: list):

@@ -656,6 +656,70 @@ void orc_maxwell(const orc_grid *gi, double *const E[3], double *const B[3],
   }
 }
 
+/* Reverse mode of the Yee solver: per step, the transposed Faraday update
+ * of Eb, the current's cotangent, then the transposed Ampere update of Bb. */
+void orc_maxwell_adjoint(const orc_grid *gi, double *const Eb[3], double *const Bb[3],
+                         double *const Jb[3], int64_t nsteps) {
+  G g;
+  mk_grid(gi, &g);
+  const int three = g.dim == 3;
+  const real dt = g.dt;
+  const real cx = dt / g.d[0], cy = dt / g.d[1], cz = three ? dt / g.d[2] : (real)0;
+  for (int64_t s = 0; s < nsteps; s++) {
+    for (int64_t k = 0; k < g.n[2]; k++)
+      for (int64_t j = 0; j < g.n[1]; j++)
+        for (int64_t i = 0; i < g.n[0]; i++) {
+          const int64_t o = node(&g, i, j, k);
+          const int64_t xm = node(&g, i - 1, j, k), ym = node(&g, i, j - 1, k);
+          const real dyBz = (real)Bb[2][o] - (real)Bb[2][ym];
+          const real dxBz = (real)Bb[2][o] - (real)Bb[2][xm];
+          const real dxBy = (real)Bb[1][o] - (real)Bb[1][xm];
+          const real dyBx = (real)Bb[0][o] - (real)Bb[0][ym];
+          real ex = (real)Eb[0][o] - cy * dyBz;
+          real ey = (real)Eb[1][o];
+          if (three) {
+            const int64_t zm = node(&g, i, j, k - 1);
+            const real dzBy = (real)Bb[1][o] - (real)Bb[1][zm];
+            const real dzBx = (real)Bb[0][o] - (real)Bb[0][zm];
+            ex = ex + cz * dzBy;
+            ey = ey - cz * dzBx;
+          }
+          ey = ey + cx * dxBz;
+          const real ez = ((real)Eb[2][o] - cx * dxBy) + cy * dyBx;
+          Eb[0][o] = (double)ex;
+          Eb[1][o] = (double)ey;
+          Eb[2][o] = (double)ez;
+          Jb[0][o] = (double)((real)Jb[0][o] - dt * ex);
+          Jb[1][o] = (double)((real)Jb[1][o] - dt * ey);
+          Jb[2][o] = (double)((real)Jb[2][o] - dt * ez);
+        }
+    for (int64_t k = 0; k < g.n[2]; k++)
+      for (int64_t j = 0; j < g.n[1]; j++)
+        for (int64_t i = 0; i < g.n[0]; i++) {
+          const int64_t o = node(&g, i, j, k);
+          const int64_t xp = node(&g, i + 1, j, k), yp = node(&g, i, j + 1, k);
+          const real dyEz = (real)Eb[2][yp] - (real)Eb[2][o];
+          const real dxEz = (real)Eb[2][xp] - (real)Eb[2][o];
+          const real dxEy = (real)Eb[1][xp] - (real)Eb[1][o];
+          const real dyEx = (real)Eb[0][yp] - (real)Eb[0][o];
+          real bx = (real)Bb[0][o] + cy * dyEz;
+          real by = (real)Bb[1][o];
+          if (three) {
+            const int64_t zp = node(&g, i, j, k + 1);
+            const real dzEy = (real)Eb[1][zp] - (real)Eb[1][o];
+            const real dzEx = (real)Eb[0][zp] - (real)Eb[0][o];
+            bx = bx - cz * dzEy;
+            by = by + cz * dzEx;
+          }
+          by = by - cx * dxEz;
+          const real bz = ((real)Bb[2][o] + cx * dxEy) - cy * dyEx;
+          Bb[0][o] = (double)bx;
+          Bb[1][o] = (double)by;
+          Bb[2][o] = (double)bz;
+        }
+  }
+}
+
 /* ---------------------------------------------------------------------- */
 /* Derivatives of L = sum W . J_final (2D3V).  Fields are static and J is
  * rebuilt from zero at every step, so only the last step's deposit reaches

@@ -127,6 +127,24 @@ int orc_fd(const orc_grid *g, double q, double m, int64_t n, const double *const
 void orc_maxwell(const orc_grid *g, double *const E[3], double *const B[3],
                  const double *const J[3], int64_t nsteps);
 
+/* Reverse mode of orc_maxwell: given the cotangents Eb, Bb of the fields
+ * after nsteps steps, overwrite them with the cotangents of the fields
+ * before, and accumulate into Jb the cotangent of the current (used in
+ * every step).  The transpose of one step taken in reverse order: the
+ * transpose of Faraday (B' = B - C_f E', C_f the forward-difference curl)
+ * then of Ampere (E' = E + C_b B - dt J, C_b the backward-difference curl),
+ * with C_f^T = C_b and C_b^T = C_f on the periodic staggered grid:
+ *   Ebx <- (Ebx - c_y dyBbz) + c_z dzBby   (backward differences of Bb)
+ *   Eby <- (Eby - c_z dzBbx) + c_x dxBbz
+ *   Ebz <- (Ebz - c_x dxBby) + c_y dyBbx
+ *   Jb  <- Jb - dt Eb
+ *   Bbx <- (Bbx + c_y dyEbz) - c_z dzEby   (forward differences of Eb)
+ *   Bby <- (Bby + c_z dzEbx) - c_x dxEbz
+ *   Bbz <- (Bbz + c_x dxEby) - c_y dyEbx
+ * (no z terms in 2D). */
+void orc_maxwell_adjoint(const orc_grid *g, double *const Eb[3], double *const Bb[3],
+                         double *const Jb[3], int64_t nsteps);
+
 /* sizeof(real) of this build */
 int32_t orc_real_size(void);
 

@@ -779,3 +779,25 @@ def test_maxwell_uniform_fields_and_current(dim):
     E1, B1 = O.maxwell(g, E, B, J, 1)
     assert np.array_equal(B1, B)
     assert np.array_equal(E1, E - g.dt * J)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_maxwell_adjoint_is_the_transpose(dim):
+    """<F(E, B, J), (Eb, Bb)> = <(E, B, J), F^T(Eb, Bb)> for the oracle's
+    field steps F and its reverse mode F^T, with random vectors (unequal
+    cell sizes, 4 steps): any wrong sign, index or coefficient in the
+    transpose breaks the identity."""
+    g = _G(dim, (10, 9, 8)[:dim], d=(0.1, 0.12, 0.09))
+    rng = np.random.default_rng(33 + dim)
+    shp = (3,) + field_shape(g)
+    E, B, J = (rng.standard_normal(shp) for _ in range(3))
+    Eb, Bb = rng.standard_normal(shp), rng.standard_normal(shp)
+    E1, B1 = O.maxwell(g, E, B, J, 4)
+    Ea, Ba, Ja = O.maxwell_adjoint(g, Eb, Bb, 4)
+    lhs = (E1 * Eb).sum() + (B1 * Bb).sum()
+    rhs = (E * Ea).sum() + (B * Ba).sum() + (J * Ja).sum()
+    scale = np.abs(E1 * Eb).sum() + np.abs(B1 * Bb).sum()
+    assert abs(lhs - rhs) <= 1e-12 * scale, (lhs, rhs)
+    # Jb accumulates
+    _, _, Jb2 = O.maxwell_adjoint(g, Eb, Bb, 4, Jb=Ja)
+    assert np.allclose(Jb2, 2 * Ja, rtol=1e-13, atol=1e-13)
