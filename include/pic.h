@@ -225,6 +225,22 @@ pic_status pic_step(pic_ctx *ctx, pic_species *sp, int32_t nsp, pic_fields *f, i
 pic_status pic_maxwell(pic_ctx *ctx, double *const e[3], double *const b[3],
                        const double *const j[3], int32_t nsteps, void *stream);
 
+/* Reverse mode of pic_maxwell: eb and bb hold, on entry, the cotangents of
+ * E and B after nsteps field steps (d L / d E_final, d L / d B_final) and on
+ * return those of E and B before them; jb (device, accumulated +=) receives
+ * the cotangent of the current used in every step.  The transpose of one
+ * step, applied nsteps times: the transposed Faraday update (the discrete
+ * curls of the staggered grid are each other's transposes) of eb with the
+ * current's cotangent jb -= dt eb, then the transposed Ampere update of bb:
+ *   Ebx <- (Ebx - c_y dyBbz) + c_z dzBby, Eby <- (Eby - c_z dzBbx) +
+ *   c_x dxBbz, Ebz <- (Ebz - c_x dxBby) + c_y dyBbx, Jb <- Jb - dt Eb,
+ *   Bbx <- (Bbx + c_y dyEbz) - c_z dzEby, Bby <- (Bby + c_z dzEbx) -
+ *   c_x dxEbz, Bbz <- (Bbz + c_x dxEby) - c_y dyEbx
+ * (backward differences of Bb, forward differences of Eb).  Timed as
+ * PIC_KERNEL_MAXWELL. */
+pic_status pic_maxwell_adjoint(pic_ctx *ctx, double *const eb[3], double *const bb[3],
+                               double *const jb[3], int32_t nsteps, void *stream);
+
 /* Cotangents of one species' particle state, indexed by particle id. */
 typedef struct {
   double *x[3]; /* d L / d position (x[2] unused in 2D) */

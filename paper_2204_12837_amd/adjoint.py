@@ -93,3 +93,26 @@ class PicSteps(torch.autograd.Function):
         E, B = fctx.saved_tensors
         du, dE, dB = backward(fctx.run, fctx.ckpts, E, B, gJ)
         return du.clone(), dE, dB, None
+
+
+class YeeSteps(torch.autograd.Function):
+    """(E1, B1) = YeeSteps.apply(E, B, J, ctx, nsteps): nsteps field-solver
+    steps (pic_maxwell) on copies of E and B, with the current J; the
+    backward is the hand-written reverse mode (pic_maxwell_adjoint), which
+    returns the cotangents of E, B and J.  The map is linear, so nothing is
+    kept but the context."""
+
+    @staticmethod
+    def forward(fctx, E, B, J, ctx: pic.Context, nsteps: int):
+        E1, B1 = E.detach().clone(), B.detach().clone()
+        ctx.maxwell(E1, B1, J.detach().contiguous(), nsteps)
+        fctx.lib_ctx, fctx.nsteps = ctx, nsteps
+        return E1, B1
+
+    @staticmethod
+    def backward(fctx, gE, gB):
+        Eb = (gE if gE is not None else torch.zeros_like(gB)).detach().clone().contiguous()
+        Bb = (gB if gB is not None else torch.zeros_like(gE)).detach().clone().contiguous()
+        Jb = torch.zeros_like(Eb)
+        fctx.lib_ctx.maxwell_adjoint(Eb, Bb, Jb, fctx.nsteps)
+        return Eb, Bb, Jb, None, None

@@ -1118,8 +1118,9 @@ pic_status pic_step(pic_ctx *c, pic_species *sp, int32_t nsp, pic_fields *f, int
   return finish(c, st);
 }
 
-pic_status pic_maxwell(pic_ctx *c, double *const e[3], double *const b[3],
-                       const double *const j[3], int32_t nsteps, void *stream) {
+namespace {
+pic_status yee_steps(pic_ctx *c, double *const e[3], double *const b[3],
+                     const double *const j[3], int32_t nsteps, bool adjoint, void *stream) {
   if (!c) return PIC_ERR_ARG;
   if (c->poisoned) return fail(c, PIC_ERR_STATE, "context unusable after a device error");
   if (!e || !b || !j) return fail(c, PIC_ERR_ARG, "null field array");
@@ -1141,10 +1142,23 @@ pic_status pic_maxwell(pic_ctx *c, double *const e[3], double *const b[3],
   }
   a.dt = c->cfg.dt;
   for (int s = 0; s < nsteps; s++) {
-    const hipError_t x = timed(c, PIC_KERNEL_MAXWELL, st, [&] { return launch_yee_step(a, st); });
+    const hipError_t x = timed(c, PIC_KERNEL_MAXWELL, st, [&] {
+      return adjoint ? launch_yee_adjoint_step(a, st) : launch_yee_step(a, st);
+    });
     if (x != hipSuccess) return hip_fail(c, x, "kernel launch");
   }
   return finish(c, st);
+}
+}  // namespace
+
+pic_status pic_maxwell(pic_ctx *c, double *const e[3], double *const b[3],
+                       const double *const j[3], int32_t nsteps, void *stream) {
+  return yee_steps(c, e, b, j, nsteps, false, stream);
+}
+
+pic_status pic_maxwell_adjoint(pic_ctx *c, double *const eb[3], double *const bb[3],
+                               double *const jb[3], int32_t nsteps, void *stream) {
+  return yee_steps(c, eb, bb, jb, nsteps, true, stream);
 }
 
 pic_status pic_adjoint(pic_ctx *c, const pic_species *ck, int32_t nsp, const pic_fields *f,

@@ -21,5 +21,8 @@ struct YeeArgs {
 
 // One Yee step: Ampere (E from B and J), then Faraday (B from the new E).
 hipError_t launch_yee_step(const YeeArgs &a, hipStream_t st);
+// Reverse mode of one step: e, b hold the cotangents (updated in place), j
+// the current's cotangent (accumulated; written through the const pointer).
+hipError_t launch_yee_adjoint_step(const YeeArgs &a, hipStream_t st);
 
 }  // namespace pic

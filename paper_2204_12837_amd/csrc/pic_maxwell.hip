@@ -38,7 +38,11 @@ constexpr int kYeeWg = 256;
 __device__ __forceinline__ int prev(int i, int n) { return i == 0 ? n - 1 : i - 1; }
 __device__ __forceinline__ int next(int i, int n) { return i == n - 1 ? 0 : i + 1; }
 
-template <int DIM>
+// ADJ: the reverse-mode form (the transposed Faraday update of the E
+// cotangent; the host passes the coefficients negated): no current term,
+// and the current's cotangent j (writable) accumulates -dt times the new
+// value.
+template <int DIM, bool ADJ>
 __global__ void __launch_bounds__(kYeeWg) k_ampere(YeeArgs a) {
   const int i = blockIdx.x * kYeeWg + threadIdx.x;
   const int nx = a.n[0], ny = a.n[1];
@@ -63,9 +67,19 @@ __global__ void __launch_bounds__(kYeeWg) k_ampere(YeeArgs a) {
   }
   ey = ey - a.c[0] * dxBz;
   const double ez = (a.e[2][o] + a.c[0] * dxBy) - a.c[1] * dyBx;
-  a.e[0][o] = ex - a.dt * a.j[0][o];
-  a.e[1][o] = ey - a.dt * a.j[1][o];
-  a.e[2][o] = ez - a.dt * a.j[2][o];
+  if constexpr (ADJ) {
+    double *const *jb = const_cast<double *const *>(a.j);
+    a.e[0][o] = ex;
+    a.e[1][o] = ey;
+    a.e[2][o] = ez;
+    jb[0][o] = jb[0][o] - a.dt * ex;
+    jb[1][o] = jb[1][o] - a.dt * ey;
+    jb[2][o] = jb[2][o] - a.dt * ez;
+  } else {
+    a.e[0][o] = ex - a.dt * a.j[0][o];
+    a.e[1][o] = ey - a.dt * a.j[1][o];
+    a.e[2][o] = ez - a.dt * a.j[2][o];
+  }
 }
 
 template <int DIM>
@@ -104,11 +118,31 @@ hipError_t launch_yee_step(const YeeArgs &a, hipStream_t st) {
   const dim3 grid((unsigned)((a.n[0] + kYeeWg - 1) / kYeeWg), (unsigned)a.n[1],
                   (unsigned)a.n[2]);
   if (a.dim == 2) {
-    hipLaunchKernelGGL(k_ampere<2>, grid, dim3(kYeeWg), 0, st, a);
+    hipLaunchKernelGGL((k_ampere<2, false>), grid, dim3(kYeeWg), 0, st, a);
     hipLaunchKernelGGL(k_faraday<2>, grid, dim3(kYeeWg), 0, st, a);
   } else {
-    hipLaunchKernelGGL(k_ampere<3>, grid, dim3(kYeeWg), 0, st, a);
+    hipLaunchKernelGGL((k_ampere<3, false>), grid, dim3(kYeeWg), 0, st, a);
     hipLaunchKernelGGL(k_faraday<3>, grid, dim3(kYeeWg), 0, st, a);
+  }
+  return hipGetLastError();
+}
+
+// Reverse mode: with e, b the cotangents and j the current's cotangent, the
+// transposed Faraday step (the Ampere kernel with negated coefficients and
+// the cotangent of the current) then the transposed Ampere step (the
+// Faraday kernel with negated coefficients): -c d = -(c d) and x + (-y) =
+// x - y exactly, so the values are those of the transposed formulas.
+hipError_t launch_yee_adjoint_step(const YeeArgs &a, hipStream_t st) {
+  YeeArgs r = a;
+  for (int k = 0; k < 3; k++) r.c[k] = -a.c[k];
+  const dim3 grid((unsigned)((a.n[0] + kYeeWg - 1) / kYeeWg), (unsigned)a.n[1],
+                  (unsigned)a.n[2]);
+  if (a.dim == 2) {
+    hipLaunchKernelGGL((k_ampere<2, true>), grid, dim3(kYeeWg), 0, st, r);
+    hipLaunchKernelGGL(k_faraday<2>, grid, dim3(kYeeWg), 0, st, r);
+  } else {
+    hipLaunchKernelGGL((k_ampere<3, true>), grid, dim3(kYeeWg), 0, st, r);
+    hipLaunchKernelGGL(k_faraday<3>, grid, dim3(kYeeWg), 0, st, r);
   }
   return hipGetLastError();
 }

@@ -57,7 +57,8 @@ class CotangentC(C.Structure):
 ENTRY_POINTS = ("pic_validate_config", "pic_num_patches", "pic_bin_width", "pic_init", "pic_free",
                 "pic_bin",
                 "pic_interp_push", "pic_project", "pic_step", "pic_check", "pic_last_error",
-                "pic_timing_enable", "pic_timing_read", "pic_adjoint", "pic_maxwell")
+                "pic_timing_enable", "pic_timing_read", "pic_adjoint", "pic_maxwell",
+                "pic_maxwell_adjoint")
 KERNELS = {"zero": 0, "ipp": 1, "rebin": 2, "interp_push": 3, "project": 4, "tag": 5, "sort": 6,
            "adjoint": 7, "exchange": 8, "slab": 9, "maxwell": 10}
 
@@ -107,6 +108,8 @@ def lib():
         L.pic_maxwell.argtypes = [C.c_void_p, C.c_void_p * 3, C.c_void_p * 3, C.c_void_p * 3,
                                   C.c_int32, C.c_void_p]
         L.pic_maxwell.restype = C.c_int
+        L.pic_maxwell_adjoint.argtypes = L.pic_maxwell.argtypes
+        L.pic_maxwell_adjoint.restype = C.c_int
         L.pic_last_error.argtypes = [C.c_void_p]
         L.pic_last_error.restype = C.c_char_p
         _lib_handle = L
@@ -303,11 +306,19 @@ class Context:
     def maxwell(self, E, B, J, nsteps: int = 1):
         """pic_maxwell: nsteps Yee updates of E and B (in place) with current J
         (tensors of shape (3, nz, ny, nx), float64, contiguous, on the device)."""
+        self._yee(lib().pic_maxwell, E, B, J, nsteps)
+
+    def maxwell_adjoint(self, Eb, Bb, Jb, nsteps: int = 1):
+        """pic_maxwell_adjoint: cotangents of the fields after nsteps steps ->
+        before (in place); the current's cotangent is added to Jb."""
+        self._yee(lib().pic_maxwell_adjoint, Eb, Bb, Jb, nsteps)
+
+    def _yee(self, fn, E, B, J, nsteps):
         for t in (E, B, J):
             if t.dtype != torch.float64 or not t.is_contiguous() or t.device != self.device:
                 raise PicError(PIC_ERR_ARG, "fields must be contiguous float64 on the device")
         ptr = lambda t: (C.c_void_p * 3)(*[t[c].data_ptr() for c in range(3)])
-        self._raise(lib().pic_maxwell(self._h, ptr(E), ptr(B), ptr(J), int(nsteps), _stream()))
+        self._raise(fn(self._h, ptr(E), ptr(B), ptr(J), int(nsteps), _stream()))
 
     def adjoint(self, ckpt: Sequence["Species"], E, B, Jbar, nsteps: int, with_deposit: bool,
                 cot: Sequence["Cotangent"], Ebar, Bbar):

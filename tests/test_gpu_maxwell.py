@@ -123,3 +123,43 @@ def test_self_consistent_loop_matches_oracle():
     gi, oi = np.argsort(s.ids.cpu().numpy()), np.argsort(o.id)
     assert np.abs(s.xs.cpu().numpy()[:, gi] - o.x[:, oi]).max() <= 1e-9
     assert np.abs(s.us.cpu().numpy()[:, gi] - o.u[:, oi]).max() <= 1e-9 * np.abs(o.u).max()
+
+
+@pytest.mark.parametrize("case", CASES)
+def test_yee_adjoint_bitwise(case):
+    """pic_maxwell_adjoint equals the oracle's reverse mode bit for bit (the
+    GPU evaluates the transposed formulas through the forward kernels with
+    negated coefficients, which is exact)."""
+    dim, n, d, steps = case
+    dd = tuple(d) + (0.1,) * (3 - len(d))
+    wl = I.custom(dim, n, n, ppc=0, dt=0.9 * I.cfl_dt(dd, dim))
+    wl.d = dd
+    Eb, Bb, Jb0 = _fields(wl, 700 + sum(n))
+    say(f"case yee adjoint {case}")
+    Eo, Bo, Jo = O.maxwell_adjoint(wl, Eb, Bb, steps, Jb=Jb0)
+    ctx = pic.Context(wl, check=True)
+    t = lambda a: torch.from_numpy(a).to("cuda:0").contiguous()
+    Eg, Bg, Jg = t(Eb), t(Bb), t(Jb0)
+    ctx.maxwell_adjoint(Eg, Bg, Jg, steps)
+    torch.cuda.synchronize()
+    ctx.close()
+    assert np.array_equal(Eg.cpu().numpy(), Eo)
+    assert np.array_equal(Bg.cpu().numpy(), Bo)
+    assert np.array_equal(Jg.cpu().numpy(), Jo)
+
+
+def test_yee_autograd_gradcheck():
+    """torch.autograd.gradcheck of YeeSteps (finite differences of the
+    linear map against the hand-written reverse mode) on a small 2D grid."""
+    from paper_2204_12837_amd import adjoint as ADJ
+
+    wl = I.custom(2, (6, 6), (6, 6), ppc=0)
+    ctx = pic.Context(wl, check=True)
+    rng = np.random.default_rng(710)
+    shp = (3, 1, 6, 6)
+    E, B, J = (torch.from_numpy(rng.standard_normal(shp)).to("cuda:0").requires_grad_(True)
+               for _ in range(3))
+    say("case yee gradcheck")
+    assert torch.autograd.gradcheck(lambda e, b, j: ADJ.YeeSteps.apply(e, b, j, ctx, 3),
+                                    (E, B, J), eps=1e-6, atol=1e-8, rtol=1e-6)
+    ctx.close()
