@@ -12,8 +12,8 @@ Prints one JSON line: particle-steps/s of the whole call, the roofline of
 the dominant kernel (the fused step kernel, HBM-bound by its bytes), the
 imbalanced workload next to the uniform one, the 3D two-species workload,
 the uniform plasma with patches too large for the LDS (x-bins), the field
-solver on the 2D and 3D grids, the adjoint workload, and the CPU oracle
-timed on a bounded sample on the host.
+solver on the 2D and 3D grids, the charge density, the adjoint workload, and
+the CPU oracle timed on a bounded sample on the host.
 """
 from __future__ import annotations
 
@@ -211,6 +211,40 @@ def run_maxwell(steps: int = 50):
     return out
 
 
+def run_rho(reps: int = 20):
+    """The charge density (pic_rho) of the 2D benchmark's 33.5M particles:
+    ms per call and GB/s of its algorithmic bytes (x, y, w read: 24 B per
+    particle; rho written: 8 B per node)."""
+    import torch
+
+    from paper_2204_12837_amd import inputs as I
+    from paper_2204_12837_amd import pic
+
+    wl = I.workload("uniform1024")
+    inp = I.generate(wl)
+    ctx = pic.Context(wl)
+    sp = pic.upload(inp, "cuda:0", n_slabs=ctx.n_slabs)
+    ctx.bin(sp)
+    rho = torch.zeros((1, wl.n[1], wl.n[0]), dtype=torch.float64, device="cuda:0")
+    ctx.rho(sp, rho)
+    torch.cuda.synchronize()
+    ctx.timing(True)
+    for _ in range(reps):
+        ctx.rho(sp, rho)
+    ms, n = ctx.timing_read()["rho"]
+    ctx.timing(False)
+    ctx.check()
+    ctx.close()
+    n_p = sp[0].n
+    del sp
+    torch.cuda.empty_cache()
+    kern = ms / n
+    gbs = (24.0 * n_p + 8.0 * wl.n_cells) / (kern * 1e-3) / 1e9
+    return {"workload": "uniform1024", "particles": n_p, "kernel_ms": kern,
+            "particles_per_s": n_p / (kern * 1e-3), "algorithmic_GBs": gbs,
+            "hbm_frac": gbs / HBM_PEAK_GBS}
+
+
 def run_adjoint(every: int = 5):
     """Forward (with checkpoints) and backward of the adjoint workload:
     L = sum W.J after 20 steps of 256^2 cells x 16 ppc, gradients with
@@ -303,7 +337,8 @@ def main(argv=None) -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-3d", action="store_true", help="skip the 3D two-species workload")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint workload")
-    ap.add_argument("--no-maxwell", action="store_true", help="skip the field solver")
+    ap.add_argument("--no-maxwell", action="store_true",
+                    help="skip the field solver and the charge density")
     ap.add_argument("--no-large-patches", action="store_true",
                     help="skip the 64x128-cell patches (x-bins) workload")
     ap.add_argument("--cpu-steps", type=int, default=8)
@@ -386,6 +421,7 @@ def main(argv=None) -> int:
         out["large_patches"] = run_large_patches(min(args.steps, 50), args.warmup)
     if not args.no_maxwell:
         out["maxwell"] = run_maxwell()
+        out["rho"] = run_rho()
     if not args.no_adjoint:
         out["adjoint"] = run_adjoint()
     out["cpu_baseline"] = None if args.no_cpu_baseline else cpu_baseline(args.cpu_steps)

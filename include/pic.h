@@ -225,6 +225,17 @@ pic_status pic_step(pic_ctx *ctx, pic_species *sp, int32_t nsp, pic_fields *f, i
 pic_status pic_maxwell(pic_ctx *ctx, double *const e[3], double *const b[3],
                        const double *const j[3], int32_t nsteps, void *stream);
 
+/* Charge density (the charge-density projection that accompanies the
+ * current projection, section "Parallelization with OpenMP task"):
+ * rho += sum over species and particles of q w S(x - node) on the primal
+ * nodes (prod(n) values, x fastest), S the quadratic B-spline of the
+ * Interpolation operator.  Particles must be sorted by patch (offset[]
+ * valid) with positions inside the box; a particle outside its patch sets
+ * the sticky position error.  Each term is (q w)(Sx Sy [Sz]); per patch the
+ * terms are summed in an on-chip tile, then added to rho with float64
+ * atomics.  Timed as PIC_KERNEL_RHO. */
+pic_status pic_rho(pic_ctx *ctx, const pic_species *sp, int32_t nsp, double *rho, void *stream);
+
 /* Reverse mode of pic_maxwell: eb and bb hold, on entry, the cotangents of
  * E and B after nsteps field steps (d L / d E_final, d L / d B_final) and on
  * return those of E and B before them; jb (device, accumulated +=) receives
@@ -282,7 +293,8 @@ enum {
   PIC_KERNEL_EXCHANGE = 8,    /* slab layout: departures, arrivals, counts, work units */
   PIC_KERNEL_SLAB = 9,        /* slab layout: dense -> slabs and back, once per call */
   PIC_KERNEL_MAXWELL = 10,    /* field solver step (Ampere and Faraday) */
-  PIC_KERNEL_COUNT = 11
+  PIC_KERNEL_RHO = 11,        /* charge density */
+  PIC_KERNEL_COUNT = 12
 };
 
 /* Observability: when on, every later launch of a kernel class is bracketed

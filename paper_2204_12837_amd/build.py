@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 SOURCES = ["pic_api.hip", "pic_kernels.hip", "pic_slab.hip", "pic_sort.hip", "pic_adjoint.hip",
-           "pic_maxwell.hip"]
+           "pic_maxwell.hip", "pic_rho.hip"]
 HEADERS = ["pic_common.h", "pic_device.h", "pic_fields.h", os.path.join(ROOT, "include", "pic.h")]
 LIB = os.path.join(HERE, "libpic.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

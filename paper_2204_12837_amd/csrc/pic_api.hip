@@ -1151,6 +1151,43 @@ pic_status yee_steps(pic_ctx *c, double *const e[3], double *const b[3],
 }
 }  // namespace
 
+pic_status pic_rho(pic_ctx *c, const pic_species *sp, int32_t nsp, double *rho, void *stream) {
+  if (!c) return PIC_ERR_ARG;
+  if (c->poisoned) return fail(c, PIC_ERR_STATE, "context unusable after a device error");
+  if (!rho) return fail(c, PIC_ERR_ARG, "null rho");
+  if (!sp || nsp < 1) return fail(c, PIC_ERR_ARG, "no species");
+  if (nsp > kRhoMaxSpecies) return fail(c, PIC_ERR_CAPACITY, "at most %d species", kRhoMaxSpecies);
+  RhoArgs a{};
+  a.dim = c->cfg.dim;
+  for (int k = 0; k < 3; k++) {
+    a.n[k] = c->g.n[k];
+    a.patch[k] = k < c->cfg.dim ? c->cfg.patch[k] : 1;
+    a.np[k] = a.n[k] / a.patch[k];
+    a.inv_d[k] = c->g.inv_d[k];
+  }
+  a.nsp = nsp;
+  for (int s = 0; s < nsp; s++) {
+    const pic_species &p = sp[s];
+    if (p.n < 0 || p.n > p.capacity) return fail(c, PIC_ERR_CAPACITY, "species %d: bad n", s);
+    for (int k = 0; k < c->cfg.dim; k++)
+      if (!p.x[k]) return fail(c, PIC_ERR_ARG, "species %d: null position", s);
+    if (!p.w || !p.offset) return fail(c, PIC_ERR_ARG, "species %d: null weight/offset", s);
+    a.s[s].q = p.q;
+    for (int k = 0; k < 3; k++) a.s[s].x[k] = k < c->cfg.dim ? p.x[k] : nullptr;
+    a.s[s].w = p.w;
+    a.s[s].off = p.offset;
+  }
+  a.rho = rho;
+  size_t tile = sizeof(double);
+  for (int k = 0; k < c->cfg.dim; k++) tile *= (size_t)(a.patch[k] + 3);
+  hipStream_t st = (hipStream_t)stream;
+  if (hipSetDevice(c->device) != hipSuccess) return fail(c, PIC_ERR_HIP, "hipSetDevice");
+  const hipError_t e =
+      timed(c, PIC_KERNEL_RHO, st, [&] { return launch_rho(a, c->err_dev, tile, st); });
+  if (e != hipSuccess) return hip_fail(c, e, "kernel launch");
+  return finish(c, st);
+}
+
 pic_status pic_maxwell(pic_ctx *c, double *const e[3], double *const b[3],
                        const double *const j[3], int32_t nsteps, void *stream) {
   return yee_steps(c, e, b, j, nsteps, false, stream);

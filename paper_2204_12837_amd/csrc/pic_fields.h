@@ -25,4 +25,26 @@ hipError_t launch_yee_step(const YeeArgs &a, hipStream_t st);
 // the current's cotangent (accumulated; written through the const pointer).
 hipError_t launch_yee_adjoint_step(const YeeArgs &a, hipStream_t st);
 
+// Charge density: per species the particles sorted by patch (offsets of
+// the configuration's patches).
+constexpr int kRhoMaxSpecies = 8;
+struct RhoArgs {
+  int dim;
+  int n[3], patch[3], np[3];
+  double inv_d[3];
+  int nsp;
+  struct Sp {
+    double q;
+    const double *x[3];
+    const double *w;
+    const int64_t *off;
+  } s[kRhoMaxSpecies];
+  double *rho;
+};
+
+// rho += sum over species and particles of q w S(x - node) on the primal
+// nodes; one workgroup per (patch, species), LDS tile of the patch's nodes
+// when it fits (tile_bytes), global atomics otherwise.
+hipError_t launch_rho(const RhoArgs &a, int *err, size_t tile_bytes, hipStream_t st);
+
 }  // namespace pic

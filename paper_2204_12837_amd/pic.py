@@ -58,9 +58,9 @@ ENTRY_POINTS = ("pic_validate_config", "pic_num_patches", "pic_bin_width", "pic_
                 "pic_bin",
                 "pic_interp_push", "pic_project", "pic_step", "pic_check", "pic_last_error",
                 "pic_timing_enable", "pic_timing_read", "pic_adjoint", "pic_maxwell",
-                "pic_maxwell_adjoint")
+                "pic_maxwell_adjoint", "pic_rho")
 KERNELS = {"zero": 0, "ipp": 1, "rebin": 2, "interp_push": 3, "project": 4, "tag": 5, "sort": 6,
-           "adjoint": 7, "exchange": 8, "slab": 9, "maxwell": 10}
+           "adjoint": 7, "exchange": 8, "slab": 9, "maxwell": 10, "rho": 11}
 
 _lib_handle = None
 
@@ -110,6 +110,8 @@ def lib():
         L.pic_maxwell.restype = C.c_int
         L.pic_maxwell_adjoint.argtypes = L.pic_maxwell.argtypes
         L.pic_maxwell_adjoint.restype = C.c_int
+        L.pic_rho.argtypes = [C.c_void_p, C.POINTER(SpeciesC), C.c_int32, C.c_void_p, C.c_void_p]
+        L.pic_rho.restype = C.c_int
         L.pic_last_error.argtypes = [C.c_void_p]
         L.pic_last_error.restype = C.c_char_p
         _lib_handle = L
@@ -307,6 +309,14 @@ class Context:
         """pic_maxwell: nsteps Yee updates of E and B (in place) with current J
         (tensors of shape (3, nz, ny, nx), float64, contiguous, on the device)."""
         self._yee(lib().pic_maxwell, E, B, J, nsteps)
+
+    def rho(self, species: Sequence[Species], rho):
+        """pic_rho: rho += charge density of the (patch-sorted) species; rho a
+        contiguous float64 tensor of shape (nz, ny, nx) on the device."""
+        if rho.dtype != torch.float64 or not rho.is_contiguous() or rho.device != self.device:
+            raise PicError(PIC_ERR_ARG, "rho must be contiguous float64 on the device")
+        arr = (SpeciesC * len(species))(*[s.cstruct() for s in species])
+        self._raise(lib().pic_rho(self._h, arr, len(species), rho.data_ptr(), _stream()))
 
     def maxwell_adjoint(self, Eb, Bb, Jb, nsteps: int = 1):
         """pic_maxwell_adjoint: cotangents of the fields after nsteps steps ->
