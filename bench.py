@@ -12,8 +12,9 @@ Prints one JSON line: particle-steps/s of the whole call, the roofline of
 the dominant kernel (the fused step kernel, HBM-bound by its bytes), the
 imbalanced workload next to the uniform one, the 3D two-species workload,
 the uniform plasma with patches too large for the LDS (x-bins), the field
-solver on the 2D and 3D grids, the charge density, the adjoint workload, and
-the CPU oracle timed on a bounded sample on the host.
+solver on the 2D and 3D grids, the charge density, the self-consistent loop
+(particles and fields), the adjoint workload, and the CPU oracle timed on a
+bounded sample on the host.
 """
 from __future__ import annotations
 
@@ -209,6 +210,35 @@ def run_maxwell(steps: int = 50):
                      "kernel_ms_per_step": kern, "algorithmic_GBs": gbs,
                      "hbm_frac": gbs / HBM_PEAK_GBS}
     return out
+
+
+def run_cycle(steps: int, warmup: int):
+    """The self-consistent loop (pic_cycle: particle step, then field step)
+    on the 2D benchmark workload, in one call."""
+    import torch
+
+    from paper_2204_12837_amd import inputs as I
+    from paper_2204_12837_amd import pic
+
+    wl = I.workload("uniform1024")
+    inp = I.generate(wl)
+    ctx = pic.Context(wl)
+    sp = pic.upload(inp, "cuda:0", n_slabs=ctx.n_slabs)
+    E, B, J = pic.upload_fields(inp, "cuda:0")
+    ctx.bin(sp)
+    ctx.cycle(sp, E, B, J, warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.cycle(sp, E, B, J, steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ctx.check()
+    ctx.close()
+    n = sum(s.n for s in sp)
+    del sp, E, B, J
+    torch.cuda.empty_cache()
+    return {"workload": "uniform1024", "particles": n, "steps": steps,
+            "ms_per_step": (t1 - t0) / steps * 1e3, "particle_steps_per_s": n * steps / (t1 - t0)}
 
 
 def run_rho(reps: int = 20):
@@ -422,6 +452,7 @@ def main(argv=None) -> int:
     if not args.no_maxwell:
         out["maxwell"] = run_maxwell()
         out["rho"] = run_rho()
+        out["cycle"] = run_cycle(min(args.steps, 50), args.warmup)
     if not args.no_adjoint:
         out["adjoint"] = run_adjoint()
     out["cpu_baseline"] = None if args.no_cpu_baseline else cpu_baseline(args.cpu_steps)

@@ -225,6 +225,16 @@ pic_status pic_step(pic_ctx *ctx, pic_species *sp, int32_t nsp, pic_fields *f, i
 pic_status pic_maxwell(pic_ctx *ctx, double *const e[3], double *const b[3],
                        const double *const j[3], int32_t nsteps, void *stream);
 
+/* The self-consistent PIC loop: nsteps times {the pic_step step on E and B
+ * (J <- its current), then one pic_maxwell field step of E and B with that
+ * J}.  Same layouts, modes, graphs and conditions as pic_step (a captured
+ * slab-layout step includes the field step); e and b are updated in place,
+ * j holds the last step's current.  Equals alternating pic_step(.., 1) and
+ * pic_maxwell(.., 1), up to the order of the particles inside a patch and
+ * the rounding of J's float64 atomic sums. */
+pic_status pic_cycle(pic_ctx *ctx, pic_species *sp, int32_t nsp, double *const e[3],
+                     double *const b[3], double *const j[3], int32_t nsteps, void *stream);
+
 /* Charge density (the charge-density projection that accompanies the
  * current projection, section "Parallelization with OpenMP task"):
  * rho += sum over species and particles of q w S(x - node) on the primal

@@ -100,6 +100,9 @@ struct pic_ctx {
   int nb = 1;                           // bins per patch
   int64_t npatch_api = 0;               // patches of the configuration
   int64_t *boff[kMaxSpecies] = {};      // [bins + 1] per species
+  // pic_cycle: every step ends with a field step on the step's fields
+  bool cycle = false;
+  YeeArgs yee{};
 };
 
 namespace {
@@ -430,11 +433,14 @@ hipError_t enqueue_step(pic_ctx *c, const pic_species *sp, int32_t nsp, const pi
       std::swap(r.s[s].w, r.s[s].wa);
       std::swap(r.s[s].id, r.s[s].ida);
     }
-  return timed(c, PIC_KERNEL_REBIN, st, [&] {
+  e = timed(c, PIC_KERNEL_REBIN, st, [&] {
     hipError_t r2 = launch_rebin(c->g, r, c->err_dev, max_segments(c, nsp), !materialize, st);
     if (r2 == hipSuccess && pers) r2 = launch_layout(c->g, r, c->units, c->qctl, st);
     return r2;
   });
+  if (e == hipSuccess && c->cycle)
+    e = timed(c, PIC_KERNEL_MAXWELL, st, [&] { return launch_yee_step(c->yee, st); });
+  return e;
 }
 
 // Everything a captured graph depends on.
@@ -442,6 +448,7 @@ std::vector<uintptr_t> graph_key(const pic_ctx *c, const pic_species *sp, int32_
                                  const pic_fields *f) {
   std::vector<uintptr_t> k;
   k.push_back((uintptr_t)nsp);
+  k.push_back((uintptr_t)c->cycle);
   for (int s = 0; s < nsp; s++) {
     const pic_species &p = sp[s];
     k.push_back((uintptr_t)p.n);
@@ -638,6 +645,8 @@ hipError_t enqueue_slab_step(pic_ctx *c, const SlabArgs &a, const pic_fields *f,
       return launch_exchange(c->g, a, c->err_dev, pers ? c->units : nullptr, c->qctl,
                              c->g.spc * kSeg, st);
     });
+  if (e == hipSuccess && c->cycle)
+    e = timed(c, PIC_KERNEL_MAXWELL, st, [&] { return launch_yee_step(c->yee, st); });
   return e;
 }
 
@@ -654,6 +663,7 @@ pic_status ensure_slab_graph(pic_ctx *c, const SlabArgs &a, const pic_fields *f,
   }
   key.push_back((uintptr_t)c->units);
   key.push_back((uintptr_t)c->pgrid_slab);
+  key.push_back((uintptr_t)c->cycle);
   GraphCache &gc = c->slab_gc;
   if (gc.exec && key == gc.key) {
     *out = gc.exec;
@@ -1119,8 +1129,9 @@ pic_status pic_step(pic_ctx *c, pic_species *sp, int32_t nsp, pic_fields *f, int
 }
 
 namespace {
-pic_status yee_steps(pic_ctx *c, double *const e[3], double *const b[3],
-                     const double *const j[3], int32_t nsteps, bool adjoint, void *stream) {
+// Field steps (forward, j read) or their reverse mode (j accumulated into).
+pic_status yee_steps(pic_ctx *c, double *const e[3], double *const b[3], double *const j[3],
+                     int32_t nsteps, bool adjoint, void *stream) {
   if (!c) return PIC_ERR_ARG;
   if (c->poisoned) return fail(c, PIC_ERR_STATE, "context unusable after a device error");
   if (!e || !b || !j) return fail(c, PIC_ERR_ARG, "null field array");
@@ -1190,7 +1201,37 @@ pic_status pic_rho(pic_ctx *c, const pic_species *sp, int32_t nsp, double *rho, 
 
 pic_status pic_maxwell(pic_ctx *c, double *const e[3], double *const b[3],
                        const double *const j[3], int32_t nsteps, void *stream) {
-  return yee_steps(c, e, b, j, nsteps, false, stream);
+  // the forward step only reads the current
+  double *jr[3] = {const_cast<double *>(j ? j[0] : nullptr), const_cast<double *>(j ? j[1] : nullptr),
+                   const_cast<double *>(j ? j[2] : nullptr)};
+  return yee_steps(c, e, b, j ? jr : nullptr, nsteps, false, stream);
+}
+
+pic_status pic_cycle(pic_ctx *c, pic_species *sp, int32_t nsp, double *const e[3],
+                     double *const b[3], double *const j[3], int32_t nsteps, void *stream) {
+  if (!c) return PIC_ERR_ARG;
+  if (!e || !b || !j) return fail(c, PIC_ERR_ARG, "null field array");
+  if (c->g.n[1] > 65535 || c->g.n[2] > 65535)
+    return fail(c, PIC_ERR_ARG, "the field solver takes at most 65535 cells along y and z");
+  pic_fields f{};
+  YeeArgs y{};
+  y.dim = c->cfg.dim;
+  for (int k = 0; k < 3; k++) {
+    f.e[k] = e[k];
+    f.b[k] = b[k];
+    f.j[k] = j[k];
+    y.n[k] = c->g.n[k];
+    y.c[k] = k < c->cfg.dim ? c->cfg.dt / c->cfg.d[k] : 0.0;
+    y.e[k] = e[k];
+    y.b[k] = b[k];
+    y.j[k] = j[k];
+  }
+  y.dt = c->cfg.dt;
+  c->cycle = true;
+  c->yee = y;
+  const pic_status r = pic_step(c, sp, nsp, &f, nsteps, stream);
+  c->cycle = false;
+  return r;
 }
 
 pic_status pic_maxwell_adjoint(pic_ctx *c, double *const eb[3], double *const bb[3],

@@ -9,20 +9,20 @@ namespace pic {
 
 // One Yee step's arguments: cells per axis (1 for an absent axis), the
 // coefficients c_a = dt / d_a (computed once on the host, 0 for an absent
-// axis) and dt.
+// axis) and dt.  j is read by the forward step and accumulated into by the
+// reverse mode.
 struct YeeArgs {
   int dim;
   int n[3];
   double c[3];
   double dt;
-  double *e[3], *b[3];
-  const double *j[3];
+  double *e[3], *b[3], *j[3];
 };
 
 // One Yee step: Ampere (E from B and J), then Faraday (B from the new E).
 hipError_t launch_yee_step(const YeeArgs &a, hipStream_t st);
 // Reverse mode of one step: e, b hold the cotangents (updated in place), j
-// the current's cotangent (accumulated; written through the const pointer).
+// the current's cotangent (accumulated).
 hipError_t launch_yee_adjoint_step(const YeeArgs &a, hipStream_t st);
 
 // Charge density: per species the particles sorted by patch (offsets of

@@ -68,13 +68,12 @@ __global__ void __launch_bounds__(kYeeWg) k_ampere(YeeArgs a) {
   ey = ey - a.c[0] * dxBz;
   const double ez = (a.e[2][o] + a.c[0] * dxBy) - a.c[1] * dyBx;
   if constexpr (ADJ) {
-    double *const *jb = const_cast<double *const *>(a.j);
     a.e[0][o] = ex;
     a.e[1][o] = ey;
     a.e[2][o] = ez;
-    jb[0][o] = jb[0][o] - a.dt * ex;
-    jb[1][o] = jb[1][o] - a.dt * ey;
-    jb[2][o] = jb[2][o] - a.dt * ez;
+    a.j[0][o] = a.j[0][o] - a.dt * ex;
+    a.j[1][o] = a.j[1][o] - a.dt * ey;
+    a.j[2][o] = a.j[2][o] - a.dt * ez;
   } else {
     a.e[0][o] = ex - a.dt * a.j[0][o];
     a.e[1][o] = ey - a.dt * a.j[1][o];

@@ -58,7 +58,7 @@ ENTRY_POINTS = ("pic_validate_config", "pic_num_patches", "pic_bin_width", "pic_
                 "pic_bin",
                 "pic_interp_push", "pic_project", "pic_step", "pic_check", "pic_last_error",
                 "pic_timing_enable", "pic_timing_read", "pic_adjoint", "pic_maxwell",
-                "pic_maxwell_adjoint", "pic_rho")
+                "pic_maxwell_adjoint", "pic_rho", "pic_cycle")
 KERNELS = {"zero": 0, "ipp": 1, "rebin": 2, "interp_push": 3, "project": 4, "tag": 5, "sort": 6,
            "adjoint": 7, "exchange": 8, "slab": 9, "maxwell": 10, "rho": 11}
 
@@ -112,6 +112,9 @@ def lib():
         L.pic_maxwell_adjoint.restype = C.c_int
         L.pic_rho.argtypes = [C.c_void_p, C.POINTER(SpeciesC), C.c_int32, C.c_void_p, C.c_void_p]
         L.pic_rho.restype = C.c_int
+        L.pic_cycle.argtypes = [C.c_void_p, C.POINTER(SpeciesC), C.c_int32, C.c_void_p * 3,
+                                C.c_void_p * 3, C.c_void_p * 3, C.c_int32, C.c_void_p]
+        L.pic_cycle.restype = C.c_int
         L.pic_last_error.argtypes = [C.c_void_p]
         L.pic_last_error.restype = C.c_char_p
         _lib_handle = L
@@ -309,6 +312,15 @@ class Context:
         """pic_maxwell: nsteps Yee updates of E and B (in place) with current J
         (tensors of shape (3, nz, ny, nx), float64, contiguous, on the device)."""
         self._yee(lib().pic_maxwell, E, B, J, nsteps)
+
+    def cycle(self, species: Sequence[Species], E, B, J, nsteps: int = 1):
+        """pic_cycle: nsteps of {particle step, field step}; E and B evolve in
+        place, J holds the last step's current."""
+        for t in (E, B, J):
+            if t.dtype != torch.float64 or not t.is_contiguous() or t.device != self.device:
+                raise PicError(PIC_ERR_ARG, "fields must be contiguous float64 on the device")
+        ptr = lambda t: (C.c_void_p * 3)(*[t[c].data_ptr() for c in range(3)])
+        self._call_sp(lib().pic_cycle, species, ptr(E), ptr(B), ptr(J), int(nsteps), _stream())
 
     def rho(self, species: Sequence[Species], rho):
         """pic_rho: rho += charge density of the (patch-sorted) species; rho a

@@ -163,3 +163,56 @@ def test_yee_autograd_gradcheck():
     assert torch.autograd.gradcheck(lambda e, b, j: ADJ.YeeSteps.apply(e, b, j, ctx, 3),
                                     (E, B, J), eps=1e-6, atol=1e-8, rtol=1e-6)
     ctx.close()
+
+
+def _oracle_loop(wl, inp, cycles):
+    sps = O.species_from(inp)
+    for s in sps:
+        O.bin(wl, s)
+    Eo, Bo = inp.E.copy(), inp.B.copy()
+    for _ in range(cycles):
+        Jo = O.step(wl, sps, Eo, Bo)
+        Eo, Bo = O.maxwell(wl, Eo, Bo, Jo, 1)
+    return sps, Eo, Bo
+
+
+CYCLE_CASES = [
+    # workload args, cycles, mode, chunk, graph, capacity_factor
+    ((2, (64, 32), (8, 8), 4, 1, 0.2), 6, 0, 0, False, None),
+    ((2, (64, 32), (8, 8), 4, 1, 0.2), 6, 1, 512, True, None),
+    ((2, (48, 24), (8, 8), 3, 1, 0.2), 4, 0, 0, True, 1.0),    # dense layout, paired graphs
+    ((3, (16, 16, 8), (8, 8, 8), 2, 2, 0.2), 4, 1, 256, False, None),
+]
+
+
+@pytest.mark.parametrize("case", CYCLE_CASES)
+def test_cycle_matches_oracle_loop(case):
+    """pic_cycle (particle step + field step per step, inside one call:
+    slab layout, persistent mode, captured graphs) follows the oracle's
+    loop to 1e-9, and keeps Gauss's law on its own output."""
+    (dim, n, patch, ppc, nsp, sigma), cycles, mode, chunk, graph, cap = case
+    wl = I.custom(dim, n, patch, ppc=ppc, seed=900 + cycles + mode, sigma=sigma, n_species=nsp,
+                  field_amp=0.05)
+    inp = I.generate(wl)
+    say(f"case cycle {case}")
+    sps, Eo, Bo = _oracle_loop(wl, inp, cycles)
+    ctx = pic.Context(wl, check=True, mode=mode, chunk=chunk, graph=graph)
+    sp = pic.upload(inp, "cuda:0", capacity_factor=cap, n_slabs=ctx.n_slabs)
+    E, B, J = pic.upload_fields(inp, "cuda:0")
+    ctx.bin(sp)
+    rho = lambda: sum(O.rho(wl, s.q, s.xs.cpu().numpy(), s.ws.cpu().numpy()) for s in sp)
+    gauss0 = _div(wl, E.cpu().numpy()) - rho()
+    ctx.cycle(sp, E, B, J, cycles)
+    torch.cuda.synchronize()
+    ctx.check()
+    gauss1 = _div(wl, E.cpu().numpy()) - rho()
+    assert np.abs(gauss1 - gauss0).max() <= 1e-11 * max(np.abs(gauss0).max(), 1.0)
+    Eg, Bg = E.cpu().numpy(), B.cpu().numpy()
+    assert np.abs(Eg - Eo).max() <= 1e-9 * np.abs(Eo).max()
+    assert np.abs(Bg - Bo).max() <= 1e-9 * np.abs(Bo).max()
+    for s, o in zip(sp, sps):
+        assert np.array_equal(s.offset.cpu().numpy(), o.off)
+        gi, oi = np.argsort(s.ids.cpu().numpy()), np.argsort(o.id)
+        assert np.abs(s.xs.cpu().numpy()[:, gi] - o.x[:, oi]).max() <= 1e-9
+        assert np.abs(s.us.cpu().numpy()[:, gi] - o.u[:, oi]).max() <= 1e-9 * max(np.abs(o.u).max(), 1e-3)
+    ctx.close()
