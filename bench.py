@@ -117,12 +117,14 @@ def run_gpu(wl, steps: int, warmup: int, mode: int = 0, chunk: int = 0, wg: int 
 
 
 def tune_persistent(wl, inp):
-    """Autotuned (chunk, wg) for the persistent launch on these inputs."""
+    """Autotuned (chunk, wg, bin_x) for the persistent launch on these inputs."""
     import torch
 
     from paper_2204_12837_amd import autotune, pic
 
-    sp = pic.upload(inp, "cuda:0")
+    # buffers with slab room for the narrowest x-bins tried
+    nb = max([wl.patch[0] // b for b in autotune.bin_candidates(wl) if b > 0] + [1])
+    sp = pic.upload(inp, "cuda:0", n_slabs=wl.n_patches * nb)
     E, B, J = pic.upload_fields(inp, "cuda:0")
     ctx = pic.Context(wl)
     ctx.bin(sp)
@@ -144,14 +146,17 @@ def run_expansion3d(steps: int, warmup: int):
     n_pp, s_pp, t_pp = run_gpu(wl, steps, warmup, inp=inp)
     tuned = tune_persistent(wl, inp)
     n_pe, s_pe, t_pe = run_gpu(wl, steps, warmup, mode=1, chunk=tuned["chunk"], wg=tuned["wg"],
-                               inp=inp)
+                               inp=inp, bin_x=tuned.get("bin_x", 0))
     ipp_pp = t_pp["ipp"][0] / t_pp["ipp"][1]
     ipp_pe = t_pe["ipp"][0] / t_pe["ipp"][1]
     abytes = algorithmic_bytes(wl, n)
     return {"workload": "expansion3d", "particles": n, "species": 2, "steps": steps,
             "per_patch": {"ns_per_particle_step": s_pp / (n * steps) * 1e9, "ipp_ms": ipp_pp},
             "persistent": {"ns_per_particle_step": s_pe / (n * steps) * 1e9, "ipp_ms": ipp_pe,
-                           "chunk": tuned["chunk"], "wg": tuned["wg"]},
+                           "chunk": tuned["chunk"], "wg": tuned["wg"],
+                           "bin_x": tuned.get("bin_x", 0),
+                           "kernel_ms": {k: round(v[0] / max(v[1], 1), 4)
+                                         for k, v in t_pe.items() if v[1]}},
             "ipp_hbm_frac_best": abytes / (min(ipp_pp, ipp_pe) * 1e-3) / 1e9 / HBM_PEAK_GBS}
 
 
@@ -422,7 +427,7 @@ def main(argv=None) -> int:
         ni, si, ti = run_gpu(wli, args.steps, args.warmup, inp=inpi)
         tuned = tune_persistent(wli, inpi)
         _, sp_, tp = run_gpu(wli, args.steps, args.warmup, mode=1, chunk=tuned["chunk"],
-                             wg=tuned["wg"], inp=inpi)
+                             wg=tuned["wg"], inp=inpi, bin_x=tuned.get("bin_x", 0))
         ns_u = secs / (n * args.steps) * 1e9
         ipp_u = ipp_avg / n * 1e6
         per_k = lambda t: {k: round(v[0] / max(v[1], 1), 4) for k, v in t.items() if v[1]}

@@ -1,8 +1,9 @@
 """Autotuner for the persistent launch: picks the work-unit size (chunk, in
-particles) and the workgroup size for a workload by timing the fused kernel
-on the live particles, and caches the choice in a JSON file keyed by the GPU
-architecture, the dimension, the patch shape and a coarse histogram of the
-per-patch populations.
+particles), the workgroup size and (in 3D) the x-bin width for a workload
+by timing a step's fused kernel and exchange on the live particles, and
+caches the choice in a JSON file keyed by the GPU architecture, the
+dimension, the patch shape and a coarse histogram of the per-patch
+populations.
 
 The paper tunes its task granularity (the bin width) by hand per physical
 set-up; this does the same search automatically.  All timing is done by
@@ -62,11 +63,19 @@ def _load(path: str) -> Dict:
         return {}
 
 
+def bin_candidates(wl) -> Tuple[int, ...]:
+    """x-bin widths to try: the library's choice (0), and in 3D half the
+    patch when that is at least 4 cells."""
+    if wl.dim == 3 and wl.patch[0] % 2 == 0 and wl.patch[0] // 2 >= 4:
+        return (0, wl.patch[0] // 2)
+    return (0,)
+
+
 def tune(wl, species: Sequence[pic.Species], E, B, J, steps: int = 3,
          chunks: Sequence[int] = CHUNKS, wgs: Sequence[int] = WGS, use_cache: bool = True,
-         path: Optional[str] = None) -> Dict:
-    """Best (chunk, wg) for the persistent launch on these particles.  The
-    particles advance by (1 + steps) steps per candidate."""
+         path: Optional[str] = None, bins: Optional[Sequence[int]] = None) -> Dict:
+    """Best (chunk, wg, bin_x) for the persistent launch on these particles.
+    The particles advance by (1 + steps) steps per candidate."""
     path = path or cache_path()
     counts = np.concatenate([np.diff(s.offset.cpu().numpy()) for s in species])
     key = _key(wl, counts)
@@ -75,23 +84,28 @@ def tune(wl, species: Sequence[pic.Species], E, B, J, steps: int = 3,
         out = dict(cache[key])
         out["cached"] = True
         return out
-    trials: List[Tuple[float, int, int]] = []
+    trials: List[Tuple[float, float, int, int, int]] = []
     if wl.dim == 3 and tuple(wgs) == WGS:
         wgs = WGS_3D
-    for wg in wgs:
-        for chunk in chunks:
-            ctx = pic.Context(wl, mode=pic.MODE_PERSISTENT, chunk=chunk, wg_size=wg)
-            ctx.bin(species)
-            ctx.step(species, E, B, J, nsteps=1)
-            ctx.timing(True)
-            ctx.step(species, E, B, J, nsteps=steps)
-            ms, n = ctx.timing_read()["ipp"]
-            ctx.check()
-            ctx.close()
-            trials.append((ms / max(n, 1), chunk, wg))
-    ms, chunk, wg = min(trials)
-    out = {"chunk": chunk, "wg": wg, "ipp_ms": ms, "key": key,
-           "trials": [{"chunk": c, "wg": w, "ipp_ms": round(t, 4)} for t, c, w in trials]}
+    bins = bin_candidates(wl) if bins is None else tuple(bins)
+    for bx in bins:
+        for wg in wgs:
+            for chunk in chunks:
+                ctx = pic.Context(wl, mode=pic.MODE_PERSISTENT, chunk=chunk, wg_size=wg, bin_x=bx)
+                ctx.bin(species)
+                ctx.step(species, E, B, J, nsteps=1)
+                ctx.timing(True)
+                ctx.step(species, E, B, J, nsteps=steps)
+                t = ctx.timing_read()
+                ctx.check()
+                ctx.close()
+                ipp = t["ipp"][0] / max(t["ipp"][1], 1)
+                exch = t["exchange"][0] / max(t["exchange"][1], 1) if "exchange" in t else 0.0
+                trials.append((ipp + exch, ipp, chunk, wg, bx))
+    _, ms, chunk, wg, bx = min(trials)
+    out = {"chunk": chunk, "wg": wg, "bin_x": bx, "ipp_ms": ms, "key": key,
+           "trials": [{"chunk": c, "wg": w, "bin_x": b, "ipp_ms": round(i, 4),
+                       "step_ms": round(t, 4)} for t, i, c, w, b in trials]}
     cache[key] = out
     try:
         os.makedirs(os.path.dirname(path), exist_ok=True)
