@@ -803,6 +803,38 @@ pic_status sort_species(pic_ctx *c, pic_species *sp, int32_t nsp, bool general, 
   return PIC_OK;
 }
 
+// Field steps (forward, j read) or their reverse mode (j accumulated into).
+pic_status yee_steps(pic_ctx *c, double *const e[3], double *const b[3], double *const j[3],
+                     int32_t nsteps, bool adjoint, void *stream) {
+  if (!c) return PIC_ERR_ARG;
+  if (c->poisoned) return fail(c, PIC_ERR_STATE, "context unusable after a device error");
+  if (!e || !b || !j) return fail(c, PIC_ERR_ARG, "null field array");
+  for (int k = 0; k < 3; k++)
+    if (!e[k] || !b[k] || !j[k]) return fail(c, PIC_ERR_ARG, "null field pointer");
+  if (nsteps < 0) return fail(c, PIC_ERR_ARG, "nsteps < 0");
+  if (c->g.n[1] > 65535 || c->g.n[2] > 65535)
+    return fail(c, PIC_ERR_ARG, "the field solver takes at most 65535 cells along y and z");
+  hipStream_t st = (hipStream_t)stream;
+  if (hipSetDevice(c->device) != hipSuccess) return fail(c, PIC_ERR_HIP, "hipSetDevice");
+  YeeArgs a{};
+  a.dim = c->cfg.dim;
+  for (int k = 0; k < 3; k++) {
+    a.n[k] = c->g.n[k];
+    a.c[k] = k < c->cfg.dim ? c->cfg.dt / c->cfg.d[k] : 0.0;
+    a.e[k] = e[k];
+    a.b[k] = b[k];
+    a.j[k] = j[k];
+  }
+  a.dt = c->cfg.dt;
+  for (int s = 0; s < nsteps; s++) {
+    const hipError_t x = timed(c, PIC_KERNEL_MAXWELL, st, [&] {
+      return adjoint ? launch_yee_adjoint_step(a, st) : launch_yee_step(a, st);
+    });
+    if (x != hipSuccess) return hip_fail(c, x, "kernel launch");
+  }
+  return finish(c, st);
+}
+
 }  // namespace
 
 extern "C" {
@@ -1128,39 +1160,6 @@ pic_status pic_step(pic_ctx *c, pic_species *sp, int32_t nsp, pic_fields *f, int
   return finish(c, st);
 }
 
-namespace {
-// Field steps (forward, j read) or their reverse mode (j accumulated into).
-pic_status yee_steps(pic_ctx *c, double *const e[3], double *const b[3], double *const j[3],
-                     int32_t nsteps, bool adjoint, void *stream) {
-  if (!c) return PIC_ERR_ARG;
-  if (c->poisoned) return fail(c, PIC_ERR_STATE, "context unusable after a device error");
-  if (!e || !b || !j) return fail(c, PIC_ERR_ARG, "null field array");
-  for (int k = 0; k < 3; k++)
-    if (!e[k] || !b[k] || !j[k]) return fail(c, PIC_ERR_ARG, "null field pointer");
-  if (nsteps < 0) return fail(c, PIC_ERR_ARG, "nsteps < 0");
-  if (c->g.n[1] > 65535 || c->g.n[2] > 65535)
-    return fail(c, PIC_ERR_ARG, "the field solver takes at most 65535 cells along y and z");
-  hipStream_t st = (hipStream_t)stream;
-  if (hipSetDevice(c->device) != hipSuccess) return fail(c, PIC_ERR_HIP, "hipSetDevice");
-  YeeArgs a{};
-  a.dim = c->cfg.dim;
-  for (int k = 0; k < 3; k++) {
-    a.n[k] = c->g.n[k];
-    a.c[k] = k < c->cfg.dim ? c->cfg.dt / c->cfg.d[k] : 0.0;
-    a.e[k] = e[k];
-    a.b[k] = b[k];
-    a.j[k] = j[k];
-  }
-  a.dt = c->cfg.dt;
-  for (int s = 0; s < nsteps; s++) {
-    const hipError_t x = timed(c, PIC_KERNEL_MAXWELL, st, [&] {
-      return adjoint ? launch_yee_adjoint_step(a, st) : launch_yee_step(a, st);
-    });
-    if (x != hipSuccess) return hip_fail(c, x, "kernel launch");
-  }
-  return finish(c, st);
-}
-}  // namespace
 
 pic_status pic_rho(pic_ctx *c, const pic_species *sp, int32_t nsp, double *rho, void *stream) {
   if (!c) return PIC_ERR_ARG;

@@ -44,6 +44,7 @@ CASES = [
     (2, (48, 48), (16, 16), 3, 2, 802),
     (3, (16, 12, 12), (8, 6, 6), 2, 2, 803),
     (2, (256, 128), (128, 128), 1, 1, 804),  # tile above 96 KB: global atomics
+    (2, (128, 64), (64, 64), 2, 2, 805),     # patches cut into x-bins by the step kernels
 ]
 
 
