@@ -801,3 +801,24 @@ def test_maxwell_adjoint_is_the_transpose(dim):
     # Jb accumulates
     _, _, Jb2 = O.maxwell_adjoint(g, Eb, Bb, 4, Jb=Ja)
     assert np.allclose(Jb2, 2 * Ja, rtol=1e-13, atol=1e-13)
+
+
+def test_oracle_matches_its_stored_digest():
+    """Regression guard: the oracle's state after 10 steps of uniform64 equals
+    the digest written by tests/golden/make_golden.py (the paper prints no
+    worked example with values for these operators, so the golden file is
+    the oracle's own, pinned output; a change to the oracle's arithmetic has
+    to rewrite it on purpose)."""
+    import json
+    import os
+    import sys
+
+    here = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+    sys.path.insert(0, here)
+    try:
+        import make_golden
+    finally:
+        sys.path.remove(here)
+    with open(os.path.join(here, "oracle_uniform64_digest.json")) as fh:
+        stored = json.load(fh)
+    assert make_golden.digest() == stored
