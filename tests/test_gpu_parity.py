@@ -264,3 +264,58 @@ def test_x_bins_split_path_and_general_sort():
     osp, _, _ = run_oracle(wl, inp, 0)
     g, _ = run_gpu(wl, inp, 0)
     compare(osp, None, None, g, None, exact_order=False)
+
+
+@pytest.mark.parametrize("layout", list(LAYOUTS))
+def test_particle_outside_its_patch_is_reported(layout):
+    """Offsets that hand patch 0 the particles of its x-neighbour: the fused
+    kernel's tile bounds check reports PIC_ERR_POS at the next check, and the
+    context then refuses work (PIC_ERR_STATE) until it is freed."""
+    import torch
+
+    from paper_2204_12837_amd import pic
+
+    wl = I.custom(2, (32, 32), (8, 8), ppc=2, seed=330)
+    inp = I.generate(wl)
+    say(f"case position error {layout}")
+    ctx = pic.Context(wl)
+    sp = pic.upload(inp, "cuda:0", capacity_factor=LAYOUTS[layout]["capacity_factor"],
+                    n_slabs=ctx.n_slabs)
+    E, B, J = pic.upload_fields(inp, "cuda:0")
+    ctx.bin(sp)
+    torch.cuda.synchronize()
+    off = sp[0].offset
+    off[1] = off[2]  # patch 0 now ends where patch 1 ends
+    ctx.step(sp, E, B, J, nsteps=3)
+    with pytest.raises(pic.PicError) as ei:
+        ctx.check()
+    assert ei.value.status == pic.PIC_ERR_POS
+    with pytest.raises(pic.PicError) as ei:
+        ctx.step(sp, E, B, J, nsteps=1)
+    assert ei.value.status == pic.PIC_ERR_STATE
+    ctx.close()
+
+
+def test_call_order_errors():
+    """pic_project without pic_interp_push, and pic_step with a sort pending,
+    are refused before anything is enqueued."""
+    from paper_2204_12837_amd import pic
+
+    wl = I.custom(2, (16, 16), (8, 8), ppc=2, seed=331)
+    inp = I.generate(wl)
+    ctx = pic.Context(wl, check=True)
+    sp = pic.upload(inp, "cuda:0")
+    E, B, J = pic.upload_fields(inp, "cuda:0")
+    ctx.bin(sp)
+    with pytest.raises(pic.PicError) as ei:
+        ctx.project(sp, J)
+    assert ei.value.status == pic.PIC_ERR_STATE
+    ctx.interp_push(sp, E, B)
+    with pytest.raises(pic.PicError) as ei:
+        ctx.step(sp, E, B, J, nsteps=1)
+    assert ei.value.status == pic.PIC_ERR_STATE
+    ctx.project(sp, J)
+    ctx.bin(sp)
+    ctx.step(sp, E, B, J, nsteps=1)  # usable again
+    ctx.check()
+    ctx.close()
