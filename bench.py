@@ -391,7 +391,8 @@ def main(argv=None) -> int:
     from paper_2204_12837_amd import inputs as I
 
     wl = I.workload(args.workload)
-    n, secs, tim = run_gpu(wl, args.steps, args.warmup)
+    inp0 = I.generate(wl)
+    n, secs, tim = run_gpu(wl, args.steps, args.warmup, inp=inp0)
     value = n * args.steps / secs
     ipp_ms, ipp_n = tim["ipp"]
     ipp_avg = ipp_ms / max(ipp_n, 1)
@@ -421,6 +422,11 @@ def main(argv=None) -> int:
         "kernel_ms": per_kernel,
         "interp_push_project_rate": n / (ipp_avg * 1e-3),
     }
+    # the same call replaying one captured graph per step (no per-kernel events)
+    _, secs_g, _ = run_gpu(wl, args.steps, args.warmup, inp=inp0, graph=True)
+    del inp0
+    out["graph_replay"] = {"ms_per_step": secs_g / args.steps * 1e3,
+                           "particle_steps_per_s": n * args.steps / secs_g}
     if not args.no_imbalanced:
         wli = I.workload("imbalanced")
         inpi = I.generate(wli)
