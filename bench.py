@@ -315,9 +315,32 @@ def run_adjoint(every: int = 5):
         times.append((t1 - t0, t2 - t1))
     fw, bw = min(times, key=lambda t: t[0] + t[1])
     n = s.x.shape[1]
-    return {"workload": "adjoint256", "particles": n, "steps": wl.steps, "checkpoint_every": every,
-            "forward_ms": fw * 1e3, "backward_ms": bw * 1e3,
-            "gradient_particle_steps_per_s": n * wl.steps / (fw + bw)}
+    out = {"workload": "adjoint256", "particles": n, "steps": wl.steps, "checkpoint_every": every,
+           "forward_ms": fw * 1e3, "backward_ms": bw * 1e3,
+           "gradient_particle_steps_per_s": n * wl.steps / (fw + bw)}
+    # the self-consistent loop (particle step + field step per step), same particles
+    crun = ADJ.CycleRun(wl, torch.from_numpy(s.x).to(dev), torch.from_numpy(s.wt).to(dev),
+                        torch.from_numpy(s.id).to(dev), s.q, s.m, wl.steps, ctx=ctx)
+    ctimes = []
+    for rep in range(2):
+        u0 = torch.from_numpy(s.u).to(dev).requires_grad_(True)
+        E = torch.from_numpy(inp.E).to(dev).requires_grad_(True)
+        B = torch.from_numpy(inp.B).to(dev).requires_grad_(True)
+        W = torch.from_numpy(inp.W).to(dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        J, E1, B1 = ADJ.PicCycle.apply(u0, E, B, crun)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        ((W * J).sum() + (E1 * E1).sum()).backward()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        crun.ctx.check()
+        ctimes.append((t1 - t0, t2 - t1))
+    cf, cb = min(ctimes, key=lambda t: t[0] + t[1])
+    out["self_consistent"] = {"forward_ms": cf * 1e3, "backward_ms": cb * 1e3,
+                              "checkpoint_every": 1}
+    return out
 
 
 def cpu_baseline(sample_steps: int):

@@ -279,7 +279,10 @@ typedef struct {
  *   f         E and B (read); f->j unused.
  *   with_deposit  1: the segment's last step is the final step, its deposit
  *             contracted with jbar seeds the cotangents; 0: cot holds, on
- *             entry, the cotangents of the state after the segment.
+ *             entry, the cotangents of the state after the segment; 2: both
+ *             (the last step's deposit enters the loss through jbar and the
+ *             later state through cot, as in a self-consistent loop where
+ *             the current drives the field solver).
  *   cot       on return: cotangents of the state at the segment start.
  *   ebar,bbar d L / d E and d L / d B, accumulated (+=).
  * The segment is recomputed from ckpt with the forward kernels' operation

@@ -358,10 +358,10 @@ __device__ __forceinline__ void wrap2(const GridDev &g, double x[2]) {
 }
 
 // One particle per thread: recompute `nsteps` steps from the checkpoint in
-// registers, then reverse them.  with_dep: the last step's deposit is
-// contracted with Jbar (the seed); otherwise the cotangents of the state
-// after the segment are read from xb/ub (by particle id).  On exit xb/ub hold
-// the cotangents of the checkpoint state.
+// registers, then reverse them.  with_dep 1: the last step's deposit is
+// contracted with Jbar (the seed); 0: the cotangents of the state after the
+// segment are read from xb/ub (by particle id); 2: both are added.  On exit
+// xb/ub hold the cotangents of the checkpoint state.
 __global__ void __launch_bounds__(128) k_adjoint(GridDev g, AdjArgs aa, AdjFields f, int nsteps,
                                                  int with_dep, int *err) {
   const AdjSp &S = aa.s[blockIdx.y];
@@ -416,6 +416,13 @@ __global__ void __launch_bounds__(128) k_adjoint(GridDev g, AdjArgs aa, AdjField
     // the start-position part joins after the position update is reversed
     x[0] = x0b[0];
     x[1] = x0b[1];
+    if (with_dep == 2) {  // and the cotangents of the state after the segment
+      xb[0] += S.xb[0][id];
+      xb[1] += S.xb[1][id];
+      ub[0] = S.ub[0][id];
+      ub[1] = S.ub[1][id];
+      ub[2] = S.ub[2][id];
+    }
   } else {
     xb[0] = S.xb[0][id];
     xb[1] = S.xb[1][id];
@@ -633,6 +640,13 @@ __global__ void __launch_bounds__(256) k_adjoint_tiled(GridDev g, AdjArgs aa, Ad
       ub[0] = ub[1] = ub[2] = 0.0;
       x[0] = x0b[0];
       x[1] = x0b[1];
+      if (with_dep == 2) {  // and the cotangents of the state after the segment
+        xb[0] += S.xb[0][id];
+        xb[1] += S.xb[1][id];
+        ub[0] = S.ub[0][id];
+        ub[1] = S.ub[1][id];
+        ub[2] = S.ub[2][id];
+      }
     } else {
       xb[0] = S.xb[0][id];
       xb[1] = S.xb[1][id];

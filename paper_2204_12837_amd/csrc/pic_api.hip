@@ -1253,6 +1253,8 @@ pic_status pic_adjoint(pic_ctx *c, const pic_species *ck, int32_t nsp, const pic
   if (!ebar || !bbar) return fail(c, PIC_ERR_ARG, "null field cotangent");
   for (int k = 0; k < 3; k++)
     if (!ebar[k] || !bbar[k]) return fail(c, PIC_ERR_ARG, "null field cotangent");
+  if (with_deposit < 0 || with_deposit > 2)
+    return fail(c, PIC_ERR_ARG, "with_deposit must be 0, 1 or 2");
   if (with_deposit && (!jbar || !jbar[0] || !jbar[1] || !jbar[2]))
     return fail(c, PIC_ERR_ARG, "with_deposit needs jbar");
   AdjArgs a{};
@@ -1285,7 +1287,7 @@ pic_status pic_adjoint(pic_ctx *c, const pic_species *ck, int32_t nsp, const pic
   if (hipSetDevice(c->device) != hipSuccess) return fail(c, PIC_ERR_HIP, "hipSetDevice");
   hipError_t e = timed(c, PIC_KERNEL_ADJOINT, st, [&] {
     return launch_adjoint(c->g, a, f->e, f->b, with_deposit ? jbar : nullptr, ebar, bbar, nsteps,
-                          with_deposit ? 1 : 0, c->err_dev, st);
+                          with_deposit, c->err_dev, st);
   });
   if (e != hipSuccess) return hip_fail(c, e, "kernel launch");
   return finish(c, st);

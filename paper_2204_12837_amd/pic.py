@@ -342,9 +342,10 @@ class Context:
         ptr = lambda t: (C.c_void_p * 3)(*[t[c].data_ptr() for c in range(3)])
         self._raise(fn(self._h, ptr(E), ptr(B), ptr(J), int(nsteps), _stream()))
 
-    def adjoint(self, ckpt: Sequence["Species"], E, B, Jbar, nsteps: int, with_deposit: bool,
+    def adjoint(self, ckpt: Sequence["Species"], E, B, Jbar, nsteps: int, with_deposit,
                 cot: Sequence["Cotangent"], Ebar, Bbar):
-        """pic_adjoint on one segment (see include/pic.h)."""
+        """pic_adjoint on one segment (see include/pic.h); with_deposit is
+        0/False, 1/True or 2."""
         arr = (SpeciesC * len(ckpt))(*[s.cstruct() for s in ckpt])
         f = fields_struct(E, B, None)
         jb = (C.c_void_p * 3)(*[Jbar[c].data_ptr() for c in range(3)]) if Jbar is not None \
@@ -353,7 +354,7 @@ class Context:
         eb = (C.c_void_p * 3)(*[Ebar[c].data_ptr() for c in range(3)])
         bb = (C.c_void_p * 3)(*[Bbar[c].data_ptr() for c in range(3)])
         rc = lib().pic_adjoint(self._h, arr, len(ckpt), C.byref(f), jb, int(nsteps),
-                               1 if with_deposit else 0, cs, eb, bb, _stream())
+                               int(with_deposit), cs, eb, bb, _stream())
         self._raise(rc)
 
     def timing(self, on: bool = True):

@@ -169,3 +169,58 @@ def test_tiled_adjoint_falls_back_outside_its_tile():
     for a, b in ((du, du2), (dE, dE2), (dB, dB2)):
         a, b = a.cpu().numpy(), b.cpu().numpy()
         assert np.max(np.abs(a - b)) <= 1e-12 * max(np.abs(a).max(), 1e-300)
+
+
+def test_self_consistent_loop_gradient_matches_oracle_fd():
+    """Gradient through the self-consistent loop (PicCycle: particle step,
+    then field step with its current, 5 times) of
+    L = <W, J_last> + <V, E_5> + <U, B_5>: its directional derivative along a
+    random (du0, dE0, dB0) equals the central difference of the oracle's own
+    loop (h = 1e-5; the difference converges to 1e-9 between h = 1e-4 and
+    1e-5 on this case)."""
+    import copy
+
+    wl = I.custom(2, (32, 32), (8, 8), ppc=4, seed=430, sigma=0.05, bz0=1.0, field_amp=0.05,
+                  steps=5)
+    inp = I.generate(wl, with_W=True)
+    rng = np.random.default_rng(431)
+    V = rng.standard_normal(inp.E.shape)
+    U = rng.standard_normal(inp.B.shape)
+    s, x = _setup(wl, inp)
+    du = rng.standard_normal(s.u.shape) * 0.01
+    dE = rng.standard_normal(inp.E.shape) * 0.01
+    dB = rng.standard_normal(inp.B.shape) * 0.01
+    say("case self-consistent loop gradient")
+
+    def oracle_loss(t):
+        inp2 = copy.deepcopy(inp)
+        inp2.species[0].u = s.u + t * du
+        E, B = inp.E + t * dE, inp.B + t * dB
+        sps = O.species_from(inp2)
+        for sp in sps:
+            O.bin(wl, sp)
+        J = None
+        for _ in range(wl.steps):
+            J = O.step(wl, sps, E, B)
+            E, B = O.maxwell(wl, E, B, J, 1)
+        return (inp.W * J).sum() + (V * E).sum() + (U * B).sum()
+
+    h = 1e-5
+    fd = (oracle_loss(h) - oracle_loss(-h)) / (2 * h)
+    dev = "cuda:0"
+    run = ADJ.CycleRun(wl, torch.from_numpy(x).to(dev), torch.from_numpy(s.wt).to(dev),
+                       torch.from_numpy(s.id).to(dev), s.q, s.m, wl.steps)
+    u0 = torch.from_numpy(s.u).to(dev).requires_grad_(True)
+    E0 = torch.from_numpy(inp.E).to(dev).contiguous().requires_grad_(True)
+    B0 = torch.from_numpy(inp.B).to(dev).contiguous().requires_grad_(True)
+    J, E, B = ADJ.PicCycle.apply(u0, E0, B0, run)
+    t = lambda a: torch.from_numpy(a).to(dev)
+    L = (t(inp.W) * J).sum() + (t(V) * E).sum() + (t(U) * B).sum()
+    L.backward()
+    torch.cuda.synchronize()
+    run.ctx.check()
+    g = (math.fsum((u0.grad.cpu().numpy() * du).ravel()) + math.fsum((E0.grad.cpu().numpy() * dE).ravel())
+         + math.fsum((B0.grad.cpu().numpy() * dB).ravel()))
+    assert abs(g - fd) <= 1e-6 * abs(fd), (g, fd)
+    # the forward value matches the oracle's loss at t = 0
+    assert abs(L.item() - oracle_loss(0.0)) <= 1e-9 * abs(oracle_loss(0.0))
