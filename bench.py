@@ -407,8 +407,9 @@ def main(argv=None) -> int:
     if args.copy_calibration > 0:
         return copy_calibration(args.copy_calibration)
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path "
-              "(see DESIGN.md for how the step would shard)", file=sys.stderr)
+        print("bench.py measures one GPU: the library has no multi-GPU path; the step would "
+              "shard by patch collections with J-halo and particle exchanges between GPUs",
+              file=sys.stderr)
         return 2
 
     from paper_2204_12837_amd import inputs as I

@@ -145,7 +145,8 @@ void orc_maxwell(const orc_grid *g, double *const E[3], double *const B[3],
 void orc_maxwell_adjoint(const orc_grid *g, double *const Eb[3], double *const Bb[3],
                          double *const Jb[3], int64_t nsteps);
 
-/* sizeof(real) of this build */
+/* sizeof(real) of this compiled variant of the oracle (double, or long double
+ * for the finite-difference references) */
 int32_t orc_real_size(void);
 
 #ifdef __cplusplus
