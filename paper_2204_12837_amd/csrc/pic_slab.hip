@@ -555,16 +555,36 @@ __global__ void __launch_bounds__(256) k_exch_out(GridDev g, SlabArgs sa, int on
 template <int DIM>
 __global__ void __launch_bounds__(256) k_exch_in(GridDev g, SlabArgs sa) {
   const SlabDev &S = sa.s[blockIdx.y];
-  if (S.ctl[1] == 2) return;
   const int Q = blockIdx.x;
+  // the state flag, the departure count and the outbox start are read
+  // together; a standing species leaves after the reads
+  const int flag = S.ctl[1];
   const int m = S.dep[Q];
   const int64_t ob = S.sb[Q];
+  if (flag == 2) return;
   for (int r = threadIdx.x; r < m; r += blockDim.x) {
     const int64_t e = ob + r;
+    // the departure's state is loaded with its destination, so only the
+    // stores wait for the slot the destination's arrival counter hands out
+    double x[DIM], u[3];
+#pragma unroll
+    for (int a = 0; a < DIM; a++) x[a] = S.ox[a][e];
+    u[0] = S.ou[0][e];
+    u[1] = S.ou[1][e];
+    u[2] = S.ou[2][e];
+    const double w = S.ow[e];
+    const int64_t id = S.oid[e];
     const int D = S.odest[e];
     const int pos = S.cnt2[D] + atomicAdd(&S.arr[D], 1);
     if (pos < S.cap[D]) {
-      copy_particle<DIM>(S.xs, S.us, S.ws, S.ids, S.sb[D] + pos, S.ox, S.ou, S.ow, S.oid, e);
+      const int64_t d = S.sb[D] + pos;
+#pragma unroll
+      for (int a = 0; a < DIM; a++) S.xs[a][d] = x[a];
+      S.us[0][d] = u[0];
+      S.us[1][d] = u[1];
+      S.us[2][d] = u[2];
+      S.ws[d] = w;
+      S.ids[d] = id;
     } else {
       S.odest[e] = D | kUnplaced;
       atomicOr(&S.ctl[1], 1);
@@ -572,19 +592,32 @@ __global__ void __launch_bounds__(256) k_exch_in(GridDev g, SlabArgs sa) {
   }
 }
 
-// Persistent mode: work units of chunk particles for the counts count(P),
-// every full unit first, then the remainders (one workgroup per species,
-// each thread a contiguous run of patches).  count must not change during
-// the call; the list goes to units + ubase, its length to qctl[2s+1] (0 if
-// the species stands still) and a zero ticket to qctl[2s].
-template <class Count>
-__device__ void make_units(const SlabDev &S, int s, int n, int chunk, bool still, Count count,
-                           Unit *units, int *qctl, int *wtot) {
+// Persistent mode: work units of chunk particles for the patch counts, every
+// full unit first, then the remainders (one workgroup per species, each
+// thread a contiguous run of patches).  first(P) gives patch P's count once
+// (it may also store it); again(P) gives it a second time.  The list goes
+// to units + ubase, its length to qctl[2s+1] (0 if the species stands
+// still) and a zero ticket to qctl[2s].
+constexpr int kUnitsCached = 8;  // counts a thread keeps in registers
+
+template <class First, class Again>
+__device__ void make_units(const SlabDev &S, int s, int n, int chunk, bool still, First first,
+                           Again again, Unit *units, int *qctl, int *wtot) {
   const int per = (n + blockDim.x - 1) / blockDim.x;
   const int p0 = min(n, (int)threadIdx.x * per), p1 = min(n, p0 + per);
+  int cc[kUnitsCached];
   int nf = 0, nr = 0;
-  for (int P = p0; P < p1; P++) {
-    const int c = count(P);
+#pragma unroll
+  for (int k = 0; k < kUnitsCached; k++) {
+    cc[k] = 0;
+    if (p0 + k < p1) {
+      cc[k] = first(p0 + k);
+      nf += cc[k] / chunk;
+      nr += cc[k] % chunk != 0;
+    }
+  }
+  for (int P = p0 + kUnitsCached; P < p1; P++) {
+    const int c = first(P);
     nf += c / chunk;
     nr += c % chunk != 0;
   }
@@ -592,8 +625,7 @@ __device__ void make_units(const SlabDev &S, int s, int n, int chunk, bool still
   int rf = block_excl_sum(nf, tf, wtot);
   int rr = tf + block_excl_sum(nr, tr, wtot);
   Unit *ul = units + S.ubase;
-  for (int P = p0; P < p1; P++) {
-    const int c = count(P);
+  auto emit = [&](int P, int c) {
     Unit un;
     un.s = s;
     un.P = P;
@@ -607,7 +639,11 @@ __device__ void make_units(const SlabDev &S, int s, int n, int chunk, bool still
       un.k1 = c;
       ul[rr++] = un;
     }
-  }
+  };
+#pragma unroll
+  for (int k = 0; k < kUnitsCached; k++)
+    if (p0 + k < p1) emit(p0 + k, cc[k]);
+  for (int P = p0 + kUnitsCached; P < p1; P++) emit(P, again(P));
   if (threadIdx.x == 0) {
     qctl[2 * s + 1] = still ? 0 : tf + tr;
     qctl[2 * s] = 0;
@@ -627,13 +663,21 @@ __global__ void __launch_bounds__(1024) k_exch_fin(GridDev g, SlabArgs sa, int *
   const int flag = S.ctl[1];
   if (flag == 2) return;
   if (flag == 0) {
+    if (units) {  // the new counts, and the work units from them, in one pass
+      make_units(
+          S, s, n, chunk, false,
+          [&](int P) {
+            const int c = S.cnt2[P] + S.arr[P];
+            S.cnt[P] = c;
+            S.arr[P] = 0;
+            return c;
+          },
+          [&](int P) { return S.cnt[P]; }, units, qctl, wtot);
+      return;
+    }
     for (int P = threadIdx.x; P < n; P += blockDim.x) {
       S.cnt[P] = S.cnt2[P] + S.arr[P];
       S.arr[P] = 0;
-    }
-    if (units) {
-      __syncthreads();  // counts written before other threads read them
-      make_units(S, s, n, chunk, false, [&](int P) { return S.cnt[P]; }, units, qctl, wtot);
     }
     return;
   }
@@ -650,9 +694,10 @@ __global__ void __launch_bounds__(1024) k_exch_fin(GridDev g, SlabArgs sa, int *
     S.ctl[1] = 2;  // no room for a new plan: the species stands still
     atomicOr(err, kErrCap);
   }
-  if (units)  // the counts the new plan's copies will set
-    make_units(S, s, n, chunk, still, [&](int P) { return S.cnt2[P] + S.arr[P]; }, units, qctl,
-               wtot);
+  if (units) {  // the counts the new plan's copies will set
+    auto need = [&](int P) { return S.cnt2[P] + S.arr[P]; };
+    make_units(S, s, n, chunk, still, need, need, units, qctl, wtot);
+  }
 }
 
 // Overflow, part 1 (grid: 2 x patches, x species): every particle goes to
@@ -709,8 +754,8 @@ __global__ void __launch_bounds__(1024) k_slab_units(GridDev g, SlabArgs sa, int
   __shared__ int wtot[16];
   const int s = blockIdx.x;
   const SlabDev &S = sa.s[s];
-  make_units(S, s, g.npatch, chunk, S.ctl[1] == 2, [&](int P) { return S.cnt[P]; }, units, qctl,
-             wtot);
+  auto count = [&](int P) { return S.cnt[P]; };
+  make_units(S, s, g.npatch, chunk, S.ctl[1] == 2, count, count, units, qctl, wtot);
 }
 
 // End of a call: dense offsets from the slab counts (one workgroup of 1024
