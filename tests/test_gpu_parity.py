@@ -11,6 +11,8 @@ Layouts: calls of three steps or more keep the particles in per-patch slabs
 when the buffers have room for them (the default capacity); with buffers of
 exactly n particles (capacity factor 1) every call uses the dense layout and
 the permutation sort."""
+import ctypes as C
+
 import numpy as np
 import pytest
 
@@ -319,3 +321,53 @@ def test_call_order_errors():
     ctx.step(sp, E, B, J, nsteps=1)  # usable again
     ctx.check()
     ctx.close()
+
+
+def _combo(seed):
+    """A seeded random combination of the step's options (dimension, sizes,
+    x-bins, launch mode, workgroup, chunk, layout, graphs, call lengths)."""
+    rng = np.random.default_rng(seed)
+    dim = 3 if seed % 3 == 2 else 2
+    if dim == 2:
+        patch = (int(rng.choice([6, 8, 12, 16, 24])), int(rng.choice([6, 8, 12])))
+        npat = (int(rng.integers(1, 5)), int(rng.integers(1, 5)))
+        ppc = int(rng.integers(1, 8))
+        wgs = [64, 128, 256, 512, 1024]
+    else:
+        patch = (int(rng.choice([6, 8, 12])), int(rng.choice([6, 8])), int(rng.choice([6, 8])))
+        npat = (int(rng.integers(1, 4)), int(rng.integers(1, 3)), int(rng.integers(1, 3)))
+        ppc = int(rng.integers(1, 3))
+        wgs = [256, 512, 1024]
+    n = tuple(p * k for p, k in zip(patch, npat))
+    divs = [b for b in range(1, patch[0] + 1) if patch[0] % b == 0 and b >= 2]
+    return dict(dim=dim, n=n, patch=patch, ppc=ppc, nsp=int(rng.integers(1, 3)),
+                sigma=float(rng.choice([0.05, 0.2, 0.4])),
+                bin_x=int(rng.choice([0] + divs)), mode=int(rng.integers(0, 2)),
+                wg=int(rng.choice(wgs)), chunk=int(rng.choice([256, 512, 2048])),
+                layout=str(rng.choice(list(LAYOUTS))), graph=bool(rng.integers(0, 2)),
+                sizes=[int(k) for k in rng.integers(1, 5, size=int(rng.integers(1, 4)))])
+
+
+@pytest.mark.parametrize("seed", range(1000, 1036))
+def test_random_option_combinations(seed):
+    """Parity with the oracle for random combinations of the step's options
+    (the bar of the other parity tests; order inside a patch is compared
+    exactly only in the dense layout without x-bins)."""
+    from paper_2204_12837_amd import pic
+
+    c = _combo(seed)
+    wl = I.custom(c["dim"], c["n"], c["patch"], ppc=c["ppc"], seed=seed, sigma=c["sigma"],
+                  n_species=c["nsp"])
+    cfg = pic.make_config(wl, mode=c["mode"], chunk=c["chunk"], wg_size=c["wg"], bin_x=c["bin_x"])
+    if pic.validate(cfg)[0] != pic.PIC_OK:
+        pytest.skip(f"configuration not valid: {pic.validate(cfg)[1]}")
+    inp = I.generate(wl)
+    steps = sum(c["sizes"])
+    say(f"case combo {seed}: {c}")
+    osp, J, A = run_oracle(wl, inp, steps)
+    lay = LAYOUTS[c["layout"]]
+    g, Jg = run_gpu(wl, inp, steps, mode=c["mode"], chunk=c["chunk"], wg_size=c["wg"],
+                    graph=c["graph"], step_sizes=c["sizes"], capacity_factor=lay["capacity_factor"],
+                    bin_x=c["bin_x"])
+    exact = lay["exact_order"] and pic.lib().pic_bin_width(C.byref(cfg)) == c["patch"][0]
+    compare(osp, J, A, g, Jg, exact_order=exact)
