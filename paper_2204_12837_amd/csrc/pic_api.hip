@@ -47,8 +47,10 @@ struct SlabScratch {
   int32_t *odest = nullptr;
 };
 
-// Static LDS of the fused kernels beside the tiles: the slab-layout kernel's
-// departure bitmap and prefix (2 x 2048 words) plus control words and slack.
+// Static LDS budget kept free beside the tiles when a configuration is
+// validated: 2 x 2048 words (the per-patch fused kernel's departure bitmap
+// and prefix take 2 x 512 of them) plus control words and slack, so the
+// tile sizes accepted leave room to grow those arrays.
 constexpr size_t kStaticLds = 2 * 2048 * 4 + 256;
 
 }  // namespace
