@@ -20,7 +20,7 @@ _I64P = C.POINTER(C.c_int64)
 
 class Grid(C.Structure):
     _fields_ = [("dim", C.c_int32), ("n", C.c_int32 * 3), ("d", C.c_double * 3),
-                ("dt", C.c_double), ("patch", C.c_int32 * 3)]
+                ("dt", C.c_double), ("patch", C.c_int32 * 3), ("reflect", C.c_int32 * 3)]
 
 
 class Species(C.Structure):
@@ -95,6 +95,7 @@ def grid(wl) -> Grid:
         g.n[a] = int(wl.n[a]) if a < wl.dim else 1
         g.d[a] = float(wl.d[a])
         g.patch[a] = int(wl.patch[a]) if a < wl.dim else 1
+        g.reflect[a] = int(getattr(wl, "reflect", (0, 0, 0))[a]) if a < wl.dim else 0
     g.dt = float(wl.dt)
     return g
 

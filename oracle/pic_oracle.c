@@ -11,6 +11,10 @@
  *     Projection (paper, section "Parallelization without tasks",
  *     Algorithm 1), with the boundary conditions themselves and the particle
  *     sort done afterwards in the synchronisation phase (same section);
+ *   - periodic or reflecting particle boundaries per axis (the paper's
+ *     radiation-pressure case reflects particles at its x borders, section
+ *     "Basic performance benchmarks"); the pre-BC operation mirrors a particle that
+ *     crossed a wall before its current is projected;
  *   - order-2 interpolation / projection shapes on a three-point stencil
  *     (paper, section "Basic performance benchmarks" and the plasma-expansion
  *     set-up);
@@ -43,6 +47,7 @@ typedef struct {
   int dim;
   int64_t n[3], patch[3], np[3], npatch, ncell;
   real d[3], inv_d[3], L[3], dt;
+  int reflect[3];
 } G;
 
 static void mk_grid(const orc_grid *g, G *G_) {
@@ -59,6 +64,7 @@ static void mk_grid(const orc_grid *g, G *G_) {
     G_->d[a] = (real)g->d[a];
     G_->inv_d[a] = (real)1 / (real)g->d[a];
     G_->L[a] = (real)G_->n[a] * (real)g->d[a];
+    G_->reflect[a] = a < g->dim && g->reflect[a] != 0;
   }
   G_->dt = (real)g->dt;
 }
@@ -363,18 +369,51 @@ static int deposit(const G *g, real q, real w, const real x0[3], const real x1[3
 }
 
 /* ---------------------------------------------------------------------- */
+/* pre-boundary-condition operation on an axis with reflecting walls at 0 and
+ * L: a pushed position that left [0, L) is mirrored back inside about the
+ * wall it crossed (x -> -x, or x -> 2L - x) and its momentum component along
+ * the axis changes sign.  Both mirror images are exact in floating point
+ * (Sterbenz's lemma: x and 2L lie within a factor two of each other); the one
+ * position that lands on L itself, x = L, is moved to the largest value below
+ * L so that it stays in the last cell.  The paper flags such particles in the
+ * pre-BC operation, which writes positions and momenta (section
+ * "Parallelization with OpenMP task"); here the mirror is applied there too,
+ * before the Projection, so the current is deposited along the mirrored move
+ * (reading in the design notes).  Returns the mirrored axes as bits. */
+static int reflect_walls(const G *g, real x1[3], real u[3]) {
+  int hit = 0;
+  for (int a = 0; a < g->dim; a++) {
+    if (!g->reflect[a]) continue;
+    if (x1[a] < 0) {
+      x1[a] = -x1[a];
+    } else if (x1[a] >= g->L[a]) {
+      x1[a] = (real)2 * g->L[a] - x1[a];
+      if (x1[a] >= g->L[a]) x1[a] = nextafter(g->L[a], (real)0);
+    } else {
+      continue;
+    }
+    u[a] = -u[a];
+    hit |= 1 << a;
+  }
+  return hit;
+}
+
 /* pre-boundary-condition operation: the patch the particle will belong to,
  * from a periodically wrapped copy of its position:
  *   if (x < 0) x += L;  if (x >= L) x -= L;   (the second test also catches
  *   x + L rounding to L), cell c = floor(x * inv_d) clamped to n-1,
  *   patch P_a = c_a / patch_a, key = Px + NPx (Py + NPy Pz).
- * Returns -1 if the position is more than one period outside the box. */
+ * A reflecting axis is not wrapped (its positions were mirrored inside).
+ * Returns -1 if the position is more than one period outside the box, or
+ * outside [0, L) on a reflecting axis. */
 static int64_t patch_key(const G *g, const real x1[3], real xw[3]) {
   int64_t P[3] = {0, 0, 0};
   for (int a = 0; a < g->dim; a++) {
     real v = x1[a];
-    if (v < 0) v += g->L[a];
-    if (v >= g->L[a]) v -= g->L[a];
+    if (!g->reflect[a]) {
+      if (v < 0) v += g->L[a];
+      if (v >= g->L[a]) v -= g->L[a];
+    }
     if (!(v >= 0 && v < g->L[a])) return -1;
     xw[a] = v;
     int64_t c = (int64_t)floor(v * g->inv_d[a]);
@@ -484,11 +523,16 @@ int orc_step(const orc_grid *gi, orc_species *sp, int32_t nsp, const double *con
         for (int c = 0; c < 3; c++) S->u[c][p] = (double)u[c];
         for (int a = 0; a < dim; a++) S->x[a][p] = (double)(x0[p - b][a] + g.dt * vel[p - b][a]);
       }
-      /* pre-BC: flag the destination patch (the wrap itself is applied in
-       * the synchronisation phase below) */
+      /* pre-BC: mirror at reflecting walls, flag the destination patch (the
+       * periodic wrap itself is applied in the synchronisation phase below) */
       for (int64_t p = b; p < e; p++) {
         real x1[3] = {0, 0, 0}, xw[3];
         for (int a = 0; a < dim; a++) x1[a] = S->x[a][p];
+        real u[3] = {S->u[0][p], S->u[1][p], S->u[2][p]};
+        if (reflect_walls(&g, x1, u)) {
+          for (int a = 0; a < dim; a++) S->x[a][p] = (double)x1[a];
+          for (int c = 0; c < 3; c++) S->u[c][p] = (double)u[c];
+        }
         keys[s][p] = patch_key(&g, x1, xw);
         if (keys[s][p] < 0) err = ORC_ERR_POS;
       }
@@ -877,6 +921,13 @@ int orc_jvp(const orc_grid *gi, double q, double m, int64_t n, const double *con
         x1[a] = xp[a] + g.dt * v[a];
         dx1[a] = dxp[a] + g.dt * dv[a];
       }
+      /* a mirror at a wall negates the tangents it negates the values of */
+      const int hit = reflect_walls(&g, x1, up);
+      for (int a = 0; a < 2; a++)
+        if (hit >> a & 1) {
+          dx1[a] = -dx1[a];
+          dup[a] = -dup[a];
+        }
       if (k == nsteps) {
         err = deposit_tangent2(&g, (real)q, (real)w[p], xp, x1, v[2], dxp, dx1, dv[2], Jr, dJr);
       } else {
@@ -932,6 +983,7 @@ static int loss_at(const G *g, real q, real m, int64_t n, const double *const x[
       interp6(g, Er, Br, xp, F, NULL);
       boris(alpha, F, up, v);
       for (int a = 0; a < 2; a++) x1[a] = xp[a] + g->dt * v[a];
+      reflect_walls(g, x1, up);
       if (k == nsteps) {
         err = deposit(g, q, (real)w[p], xp, x1, v[2], Jr, NULL);
       } else {

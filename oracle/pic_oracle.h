@@ -36,6 +36,11 @@ typedef struct {
   double d[3];      /* cell sizes */
   double dt;        /* time step */
   int32_t patch[3]; /* patch size in cells per axis; patch[2] = 1 in 2D */
+  int32_t reflect[3]; /* particle boundary per axis: 0 periodic, 1 reflecting
+                         walls at 0 and L (the paper's reflective particle
+                         condition of its radiation-pressure case, section
+                         "Basic performance benchmarks"); fields stay
+                         periodic */
 } orc_grid;
 
 typedef struct {
@@ -73,7 +78,8 @@ int orc_deposit(const orc_grid *g, double q, double w, const double x0[3],
                 const double x1[3], double vz, double *const J[3], double *const A[3]);
 
 /* Periodic wrap, patch key and stable counting sort by patch (in place);
- * writes s->off. */
+ * writes s->off.  On a reflecting axis a position outside [0, L) is an
+ * error (ORC_ERR_POS), not wrapped. */
 int orc_bin(const orc_grid *g, orc_species *s);
 
 /* One PIC step of the macro-particle operators for nsp species already

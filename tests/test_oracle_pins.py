@@ -6,6 +6,7 @@ independent brute-force evaluation written from a different definition
 (e.g. the B-spline's piecewise formula instead of the oracle's weights).
 """
 import math
+from dataclasses import replace as dataclasses_replace
 from decimal import Decimal, getcontext
 from fractions import Fraction
 
@@ -546,6 +547,125 @@ def test_step_species_linearity_and_order_invariance():
 
 
 # --------------------------------------------------------------------------
+# reflecting walls (particle boundary condition)
+
+def _walls(wl, axes):
+    import dataclasses
+    return dataclasses.replace(wl, reflect=tuple(int(a in axes) for a in range(3)))
+
+
+def _fold(y, L):
+    """Straight-line coordinate y unfolded past walls at 0 and L, folded back
+    into [0, L] (a triangle wave), and the parity of the number of walls hit."""
+    m = np.mod(y, 2 * L)
+    back = m > L
+    return np.where(back, 2 * L - m, m), back
+
+
+@pytest.mark.parametrize("axes", [(0,), (1,), (0, 1)])
+def test_walls_free_streaming_is_the_folded_line(axes):
+    """Without fields every particle moves on a straight line; walls fold that
+    line into the box.  After k steps each position is the fold of x0 + k dt v
+    and each momentum component has the sign of the fold's parity."""
+    wl = _walls(I.custom(2, (24, 16), (8, 8), ppc=3, seed=41, sigma=0.8), axes)
+    inp = I.generate(wl)
+    inp.E[:] = 0
+    inp.B[:] = 0
+    sps = O.species_from(inp)
+    s = sps[0]
+    O.bin(wl, s)
+    o = np.argsort(s.id)
+    x0, u0 = s.x[:, o].copy(), s.u[:, o].copy()
+    k = 12
+    for _ in range(k):
+        O.step(wl, sps, inp.E, inp.B)
+    o = np.argsort(s.id)
+    x, u = s.x[:, o], s.u[:, o]
+    gam = np.sqrt(1 + (u0 ** 2).sum(axis=0))
+    hits = 0
+    for a in range(2):
+        L = wl.n[a] * wl.d[a]
+        y = x0[a] + k * wl.dt * u0[a] / gam
+        if a in axes:
+            want, flipped = _fold(y, L)
+            # particles whose line ends within rounding of a wall are ambiguous
+            ok = (np.abs(np.mod(y + L / 2, L) - L / 2) > 1e-9) & (np.abs(np.mod(y, L) - L / 2) < L / 2 - 1e-9)
+            assert np.array_equal(u[a, ok], np.where(flipped, -u0[a], u0[a])[ok])
+            hits += int(flipped[ok].sum())
+        else:
+            want = np.mod(y, L)
+            ok = np.abs(np.mod(y + L / 2, L) - L / 2) > 1e-9
+            assert np.array_equal(u[a], u0[a])
+        assert np.max(np.abs(x[a, ok] - want[ok])) <= 1e-13 * L
+        assert np.all(x[a] >= 0) and np.all(x[a] < L)
+    assert np.array_equal(u[2], u0[2])
+    assert hits > 50  # many particles met a wall
+    # every particle sits in the patch its offsets say
+    cells = np.minimum(np.floor(s.x / np.array(wl.d[:2])[:, None]).astype(np.int64),
+                       np.array(wl.n[:2])[:, None] - 1)
+    P = cells[0] // wl.patch[0] + (wl.n[0] // wl.patch[0]) * (cells[1] // wl.patch[1])
+    assert np.array_equal(np.diff(s.off), np.bincount(P, minlength=wl.n_patches))
+    assert np.all(np.diff(P) >= 0)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_walls_keep_charge_continuity(dim):
+    """A mirrored particle deposits the current of the move from its start to
+    its mirrored position, so the deposit still satisfies the discrete
+    continuity equation at every node, and the total current is the sum of
+    q w (x1 - x0) / dt over those moves (no wrap on a walled axis).  A deposit
+    along the unmirrored path would leave a charge residual at the walls."""
+    if dim == 2:
+        wl = _walls(I.custom(2, (16, 24), (8, 8), ppc=6, seed=42, sigma=0.5, n_species=2), (0, 1))
+    else:
+        wl = _walls(I.custom(3, (16, 8, 8), (8, 8, 8), ppc=3, seed=43, sigma=0.5, n_species=2), (0, 2))
+    inp = I.generate(wl)
+    sps = O.species_from(inp)
+    for s in sps:
+        O.bin(wl, s)
+    rho0 = sum(O.rho(wl, s.q, s.x, s.w) for s in sps)
+    before = []
+    for s in sps:
+        o = np.argsort(s.id)
+        before.append((s.x[:, o].copy(), s.u[:, o].copy()))
+    J = O.step(wl, sps, inp.E, inp.B)
+    rho1 = sum(O.rho(wl, s.q, s.x, s.w) for s in sps)
+    res = (rho1 - rho0) / wl.dt + _div(wl, J)
+    assert np.max(np.abs(res)) <= 1e-13 * np.abs(rho0).max() / wl.dt
+    flips = 0
+    for a in range(dim):
+        L = wl.n[a] * wl.d[a]
+        tot = 0.0
+        for s, (xb, ub) in zip(sps, before):
+            o = np.argsort(s.id)
+            dx = s.x[a, o] - xb[a]
+            if not wl.reflect[a]:
+                dx = (dx + L / 2) % L - L / 2
+            else:
+                flips += int((np.sign(s.u[a, o]) != np.sign(ub[a])).sum())
+            tot += (s.q * s.w[o] * dx).sum() / wl.dt
+        assert abs(J[a].sum() - tot) <= 1e-12 * max(1.0, abs(tot))
+    assert flips > 0
+
+
+def test_walls_bin_rejects_positions_outside_the_box():
+    """On a walled axis a position outside [0, L) is an error, not wrapped;
+    the periodic axis still wraps."""
+    wl = _walls(I.custom(2, (16, 16), (8, 8), ppc=1, seed=44), (0,))
+    inp = I.generate(wl)
+    sp = O.species_from(inp)[0]
+    L = wl.n[1] * wl.d[1]
+    sp.x[1, 0] = -0.25 * L
+    O.bin(wl, sp)
+    assert np.all(sp.x[1] >= 0)
+    for bad in (-1e-3, wl.n[0] * wl.d[0]):
+        sp2 = O.species_from(inp)[0]
+        sp2.x[0, 3] = bad
+        with pytest.raises(O.OracleError):
+            O.bin(wl, sp2)
+
+
+# --------------------------------------------------------------------------
 # derivatives
 
 def _small_adjoint_case(seed=17, steps=4):
@@ -569,6 +689,28 @@ def test_jvp_matches_extended_precision_fd():
         fd, L0 = O.fd(wl, sp.q, sp.m, sp.x, sp.u, sp.w, inp.E, inp.B, inp.W, du, dE, dB, h=1e-6)
         assert abs(L0 - math.fsum((inp.W * J).ravel())) <= 1e-13 * max(1, abs(L0))
         assert abs(g - fd) <= 1e-7 * abs(fd), (kind, g, fd)
+
+
+def test_jvp_with_walls_matches_extended_precision_fd():
+    """Through reflecting walls (fast particles, so many mirror images in
+    four steps) the tangent still equals the central difference."""
+    wl = _walls(I.custom(2, (16, 16), (8, 8), ppc=3, seed=45, sigma=0.6, bz0=1.0, steps=4),
+                (0, 1))
+    inp = I.generate(wl, with_W=True)
+    sp = O.species_from(inp)[0]
+    O.bin(wl, sp)
+    rng = np.random.default_rng(46)
+    du = rng.normal(size=sp.u.shape)
+    dE = rng.normal(size=inp.E.shape) * 0.01
+    J, dJ = O.jvp(wl, sp.q, sp.m, sp.x, sp.u, sp.w, inp.E, inp.B, du, dE, None)
+    g = math.fsum((inp.W * dJ).ravel())
+    fd, L0 = O.fd(wl, sp.q, sp.m, sp.x, sp.u, sp.w, inp.E, inp.B, inp.W, du, dE, None, h=1e-6)
+    assert abs(L0 - math.fsum((inp.W * J).ravel())) <= 1e-13 * max(1, abs(L0))
+    assert abs(g - fd) <= 1e-7 * abs(fd), (g, fd)
+    # the walls matter: the periodic run's J differs
+    Jp, _ = O.jvp(dataclasses_replace(wl, reflect=(0, 0, 0)), sp.q, sp.m, sp.x, sp.u, sp.w,
+                  inp.E, inp.B, du, dE, None)
+    assert np.abs(Jp - J).max() > 1e-6 * np.abs(J).max()
 
 
 def test_jvp_is_linear_in_direction():
