@@ -108,6 +108,25 @@ typedef struct {
                           bin per patch, the particles inside a patch are
                           ordered by bin, and pic_step and pic_interp_push
                           first sort them by bin (one general sort per call). */
+  int32_t reflect[3];  /* particle boundary per axis (reflect[2] ignored in
+                          2D): 0 = periodic; 1 = reflecting walls at 0 and
+                          L = n d, the paper's reflective particle condition
+                          (section "Basic performance benchmarks", its
+                          radiation-pressure case).  In the pre-BC
+                          operation, which writes positions and momenta
+                          (section "Parallelization with OpenMP task"), a
+                          particle pushed across a wall is mirrored back
+                          inside (x -> -x, x -> 2L - x; x = L exactly goes
+                          to the largest double below L) and its momentum
+                          component along the axis changes sign, before its
+                          current is projected: the deposit follows the
+                          mirrored move and stays charge-conserving.  Fields
+                          and current stay periodic arrays: nodes beyond a
+                          wall are read and written at their periodic
+                          images.  pic_bin reports PIC_ERR_POS for a position
+                          outside [0, L) on a walled axis instead of
+                          wrapping it.  pic_adjoint differentiates through
+                          the mirror. */
 } pic_config;
 
 typedef struct {

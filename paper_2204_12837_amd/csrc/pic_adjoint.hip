@@ -348,6 +348,20 @@ __device__ __forceinline__ bool deposit_adj(const GridDev &g, const AdjFields &f
   return true;
 }
 
+// Transpose of the mirror at reflecting walls (bit a of h: axis a was
+// mirrored): the cotangents of the position and momentum components along a
+// mirrored axis change sign.
+__device__ __forceinline__ void unmirror(uint32_t h, double xb[2], double ub[3]) {
+  if (h & 1) {
+    xb[0] = -xb[0];
+    ub[0] = -ub[0];
+  }
+  if (h & 2) {
+    xb[1] = -xb[1];
+    ub[1] = -ub[1];
+  }
+}
+
 __device__ __forceinline__ void wrap2(const GridDev &g, double x[2]) {
   for (int a = 0; a < 2; a++) {
     double v = x[a];
@@ -376,6 +390,7 @@ __global__ void __launch_bounds__(128) k_adjoint(GridDev g, AdjArgs aa, AdjField
   double x[2] = {S.x[0][p], S.x[1][p]};
   double u[3] = {S.u[0][p], S.u[1][p], S.u[2][p]};
   double xlast[2] = {0, 0}, xend[2] = {0, 0}, vend[3] = {0, 0, 0};
+  uint32_t hits = 0;  // axes mirrored at a wall, two bits per step
 #pragma unroll
   for (int k = 0; k < kAdjMaxSteps; k++) {
     if (k < nsteps) {
@@ -387,7 +402,8 @@ __global__ void __launch_bounds__(128) k_adjoint(GridDev g, AdjArgs aa, AdjField
       double F[6], v[3];
       interp_g(g, f, x, F);
       boris_f(S.alpha, F, u, v);
-      double x1[2] = {x[0] + g.dt * v[0], x[1] + g.dt * v[1]};
+      double x1[3] = {x[0] + g.dt * v[0], x[1] + g.dt * v[1], 0.0};
+      if (g.reflect) hits |= (uint32_t)reflect_walls<2>(g, x1, u) << (2 * k);
       if (k == nsteps - 1) {
         xlast[0] = x[0];
         xlast[1] = x[1];
@@ -434,7 +450,10 @@ __global__ void __launch_bounds__(128) k_adjoint(GridDev g, AdjArgs aa, AdjField
 #pragma unroll
   for (int k = kAdjMaxSteps - 1; k >= 0; k--) {
     if (k < nsteps) {
-      // step k: state (xs[k], us[k]) -> x_{k+1} = x + dt v(u'), u'
+      // step k: state (xs[k], us[k]) -> x_{k+1} = x + dt v(u'), u', each
+      // then mirrored at a wall it crossed: the mirror negates the
+      // cotangents of the components it negates
+      unmirror(hits >> (2 * k), xb, ub);
       double F[6];
       interp_g(g, f, xs[k], F);
       double vb[3] = {g.dt * xb[0], g.dt * xb[1], 0.0};
@@ -604,6 +623,7 @@ __global__ void __launch_bounds__(256) k_adjoint_tiled(GridDev g, AdjArgs aa, Ad
     double x[2] = {S.x[0][p], S.x[1][p]};
     double u[3] = {S.u[0][p], S.u[1][p], S.u[2][p]};
     double xlast[2] = {0, 0}, xend[2] = {0, 0}, vend[3] = {0, 0, 0};
+    uint32_t hits = 0;  // axes mirrored at a wall, two bits per step
 #pragma unroll
     for (int k = 0; k < NS; k++) {
       xs[k][0] = x[0];
@@ -614,7 +634,8 @@ __global__ void __launch_bounds__(256) k_adjoint_tiled(GridDev g, AdjArgs aa, Ad
       double F[6], v[3];
       interp_t(g, t, f, x, F);
       boris_f(S.alpha, F, u, v);
-      double x1[2] = {x[0] + g.dt * v[0], x[1] + g.dt * v[1]};
+      double x1[3] = {x[0] + g.dt * v[0], x[1] + g.dt * v[1], 0.0};
+      if (g.reflect) hits |= (uint32_t)reflect_walls<2>(g, x1, u) << (2 * k);
       if (k == NS - 1) {
         xlast[0] = x[0];
         xlast[1] = x[1];
@@ -657,6 +678,7 @@ __global__ void __launch_bounds__(256) k_adjoint_tiled(GridDev g, AdjArgs aa, Ad
     }
 #pragma unroll
     for (int k = NS - 1; k >= 0; k--) {
+      unmirror(hits >> (2 * k), xb, ub);
       double F[6];
       interp_t(g, t, f, xs[k], F);
       double vb[3] = {g.dt * xb[0], g.dt * xb[1], 0.0};

@@ -188,6 +188,8 @@ GridDev make_grid(const pic_config *c) {
     g.d_over_dt[a] = d / c->dt;
   }
   g.dt = c->dt;
+  for (int a = 0; a < c->dim; a++)
+    if (c->reflect[a]) g.reflect |= 1 << a;
   return g;
 }
 
@@ -913,6 +915,12 @@ pic_status pic_validate_config(const pic_config *c, char *msg, size_t len) {
     set_msg(msg, len, "unknown flag bits 0x%x", c->flags);
     return PIC_ERR_ARG;
   }
+  for (int a = 0; a < c->dim; a++)
+    if (c->reflect[a] != 0 && c->reflect[a] != 1) {
+      set_msg(msg, len, "reflect[%d]=%d must be 0 (periodic) or 1 (reflecting walls)", a,
+              c->reflect[a]);
+      return PIC_ERR_ARG;
+    }
   if (c->bin_x < 0 || (c->bin_x > 0 && c->patch[0] % c->bin_x)) {
     set_msg(msg, len, "bin_x=%d must be 0 (auto) or divide patch[0]=%d", c->bin_x, c->patch[0]);
     return PIC_ERR_ARG;

@@ -28,7 +28,36 @@ struct GridDev {
   double L[3];    // n * d
   double dt;
   double d_over_dt[3];
+  int reflect;    // bit a set: reflecting particle walls at 0 and L on axis a
 };
+
+// pre-BC at reflecting walls: a pushed position x1 that left [0, L) on a
+// walled axis is mirrored back inside about the wall it crossed (x -> -x or
+// x -> 2L - x; both exact in floating point, as x and 2L lie within a factor
+// two of each other) and the momentum component along that axis changes
+// sign.  The one position that lands on L itself (x1 = L) goes to the
+// largest double below L.  Returns the mirrored axes as bits.
+template <int DIM>
+__device__ __forceinline__ int reflect_walls(const GridDev &g, double x1[3], double u[3]) {
+  int hit = 0;
+#pragma unroll
+  for (int a = 0; a < DIM; a++) {
+    if (!((g.reflect >> a) & 1)) continue;
+    double v = x1[a];
+    if (v < 0.0) {
+      v = -v;
+    } else if (v >= g.L[a]) {
+      v = 2.0 * g.L[a] - v;
+      if (v >= g.L[a]) v = nextafter(g.L[a], 0.0);
+    } else {
+      continue;
+    }
+    x1[a] = v;
+    u[a] = -u[a];
+    hit |= 1 << a;
+  }
+  return hit;
+}
 
 // One species as the kernels see it (device pointers).
 struct SpDev {

@@ -625,9 +625,11 @@ struct Blk {
 };
 
 // Interpolation, Push, Projection and pre-BC of one particle: advances x
-// (wrapped) and u in place and returns its neighbour code (CENTER when the
-// particle is rejected, with the error bit set).
-template <int DIM>
+// (wrapped, or mirrored at reflecting walls before the Projection) and u in
+// place and returns its neighbour code (CENTER when the particle is
+// rejected, with the error bit set).  WALLS = false compiles the walls out
+// (a kernel instance for periodic grids only).
+template <int DIM, bool WALLS>
 __device__ __forceinline__ int step_particle(const GridDev &g, const TileGeom &t, const double *tEB,
                                              double *tJ, double q, double alpha, double w,
                                              double x[3], double u[3], int &bad) {
@@ -645,10 +647,19 @@ __device__ __forceinline__ int step_particle(const GridDev &g, const TileGeom &t
   double x1[3];
   Win win[DIM];
   bool ok = true;
+  if constexpr (WALLS) {
 #pragma unroll
-  for (int a = 0; a < DIM; a++) {
-    x1[a] = x[a] + g.dt * v[a];
-    ok = ok && esk_win(sh.p[a], x1[a] * g.inv_d[a], sh.p[a].i + 1 + t.org[a], win[a]);
+    for (int a = 0; a < DIM; a++) x1[a] = x[a] + g.dt * v[a];
+    if (g.reflect) reflect_walls<DIM>(g, x1, u);
+#pragma unroll
+    for (int a = 0; a < DIM; a++)
+      ok = ok && esk_win(sh.p[a], x1[a] * g.inv_d[a], sh.p[a].i + 1 + t.org[a], win[a]);
+  } else {
+#pragma unroll
+    for (int a = 0; a < DIM; a++) {
+      x1[a] = x[a] + g.dt * v[a];
+      ok = ok && esk_win(sh.p[a], x1[a] * g.inv_d[a], sh.p[a].i + 1 + t.org[a], win[a]);
+    }
   }
   if (ok)
     deposit<DIM>(g, tJ, t.TJ, t.Jx, t.Jxy, q * w, win, v[2]);

@@ -52,7 +52,7 @@ namespace {
 // is issued unconditionally (prefetches past the wave's end reload its last
 // block), which keeps the memory-counter waits exact; only a partial last
 // block runs masked.
-template <int DIM, bool GATHER>
+template <int DIM, bool GATHER, bool WALLS>
 __device__ __forceinline__ void ipp_segments(const GridDev &g, const SpDev &S, const TileGeom &t,
                                              const double *tEB, double *tJ, int P, int k0, int k1,
                                              int &bad) {
@@ -89,7 +89,7 @@ __device__ __forceinline__ void ipp_segments(const GridDev &g, const SpDev &S, c
     u[0] = pc.u[0];
     u[1] = pc.u[1];
     u[2] = pc.u[2];
-    const int code = step_particle<DIM>(g, t, tEB, tJ, q, alpha, pc.w, x, u, bad);
+    const int code = step_particle<DIM, WALLS>(g, t, tEB, tJ, q, alpha, pc.w, x, u, bad);
 #pragma unroll
     for (int a = 0; a < DIM; a++) at(xo[a], i) = x[a];
     at(uo[0], i) = u[0];
@@ -121,7 +121,7 @@ __device__ __forceinline__ void ipp_segments(const GridDev &g, const SpDev &S, c
       u[0] = pc.u[0];
       u[1] = pc.u[1];
       u[2] = pc.u[2];
-      code = step_particle<DIM>(g, t, tEB, tJ, q, alpha, pc.w, x, u, bad);
+      code = step_particle<DIM, WALLS>(g, t, tEB, tJ, q, alpha, pc.w, x, u, bad);
 #pragma unroll
       for (int a = 0; a < DIM; a++) at(xo[a], i) = x[a];
       at(uo[0], i) = u[0];
@@ -139,7 +139,8 @@ __device__ __forceinline__ void ipp_segments(const GridDev &g, const SpDev &S, c
 }
 
 // Per-patch launch: one workgroup per (patch, species), all its segments.
-template <int DIM, bool GATHER>
+// WALLS: instance with reflecting walls (the periodic one compiles them out).
+template <int DIM, bool GATHER, bool WALLS>
 __global__ void __launch_bounds__(kMaxWg<DIM>, kMinWaves<DIM>) k_ipp(GridDev g, SpArgs sa, Fields f, int *err) {
   extern __shared__ __align__(16) double lds[];
   const int P = blockIdx.x;
@@ -151,7 +152,7 @@ __global__ void __launch_bounds__(kMaxWg<DIM>, kMinWaves<DIM>) k_ipp(GridDev g, 
   zero_tile<DIM>(tJ, 3 * t.TJ);
   __syncthreads();
   int bad = 0;
-  ipp_segments<DIM, GATHER>(g, S, t, tEB, tJ, P, 0, S.sstart[P + 1] - S.sstart[P], bad);
+  ipp_segments<DIM, GATHER, WALLS>(g, S, t, tEB, tJ, P, 0, S.sstart[P + 1] - S.sstart[P], bad);
   if (bad) atomicOr(err, bad);
   __syncthreads();
   flush_j<DIM>(g, t, tJ, f.j);
@@ -163,7 +164,7 @@ __global__ void __launch_bounds__(kMaxWg<DIM>, kMinWaves<DIM>) k_ipp(GridDev g, 
 // The E/B tile is restaged and the J tile flushed only when the patch changes
 // between a workgroup's consecutive units (E/B and J do not depend on the
 // species).
-template <int DIM, bool GATHER>
+template <int DIM, bool GATHER, bool WALLS>
 __global__ void __launch_bounds__(kMaxWg<DIM>, kMinWaves<DIM>) k_ipp_persistent(GridDev g, SpArgs sa, Fields f, int *err,
                                                         const Unit *units, int *qctl) {
   extern __shared__ __align__(16) double lds[];
@@ -194,7 +195,7 @@ __global__ void __launch_bounds__(kMaxWg<DIM>, kMinWaves<DIM>) k_ipp_persistent(
         __syncthreads();
         curP = un.P;
       }
-      ipp_segments<DIM, GATHER>(g, sa.s[s], t, tEB, tJ, un.P, un.k0, un.k1, bad);
+      ipp_segments<DIM, GATHER, WALLS>(g, sa.s[s], t, tEB, tJ, un.P, un.k0, un.k1, bad);
       __syncthreads();  // this unit's deposits are done before any flush
     }
   }
@@ -202,7 +203,9 @@ __global__ void __launch_bounds__(kMaxWg<DIM>, kMinWaves<DIM>) k_ipp_persistent(
   if (bad) atomicOr(err, bad);
 }
 
-// Split path, first half: Interpolation + Push; saves the start positions.
+// Split path, first half: Interpolation + Push (and the mirror at reflecting
+// walls, so that the Projection deposits along the mirrored move); saves the
+// start positions.
 template <int DIM>
 __global__ void __launch_bounds__(kMaxWg<DIM>) k_interp_push(GridDev g, SpArgs sa, Fields f, int *err) {
   extern __shared__ __align__(16) double lds[];
@@ -231,8 +234,12 @@ __global__ void __launch_bounds__(kMaxWg<DIM>) k_interp_push(GridDev g, SpArgs s
     const Shapes sh = shapes_at<DIM>(xi, t.org);
     interp6<DIM>(lds, t.TE, t.Tx, t.Txy, sh, F);
     boris(S.alpha, F, u, v);
+    double x1[3];
 #pragma unroll
-    for (int a = 0; a < DIM; a++) S.x[a][i] = x[a] + g.dt * v[a];
+    for (int a = 0; a < DIM; a++) x1[a] = x[a] + g.dt * v[a];
+    if (g.reflect) reflect_walls<DIM>(g, x1, u);
+#pragma unroll
+    for (int a = 0; a < DIM; a++) S.x[a][i] = x1[a];
     S.u[0][i] = u[0];
     S.u[1][i] = u[1];
     S.u[2][i] = u[2];
@@ -561,14 +568,14 @@ hipError_t launch_zero(double *const j[3], int64_t ncell, hipStream_t st) {
   return hipGetLastError();
 }
 
-template <int DIM, bool GATHER>
+template <int DIM, bool GATHER, bool WALLS>
 void launch_ipp_t(const GridDev &g, const SpArgs &sa, const Fields &f, int *err, int wg,
                   size_t lds, hipStream_t st) {
   if (DIM == 3)
-    (void)hipFuncSetAttribute((const void *)k_ipp<DIM, GATHER>,
+    (void)hipFuncSetAttribute((const void *)k_ipp<DIM, GATHER, WALLS>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  hipLaunchKernelGGL((k_ipp<DIM, GATHER>), dim3(g.npatch, sa.nsp), dim3(wg), lds, st, g, sa, f,
-                     err);
+  hipLaunchKernelGGL((k_ipp<DIM, GATHER, WALLS>), dim3(g.npatch, sa.nsp), dim3(wg), lds, st, g,
+                     sa, f, err);
 }
 
 hipError_t launch_ipp(const GridDev &g, const SpArgs &sa, const double *const e[3],
@@ -576,12 +583,17 @@ hipError_t launch_ipp(const GridDev &g, const SpArgs &sa, const double *const e[
                       hipStream_t st) {
   const Fields f = mkfields(e, b, j);
   const size_t lds = lds_bytes_ipp(g);
-  if (g.dim == 2)
-    sa.gather ? launch_ipp_t<2, true>(g, sa, f, err, wg, lds, st)
-              : launch_ipp_t<2, false>(g, sa, f, err, wg, lds, st);
-  else
-    sa.gather ? launch_ipp_t<3, true>(g, sa, f, err, wg, lds, st)
-              : launch_ipp_t<3, false>(g, sa, f, err, wg, lds, st);
+  const int v = (g.dim == 3 ? 4 : 0) + (sa.gather ? 2 : 0) + (g.reflect ? 1 : 0);
+  switch (v) {
+    case 0: launch_ipp_t<2, false, false>(g, sa, f, err, wg, lds, st); break;
+    case 1: launch_ipp_t<2, false, true>(g, sa, f, err, wg, lds, st); break;
+    case 2: launch_ipp_t<2, true, false>(g, sa, f, err, wg, lds, st); break;
+    case 3: launch_ipp_t<2, true, true>(g, sa, f, err, wg, lds, st); break;
+    case 4: launch_ipp_t<3, false, false>(g, sa, f, err, wg, lds, st); break;
+    case 5: launch_ipp_t<3, false, true>(g, sa, f, err, wg, lds, st); break;
+    case 6: launch_ipp_t<3, true, false>(g, sa, f, err, wg, lds, st); break;
+    default: launch_ipp_t<3, true, true>(g, sa, f, err, wg, lds, st); break;
+  }
   return hipGetLastError();
 }
 
@@ -650,22 +662,29 @@ hipError_t launch_layout(const GridDev &g, const SpArgs &sa, Unit *units, int *q
   return hipGetLastError();
 }
 
-template <int DIM, bool GATHER>
+template <int DIM, bool GATHER, bool WALLS>
 int blocks_per_cu(int wg, size_t lds) {
   if (DIM == 3)
-    (void)hipFuncSetAttribute((const void *)k_ipp_persistent<DIM, GATHER>,
+    (void)hipFuncSetAttribute((const void *)k_ipp_persistent<DIM, GATHER, WALLS>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   int n = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_ipp_persistent<DIM, GATHER>, wg, lds) !=
-      hipSuccess)
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_ipp_persistent<DIM, GATHER, WALLS>, wg,
+                                                   lds) != hipSuccess)
     return 1;
   return n;
 }
 
+template <int DIM, bool WALLS>
+int blocks_per_cu_both(int wg, size_t lds) {
+  return std::min(blocks_per_cu<DIM, true, WALLS>(wg, lds), blocks_per_cu<DIM, false, WALLS>(wg, lds));
+}
+
 int persistent_grid(const GridDev &g, int wg) {
   const size_t lds = lds_bytes_ipp(g);
-  int per_cu = g.dim == 2 ? std::min(blocks_per_cu<2, true>(wg, lds), blocks_per_cu<2, false>(wg, lds))
-                          : std::min(blocks_per_cu<3, true>(wg, lds), blocks_per_cu<3, false>(wg, lds));
+  int per_cu = g.dim == 2 ? (g.reflect ? blocks_per_cu_both<2, true>(wg, lds)
+                                       : blocks_per_cu_both<2, false>(wg, lds))
+                          : (g.reflect ? blocks_per_cu_both<3, true>(wg, lds)
+                                       : blocks_per_cu_both<3, false>(wg, lds));
   int dev = 0, ncu = 0;
   if (per_cu < 1) per_cu = 1;
   if (hipGetDevice(&dev) != hipSuccess ||
@@ -675,14 +694,14 @@ int persistent_grid(const GridDev &g, int wg) {
   return per_cu * ncu;
 }
 
-template <int DIM, bool GATHER>
+template <int DIM, bool GATHER, bool WALLS>
 void launch_pers_t(const GridDev &g, const SpArgs &sa, const Fields &f, int *err,
                    const Unit *units, int *qctl, int grid, int wg, size_t lds, hipStream_t st) {
   if (DIM == 3)
-    (void)hipFuncSetAttribute((const void *)k_ipp_persistent<DIM, GATHER>,
+    (void)hipFuncSetAttribute((const void *)k_ipp_persistent<DIM, GATHER, WALLS>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  hipLaunchKernelGGL((k_ipp_persistent<DIM, GATHER>), dim3(grid), dim3(wg), lds, st, g, sa, f,
-                     err, units, qctl);
+  hipLaunchKernelGGL((k_ipp_persistent<DIM, GATHER, WALLS>), dim3(grid), dim3(wg), lds, st, g, sa,
+                     f, err, units, qctl);
 }
 
 hipError_t launch_ipp_persistent(const GridDev &g, const SpArgs &sa, const double *const e[3],
@@ -690,12 +709,17 @@ hipError_t launch_ipp_persistent(const GridDev &g, const SpArgs &sa, const doubl
                                  const Unit *units, int *qctl, int grid, int wg, hipStream_t st) {
   const Fields f = mkfields(e, b, j);
   const size_t lds = lds_bytes_ipp(g);
-  if (g.dim == 2)
-    sa.gather ? launch_pers_t<2, true>(g, sa, f, err, units, qctl, grid, wg, lds, st)
-              : launch_pers_t<2, false>(g, sa, f, err, units, qctl, grid, wg, lds, st);
-  else
-    sa.gather ? launch_pers_t<3, true>(g, sa, f, err, units, qctl, grid, wg, lds, st)
-              : launch_pers_t<3, false>(g, sa, f, err, units, qctl, grid, wg, lds, st);
+  const int v = (g.dim == 3 ? 4 : 0) + (sa.gather ? 2 : 0) + (g.reflect ? 1 : 0);
+  switch (v) {
+    case 0: launch_pers_t<2, false, false>(g, sa, f, err, units, qctl, grid, wg, lds, st); break;
+    case 1: launch_pers_t<2, false, true>(g, sa, f, err, units, qctl, grid, wg, lds, st); break;
+    case 2: launch_pers_t<2, true, false>(g, sa, f, err, units, qctl, grid, wg, lds, st); break;
+    case 3: launch_pers_t<2, true, true>(g, sa, f, err, units, qctl, grid, wg, lds, st); break;
+    case 4: launch_pers_t<3, false, false>(g, sa, f, err, units, qctl, grid, wg, lds, st); break;
+    case 5: launch_pers_t<3, false, true>(g, sa, f, err, units, qctl, grid, wg, lds, st); break;
+    case 6: launch_pers_t<3, true, false>(g, sa, f, err, units, qctl, grid, wg, lds, st); break;
+    default: launch_pers_t<3, true, true>(g, sa, f, err, units, qctl, grid, wg, lds, st); break;
+  }
   return hipGetLastError();
 }
 

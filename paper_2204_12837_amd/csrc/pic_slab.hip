@@ -128,7 +128,7 @@ __global__ void __launch_bounds__(256) k_slab_in(GridDev g, SlabArgs sa) {
 // of a full block is unconditional (a prefetch past the range reloads its
 // last particle), so the memory-counter waits stay exact.  The neighbour code
 // of each particle goes to code[].
-template <int DIM>
+template <int DIM, bool WALLS>
 __device__ __forceinline__ void ipp_slab(const GridDev &g, const SlabDev &S, const TileGeom &t,
                                          const double *tEB, double *tJ, int P, uint32_t r0,
                                          uint32_t r1, int &bad, uint32_t *bits) {
@@ -167,7 +167,7 @@ __device__ __forceinline__ void ipp_slab(const GridDev &g, const SlabDev &S, con
     u[0] = pc.u[0];
     u[1] = pc.u[1];
     u[2] = pc.u[2];
-    const int code = step_particle<DIM>(g, t, tEB, tJ, q, alpha, pc.w, x, u, bad);
+    const int code = step_particle<DIM, WALLS>(g, t, tEB, tJ, q, alpha, pc.w, x, u, bad);
 #pragma unroll
     for (int a = 0; a < DIM; a++) at(S.xs[a], i) = x[a];
     at(S.us[0], i) = u[0];
@@ -190,7 +190,7 @@ __device__ __forceinline__ void ipp_slab(const GridDev &g, const SlabDev &S, con
       u[0] = pc.u[0];
       u[1] = pc.u[1];
       u[2] = pc.u[2];
-      const int code = step_particle<DIM>(g, t, tEB, tJ, q, alpha, pc.w, x, u, bad);
+      const int code = step_particle<DIM, WALLS>(g, t, tEB, tJ, q, alpha, pc.w, x, u, bad);
 #pragma unroll
       for (int a = 0; a < DIM; a++) at(S.xs[a], i) = x[a];
       at(S.us[0], i) = u[0];
@@ -305,8 +305,9 @@ __device__ void depart_in_kernel(const GridDev &g, const SlabDev &S, int P, int 
 template <int DIM>
 constexpr int kSlabMinWaves = DIM == 2 ? 4 : 2;
 
-// Per-patch launch: one workgroup per (patch, species).
-template <int DIM>
+// Per-patch launch: one workgroup per (patch, species).  WALLS: instance
+// with reflecting walls (the periodic one compiles them out).
+template <int DIM, bool WALLS>
 __global__ void __launch_bounds__(kMaxWgSlab<DIM>, kSlabMinWaves<DIM>) k_ipp_slab(GridDev g, SlabArgs sa, Fields f, int *err) {
   extern __shared__ __align__(16) double lds[];
   __shared__ uint32_t bits[kBitWords];
@@ -325,7 +326,7 @@ __global__ void __launch_bounds__(kMaxWgSlab<DIM>, kSlabMinWaves<DIM>) k_ipp_sla
   for (int k = threadIdx.x; k < kBitWords; k += blockDim.x) bits[k] = 0u;
   __syncthreads();
   int bad = 0;
-  ipp_slab<DIM>(g, S, t, tEB, tJ, P, 0u, (uint32_t)c, bad, mark ? bits : nullptr);
+  ipp_slab<DIM, WALLS>(g, S, t, tEB, tJ, P, 0u, (uint32_t)c, bad, mark ? bits : nullptr);
   if (bad) atomicOr(err, bad);
   __syncthreads();
   flush_j<DIM>(g, t, tJ, f.j);
@@ -338,7 +339,7 @@ __global__ void __launch_bounds__(kMaxWgSlab<DIM>, kSlabMinWaves<DIM>) k_ipp_sla
 // Persistent launch: workgroups pop (patch, particle range) units of each
 // species in turn (ticket qctl[2s], count qctl[2s+1], list at units +
 // ubase); E/B is restaged and J flushed only when the patch changes.
-template <int DIM>
+template <int DIM, bool WALLS>
 __global__ void __launch_bounds__(kMaxWgSlab<DIM>, kSlabMinWaves<DIM>) k_ipp_slab_persistent(GridDev g, SlabArgs sa, Fields f, int *err,
                                                                     const Unit *units, int *qctl) {
   extern __shared__ __align__(16) double lds[];
@@ -371,7 +372,7 @@ __global__ void __launch_bounds__(kMaxWgSlab<DIM>, kSlabMinWaves<DIM>) k_ipp_sla
         __syncthreads();
         curP = un.P;
       }
-      ipp_slab<DIM>(g, S, t, tEB, tJ, un.P, (uint32_t)un.k0, (uint32_t)un.k1, bad, nullptr);
+      ipp_slab<DIM, WALLS>(g, S, t, tEB, tJ, un.P, (uint32_t)un.k0, (uint32_t)un.k1, bad, nullptr);
       __syncthreads();  // this unit's deposits are done before any flush
     }
   }
@@ -792,19 +793,38 @@ hipError_t launch_slab_begin(const GridDev &g, const SlabArgs &sa, int *err, hip
   return hipGetLastError();
 }
 
+template <int DIM, bool WALLS>
+void ipp_slab_t(const GridDev &g, const SlabArgs &sa, const Fields &f, int *err, int wg, size_t lds,
+                hipStream_t st) {
+  if (DIM == 3)
+    (void)hipFuncSetAttribute((const void *)k_ipp_slab<DIM, WALLS>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  hipLaunchKernelGGL((k_ipp_slab<DIM, WALLS>), dim3(g.npatch, sa.nsp), dim3(wg), lds, st, g, sa, f,
+                     err);
+}
+
 hipError_t launch_ipp_slab(const GridDev &g, const SlabArgs &sa, const double *const e[3],
                            const double *const b[3], double *const j[3], int *err, int wg,
                            hipStream_t st) {
   const Fields f = mkfields(e, b, j);
   const size_t lds = lds_bytes_ipp(g);
-  if (g.dim == 2) {
-    hipLaunchKernelGGL(k_ipp_slab<2>, dim3(g.npatch, sa.nsp), dim3(wg), lds, st, g, sa, f, err);
-  } else {
-    (void)hipFuncSetAttribute((const void *)k_ipp_slab<3>,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL(k_ipp_slab<3>, dim3(g.npatch, sa.nsp), dim3(wg), lds, st, g, sa, f, err);
-  }
+  if (g.dim == 2)
+    g.reflect ? ipp_slab_t<2, true>(g, sa, f, err, wg, lds, st)
+              : ipp_slab_t<2, false>(g, sa, f, err, wg, lds, st);
+  else
+    g.reflect ? ipp_slab_t<3, true>(g, sa, f, err, wg, lds, st)
+              : ipp_slab_t<3, false>(g, sa, f, err, wg, lds, st);
   return hipGetLastError();
+}
+
+template <int DIM, bool WALLS>
+void ipp_slab_pers_t(const GridDev &g, const SlabArgs &sa, const Fields &f, int *err,
+                     const Unit *units, int *qctl, int grid, int wg, size_t lds, hipStream_t st) {
+  if (DIM == 3)
+    (void)hipFuncSetAttribute((const void *)k_ipp_slab_persistent<DIM, WALLS>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  hipLaunchKernelGGL((k_ipp_slab_persistent<DIM, WALLS>), dim3(grid), dim3(wg), lds, st, g, sa, f,
+                     err, units, qctl);
 }
 
 hipError_t launch_ipp_slab_persistent(const GridDev &g, const SlabArgs &sa,
@@ -813,30 +833,34 @@ hipError_t launch_ipp_slab_persistent(const GridDev &g, const SlabArgs &sa,
                                       int grid, int wg, hipStream_t st) {
   const Fields f = mkfields(e, b, j);
   const size_t lds = lds_bytes_ipp(g);
-  if (g.dim == 2) {
-    hipLaunchKernelGGL(k_ipp_slab_persistent<2>, dim3(grid), dim3(wg), lds, st, g, sa, f, err,
-                       units, qctl);
-  } else {
-    (void)hipFuncSetAttribute((const void *)k_ipp_slab_persistent<3>,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL(k_ipp_slab_persistent<3>, dim3(grid), dim3(wg), lds, st, g, sa, f, err,
-                       units, qctl);
-  }
+  if (g.dim == 2)
+    g.reflect ? ipp_slab_pers_t<2, true>(g, sa, f, err, units, qctl, grid, wg, lds, st)
+              : ipp_slab_pers_t<2, false>(g, sa, f, err, units, qctl, grid, wg, lds, st);
+  else
+    g.reflect ? ipp_slab_pers_t<3, true>(g, sa, f, err, units, qctl, grid, wg, lds, st)
+              : ipp_slab_pers_t<3, false>(g, sa, f, err, units, qctl, grid, wg, lds, st);
   return hipGetLastError();
+}
+
+template <int DIM, bool WALLS>
+int slab_blocks_t(int wg, size_t lds) {
+  if (DIM == 3)
+    (void)hipFuncSetAttribute((const void *)k_ipp_slab_persistent<DIM, WALLS>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  int n = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_ipp_slab_persistent<DIM, WALLS>, wg,
+                                                   lds) != hipSuccess)
+    return 0;
+  return n;
 }
 
 int slab_persistent_blocks_per_cu(const GridDev &g, int wg) {
   const size_t lds = lds_bytes_ipp(g);
-  int n = 0;
-  hipError_t e;
-  if (g.dim == 2) {
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_ipp_slab_persistent<2>, wg, lds);
-  } else {
-    (void)hipFuncSetAttribute((const void *)k_ipp_slab_persistent<3>,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_ipp_slab_persistent<3>, wg, lds);
-  }
-  return e == hipSuccess && n > 0 ? n : 1;
+  const int n = g.dim == 2 ? (g.reflect ? slab_blocks_t<2, true>(wg, lds)
+                                        : slab_blocks_t<2, false>(wg, lds))
+                           : (g.reflect ? slab_blocks_t<3, true>(wg, lds)
+                                        : slab_blocks_t<3, false>(wg, lds));
+  return n > 0 ? n : 1;
 }
 
 hipError_t launch_exchange(const GridDev &g, const SlabArgs &sa, int *err, Unit *units, int *qctl,

@@ -1,5 +1,6 @@
 // General sort of particles by patch, for input in any order (e.g. freshly
-// loaded particles): periodic wrap, patch key, stable radix sort of
+// loaded particles): periodic wrap (a position outside the box on an axis
+// with reflecting walls is an error), patch key, stable radix sort of
 // (key, index) pairs, gather into the second buffer set, patch offsets.
 // The per-step sort after a push uses the neighbour-code counting sort in
 // pic_kernels.hip instead; both give the same stable order.
@@ -20,8 +21,10 @@ __global__ void k_keys(GridDev g, SpDev s, int32_t *keys, int64_t *idx, int *err
     int key = 0, mul = 1;
     for (int a = 0; a < g.dim; a++) {
       double v = s.x[a][i];
-      if (v < 0.0) v += g.L[a];
-      if (v >= g.L[a]) v -= g.L[a];
+      if (!((g.reflect >> a) & 1)) {  // a walled axis is not wrapped
+        if (v < 0.0) v += g.L[a];
+        if (v >= g.L[a]) v -= g.L[a];
+      }
       if (!(v >= 0.0 && v < g.L[a])) {
         bad |= kErrPos;
         v = 0.0;

@@ -36,7 +36,7 @@ class ConfigC(C.Structure):
     _fields_ = [("dim", C.c_int32), ("n", C.c_int32 * 3), ("d", C.c_double * 3), ("dt", C.c_double),
                 ("patch", C.c_int32 * 3), ("shape_order", C.c_int32), ("mode", C.c_int32),
                 ("chunk", C.c_int32), ("wg_size", C.c_int32), ("flags", C.c_uint32),
-                ("bin_x", C.c_int32)]
+                ("bin_x", C.c_int32), ("reflect", C.c_int32 * 3)]
 
 
 class SpeciesC(C.Structure):
@@ -122,8 +122,9 @@ def lib():
 
 
 def make_config(wl, mode=MODE_PER_PATCH, chunk=0, wg_size=0, flags=0, bin_x=0) -> ConfigC:
-    """Config struct from a workload description (dim, n, d, dt, patch);
-    bin_x = 0 lets the library choose the x-bin width."""
+    """Config struct from a workload description (dim, n, d, dt, patch and,
+    if it has one, reflect: per-axis reflecting particle walls); bin_x = 0
+    lets the library choose the x-bin width."""
     c = ConfigC()
     c.dim = wl.dim
     for a in range(3):
@@ -134,6 +135,9 @@ def make_config(wl, mode=MODE_PER_PATCH, chunk=0, wg_size=0, flags=0, bin_x=0) -
     c.shape_order = 2
     c.mode, c.chunk, c.wg_size, c.flags = mode, chunk, wg_size, flags
     c.bin_x = bin_x
+    walls = getattr(wl, "reflect", (0, 0, 0))
+    for a in range(wl.dim):
+        c.reflect[a] = int(walls[a])
     return c
 
 
