@@ -19,6 +19,7 @@ bounded sample on the host.
 from __future__ import annotations
 
 import argparse
+import dataclasses
 import hashlib
 import json
 import os
@@ -479,6 +480,18 @@ def main(argv=None) -> int:
             "ipp_speedup_persistent_vs_per_patch": ipp_pp / ipp_pe,
             "step_ratio_persistent_vs_uniform": (sp_ / ni) / (secs / n),
             "step_speedup_persistent_vs_per_patch": si / sp_,
+        }
+        # the same workload with reflecting particle walls along x (the paper's
+        # radiation-pressure case: reflective in x, periodic in y), persistent
+        wlw = dataclasses.replace(wli, reflect=(1, 0, 0))
+        _, sw, tw = run_gpu(wlw, args.steps, args.warmup, mode=1, chunk=tuned["chunk"],
+                            wg=tuned["wg"], inp=inpi, bin_x=tuned.get("bin_x", 0))
+        ipp_w = tw["ipp"][0] / tw["ipp"][1]
+        out["imbalanced"]["x_walls_persistent"] = {
+            "ns_per_particle_step": sw / (ni * args.steps) * 1e9, "kernel_ms": per_k(tw),
+            "ipp_ns_per_particle": ipp_w / ni * 1e6,
+            "ipp_ratio_vs_periodic": ipp_w / ipp_pe,
+            "step_ratio_vs_periodic": sw / sp_,
         }
     if not args.no_3d:
         out["expansion3d"] = run_expansion3d(min(args.steps, 50), args.warmup)

@@ -91,7 +91,8 @@ def _run(name, steps, mode, chunk, wg, windows, **over):
     wl = I.workload(name, **over)
     inp = I.generate(wl)
     n = sum(s.id.size for s in inp.species)
-    say(f"case {name} full size ({n} particles), {steps} steps, mode={mode} chunk={chunk} wg={wg}")
+    say(f"case {name} {over} full size ({n} particles), {steps} steps, mode={mode} chunk={chunk} "
+        f"wg={wg}")
     sp, J = _gpu_run(wl, inp, steps, mode, chunk, wg)
     Jg = J.cpu().numpy()
     for a0, npw in windows:
@@ -126,3 +127,11 @@ def test_uniform1024_large_patches():
     one window across the periodic corner."""
     _run("uniform1024", 10, 0, 0, 0, [((-64, -128), (1, 1)), ((448, 384), (2, 1))],
          patch=(64, 128, 1))
+
+
+def test_imbalanced_with_x_walls_persistent():
+    """The imbalanced workload with reflecting particle walls along x,
+    persistent launch: a window on the right wall (the background plasma
+    reaches it) and one on the bump."""
+    _run("imbalanced", 8, 1, 2048, 256, [((2016, 200), (2, 3)), ((1520, 96), (2, 2))],
+         reflect=(1, 0, 0))
