@@ -20,7 +20,7 @@ _I64P = C.POINTER(C.c_int64)
 
 class Grid(C.Structure):
     _fields_ = [("dim", C.c_int32), ("n", C.c_int32 * 3), ("d", C.c_double * 3),
-                ("dt", C.c_double), ("patch", C.c_int32 * 3), ("reflect", C.c_int32 * 3)]
+                ("dt", C.c_double), ("patch", C.c_int32 * 3), ("bc", C.c_int32 * 3)]
 
 
 class Species(C.Structure):
@@ -95,7 +95,7 @@ def grid(wl) -> Grid:
         g.n[a] = int(wl.n[a]) if a < wl.dim else 1
         g.d[a] = float(wl.d[a])
         g.patch[a] = int(wl.patch[a]) if a < wl.dim else 1
-        g.reflect[a] = int(getattr(wl, "reflect", (0, 0, 0))[a]) if a < wl.dim else 0
+        g.bc[a] = int(getattr(wl, "particle_bc", (0, 0, 0))[a]) if a < wl.dim else 0
     g.dt = float(wl.dt)
     return g
 
@@ -170,6 +170,16 @@ class OSpecies:
         s.off = self.off.ctypes.data_as(_I64P)
         return s
 
+    def follow(self, s: Species):
+        """Keep the first s.n particles (the oracle deletes particles at
+        removing walls, compacting the survivors to the front)."""
+        n = int(s.n)
+        if n != self.n:
+            self.x = self.x[:, :n].copy()
+            self.u = self.u[:, :n].copy()
+            self.w = self.w[:n].copy()
+            self.id = self.id[:n].copy()
+
 
 def species_from(inputs) -> List[OSpecies]:
     npch = inputs.wl.n_patches
@@ -178,7 +188,9 @@ def species_from(inputs) -> List[OSpecies]:
 
 def bin(wl, sp: OSpecies):
     s = sp.cstruct()
-    _check(_lib().orc_bin(C.byref(grid(wl)), C.byref(s)))
+    rc = _lib().orc_bin(C.byref(grid(wl)), C.byref(s))
+    sp.follow(s)
+    _check(rc)
 
 
 def step(wl, sps: List[OSpecies], E, B, with_abs=False):
@@ -196,7 +208,10 @@ def step(wl, sps: List[OSpecies], E, B, with_abs=False):
     if with_abs:
         keep = _arr3(A.reshape(3, -1))
         Ap = C.cast(C.pointer(keep), C.c_void_p)
-    _check(_lib().orc_step(C.byref(grid(wl)), arr, len(sps), _arr3(Ef), _arr3(Bf), _arr3(Jf), Ap))
+    rc = _lib().orc_step(C.byref(grid(wl)), arr, len(sps), _arr3(Ef), _arr3(Bf), _arr3(Jf), Ap)
+    for sp, cs in zip(sps, arr):
+        sp.follow(cs)
+    _check(rc)
     return (J, A) if with_abs else J
 
 

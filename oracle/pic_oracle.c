@@ -11,10 +11,13 @@
  *     Projection (paper, section "Parallelization without tasks",
  *     Algorithm 1), with the boundary conditions themselves and the particle
  *     sort done afterwards in the synchronisation phase (same section);
- *   - periodic or reflecting particle boundaries per axis (the paper's
- *     radiation-pressure case reflects particles at its x borders, section
- *     "Basic performance benchmarks"); the pre-BC operation mirrors a particle that
- *     crossed a wall before its current is projected;
+ *   - periodic, reflecting or removing particle boundaries per axis (the
+ *     paper's radiation-pressure case reflects particles at its x borders,
+ *     section "Basic performance benchmarks"; the pre-BC operation flags
+ *     particles to delete, section "Parallelization without tasks"); the
+ *     pre-BC operation mirrors a particle that crossed a reflecting wall
+ *     before its current is projected, and a particle that crossed a
+ *     removing wall deposits nothing and is deleted at the sort;
  *   - order-2 interpolation / projection shapes on a three-point stencil
  *     (paper, section "Basic performance benchmarks" and the plasma-expansion
  *     set-up);
@@ -47,7 +50,7 @@ typedef struct {
   int dim;
   int64_t n[3], patch[3], np[3], npatch, ncell;
   real d[3], inv_d[3], L[3], dt;
-  int reflect[3];
+  int bc[3];
 } G;
 
 static void mk_grid(const orc_grid *g, G *G_) {
@@ -64,7 +67,7 @@ static void mk_grid(const orc_grid *g, G *G_) {
     G_->d[a] = (real)g->d[a];
     G_->inv_d[a] = (real)1 / (real)g->d[a];
     G_->L[a] = (real)G_->n[a] * (real)g->d[a];
-    G_->reflect[a] = a < g->dim && g->reflect[a] != 0;
+    G_->bc[a] = a < g->dim ? g->bc[a] : ORC_BC_PERIODIC;
   }
   G_->dt = (real)g->dt;
 }
@@ -369,21 +372,32 @@ static int deposit(const G *g, real q, real w, const real x0[3], const real x1[3
 }
 
 /* ---------------------------------------------------------------------- */
-/* pre-boundary-condition operation on an axis with reflecting walls at 0 and
- * L: a pushed position that left [0, L) is mirrored back inside about the
- * wall it crossed (x -> -x, or x -> 2L - x) and its momentum component along
- * the axis changes sign.  Both mirror images are exact in floating point
- * (Sterbenz's lemma: x and 2L lie within a factor two of each other); the one
- * position that lands on L itself, x = L, is moved to the largest value below
- * L so that it stays in the last cell.  The paper flags such particles in the
+/* pre-boundary-condition operation at walls.  A pushed position outside
+ * [0, L) on an axis with removing walls marks the particle for deletion: it
+ * deposits no current in this step (its weight is spent) and the sort of
+ * the synchronisation phase drops it; the function then returns -1 and
+ * changes nothing.  Otherwise, on an axis with reflecting walls, a position
+ * that left [0, L) is mirrored back inside about the wall it crossed
+ * (x -> -x, or x -> 2L - x) and its momentum component along the axis
+ * changes sign.  Both mirror images are exact in floating point (Sterbenz's
+ * lemma: x and 2L lie within a factor two of each other); the one position
+ * that lands on L itself, x = L, is moved to the largest value below L so
+ * that it stays in the last cell.  The paper flags such particles in the
  * pre-BC operation, which writes positions and momenta (section
  * "Parallelization with OpenMP task"); here the mirror is applied there too,
  * before the Projection, so the current is deposited along the mirrored move
- * (reading in the design notes).  Returns the mirrored axes as bits. */
-static int reflect_walls(const G *g, real x1[3], real u[3]) {
+ * (readings in the design notes).  Returns the mirrored axes as bits. */
+static int outside_removing(const G *g, const real x[3]) {
+  for (int a = 0; a < g->dim; a++)
+    if (g->bc[a] == ORC_BC_REMOVE && !(x[a] >= 0 && x[a] < g->L[a])) return 1;
+  return 0;
+}
+
+static int walls(const G *g, real x1[3], real u[3]) {
+  if (outside_removing(g, x1)) return -1;
   int hit = 0;
   for (int a = 0; a < g->dim; a++) {
-    if (!g->reflect[a]) continue;
+    if (g->bc[a] != ORC_BC_REFLECT) continue;
     if (x1[a] < 0) {
       x1[a] = -x1[a];
     } else if (x1[a] >= g->L[a]) {
@@ -403,14 +417,14 @@ static int reflect_walls(const G *g, real x1[3], real u[3]) {
  *   if (x < 0) x += L;  if (x >= L) x -= L;   (the second test also catches
  *   x + L rounding to L), cell c = floor(x * inv_d) clamped to n-1,
  *   patch P_a = c_a / patch_a, key = Px + NPx (Py + NPy Pz).
- * A reflecting axis is not wrapped (its positions were mirrored inside).
+ * An axis with walls is not wrapped (its positions were mirrored inside).
  * Returns -1 if the position is more than one period outside the box, or
- * outside [0, L) on a reflecting axis. */
+ * outside [0, L) on an axis with walls. */
 static int64_t patch_key(const G *g, const real x1[3], real xw[3]) {
   int64_t P[3] = {0, 0, 0};
   for (int a = 0; a < g->dim; a++) {
     real v = x1[a];
-    if (!g->reflect[a]) {
+    if (g->bc[a] == ORC_BC_PERIODIC) {
       if (v < 0) v += g->L[a];
       if (v >= g->L[a]) v -= g->L[a];
     }
@@ -423,33 +437,44 @@ static int64_t patch_key(const G *g, const real x1[3], real xw[3]) {
   return P[0] + g->np[0] * (P[1] + g->np[1] * P[2]);
 }
 
-/* Stable counting sort of one species by key (keys in [0, npatch)). */
+/* key of a particle deleted at a removing wall */
+#define REMOVED (-2)
+
+/* Stable counting sort of one species by key (keys in [0, npatch), or
+ * REMOVED: the particle is dropped and s->n shrinks). */
 static void sort_by_key(const G *g, orc_species *s, const int64_t *key) {
   const int64_t n = s->n, np = g->npatch;
   int64_t *cnt = calloc((size_t)np + 1, sizeof(int64_t));
-  for (int64_t p = 0; p < n; p++) cnt[key[p] + 1]++;
+  for (int64_t p = 0; p < n; p++)
+    if (key[p] != REMOVED) cnt[key[p] + 1]++;
   for (int64_t P = 0; P < np; P++) cnt[P + 1] += cnt[P];
   for (int64_t P = 0; P <= np; P++) s->off[P] = cnt[P];
+  const int64_t kept = cnt[np];
   int64_t *dest = malloc((size_t)(n ? n : 1) * sizeof(int64_t));
-  for (int64_t p = 0; p < n; p++) dest[p] = cnt[key[p]]++;
+  for (int64_t p = 0; p < n; p++) dest[p] = key[p] == REMOVED ? -1 : cnt[key[p]]++;
   double *tmp = malloc((size_t)(n ? n : 1) * sizeof(double));
   int64_t *itmp = malloc((size_t)(n ? n : 1) * sizeof(int64_t));
   double *arrs[7] = {s->x[0], s->x[1], g->dim == 3 ? s->x[2] : NULL, s->u[0], s->u[1], s->u[2],
                      s->w};
   for (int k = 0; k < 7; k++) {
     if (!arrs[k]) continue;
-    for (int64_t p = 0; p < n; p++) tmp[dest[p]] = arrs[k][p];
-    memcpy(arrs[k], tmp, (size_t)n * sizeof(double));
+    for (int64_t p = 0; p < n; p++)
+      if (dest[p] >= 0) tmp[dest[p]] = arrs[k][p];
+    memcpy(arrs[k], tmp, (size_t)kept * sizeof(double));
   }
-  for (int64_t p = 0; p < n; p++) itmp[dest[p]] = s->id[p];
-  memcpy(s->id, itmp, (size_t)n * sizeof(int64_t));
+  for (int64_t p = 0; p < n; p++)
+    if (dest[p] >= 0) itmp[dest[p]] = s->id[p];
+  memcpy(s->id, itmp, (size_t)kept * sizeof(int64_t));
+  s->n = kept;
   free(cnt);
   free(dest);
   free(tmp);
   free(itmp);
 }
 
-/* Boundary condition (periodic wrap) and sort: the synchronisation phase. */
+/* Boundary conditions (periodic wrap, deletion outside a removing axis) and
+ * sort: the synchronisation phase.  A position outside a reflecting axis is
+ * an error here: only the pre-BC operation mirrors (pushed positions). */
 int orc_bin(const orc_grid *gi, orc_species *s) {
   G g;
   mk_grid(gi, &g);
@@ -457,6 +482,10 @@ int orc_bin(const orc_grid *gi, orc_species *s) {
   for (int64_t p = 0; p < s->n; p++) {
     real x[3] = {0, 0, 0}, xw[3] = {0, 0, 0};
     for (int a = 0; a < g.dim; a++) x[a] = s->x[a][p];
+    if (outside_removing(&g, x)) {  /* deleted */
+      key[p] = REMOVED;
+      continue;
+    }
     key[p] = patch_key(&g, x, xw);
     if (key[p] < 0) {
       free(key);
@@ -523,13 +552,19 @@ int orc_step(const orc_grid *gi, orc_species *sp, int32_t nsp, const double *con
         for (int c = 0; c < 3; c++) S->u[c][p] = (double)u[c];
         for (int a = 0; a < dim; a++) S->x[a][p] = (double)(x0[p - b][a] + g.dt * vel[p - b][a]);
       }
-      /* pre-BC: mirror at reflecting walls, flag the destination patch (the
-       * periodic wrap itself is applied in the synchronisation phase below) */
+      /* pre-BC: flag particles leaving through a removing wall, mirror at
+       * reflecting walls, flag the destination patch (the periodic wrap
+       * itself is applied in the synchronisation phase below) */
       for (int64_t p = b; p < e; p++) {
         real x1[3] = {0, 0, 0}, xw[3];
         for (int a = 0; a < dim; a++) x1[a] = S->x[a][p];
         real u[3] = {S->u[0][p], S->u[1][p], S->u[2][p]};
-        if (reflect_walls(&g, x1, u)) {
+        const int hit = walls(&g, x1, u);
+        if (hit < 0) {
+          keys[s][p] = REMOVED;
+          continue;
+        }
+        if (hit) {
           for (int a = 0; a < dim; a++) S->x[a][p] = (double)x1[a];
           for (int c = 0; c < 3; c++) S->u[c][p] = (double)u[c];
         }
@@ -538,16 +573,19 @@ int orc_step(const orc_grid *gi, orc_species *sp, int32_t nsp, const double *con
       }
       /* Projection */
       for (int64_t p = b; p < e && !err; p++) {
+        if (keys[s][p] == REMOVED) continue;
         real x1[3] = {0, 0, 0};
         for (int a = 0; a < dim; a++) x1[a] = S->x[a][p];
         err = deposit(&g, q, (real)S->w[p], x0[p - b], x1, vel[p - b][2], Jr, A ? Ar : NULL);
       }
     }
   }
-  /* synchronisation: boundary conditions, then the sort by patch */
+  /* synchronisation: boundary conditions (periodic wrap; the sort drops the
+   * particles flagged for deletion), then the sort by patch */
   for (int s = 0; s < nsp && !err; s++) {
     orc_species *S = &sp[s];
     for (int64_t p = 0; p < S->n; p++) {
+      if (keys[s][p] == REMOVED) continue;
       real x1[3] = {0, 0, 0}, xw[3] = {0, 0, 0};
       for (int a = 0; a < dim; a++) x1[a] = S->x[a][p];
       patch_key(&g, x1, xw);
@@ -921,8 +959,10 @@ int orc_jvp(const orc_grid *gi, double q, double m, int64_t n, const double *con
         x1[a] = xp[a] + g.dt * v[a];
         dx1[a] = dxp[a] + g.dt * dv[a];
       }
-      /* a mirror at a wall negates the tangents it negates the values of */
-      const int hit = reflect_walls(&g, x1, up);
+      /* a removed particle contributes nothing more; a mirror at a wall
+       * negates the tangents it negates the values of */
+      const int hit = walls(&g, x1, up);
+      if (hit < 0) break;
       for (int a = 0; a < 2; a++)
         if (hit >> a & 1) {
           dx1[a] = -dx1[a];
@@ -983,7 +1023,7 @@ static int loss_at(const G *g, real q, real m, int64_t n, const double *const x[
       interp6(g, Er, Br, xp, F, NULL);
       boris(alpha, F, up, v);
       for (int a = 0; a < 2; a++) x1[a] = xp[a] + g->dt * v[a];
-      reflect_walls(g, x1, up);
+      if (walls(g, x1, up) < 0) break;  /* removed: contributes nothing more */
       if (k == nsteps) {
         err = deposit(g, q, (real)w[p], xp, x1, v[2], Jr, NULL);
       } else {

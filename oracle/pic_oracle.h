@@ -29,6 +29,7 @@ extern "C" {
 #endif
 
 enum { ORC_OK = 0, ORC_ERR_CFL = 1, ORC_ERR_POS = 2, ORC_ERR_ARG = 3 };
+enum { ORC_BC_PERIODIC = 0, ORC_BC_REFLECT = 1, ORC_BC_REMOVE = 2 };
 
 typedef struct {
   int32_t dim;      /* 2 (2D3V) or 3 (3D3V) */
@@ -36,11 +37,14 @@ typedef struct {
   double d[3];      /* cell sizes */
   double dt;        /* time step */
   int32_t patch[3]; /* patch size in cells per axis; patch[2] = 1 in 2D */
-  int32_t reflect[3]; /* particle boundary per axis: 0 periodic, 1 reflecting
-                         walls at 0 and L (the paper's reflective particle
-                         condition of its radiation-pressure case, section
-                         "Basic performance benchmarks"); fields stay
-                         periodic */
+  int32_t bc[3];    /* particle boundary per axis: ORC_BC_PERIODIC,
+                       ORC_BC_REFLECT (walls at 0 and L mirror particles:
+                       the paper's reflective particle condition of its
+                       radiation-pressure case, section "Basic performance
+                       benchmarks") or ORC_BC_REMOVE (particles that leave
+                       [0, L) are deleted: the paper's "delete" condition,
+                       section "Parallelization without tasks"); fields
+                       stay periodic */
 } orc_grid;
 
 typedef struct {
@@ -79,14 +83,17 @@ int orc_deposit(const orc_grid *g, double q, double w, const double x0[3],
 
 /* Periodic wrap, patch key and stable counting sort by patch (in place);
  * writes s->off.  On a reflecting axis a position outside [0, L) is an
- * error (ORC_ERR_POS), not wrapped. */
+ * error (ORC_ERR_POS), not wrapped; on a removing axis the particle is
+ * deleted (s->n shrinks). */
 int orc_bin(const orc_grid *g, orc_species *s);
 
 /* One PIC step of the macro-particle operators for nsp species already
  * sorted by patch (s->off valid): J <- 0, then per patch, per species,
  * Interpolation, Push, pre-BC, Projection; then the periodic boundary
- * condition and the sort.  A (optional) receives, per node, the sum of the
- * absolute values of all products that entered J there. */
+ * condition and the sort.  A particle that leaves through a removing wall
+ * deposits no current and is deleted by the sort (sp[s].n shrinks).  A
+ * (optional) receives, per node, the sum of the absolute values of all
+ * products that entered J there. */
 int orc_step(const orc_grid *g, orc_species *sp, int32_t nsp, const double *const E[3],
              const double *const B[3], double *const J[3], double *const A[3]);
 

@@ -64,8 +64,9 @@ class Workload:
     steps: int
     seed: int
     ckpt: int = 0
-    # particle boundary per axis: 0 periodic, 1 reflecting walls at 0 and L
-    reflect: tuple = (0, 0, 0)
+    # particle boundary per axis: 0 periodic, 1 reflecting walls at 0 and L,
+    # 2 removing walls (particles leaving [0, L) are deleted)
+    particle_bc: tuple = (0, 0, 0)
 
     @property
     def n_patches(self) -> int:

@@ -551,7 +551,7 @@ def test_step_species_linearity_and_order_invariance():
 
 def _walls(wl, axes):
     import dataclasses
-    return dataclasses.replace(wl, reflect=tuple(int(a in axes) for a in range(3)))
+    return dataclasses.replace(wl, particle_bc=tuple(int(a in axes) for a in range(3)))
 
 
 def _fold(y, L):
@@ -639,7 +639,7 @@ def test_walls_keep_charge_continuity(dim):
         for s, (xb, ub) in zip(sps, before):
             o = np.argsort(s.id)
             dx = s.x[a, o] - xb[a]
-            if not wl.reflect[a]:
+            if not wl.particle_bc[a]:
                 dx = (dx + L / 2) % L - L / 2
             else:
                 flips += int((np.sign(s.u[a, o]) != np.sign(ub[a])).sum())
@@ -663,6 +663,113 @@ def test_walls_bin_rejects_positions_outside_the_box():
         sp2.x[0, 3] = bad
         with pytest.raises(O.OracleError):
             O.bin(wl, sp2)
+
+
+def _bcs(wl, bc):
+    import dataclasses
+    return dataclasses.replace(wl, particle_bc=tuple(bc) + (0,) * (3 - len(bc)))
+
+
+@pytest.mark.parametrize("bc", [(2, 0), (0, 2), (2, 1)])
+def test_remove_free_streaming_keeps_exactly_the_particles_inside(bc):
+    """Without fields every particle moves on a straight line, monotone along
+    each axis: after k steps the survivors are exactly the particles whose
+    line ends inside [0, L) on every removing axis (the others left through a
+    wall and were deleted), at their straight-line positions (folded at a
+    reflecting wall, wrapped on a periodic axis), and every patch's particles
+    stay contiguous in input order."""
+    wl = _bcs(I.custom(2, (24, 16), (8, 8), ppc=3, seed=47, sigma=0.8), bc)
+    inp = I.generate(wl)
+    inp.E[:] = 0
+    inp.B[:] = 0
+    sps = O.species_from(inp)
+    s = sps[0]
+    O.bin(wl, s)
+    o = np.argsort(s.id)
+    ids0, x0, u0 = s.id[o].copy(), s.x[:, o].copy(), s.u[:, o].copy()
+    k = 10
+    for _ in range(k):
+        O.step(wl, sps, inp.E, inp.B)
+    gam = np.sqrt(1 + (u0 ** 2).sum(axis=0))
+    y = x0 + k * wl.dt * u0[:2] / gam
+    L = np.array([wl.n[a] * wl.d[a] for a in range(2)])
+    inside = np.ones(ids0.size, bool)
+    sure = np.ones(ids0.size, bool)
+    for a in range(2):
+        if bc[a] == 2:
+            inside &= (y[a] >= 0) & (y[a] < L[a])
+            sure &= (np.abs(y[a]) > 1e-9) & (np.abs(y[a] - L[a]) > 1e-9)
+    got = np.isin(ids0, s.id)
+    assert np.array_equal(got[sure], inside[sure])
+    assert 100 < int((~inside).sum()) < ids0.size - 100  # many deleted, many kept
+    # survivors: straight-line positions, momenta unchanged but for mirrors
+    o = np.argsort(s.id)
+    keep = np.isin(ids0, s.id)
+    for a in range(2):
+        want = y[a, keep]
+        if bc[a] == 0:
+            want = np.mod(want, L[a])
+        elif bc[a] == 1:
+            want, flip = _fold(want, L[a])
+        ok = np.abs(np.mod(want + L[a] / 2, L[a]) - L[a] / 2) > 1e-9
+        assert np.max(np.abs(s.x[a, o][ok] - want[ok])) <= 1e-13 * L[a]
+    assert np.array_equal(np.abs(s.u[:, o]), np.abs(u0[:, keep]))
+    assert s.off[-1] == s.id.size and np.all(np.diff(s.off) >= 0)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_remove_continuity_holds_for_the_survivors(dim):
+    """A particle that leaves through a removing wall deposits nothing in that
+    step and is deleted, so the deposit satisfies the discrete continuity
+    equation of the survivors: (rho1 - (rho0 - rho_removed)) / dt + div J = 0
+    at every node, where rho_removed is the removed particles' density at
+    their start positions; the total charge falls by theirs."""
+    if dim == 2:
+        wl = _bcs(I.custom(2, (16, 24), (8, 8), ppc=6, seed=48, sigma=0.5, n_species=2), (2, 1))
+    else:
+        wl = _bcs(I.custom(3, (16, 8, 8), (8, 8, 8), ppc=3, seed=49, sigma=0.5, n_species=2),
+                  (2, 0, 2))
+    inp = I.generate(wl)
+    sps = O.species_from(inp)
+    for s in sps:
+        O.bin(wl, s)
+    before = [(s.q, s.x.copy(), s.w.copy(), s.id.copy()) for s in sps]
+    rho0 = sum(O.rho(wl, s.q, s.x, s.w) for s in sps)
+    J = O.step(wl, sps, inp.E, inp.B)
+    rho1 = sum(O.rho(wl, s.q, s.x, s.w) for s in sps)
+    rho_rm = 0.0
+    n_rm = 0
+    for (q, x, w, ids), s in zip(before, sps):
+        gone = ~np.isin(ids, s.id)
+        n_rm += int(gone.sum())
+        rho_rm = rho_rm + O.rho(wl, q, x[:, gone], w[gone])
+    assert n_rm > 20
+    res = (rho1 - (rho0 - rho_rm)) / wl.dt + _div(wl, J)
+    assert np.max(np.abs(res)) <= 1e-13 * np.abs(rho0).max() / wl.dt
+    # the removed particles' charge did leave: plain continuity fails
+    assert np.max(np.abs((rho1 - rho0) / wl.dt + _div(wl, J))) > 1e-3 * np.abs(rho0).max() / wl.dt
+    q_rm = sum(q * w[~np.isin(ids, s.id)].sum() for (q, x, w, ids), s in zip(before, sps))
+    assert abs((rho0 - rho1).sum() - q_rm) <= 1e-12 * np.abs(rho0).sum()
+
+
+def test_remove_bin_deletes_positions_outside_the_box():
+    """orc_bin deletes a particle outside a removing axis (and still wraps
+    the periodic one); the rest keep their stable order."""
+    wl = _bcs(I.custom(2, (16, 16), (8, 8), ppc=2, seed=50), (2, 0))
+    inp = I.generate(wl)
+    sp = O.species_from(inp)[0]
+    Lx, Ly = wl.n[0] * wl.d[0], wl.n[1] * wl.d[1]
+    sp.x[0, 3] = -1e-12
+    sp.x[0, 7] = Lx
+    sp.x[1, 9] = -0.5 * Ly
+    gone = sp.id[[3, 7]].copy()
+    n0 = sp.n
+    O.bin(wl, sp)
+    assert sp.n == n0 - 2 and sp.off[-1] == n0 - 2
+    assert not np.isin(gone, sp.id).any()
+    assert np.all(sp.x[1] >= 0)
+    for P in range(wl.n_patches):
+        assert np.all(np.diff(sp.id[sp.off[P]:sp.off[P + 1]]) > 0)
 
 
 # --------------------------------------------------------------------------
@@ -708,9 +815,34 @@ def test_jvp_with_walls_matches_extended_precision_fd():
     assert abs(L0 - math.fsum((inp.W * J).ravel())) <= 1e-13 * max(1, abs(L0))
     assert abs(g - fd) <= 1e-7 * abs(fd), (g, fd)
     # the walls matter: the periodic run's J differs
-    Jp, _ = O.jvp(dataclasses_replace(wl, reflect=(0, 0, 0)), sp.q, sp.m, sp.x, sp.u, sp.w,
+    Jp, _ = O.jvp(dataclasses_replace(wl, particle_bc=(0, 0, 0)), sp.q, sp.m, sp.x, sp.u, sp.w,
                   inp.E, inp.B, du, dE, None)
     assert np.abs(Jp - J).max() > 1e-6 * np.abs(J).max()
+
+
+def test_jvp_with_removing_walls_matches_extended_precision_fd():
+    """Particles deleted at a removing wall stop contributing; the tangent of
+    the survivors' current still equals the central difference."""
+    wl = _bcs(I.custom(2, (16, 16), (8, 8), ppc=3, seed=51, sigma=0.6, bz0=1.0, steps=4), (2, 1))
+    inp = I.generate(wl, with_W=True)
+    sp = O.species_from(inp)[0]
+    O.bin(wl, sp)
+    rng = np.random.default_rng(52)
+    du = rng.normal(size=sp.u.shape)
+    dB = rng.normal(size=inp.B.shape) * 0.01
+    J, dJ = O.jvp(wl, sp.q, sp.m, sp.x, sp.u, sp.w, inp.E, inp.B, du, None, dB)
+    g = math.fsum((inp.W * dJ).ravel())
+    fd, L0 = O.fd(wl, sp.q, sp.m, sp.x, sp.u, sp.w, inp.E, inp.B, inp.W, du, None, dB, h=1e-6)
+    assert abs(L0 - math.fsum((inp.W * J).ravel())) <= 1e-13 * max(1, abs(L0))
+    assert abs(g - fd) <= 1e-7 * abs(fd), (g, fd)
+    # J equals the step oracle's after the same steps
+    c = O.OSpecies(sp.q, sp.m, sp.x, sp.u, sp.w, sp.id, wl.n_patches)
+    c.off[:] = sp.off
+    Js = None
+    for _ in range(wl.steps):
+        Js = O.step(wl, [c], inp.E, inp.B)
+    assert c.n < sp.n
+    assert np.max(np.abs(J - Js)) <= 1e-14 * np.abs(Js).max()
 
 
 def test_jvp_is_linear_in_direction():
