@@ -483,7 +483,7 @@ def main(argv=None) -> int:
         }
         # the same workload with reflecting particle walls along x (the paper's
         # radiation-pressure case: reflective in x, periodic in y), persistent
-        wlw = dataclasses.replace(wli, reflect=(1, 0, 0))
+        wlw = dataclasses.replace(wli, particle_bc=(1, 0, 0))
         _, sw, tw = run_gpu(wlw, args.steps, args.warmup, mode=1, chunk=tuned["chunk"],
                             wg=tuned["wg"], inp=inpi, bin_x=tuned.get("bin_x", 0))
         ipp_w = tw["ipp"][0] / tw["ipp"][1]
@@ -492,6 +492,15 @@ def main(argv=None) -> int:
             "ipp_ns_per_particle": ipp_w / ni * 1e6,
             "ipp_ratio_vs_periodic": ipp_w / ipp_pe,
             "step_ratio_vs_periodic": sw / sp_,
+        }
+        # and with removing walls along x (particles reaching them are deleted)
+        wlr = dataclasses.replace(wli, particle_bc=(2, 0, 0))
+        _, sr, tr = run_gpu(wlr, args.steps, args.warmup, mode=1, chunk=tuned["chunk"],
+                            wg=tuned["wg"], inp=inpi, bin_x=tuned.get("bin_x", 0))
+        out["imbalanced"]["x_remove_persistent"] = {
+            "ns_per_particle_step": sr / (ni * args.steps) * 1e9, "kernel_ms": per_k(tr),
+            "ipp_ratio_vs_periodic": (tr["ipp"][0] / tr["ipp"][1]) / ipp_pe,
+            "step_ratio_vs_periodic": sr / sp_,
         }
     if not args.no_3d:
         out["expansion3d"] = run_expansion3d(min(args.steps, 50), args.warmup)

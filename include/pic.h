@@ -65,6 +65,9 @@ typedef enum {
 
 enum { PIC_MODE_PER_PATCH = 0, PIC_MODE_PERSISTENT = 1 };
 
+/* particle boundary condition of an axis (pic_config.particle_bc) */
+enum { PIC_BC_PERIODIC = 0, PIC_BC_REFLECT = 1, PIC_BC_REMOVE = 2 };
+
 enum {
   PIC_FLAG_CHECK = 1, /* every call waits for its stream and reports device errors */
   PIC_FLAG_GRAPH = 2  /* pic_step replays a captured HIP graph of its steps
@@ -108,25 +111,40 @@ typedef struct {
                           bin per patch, the particles inside a patch are
                           ordered by bin, and pic_step and pic_interp_push
                           first sort them by bin (one general sort per call). */
-  int32_t reflect[3];  /* particle boundary per axis (reflect[2] ignored in
-                          2D): 0 = periodic; 1 = reflecting walls at 0 and
-                          L = n d, the paper's reflective particle condition
-                          (section "Basic performance benchmarks", its
-                          radiation-pressure case).  In the pre-BC
-                          operation, which writes positions and momenta
-                          (section "Parallelization with OpenMP task"), a
-                          particle pushed across a wall is mirrored back
-                          inside (x -> -x, x -> 2L - x; x = L exactly goes
-                          to the largest double below L) and its momentum
-                          component along the axis changes sign, before its
-                          current is projected: the deposit follows the
-                          mirrored move and stays charge-conserving.  Fields
+  int32_t particle_bc[3]; /* particle boundary per axis, PIC_BC_* (ignored
+                          for z in 2D); walls sit at 0 and L = n d.  Fields
                           and current stay periodic arrays: nodes beyond a
                           wall are read and written at their periodic
-                          images.  pic_bin reports PIC_ERR_POS for a position
-                          outside [0, L) on a walled axis instead of
-                          wrapping it.  pic_adjoint differentiates through
-                          the mirror. */
+                          images.
+                          PIC_BC_REFLECT: the paper's reflective particle
+                          condition (section "Basic performance
+                          benchmarks", its radiation-pressure case).  In the
+                          pre-BC operation, which writes positions and
+                          momenta (section "Parallelization with OpenMP
+                          task"), a particle pushed across a wall is
+                          mirrored back inside (x -> -x, x -> 2L - x; x = L
+                          exactly goes to the largest double below L) and
+                          its momentum component along the axis changes
+                          sign, before its current is projected: the
+                          deposit follows the mirrored move and stays
+                          charge-conserving.  pic_bin reports PIC_ERR_POS
+                          for a position outside [0, L) on such an axis
+                          instead of wrapping it.  pic_adjoint
+                          differentiates through the mirror.
+                          PIC_BC_REMOVE: the paper's "delete" condition
+                          (section "Parallelization without tasks": pre-BC
+                          flags the particles, the synchronisation applies
+                          the condition).  A particle pushed outside
+                          [0, L) on such an axis deposits no current in
+                          that step and is deleted; pic_bin deletes a
+                          position outside [0, L) on it.  pic_step,
+                          pic_cycle and pic_bin then wait for their stream
+                          and set each species' n to the surviving count
+                          (its particles are the first n of the arrays, as
+                          always); pic_step and pic_cycle need buffers with
+                          the slab layout's room for every call length
+                          (PIC_ERR_CAPACITY otherwise); pic_adjoint rejects
+                          the configuration (PIC_ERR_ARG). */
 } pic_config;
 
 typedef struct {

@@ -403,7 +403,7 @@ __global__ void __launch_bounds__(128) k_adjoint(GridDev g, AdjArgs aa, AdjField
       interp_g(g, f, x, F);
       boris_f(S.alpha, F, u, v);
       double x1[3] = {x[0] + g.dt * v[0], x[1] + g.dt * v[1], 0.0};
-      if (g.reflect) hits |= (uint32_t)reflect_walls<2>(g, x1, u) << (2 * k);
+      if (g.reflect) hits |= (uint32_t)wall_bc<2>(g, x1, u) << (2 * k);  // no removing walls here
       if (k == nsteps - 1) {
         xlast[0] = x[0];
         xlast[1] = x[1];
@@ -635,7 +635,7 @@ __global__ void __launch_bounds__(256) k_adjoint_tiled(GridDev g, AdjArgs aa, Ad
       interp_t(g, t, f, x, F);
       boris_f(S.alpha, F, u, v);
       double x1[3] = {x[0] + g.dt * v[0], x[1] + g.dt * v[1], 0.0};
-      if (g.reflect) hits |= (uint32_t)reflect_walls<2>(g, x1, u) << (2 * k);
+      if (g.reflect) hits |= (uint32_t)wall_bc<2>(g, x1, u) << (2 * k);  // no removing walls here
       if (k == NS - 1) {
         xlast[0] = x[0];
         xlast[1] = x[1];

@@ -188,8 +188,10 @@ GridDev make_grid(const pic_config *c) {
     g.d_over_dt[a] = d / c->dt;
   }
   g.dt = c->dt;
-  for (int a = 0; a < c->dim; a++)
-    if (c->reflect[a]) g.reflect |= 1 << a;
+  for (int a = 0; a < c->dim; a++) {
+    if (c->particle_bc[a] == PIC_BC_REFLECT) g.reflect |= 1 << a;
+    if (c->particle_bc[a] == PIC_BC_REMOVE) g.remove |= 1 << a;
+  }
   return g;
 }
 
@@ -394,6 +396,23 @@ hipError_t timed(pic_ctx *c, int kind, hipStream_t st, F &&fn) {
 
 pic_status finish(pic_ctx *c, hipStream_t st) {
   if (c->cfg.flags & PIC_FLAG_CHECK) return pic_check(c, st);
+  return PIC_OK;
+}
+
+// Removing walls: the particles that survive a call are the first
+// offset[npatch] of each species; wait for the stream and hand the caller
+// the new counts.
+pic_status update_counts(pic_ctx *c, pic_species *sp, int32_t nsp, hipStream_t st) {
+  if (!c->g.remove) return PIC_OK;
+  for (int s = 0; s < nsp; s++) {
+    int64_t n = 0;
+    hipError_t e = hipMemcpyAsync(&n, sp[s].offset + c->npatch_api, sizeof(n),
+                                  hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail(c, e, "reading the surviving count");
+    if (n < 0 || n > sp[s].n) return fail(c, PIC_ERR_STATE, "species %d: bad surviving count", s);
+    sp[s].n = n;
+  }
   return PIC_OK;
 }
 
@@ -916,9 +935,9 @@ pic_status pic_validate_config(const pic_config *c, char *msg, size_t len) {
     return PIC_ERR_ARG;
   }
   for (int a = 0; a < c->dim; a++)
-    if (c->reflect[a] != 0 && c->reflect[a] != 1) {
-      set_msg(msg, len, "reflect[%d]=%d must be 0 (periodic) or 1 (reflecting walls)", a,
-              c->reflect[a]);
+    if (c->particle_bc[a] < PIC_BC_PERIODIC || c->particle_bc[a] > PIC_BC_REMOVE) {
+      set_msg(msg, len, "particle_bc[%d]=%d must be PIC_BC_PERIODIC, PIC_BC_REFLECT or PIC_BC_REMOVE",
+              a, c->particle_bc[a]);
       return PIC_ERR_ARG;
     }
   if (c->bin_x < 0 || (c->bin_x > 0 && c->patch[0] % c->bin_x)) {
@@ -1081,8 +1100,11 @@ pic_status pic_bin(pic_ctx *c, pic_species *sp, int32_t nsp, void *stream) {
   if (hipSetDevice(c->device) != hipSuccess) return fail(c, PIC_ERR_HIP, "hipSetDevice");
   if (c->moved && nsp != c->moved_nsp)
     return fail(c, PIC_ERR_STATE, "pic_bin after pic_interp_push needs the same species");
-  if ((r = sort_species(c, sp, nsp, !c->moved, st)) != PIC_OK) return r;
-  return finish(c, st);
+  // removing walls: the general sort, whose keys drop deleted particles past
+  // the last patch (the neighbour-code sort keeps every particle)
+  if ((r = sort_species(c, sp, nsp, !c->moved || c->g.remove, st)) != PIC_OK) return r;
+  if ((r = finish(c, st)) != PIC_OK) return r;
+  return update_counts(c, sp, nsp, st);
 }
 
 pic_status pic_interp_push(pic_ctx *c, pic_species *sp, int32_t nsp, const pic_fields *f,
@@ -1135,7 +1157,12 @@ pic_status pic_step(pic_ctx *c, pic_species *sp, int32_t nsp, pic_fields *f, int
   if (nsteps == 0) return finish(c, st);
   // x-bins: the particles arrive sorted by patch; the kernels need them by bin
   if (c->nb > 1 && (r = sort_species(c, sp, nsp, true, st)) != PIC_OK) return r;
-  if (nsteps >= 3 && slab_fits(c, sp, nsp)) {
+  // removing walls delete particles only in the slab layout's exchange, so
+  // every call takes it there
+  if (c->g.remove && !slab_fits(c, sp, nsp))
+    return fail(c, PIC_ERR_CAPACITY,
+                "removing walls need buffers with the slab layout's room (n + n/8 + 80 per slab)");
+  if ((nsteps >= 3 || c->g.remove) && slab_fits(c, sp, nsp)) {
     if ((r = step_slab(c, sp, nsp, f, nsteps, st)) != PIC_OK) return r;
   } else {
     // The first step updates the particles in place and records the sort as
@@ -1167,7 +1194,8 @@ pic_status pic_step(pic_ctx *c, pic_species *sp, int32_t nsp, pic_fields *f, int
   }
   const hipError_t e = api_offsets(c, sp, nsp, st);
   if (e != hipSuccess) return hip_fail(c, e, "kernel launch");
-  return finish(c, st);
+  if ((r = finish(c, st)) != PIC_OK) return r;
+  return update_counts(c, sp, nsp, st);
 }
 
 
@@ -1255,6 +1283,8 @@ pic_status pic_adjoint(pic_ctx *c, const pic_species *ck, int32_t nsp, const pic
   if (!c) return PIC_ERR_ARG;
   if (c->poisoned) return fail(c, PIC_ERR_STATE, "context unusable after a device error");
   if (c->cfg.dim != 2) return fail(c, PIC_ERR_ARG, "pic_adjoint supports 2D3V only");
+  if (c->g.remove)
+    return fail(c, PIC_ERR_ARG, "pic_adjoint does not differentiate through removing walls");
   if (!ck || nsp < 1 || nsp > kMaxSpecies || !cot)
     return fail(c, PIC_ERR_ARG, "bad species or cotangent arguments");
   if (nsteps < 1 || nsteps > kAdjMaxSteps)

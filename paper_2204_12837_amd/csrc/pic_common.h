@@ -29,16 +29,37 @@ struct GridDev {
   double dt;
   double d_over_dt[3];
   int reflect;    // bit a set: reflecting particle walls at 0 and L on axis a
+  int remove;     // bit a set: removing particle walls at 0 and L on axis a
 };
 
-// pre-BC at reflecting walls: a pushed position x1 that left [0, L) on a
-// walled axis is mirrored back inside about the wall it crossed (x -> -x or
+// Neighbour code of a particle deleted at a removing wall (no destination).
+constexpr int kGone = 31;
+
+// Whether any axis has particle walls (the kernels' WALLS instances).
+__host__ __device__ inline bool has_walls(const GridDev &g) { return (g.reflect | g.remove) != 0; }
+
+// Whether x lies outside [0, L) on an axis with removing walls.
+template <int DIM>
+__device__ __forceinline__ bool outside_removing(const GridDev &g, const double x[3]) {
+  bool out = false;
+#pragma unroll
+  for (int a = 0; a < DIM; a++)
+    if ((g.remove >> a) & 1) out = out || !(x[a] >= 0.0 && x[a] < g.L[a]);
+  return out;
+}
+
+// pre-BC at walls.  A pushed position x1 outside [0, L) on an axis with
+// removing walls marks the particle for deletion: -1 is returned and nothing
+// changes (the particle deposits no current and the synchronisation drops
+// it).  Otherwise, on an axis with reflecting walls, a position that left
+// [0, L) is mirrored back inside about the wall it crossed (x -> -x or
 // x -> 2L - x; both exact in floating point, as x and 2L lie within a factor
 // two of each other) and the momentum component along that axis changes
 // sign.  The one position that lands on L itself (x1 = L) goes to the
 // largest double below L.  Returns the mirrored axes as bits.
 template <int DIM>
-__device__ __forceinline__ int reflect_walls(const GridDev &g, double x1[3], double u[3]) {
+__device__ __forceinline__ int wall_bc(const GridDev &g, double x1[3], double u[3]) {
+  if (g.remove && outside_removing<DIM>(g, x1)) return -1;
   int hit = 0;
 #pragma unroll
   for (int a = 0; a < DIM; a++) {

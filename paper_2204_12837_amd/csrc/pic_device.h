@@ -389,8 +389,10 @@ __device__ __forceinline__ int dest_code(const GridDev &g, const int lo[3], doub
   return code;
 }
 
-// Destination patch of code c from patch coordinates pc.
+// Destination patch of code c from patch coordinates pc (-1 for kGone: the
+// particle is deleted).
 __device__ __forceinline__ int dest_patch(const GridDev &g, const int pc[3], int c) {
+  if (c == kGone) return -1;
   int D = 0, mul = 1;
   for (int a = 0; a < 3; a++) {
     int delta = 0;
@@ -627,8 +629,9 @@ struct Blk {
 // Interpolation, Push, Projection and pre-BC of one particle: advances x
 // (wrapped, or mirrored at reflecting walls before the Projection) and u in
 // place and returns its neighbour code (CENTER when the particle is
-// rejected, with the error bit set).  WALLS = false compiles the walls out
-// (a kernel instance for periodic grids only).
+// rejected, with the error bit set; kGone, with no deposit, when it left
+// through a removing wall).  WALLS = false compiles the walls out (a kernel
+// instance for periodic grids only).
 template <int DIM, bool WALLS>
 __device__ __forceinline__ int step_particle(const GridDev &g, const TileGeom &t, const double *tEB,
                                              double *tJ, double q, double alpha, double w,
@@ -650,7 +653,11 @@ __device__ __forceinline__ int step_particle(const GridDev &g, const TileGeom &t
   if constexpr (WALLS) {
 #pragma unroll
     for (int a = 0; a < DIM; a++) x1[a] = x[a] + g.dt * v[a];
-    if (g.reflect) reflect_walls<DIM>(g, x1, u);
+    if ((g.reflect | g.remove) && wall_bc<DIM>(g, x1, u) < 0) {
+#pragma unroll
+      for (int a = 0; a < DIM; a++) x[a] = x1[a];
+      return kGone;  // deleted at a removing wall: no deposit
+    }
 #pragma unroll
     for (int a = 0; a < DIM; a++)
       ok = ok && esk_win(sh.p[a], x1[a] * g.inv_d[a], sh.p[a].i + 1 + t.org[a], win[a]);

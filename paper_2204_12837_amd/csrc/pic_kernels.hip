@@ -203,9 +203,9 @@ __global__ void __launch_bounds__(kMaxWg<DIM>, kMinWaves<DIM>) k_ipp_persistent(
   if (bad) atomicOr(err, bad);
 }
 
-// Split path, first half: Interpolation + Push (and the mirror at reflecting
-// walls, so that the Projection deposits along the mirrored move); saves the
-// start positions.
+// Split path, first half: Interpolation + Push (and the walls: the mirror at
+// reflecting walls, so that the Projection deposits along the mirrored move);
+// saves the start positions.
 template <int DIM>
 __global__ void __launch_bounds__(kMaxWg<DIM>) k_interp_push(GridDev g, SpArgs sa, Fields f, int *err) {
   extern __shared__ __align__(16) double lds[];
@@ -237,7 +237,9 @@ __global__ void __launch_bounds__(kMaxWg<DIM>) k_interp_push(GridDev g, SpArgs s
     double x1[3];
 #pragma unroll
     for (int a = 0; a < DIM; a++) x1[a] = x[a] + g.dt * v[a];
-    if (g.reflect) reflect_walls<DIM>(g, x1, u);
+    // a particle leaving through a removing wall keeps its position outside
+    // the box: the Projection skips it and pic_bin deletes it
+    if (g.reflect | g.remove) wall_bc<DIM>(g, x1, u);
 #pragma unroll
     for (int a = 0; a < DIM; a++) S.x[a][i] = x1[a];
     S.u[0][i] = u[0];
@@ -266,6 +268,12 @@ __global__ void __launch_bounds__(kMaxWg<DIM>) k_project(GridDev g, SpArgs sa, F
     if (!in_patch<DIM>(t, xi0)) {
       bad |= kErrPos;
       continue;
+    }
+    if (g.remove) {  // left through a removing wall: deleted, deposits nothing
+      double x1[3];
+#pragma unroll
+      for (int a = 0; a < DIM; a++) x1[a] = S.x[a][i];
+      if (outside_removing<DIM>(g, x1)) continue;
     }
     const double u0 = S.u[0][i], u1 = S.u[1][i], u2 = S.u[2][i];
     const double gam = sqrt(1.0 + ((u0 * u0 + u1 * u1) + u2 * u2));
@@ -583,7 +591,7 @@ hipError_t launch_ipp(const GridDev &g, const SpArgs &sa, const double *const e[
                       hipStream_t st) {
   const Fields f = mkfields(e, b, j);
   const size_t lds = lds_bytes_ipp(g);
-  const int v = (g.dim == 3 ? 4 : 0) + (sa.gather ? 2 : 0) + (g.reflect ? 1 : 0);
+  const int v = (g.dim == 3 ? 4 : 0) + (sa.gather ? 2 : 0) + (has_walls(g) ? 1 : 0);
   switch (v) {
     case 0: launch_ipp_t<2, false, false>(g, sa, f, err, wg, lds, st); break;
     case 1: launch_ipp_t<2, false, true>(g, sa, f, err, wg, lds, st); break;
@@ -681,9 +689,9 @@ int blocks_per_cu_both(int wg, size_t lds) {
 
 int persistent_grid(const GridDev &g, int wg) {
   const size_t lds = lds_bytes_ipp(g);
-  int per_cu = g.dim == 2 ? (g.reflect ? blocks_per_cu_both<2, true>(wg, lds)
+  int per_cu = g.dim == 2 ? (has_walls(g) ? blocks_per_cu_both<2, true>(wg, lds)
                                        : blocks_per_cu_both<2, false>(wg, lds))
-                          : (g.reflect ? blocks_per_cu_both<3, true>(wg, lds)
+                          : (has_walls(g) ? blocks_per_cu_both<3, true>(wg, lds)
                                        : blocks_per_cu_both<3, false>(wg, lds));
   int dev = 0, ncu = 0;
   if (per_cu < 1) per_cu = 1;
@@ -709,7 +717,7 @@ hipError_t launch_ipp_persistent(const GridDev &g, const SpArgs &sa, const doubl
                                  const Unit *units, int *qctl, int grid, int wg, hipStream_t st) {
   const Fields f = mkfields(e, b, j);
   const size_t lds = lds_bytes_ipp(g);
-  const int v = (g.dim == 3 ? 4 : 0) + (sa.gather ? 2 : 0) + (g.reflect ? 1 : 0);
+  const int v = (g.dim == 3 ? 4 : 0) + (sa.gather ? 2 : 0) + (has_walls(g) ? 1 : 0);
   switch (v) {
     case 0: launch_pers_t<2, false, false>(g, sa, f, err, units, qctl, grid, wg, lds, st); break;
     case 1: launch_pers_t<2, false, true>(g, sa, f, err, units, qctl, grid, wg, lds, st); break;

@@ -576,6 +576,7 @@ __global__ void __launch_bounds__(256) k_exch_in(GridDev g, SlabArgs sa) {
     const double w = S.ow[e];
     const int64_t id = S.oid[e];
     const int D = S.odest[e];
+    if (D < 0) continue;  // deleted at a removing wall
     const int pos = S.cnt2[D] + atomicAdd(&S.arr[D], 1);
     if (pos < S.cap[D]) {
       const int64_t d = S.sb[D] + pos;
@@ -721,7 +722,7 @@ __global__ void __launch_bounds__(256) k_reslab_move(GridDev g, SlabArgs sa) {
   for (int r = threadIdx.x; r < m; r += blockDim.x) {
     const int64_t e = ob + r;
     const int dv = S.odest[e];
-    if (!(dv & kUnplaced)) continue;
+    if (dv < 0 || !(dv & kUnplaced)) continue;  // deleted, or placed
     const int D = dv & ~kUnplaced;
     const int placed = min(S.arr[D], S.cap[D] - S.cnt2[D]);
     const int64_t pos = (int64_t)S.cnt2[D] + placed + atomicAdd(&S.arr2[D], 1);
@@ -809,10 +810,10 @@ hipError_t launch_ipp_slab(const GridDev &g, const SlabArgs &sa, const double *c
   const Fields f = mkfields(e, b, j);
   const size_t lds = lds_bytes_ipp(g);
   if (g.dim == 2)
-    g.reflect ? ipp_slab_t<2, true>(g, sa, f, err, wg, lds, st)
+    has_walls(g) ? ipp_slab_t<2, true>(g, sa, f, err, wg, lds, st)
               : ipp_slab_t<2, false>(g, sa, f, err, wg, lds, st);
   else
-    g.reflect ? ipp_slab_t<3, true>(g, sa, f, err, wg, lds, st)
+    has_walls(g) ? ipp_slab_t<3, true>(g, sa, f, err, wg, lds, st)
               : ipp_slab_t<3, false>(g, sa, f, err, wg, lds, st);
   return hipGetLastError();
 }
@@ -834,10 +835,10 @@ hipError_t launch_ipp_slab_persistent(const GridDev &g, const SlabArgs &sa,
   const Fields f = mkfields(e, b, j);
   const size_t lds = lds_bytes_ipp(g);
   if (g.dim == 2)
-    g.reflect ? ipp_slab_pers_t<2, true>(g, sa, f, err, units, qctl, grid, wg, lds, st)
+    has_walls(g) ? ipp_slab_pers_t<2, true>(g, sa, f, err, units, qctl, grid, wg, lds, st)
               : ipp_slab_pers_t<2, false>(g, sa, f, err, units, qctl, grid, wg, lds, st);
   else
-    g.reflect ? ipp_slab_pers_t<3, true>(g, sa, f, err, units, qctl, grid, wg, lds, st)
+    has_walls(g) ? ipp_slab_pers_t<3, true>(g, sa, f, err, units, qctl, grid, wg, lds, st)
               : ipp_slab_pers_t<3, false>(g, sa, f, err, units, qctl, grid, wg, lds, st);
   return hipGetLastError();
 }
@@ -856,9 +857,9 @@ int slab_blocks_t(int wg, size_t lds) {
 
 int slab_persistent_blocks_per_cu(const GridDev &g, int wg) {
   const size_t lds = lds_bytes_ipp(g);
-  const int n = g.dim == 2 ? (g.reflect ? slab_blocks_t<2, true>(wg, lds)
+  const int n = g.dim == 2 ? (has_walls(g) ? slab_blocks_t<2, true>(wg, lds)
                                         : slab_blocks_t<2, false>(wg, lds))
-                           : (g.reflect ? slab_blocks_t<3, true>(wg, lds)
+                           : (has_walls(g) ? slab_blocks_t<3, true>(wg, lds)
                                         : slab_blocks_t<3, false>(wg, lds));
   return n > 0 ? n : 1;
 }

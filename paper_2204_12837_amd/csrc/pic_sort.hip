@@ -1,6 +1,8 @@
 // General sort of particles by patch, for input in any order (e.g. freshly
 // loaded particles): periodic wrap (a position outside the box on an axis
-// with reflecting walls is an error), patch key, stable radix sort of
+// with reflecting walls is an error; one outside an axis with removing walls
+// is deleted: its key sorts past the last patch, so the patch offsets end
+// before it), patch key, stable radix sort of
 // (key, index) pairs, gather into the second buffer set, patch offsets.
 // The per-step sort after a push uses the neighbour-code counting sort in
 // pic_kernels.hip instead; both give the same stable order.
@@ -18,10 +20,20 @@ __global__ void k_keys(GridDev g, SpDev s, int32_t *keys, int64_t *idx, int *err
   int bad = 0;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < s.n;
        i += (int64_t)gridDim.x * blockDim.x) {
+    idx[i] = i;
+    if (g.remove) {  // outside a removing wall: deleted (sorts past the last patch)
+      double x[3] = {0.0, 0.0, 0.0};
+      for (int a = 0; a < g.dim; a++) x[a] = s.x[a][i];
+      const bool out = g.dim == 2 ? outside_removing<2>(g, x) : outside_removing<3>(g, x);
+      if (out) {
+        keys[i] = g.npatch;
+        continue;
+      }
+    }
     int key = 0, mul = 1;
     for (int a = 0; a < g.dim; a++) {
       double v = s.x[a][i];
-      if (!((g.reflect >> a) & 1)) {  // a walled axis is not wrapped
+      if (!(((g.reflect | g.remove) >> a) & 1)) {  // a walled axis is not wrapped
         if (v < 0.0) v += g.L[a];
         if (v >= g.L[a]) v -= g.L[a];
       }
@@ -36,7 +48,6 @@ __global__ void k_keys(GridDev g, SpDev s, int32_t *keys, int64_t *idx, int *err
       mul *= g.np[a];
     }
     keys[i] = key;
-    idx[i] = i;
   }
   if (bad) atomicOr(err, bad);
 }
@@ -95,8 +106,11 @@ hipError_t general_sort(const GridDev &g, SpDev &s, SortScratch &scr, int *err, 
     if ((e = grow(scr.idx_out, s.n)) != hipSuccess) return e;
     scr.cap = s.n;
   }
+  // keys lie in [0, npatch), and at npatch for particles deleted at a
+  // removing wall
+  const long long nkeys = (long long)g.npatch + (g.remove ? 1 : 0);
   int bits = 1;
-  while ((1ll << bits) < (long long)g.npatch) bits++;
+  while ((1ll << bits) < nkeys) bits++;
   size_t need = 0;
   e = hipcub::DeviceRadixSort::SortPairs(nullptr, need, scr.keys, scr.keys_out, scr.idx,
                                          scr.idx_out, (int)s.n, 0, bits, st);

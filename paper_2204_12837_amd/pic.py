@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(HERE, "libpic.so")
 PIC_OK, PIC_ERR_ARG, PIC_ERR_HIP, PIC_ERR_CAPACITY, PIC_ERR_CFL, PIC_ERR_POS, PIC_ERR_STATE = range(7)
 STATUS_NAMES = {0: "PIC_OK", 1: "PIC_ERR_ARG", 2: "PIC_ERR_HIP", 3: "PIC_ERR_CAPACITY",
                 4: "PIC_ERR_CFL", 5: "PIC_ERR_POS", 6: "PIC_ERR_STATE"}
+BC_PERIODIC, BC_REFLECT, BC_REMOVE = 0, 1, 2
 MODE_PER_PATCH, MODE_PERSISTENT = 0, 1
 FLAG_CHECK, FLAG_GRAPH = 1, 2
 
@@ -36,7 +37,7 @@ class ConfigC(C.Structure):
     _fields_ = [("dim", C.c_int32), ("n", C.c_int32 * 3), ("d", C.c_double * 3), ("dt", C.c_double),
                 ("patch", C.c_int32 * 3), ("shape_order", C.c_int32), ("mode", C.c_int32),
                 ("chunk", C.c_int32), ("wg_size", C.c_int32), ("flags", C.c_uint32),
-                ("bin_x", C.c_int32), ("reflect", C.c_int32 * 3)]
+                ("bin_x", C.c_int32), ("particle_bc", C.c_int32 * 3)]
 
 
 class SpeciesC(C.Structure):
@@ -123,8 +124,8 @@ def lib():
 
 def make_config(wl, mode=MODE_PER_PATCH, chunk=0, wg_size=0, flags=0, bin_x=0) -> ConfigC:
     """Config struct from a workload description (dim, n, d, dt, patch and,
-    if it has one, reflect: per-axis reflecting particle walls); bin_x = 0
-    lets the library choose the x-bin width."""
+    if it has one, particle_bc: per-axis particle boundaries, BC_*); bin_x =
+    0 lets the library choose the x-bin width."""
     c = ConfigC()
     c.dim = wl.dim
     for a in range(3):
@@ -135,9 +136,9 @@ def make_config(wl, mode=MODE_PER_PATCH, chunk=0, wg_size=0, flags=0, bin_x=0) -
     c.shape_order = 2
     c.mode, c.chunk, c.wg_size, c.flags = mode, chunk, wg_size, flags
     c.bin_x = bin_x
-    walls = getattr(wl, "reflect", (0, 0, 0))
+    bc = getattr(wl, "particle_bc", (0, 0, 0))
     for a in range(wl.dim):
-        c.reflect[a] = int(walls[a])
+        c.particle_bc[a] = int(bc[a])
     return c
 
 
@@ -198,7 +199,9 @@ class Species:
         return s
 
     def adopt(self, s: SpeciesC):
-        """Follow the buffer swap the library made in the struct."""
+        """Follow the buffer swap the library made in the struct, and the
+        particle count (removing walls delete particles)."""
+        self.n = int(s.n)
         if s.w != self.w.data_ptr():
             assert s.w == self.w_alt.data_ptr()
             self.x, self.x_alt = self.x_alt, self.x

@@ -134,4 +134,10 @@ def test_imbalanced_with_x_walls_persistent():
     persistent launch: a window on the right wall (the background plasma
     reaches it) and one on the bump."""
     _run("imbalanced", 8, 1, 2048, 256, [((2016, 200), (2, 3)), ((1520, 96), (2, 2))],
-         reflect=(1, 0, 0))
+         particle_bc=(1, 0, 0))
+
+
+def test_imbalanced_with_removing_x_walls_persistent():
+    """The same with removing walls along x: particles that reach the right
+    wall are deleted, on the GPU as in the oracle (window at the wall)."""
+    _run("imbalanced", 8, 1, 2048, 256, [((2016, 200), (2, 3))], particle_bc=(2, 0, 0))
