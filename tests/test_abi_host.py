@@ -132,3 +132,49 @@ def test_null_arguments():
     L.pic_free(None)  # no-op
     assert L.pic_check(None, None) == pic.PIC_ERR_ARG
     assert L.pic_last_error(None) == b"null context"
+
+
+def test_binding_struct_layouts_match_the_header(tmp_path):
+    """The ctypes structures have the size and field offsets that a C
+    compiler gives the header's structs (a mismatch would pass garbage
+    through the ABI silently)."""
+    import shutil
+    import subprocess
+
+    if shutil.which("gcc") is None:
+        pytest.skip("no C compiler")
+    structs = {"pic_config": pic.ConfigC, "pic_species": pic.SpeciesC, "pic_fields": pic.FieldsC,
+               "pic_cotangent": pic.CotangentC}
+    lines = ["#include <stddef.h>", "#include <stdio.h>", '#include "pic.h"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f, _ in py._fields_:
+            lines.append(f'  printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+    subprocess.run(["gcc", "-std=c11", "-I", inc, str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {}
+    for line in out:
+        if line:
+            name, field, val = line.split()
+            got[(name, field)] = int(val)
+    for cname, py in structs.items():
+        assert got[(cname, "size")] == C.sizeof(py), cname
+        for f, _ in py._fields_:
+            assert got[(cname, f)] == getattr(py, f).offset, (cname, f)
+
+
+@pytest.mark.parametrize("bc", [(3, 0, 0), (0, -1, 0)])
+def test_invalid_particle_boundaries_rejected(bc):
+    import dataclasses
+
+    wl = dataclasses.replace(I.custom(2, (32, 32), (8, 8), ppc=1), particle_bc=bc)
+    rc, msg = pic.validate(pic.make_config(wl))
+    assert rc == pic.PIC_ERR_ARG and "particle_bc" in msg, msg
+    for ok in ((1, 2, 0), (2, 2, 0), (0, 1, 0)):
+        wl = dataclasses.replace(wl, particle_bc=ok)
+        assert pic.validate(pic.make_config(wl))[0] == pic.PIC_OK
