@@ -11,7 +11,9 @@
  *
  * Conventions shared by every entry point
  *   Units     normalised: c = 1, charge in e, mass in m_e, u = p/(m c).
- *   Grid      periodic, n[a] cells of size d[a] per axis; each field
+ *   Grid      periodic fields, n[a] cells of size d[a] per axis
+ *             (particles see periodic, reflecting or removing boundaries
+ *             per axis, pic_config.particle_bc); each field
  *             component is a device array of prod(n) float64 values, x
  *             fastest, entry (i,j,k) at ((i+sx/2)d_x, (j+sy/2)d_y,
  *             (k+sz/2)d_z) with stagger bits Ex(1,0,0) Ey(0,1,0) Ez(0,0,1)
@@ -194,21 +196,25 @@ void pic_free(pic_ctx *ctx);
  * operators).  For each species: periodic wrap of every position, patch
  * key, stable counting sort by patch into the *_alt arrays, offset[]
  * written, then the two buffer sets are swapped in *sp.  Accepts particles
- * in any order and anywhere within one period of the box. */
+ * in any order and anywhere within one period of the box (within the box on
+ * a reflecting axis; outside it on a removing axis they are deleted and
+ * sp[s].n is updated, see pic_config.particle_bc). */
 pic_status pic_bin(pic_ctx *ctx, pic_species *sp, int32_t nsp, void *stream);
 
 /* Interpolation + Push (paper: the first two operators).  Particles must be
  * sorted by patch (offset[] valid, e.g. after pic_bin).  Gathers E and B at
  * each position with the quadratic shape, advances u by the relativistic
  * Boris push and x by dt*v.  Positions are left unwrapped (the boundary
- * condition belongs to the sort); the start-of-step positions are kept in
- * the context for pic_project.  J is not touched. */
+ * condition belongs to the sort), except that they are mirrored at
+ * reflecting walls; the start-of-step positions are kept in the context
+ * for pic_project.  J is not touched. */
 pic_status pic_interp_push(pic_ctx *ctx, pic_species *sp, int32_t nsp, const pic_fields *f,
                            void *stream);
 
 /* Projection (paper: the fourth operator): J += Esirkepov deposit of every
  * particle's move from the positions saved by the preceding pic_interp_push
  * on this context to the current (unwrapped) positions.  Does not zero J.
+ * A particle outside a removing axis deposits nothing (pic_bin deletes it).
  * PIC_ERR_STATE without a preceding pic_interp_push. */
 pic_status pic_project(pic_ctx *ctx, const pic_species *sp, int32_t nsp, pic_fields *f,
                        void *stream);
@@ -235,7 +241,8 @@ pic_status pic_project(pic_ctx *ctx, const pic_species *sp, int32_t nsp, pic_fie
  * (patch, particle range) units from a device queue.  With PIC_FLAG_GRAPH
  * (and timing off) the steps replay a captured HIP graph (one step in the
  * slab layout, two otherwise).  The context owns an outbox of capacity
- * particles per species for the slab layout. */
+ * particles per species for the slab layout.  With removing walls every
+ * call takes the slab layout and updates sp[s].n on return. */
 pic_status pic_step(pic_ctx *ctx, pic_species *sp, int32_t nsp, pic_fields *f, int32_t nsteps,
                     void *stream);
 
