@@ -367,6 +367,28 @@ def cpu_baseline(sample_steps: int):
             "seconds": round(dt, 3)}
 
 
+def copy_bandwidth(gib: float = 2.0, reps: int = 5) -> float:
+    """Measured HBM bandwidth of a plain float64 device-to-device copy of
+    `gib` GiB (bytes read plus bytes written per second, in GB/s), timed
+    with events on the current stream after one untimed copy."""
+    import torch
+
+    n = int(gib * 2 ** 30 / 8)
+    src = torch.rand(n, dtype=torch.float64, device="cuda:0")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    t1.record()
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1) / reps
+    del src, dst
+    torch.cuda.empty_cache()
+    return 2 * n * 8 / (ms * 1e-3) / 1e9
+
+
 def copy_calibration(gib: float) -> int:
     """A plain float64 device-to-device copy of known size: reads and writes
     `gib` GiB each per launch."""
@@ -424,6 +446,7 @@ def main(argv=None) -> int:
     abytes = algorithmic_bytes(wl, n)
     achieved = abytes / (ipp_avg * 1e-3) / 1e9
     traffic = measured_traffic(args.workload)
+    copy_bw = copy_bandwidth()
     per_kernel = {k: round(v[0] / max(v[1], 1), 4) for k, v in tim.items() if v[1]}
     out = {
         "metric": METRIC,
@@ -443,7 +466,11 @@ def main(argv=None) -> int:
                    "species": len(wl.species), "mode": "per_patch", "layout": "slab"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": FUSED_KERNEL, "algorithmic_bytes": abytes, "avg_ms": ipp_avg},
+                     "kernel": FUSED_KERNEL, "algorithmic_bytes": abytes, "avg_ms": ipp_avg,
+                     # the same achieved rate against a measured plain copy
+                     "copy_GBps_measured": copy_bw, "frac_of_copy": achieved / copy_bw,
+                     # bytes the counters saw per launch, per second of the kernel
+                     "traffic_GBps": (traffic / (ipp_avg * 1e-3) / 1e9) if traffic else None},
         "kernel_ms": per_kernel,
         "interp_push_project_rate": n / (ipp_avg * 1e-3),
     }
