@@ -69,6 +69,24 @@ def measured_traffic(workload: str):
     return t.get("bytes_per_launch")
 
 
+FP64_PEAK_TFLOPS = 78.6  # MI355X float64 vector peak
+
+
+def measured_valu(workload: str):
+    """Per-particle float64 operations and LDS instructions of the 3D fused
+    kernel from the committed rocprofv3 counter summary, if it was taken on
+    the current kernel source."""
+    path = os.path.join(ROOT, "profiles", "k_ipp_slab3d_expansion3d_valu.json")
+    try:
+        with open(path) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if t.get("workload") != workload or t.get("kernel_source_sha") != kernel_source_hash():
+        return None
+    return t
+
+
 def cpu_model() -> str:
     try:
         with open("/proc/cpuinfo") as fh:
@@ -151,7 +169,18 @@ def run_expansion3d(steps: int, warmup: int):
     ipp_pp = t_pp["ipp"][0] / t_pp["ipp"][1]
     ipp_pe = t_pe["ipp"][0] / t_pe["ipp"][1]
     abytes = algorithmic_bytes(wl, n)
-    return {"workload": "expansion3d", "particles": n, "species": 2, "steps": steps,
+    # float64 vector roofline: executed operations per particle (counters)
+    # over the faster launch's average fused-kernel duration
+    valu = measured_valu("expansion3d")
+    alu = None
+    if valu:
+        tf = valu["fp64_flops_per_particle"] * n / (min(ipp_pp, ipp_pe) * 1e-3) / 1e12
+        alu = {"bound": "alu", "achieved": tf, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+               "frac": tf / FP64_PEAK_TFLOPS,
+               "fp64_flops_per_particle": valu["fp64_flops_per_particle"],
+               "lds_instructions_per_particle": valu["lds_per_particle"],
+               "lds_instructions_per_s": valu["lds_per_particle"] * n / (min(ipp_pp, ipp_pe) * 1e-3)}
+    return {"workload": "expansion3d", "particles": n, "species": 2, "steps": steps, "alu": alu,
             "per_patch": {"ns_per_particle_step": s_pp / (n * steps) * 1e9, "ipp_ms": ipp_pp},
             "persistent": {"ns_per_particle_step": s_pe / (n * steps) * 1e9, "ipp_ms": ipp_pe,
                            "chunk": tuned["chunk"], "wg": tuned["wg"],
