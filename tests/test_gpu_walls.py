@@ -308,3 +308,35 @@ def test_remove_in_the_self_consistent_loop():
     assert np.array_equal(sp[0].offset.cpu().numpy(), sps[0].off)
     assert np.array_equal(np.sort(sp[0].ids.cpu().numpy()), np.sort(sps[0].id))
     ctx.close()
+
+
+def test_remove_every_particle_then_step_again():
+    """Every particle flies at 0.98 c towards a removing wall: after enough
+    steps none is left (n = 0, every offset 0, as in the oracle), and a
+    further call on the empty species runs and deposits nothing."""
+    import torch
+
+    from paper_2204_12837_amd import pic
+
+    wl = _bcs(I.custom(2, (16, 16), (8, 8), ppc=3, seed=530), (2, 0))
+    inp = I.generate(wl)
+    inp.E[:] = 0
+    inp.B[:] = 0
+    inp.species[0].u[0] = 5.0
+    steps = 30  # 16 cells of 0.1 at 0.98 c and dt 0.067: all gone after 25
+    osp, J, A = run_oracle(wl, inp, steps)
+    assert osp[0].n == 0 and not osp[0].off.any()
+    say("case remove everything")
+    ctx = pic.Context(wl, check=True)
+    sp = pic.upload(inp, "cuda:0", n_slabs=ctx.n_slabs)
+    E, B, Jg = pic.upload_fields(inp, "cuda:0")
+    ctx.bin(sp)
+    ctx.step(sp, E, B, Jg, nsteps=steps)
+    torch.cuda.synchronize()
+    ctx.check()
+    assert sp[0].n == 0 and not sp[0].offset.cpu().numpy().any()
+    ctx.step(sp, E, B, Jg, nsteps=2)
+    torch.cuda.synchronize()
+    ctx.check()
+    assert sp[0].n == 0 and not Jg.cpu().numpy().any()
+    ctx.close()
