@@ -145,8 +145,9 @@ typedef struct {
                           (its particles are the first n of the arrays, as
                           always); pic_step and pic_cycle need buffers with
                           the slab layout's room for every call length
-                          (PIC_ERR_CAPACITY otherwise); pic_adjoint rejects
-                          the configuration (PIC_ERR_ARG). */
+                          (PIC_ERR_CAPACITY otherwise).  In pic_adjoint a
+                          particle deleted inside the segment contributes
+                          nothing: its cotangents are zero. */
 } pic_config;
 
 typedef struct {

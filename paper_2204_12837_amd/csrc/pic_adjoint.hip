@@ -391,9 +391,10 @@ __global__ void __launch_bounds__(128) k_adjoint(GridDev g, AdjArgs aa, AdjField
   double u[3] = {S.u[0][p], S.u[1][p], S.u[2][p]};
   double xlast[2] = {0, 0}, xend[2] = {0, 0}, vend[3] = {0, 0, 0};
   uint32_t hits = 0;  // axes mirrored at a wall, two bits per step
+  bool gone = false;  // deleted at a removing wall inside the segment
 #pragma unroll
   for (int k = 0; k < kAdjMaxSteps; k++) {
-    if (k < nsteps) {
+    if (k < nsteps && !gone) {
       xs[k][0] = x[0];
       xs[k][1] = x[1];
       us[k][0] = u[0];
@@ -403,7 +404,11 @@ __global__ void __launch_bounds__(128) k_adjoint(GridDev g, AdjArgs aa, AdjField
       interp_g(g, f, x, F);
       boris_f(S.alpha, F, u, v);
       double x1[3] = {x[0] + g.dt * v[0], x[1] + g.dt * v[1], 0.0};
-      if (g.reflect) hits |= (uint32_t)wall_bc<2>(g, x1, u) << (2 * k);  // no removing walls here
+      if (g.reflect | g.remove) {
+        const int h = wall_bc<2>(g, x1, u);
+        gone = h < 0;
+        if (!gone) hits |= (uint32_t)h << (2 * k);
+      }
       if (k == nsteps - 1) {
         xlast[0] = x[0];
         xlast[1] = x[1];
@@ -417,6 +422,11 @@ __global__ void __launch_bounds__(128) k_adjoint(GridDev g, AdjArgs aa, AdjField
       x[0] = x1[0];
       x[1] = x1[1];
     }
+  }
+  if (gone) {  // no later state and no deposit: nothing depends on its start
+    S.xb[0][id] = S.xb[1][id] = 0.0;
+    S.ub[0][id] = S.ub[1][id] = S.ub[2][id] = 0.0;
+    return;
   }
   double xb[2], ub[3], vzb = 0.0;
   if (with_dep) {
@@ -624,8 +634,10 @@ __global__ void __launch_bounds__(256) k_adjoint_tiled(GridDev g, AdjArgs aa, Ad
     double u[3] = {S.u[0][p], S.u[1][p], S.u[2][p]};
     double xlast[2] = {0, 0}, xend[2] = {0, 0}, vend[3] = {0, 0, 0};
     uint32_t hits = 0;  // axes mirrored at a wall, two bits per step
+    bool gone = false;  // deleted at a removing wall inside the segment
 #pragma unroll
     for (int k = 0; k < NS; k++) {
+      if (gone) break;
       xs[k][0] = x[0];
       xs[k][1] = x[1];
       us[k][0] = u[0];
@@ -635,7 +647,11 @@ __global__ void __launch_bounds__(256) k_adjoint_tiled(GridDev g, AdjArgs aa, Ad
       interp_t(g, t, f, x, F);
       boris_f(S.alpha, F, u, v);
       double x1[3] = {x[0] + g.dt * v[0], x[1] + g.dt * v[1], 0.0};
-      if (g.reflect) hits |= (uint32_t)wall_bc<2>(g, x1, u) << (2 * k);  // no removing walls here
+      if (g.reflect | g.remove) {
+        const int h = wall_bc<2>(g, x1, u);
+        gone = h < 0;
+        if (!gone) hits |= (uint32_t)h << (2 * k);
+      }
       if (k == NS - 1) {
         xlast[0] = x[0];
         xlast[1] = x[1];
@@ -648,6 +664,11 @@ __global__ void __launch_bounds__(256) k_adjoint_tiled(GridDev g, AdjArgs aa, Ad
       wrap2(g, x1);
       x[0] = x1[0];
       x[1] = x1[1];
+    }
+    if (gone) {  // no later state and no deposit: nothing depends on its start
+      S.xb[0][id] = S.xb[1][id] = 0.0;
+      S.ub[0][id] = S.ub[1][id] = S.ub[2][id] = 0.0;
+      continue;
     }
     double xb[2], ub[3], vzb = 0.0;
     if (with_dep) {

@@ -1283,8 +1283,6 @@ pic_status pic_adjoint(pic_ctx *c, const pic_species *ck, int32_t nsp, const pic
   if (!c) return PIC_ERR_ARG;
   if (c->poisoned) return fail(c, PIC_ERR_STATE, "context unusable after a device error");
   if (c->cfg.dim != 2) return fail(c, PIC_ERR_ARG, "pic_adjoint supports 2D3V only");
-  if (c->g.remove)
-    return fail(c, PIC_ERR_ARG, "pic_adjoint does not differentiate through removing walls");
   if (!ck || nsp < 1 || nsp > kMaxSpecies || !cot)
     return fail(c, PIC_ERR_ARG, "bad species or cotangent arguments");
   if (nsteps < 1 || nsteps > kAdjMaxSteps)

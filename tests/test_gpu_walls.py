@@ -222,14 +222,11 @@ def test_remove_3d_two_species(mode):
     _remove_case(wl, 4, **kw)
 
 
-def test_remove_needs_slab_room_and_no_adjoint():
-    import torch
-
-    from paper_2204_12837_amd import adjoint as ADJ
+def test_remove_needs_slab_room():
     from paper_2204_12837_amd import pic
 
     wl = _bcs(I.custom(2, (16, 16), (8, 8), ppc=2, seed=527, steps=2), (2, 0))
-    inp = I.generate(wl, with_W=True)
+    inp = I.generate(wl)
     ctx = pic.Context(wl, device=0, check=True)
     sp = pic.upload(inp, "cuda:0", capacity_factor=1.0)
     E, B, J = pic.upload_fields(inp, "cuda:0")
@@ -238,16 +235,54 @@ def test_remove_needs_slab_room_and_no_adjoint():
         ctx.step(sp, E, B, J, nsteps=1)
     assert e.value.status == pic.PIC_ERR_CAPACITY
     ctx.close()
+
+
+@pytest.mark.parametrize("every", [3, 7])
+def test_remove_adjoint_matches_oracle_jvp(every):
+    """Reverse mode with removing walls: particles deleted inside a segment
+    contribute nothing (zero cotangents), the others through every step;
+    <grad, d> equals the oracle's tangent, which deletes the same particles
+    (checkpoints every 3 steps: deletions inside and across segments)."""
+    import torch
+
+    from paper_2204_12837_amd import adjoint as ADJ
+
+    wl = _bcs(I.custom(2, (32, 32), (8, 8), ppc=4, seed=531, sigma=0.5, bz0=1.0, steps=7),
+              (2, 1))
+    inp = I.generate(wl, with_W=True)
     s = inp.species[0]
     dev = "cuda:0"
-    with pytest.raises(RuntimeError) as e:  # raised inside autograd's backward
-        run = ADJ.StepRun(wl, torch.from_numpy(s.x).to(dev), torch.from_numpy(s.wt).to(dev),
-                          torch.from_numpy(s.id).to(dev), s.q, s.m, wl.steps, 2)
-        u0 = torch.from_numpy(s.u).to(dev).requires_grad_(True)
-        Jt = ADJ.PicSteps.apply(u0, torch.from_numpy(inp.E).to(dev), torch.from_numpy(inp.B).to(dev),
-                                run)
-        (torch.from_numpy(inp.W).to(dev) * Jt).sum().backward()
-    assert "removing walls" in str(e.value)
+    run = ADJ.StepRun(wl, torch.from_numpy(s.x).to(dev), torch.from_numpy(s.wt).to(dev),
+                      torch.from_numpy(s.id).to(dev), s.q, s.m, wl.steps, every)
+    u0 = torch.from_numpy(s.u).to(dev).requires_grad_(True)
+    E = torch.from_numpy(inp.E).to(dev).requires_grad_(True)
+    B = torch.from_numpy(inp.B).to(dev).requires_grad_(True)
+    W = torch.from_numpy(inp.W).to(dev)
+    say(f"case remove adjoint every={every}")
+    J = ADJ.PicSteps.apply(u0, E, B, run)
+    (W * J).sum().backward()
+    torch.cuda.synchronize()
+    run.ctx.check()
+    gu, gE, gB = u0.grad.cpu().numpy(), E.grad.cpu().numpy(), B.grad.cpu().numpy()
+    rng = np.random.default_rng(532)
+    du = rng.normal(size=s.u.shape)
+    dE = rng.normal(size=inp.E.shape)
+    dB = rng.normal(size=inp.B.shape)
+    Jo, dJ = O.jvp(wl, s.q, s.m, s.x, s.u, s.wt, inp.E, inp.B, du, dE, dB)
+    ref = math.fsum((inp.W * dJ).ravel())
+    terms = [gu * du, gE * dE, gB * dB]
+    got = math.fsum(math.fsum(t.ravel()) for t in terms)
+    scale = math.fsum(math.fsum(np.abs(t).ravel()) for t in terms)
+    assert abs(got - ref) <= 1e-11 * scale, (got, ref, scale)
+    assert np.max(np.abs(J.detach().cpu().numpy() - Jo)) <= 1e-12 * np.abs(Jo).max()
+    # deleted particles have exactly zero momentum gradients, and there are many
+    osp = O.species_from(inp)
+    O.bin(wl, osp[0])
+    for _ in range(wl.steps):
+        O.step(wl, osp, inp.E, inp.B)
+    gone = ~np.isin(s.id, osp[0].id)
+    assert gone.sum() > 20
+    assert not gu[:, gone].any() and np.abs(gu[:, ~gone]).max() > 0
 
 
 def test_remove_bin_deletes_positions_outside_the_box():
