@@ -258,7 +258,9 @@ def _stream():
 
 
 class Context:
-    """A library context (pic_init / pic_free)."""
+    """A library context (pic_init / pic_free) for the workload's grid,
+    patches and particle boundaries (wl.particle_bc, BC_* per axis; with
+    BC_REMOVE the calls that delete particles update each Species.n)."""
 
     def __init__(self, wl, device: int = 0, mode=MODE_PER_PATCH, chunk=0, wg_size=0,
                  check=False, graph=False, bin_x=0):
