@@ -1078,8 +1078,9 @@ def test_maxwell_adjoint_is_the_transpose(dim):
 
 
 def test_oracle_matches_its_stored_digest():
-    """Regression guard: the oracle's state after 10 steps of uniform64 equals
-    the digest written by tests/golden/make_golden.py (the paper prints no
+    """Regression guard: the oracle's state after 10 steps of uniform64, and
+    of a fast plasma between removing and reflecting walls, equals the digest
+    written by tests/golden/make_golden.py (the paper prints no
     worked example with values for these operators, so the golden file is
     the oracle's own, pinned output; a change to the oracle's arithmetic has
     to rewrite it on purpose)."""
@@ -1096,3 +1097,8 @@ def test_oracle_matches_its_stored_digest():
     with open(os.path.join(here, "oracle_uniform64_digest.json")) as fh:
         stored = json.load(fh)
     assert make_golden.digest() == stored
+    with open(os.path.join(here, "oracle_walls_digest.json")) as fh:
+        stored = json.load(fh)
+    got = make_golden.digest(walls=True)
+    assert got == stored
+    assert got["particles"] < 32 * 24 * 6  # particles were deleted
