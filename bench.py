@@ -191,6 +191,49 @@ def run_expansion3d(steps: int, warmup: int):
             "ipp_hbm_frac_best": abytes / (min(ipp_pp, ipp_pe) * 1e-3) / 1e9 / HBM_PEAK_GBS}
 
 
+def run_split(steps: int = 10):
+    """The split entry points on the uniform workload: per step J <- 0,
+    pic_interp_push, pic_project and pic_bin (the operators one call at a
+    time, the sort by neighbour code), timed per kernel class with the
+    library's HIP events."""
+    import torch
+
+    from paper_2204_12837_amd import inputs as I
+    from paper_2204_12837_amd import pic
+
+    wl = I.workload("uniform1024")
+    inp = I.generate(wl)
+    n = sum(s.x.shape[1] for s in inp.species)
+    ctx = pic.Context(wl, device=0)
+    sp = pic.upload(inp, "cuda:0", capacity_factor=1.0)
+    E, B, J = pic.upload_fields(inp, "cuda:0")
+    ctx.bin(sp)
+    for _ in range(2):  # warm-up
+        J.zero_()
+        ctx.interp_push(sp, E, B)
+        ctx.project(sp, J)
+        ctx.bin(sp)
+    torch.cuda.synchronize()
+    ctx.timing(True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        J.zero_()
+        ctx.interp_push(sp, E, B)
+        ctx.project(sp, J)
+        ctx.bin(sp)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ctx.check()
+    tim = ctx.timing_read()
+    ctx.timing(False)
+    ctx.close()
+    del sp, E, B, J
+    torch.cuda.empty_cache()
+    return {"workload": "uniform1024", "particles": n, "steps": steps,
+            "ms_per_step": (t1 - t0) / steps * 1e3,
+            "kernel_ms": {k: round(v[0] / max(v[1], 1), 4) for k, v in tim.items() if v[1]}}
+
+
 def run_large_patches(steps: int, warmup: int):
     """The uniform plasma with patches of 64 x 128 cells, whose E/B and J
     tiles exceed the LDS: the library cuts them into x-bins (per-patch
@@ -567,6 +610,7 @@ def main(argv=None) -> int:
         out["expansion3d"] = run_expansion3d(min(args.steps, 50), args.warmup)
     if not args.no_large_patches:
         out["large_patches"] = run_large_patches(min(args.steps, 50), args.warmup)
+    out["split_entry_points"] = run_split()
     if not args.no_maxwell:
         out["maxwell"] = run_maxwell()
         out["rho"] = run_rho()
