@@ -234,6 +234,43 @@ def run_split(steps: int = 10):
             "kernel_ms": {k: round(v[0] / max(v[1], 1), 4) for k, v in tim.items() if v[1]}}
 
 
+def run_short_calls(calls: int = 10):
+    """pic_step calls of one step each on the uniform workload: the dense
+    layout (fused kernel writing neighbour-code tags, then the counting
+    sort that restores per-patch order), as a caller that steps one at a
+    time sees it."""
+    import torch
+
+    from paper_2204_12837_amd import inputs as I
+    from paper_2204_12837_amd import pic
+
+    wl = I.workload("uniform1024")
+    inp = I.generate(wl)
+    n = sum(s.x.shape[1] for s in inp.species)
+    ctx = pic.Context(wl, device=0)
+    sp = pic.upload(inp, "cuda:0", capacity_factor=1.0)
+    E, B, J = pic.upload_fields(inp, "cuda:0")
+    ctx.bin(sp)
+    for _ in range(2):
+        ctx.step(sp, E, B, J, nsteps=1)
+    torch.cuda.synchronize()
+    ctx.timing(True)
+    t0 = time.perf_counter()
+    for _ in range(calls):
+        ctx.step(sp, E, B, J, nsteps=1)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ctx.check()
+    tim = ctx.timing_read()
+    ctx.timing(False)
+    ctx.close()
+    del sp, E, B, J
+    torch.cuda.empty_cache()
+    return {"workload": "uniform1024", "particles": n, "calls": calls, "layout": "dense",
+            "ms_per_step": (t1 - t0) / calls * 1e3,
+            "kernel_ms": {k: round(v[0] / max(v[1], 1), 4) for k, v in tim.items() if v[1]}}
+
+
 def run_large_patches(steps: int, warmup: int):
     """The uniform plasma with patches of 64 x 128 cells, whose E/B and J
     tiles exceed the LDS: the library cuts them into x-bins (per-patch
@@ -611,6 +648,7 @@ def main(argv=None) -> int:
     if not args.no_large_patches:
         out["large_patches"] = run_large_patches(min(args.steps, 50), args.warmup)
     out["split_entry_points"] = run_split()
+    out["one_step_calls"] = run_short_calls()
     if not args.no_maxwell:
         out["maxwell"] = run_maxwell()
         out["rho"] = run_rho()
