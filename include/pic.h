@@ -33,6 +33,8 @@
  *             scratch (keys, counts, saved positions, error word).
  *   Streams   work is enqueued on the given HIP stream (NULL = the null
  *             stream) and returns without waiting, except where stated.
+ *             The calls on one context share its scratch: issue them on
+ *             one stream (or order the streams), never concurrently.
  *   Errors    host-detectable errors (bad config, null pointer, count above
  *             capacity, wrong call order) return at once with nothing
  *             enqueued.  Errors found by kernels (a particle moving more than
