@@ -72,6 +72,21 @@ def measured_traffic(workload: str):
 FP64_PEAK_TFLOPS = 78.6  # MI355X float64 vector peak
 
 
+def measured_lds(workload: str):
+    """Per-particle LDS instructions and float64 LDS atomics of the 2D fused
+    kernel from the committed rocprofv3 counter summary, if it was taken on
+    the current kernel source."""
+    path = os.path.join(ROOT, "profiles", "k_ipp_slab_uniform1024_lds.json")
+    try:
+        with open(path) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if t.get("workload") != workload or t.get("kernel_source_sha") != kernel_source_hash():
+        return None
+    return t
+
+
 def measured_valu(workload: str):
     """Per-particle float64 operations and LDS instructions of the 3D fused
     kernel from the committed rocprofv3 counter summary, if it was taken on
@@ -560,6 +575,7 @@ def main(argv=None) -> int:
     achieved = abytes / (ipp_avg * 1e-3) / 1e9
     traffic = measured_traffic(args.workload)
     copy_bw = copy_bandwidth()
+    lds = measured_lds(args.workload)
     per_kernel = {k: round(v[0] / max(v[1], 1), 4) for k, v in tim.items() if v[1]}
     out = {
         "metric": METRIC,
@@ -583,7 +599,11 @@ def main(argv=None) -> int:
                      # the same achieved rate against a measured plain copy
                      "copy_GBps_measured": copy_bw, "frac_of_copy": achieved / copy_bw,
                      # bytes the counters saw per launch, per second of the kernel
-                     "traffic_GBps": (traffic / (ipp_avg * 1e-3) / 1e9) if traffic else None},
+                     "traffic_GBps": (traffic / (ipp_avg * 1e-3) / 1e9) if traffic else None,
+                     # the second ceiling: float64 LDS atomic adds per second
+                     "lds_atomics_per_particle": lds["lds_atomics_per_particle"] if lds else None,
+                     "lds_atomics_per_s": (lds["lds_atomics_per_particle"] * n / (ipp_avg * 1e-3))
+                     if lds else None},
         "kernel_ms": per_kernel,
         "with_kernel_events": {"ms_per_step": secs_ev / args.steps * 1e3},
         "interp_push_project_rate": n / (ipp_avg * 1e-3),
