@@ -10,6 +10,7 @@ from __future__ import annotations
 import os
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
@@ -42,16 +43,22 @@ def _stale(out: str, deps) -> bool:
 def build(force: bool = True, verbose: bool = False) -> str:
     os.makedirs(os.path.join(CSRC, "_build"), exist_ok=True)
     hdrs = [h if os.path.isabs(h) else os.path.join(CSRC, h) for h in HEADERS]
-    objs = []
+    objs, cmds = [], []
     for src in SOURCES:
         s = os.path.join(CSRC, src)
         o = _obj(src)
         objs.append(o)
         if force or _stale(o, [s, *hdrs]):
-            cmd = [HIPCC, *FLAGS, "-c", s, "-o", o]
-            if verbose:
-                print(" ".join(cmd), flush=True)
-            subprocess.run(cmd, check=True)
+            cmds.append([HIPCC, *FLAGS, "-c", s, "-o", o])
+
+    def compile_one(cmd):
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        subprocess.run(cmd, check=True)
+
+    # one hipcc per source, at most as many at once as there are CPUs (8 here)
+    with ThreadPoolExecutor(max_workers=min(len(cmds), os.cpu_count() or 1) or 1) as ex:
+        list(ex.map(compile_one, cmds))
     if force or _stale(LIB, objs):
         tmp = LIB + ".tmp"
         cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
