@@ -249,6 +249,28 @@ pic_status pic_project(pic_ctx *ctx, const pic_species *sp, int32_t nsp, pic_fie
 pic_status pic_step(pic_ctx *ctx, pic_species *sp, int32_t nsp, pic_fields *f, int32_t nsteps,
                     void *stream);
 
+/* pic_step without any device allocation, for callers that cannot
+ * allocate: code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc.  Same computation and result as pic_step in the
+ * dense layout (every step sorts by neighbour code; the order inside a patch
+ * stays that of the previous step), in the same buffers and with the same
+ * swap of the two buffer sets in *sp.  Its scratch (per species: 4 + 4
+ * bytes per particle, the per-segment code counts, per-patch arrays; in
+ * persistent mode the work units) is carved from a static device array of
+ * 64 MiB that the library holds on every GPU it runs on until the process
+ * ends -- about 6 million 2D particles in total (the exact need is
+ * reported in the error message).  Beyond that, PIC_ERR_CAPACITY with
+ * nothing enqueued.  Not for configurations with x-bins or removing walls
+ * (PIC_ERR_ARG: those need pic_step's allocating paths); PIC_FLAG_GRAPH is
+ * ignored and pic_timing_* do not cover these launches.
+ * Every call on one GPU shares that GPU's array, and each call starts by
+ * rebuilding what it needs there from the offsets: calls that overlap on
+ * one GPU (other contexts, other streams, other host threads) race and
+ * must be ordered by the caller.  Afterwards the other entry points on this
+ * context rebuild their own segment starts from the offsets. */
+pic_status pic_step_noalloc(pic_ctx *ctx, pic_species *sp, int32_t nsp, pic_fields *f,
+                            int32_t nsteps, void *stream);
+
 /* Field solver of the PIC loop (the paper's loop solves Maxwell's equations
  * on the grid with the current densities of the Projection as sources,
  * section "Parallelization without tasks"): nsteps steps of Yee's

@@ -9,6 +9,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <utility>
 #include <vector>
 
@@ -18,7 +19,31 @@
 
 using namespace pic;
 
+// Device scratch of pic_step_noalloc: one copy per GPU, held from the
+// library's load on that GPU until the process ends.  In host code this name
+// stands for a host-side symbol, not a device address: pic_init looks up
+// the address of the current GPU's copy with hipGetSymbolAddress once per
+// device, and only that address is ever passed to kernels.
+constexpr size_t kNoAllocBytes = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
 namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_noalloc_mu;
+void *g_noalloc_ptr[kMaxDevices] = {};
+
+// Device address of this GPU's copy of the static scratch (the device must
+// be current); nullptr if the lookup fails.
+void *noalloc_scratch(int device) {
+  if (device < 0 || device >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lk(g_noalloc_mu);
+  if (!g_noalloc_ptr[device]) {
+    void *p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) == hipSuccess) g_noalloc_ptr[device] = p;
+  }
+  return g_noalloc_ptr[device];
+}
 
 struct SpScratch {
   int64_t cap = 0;      // particle capacity the buffers below were sized for
@@ -105,6 +130,11 @@ struct pic_ctx {
   // pic_cycle: every step ends with a field step on the step's fields
   bool cycle = false;
   YeeArgs yee{};
+  // pic_step_noalloc: this device's static scratch; layout_stale: the
+  // segment starts and work units in sp[] do not describe the particles
+  // (pic_step_noalloc sorted them with its own scratch)
+  void *noalloc = nullptr;
+  bool layout_stale = false;
 };
 
 namespace {
@@ -300,13 +330,16 @@ pic_status ensure_scratch(pic_ctx *c, const pic_species *sp, int32_t nsp, bool x
   return PIC_OK;
 }
 
-int64_t max_segments(const pic_ctx *c, int32_t nsp) {
+int64_t max_segments(const SpScratch *scr, int32_t nsp) {
   int64_t m = 1;
-  for (int s = 0; s < nsp; s++) m = std::max(m, c->sp[s].maxseg);
+  for (int s = 0; s < nsp; s++) m = std::max(m, scr[s].maxseg);
   return m;
 }
 
-SpArgs make_args(pic_ctx *c, const pic_species *sp, int32_t nsp) {
+// Kernel arguments of the species with their scratch from scr (the
+// context's own, c->sp, unless a caller passes another set).
+SpArgs make_args(pic_ctx *c, const pic_species *sp, int32_t nsp, const SpScratch *scr = nullptr) {
+  if (!scr) scr = c->sp;
   SpArgs a{};
   a.nsp = nsp;
   for (int s = 0; s < nsp; s++) {
@@ -320,25 +353,25 @@ SpArgs make_args(pic_ctx *c, const pic_species *sp, int32_t nsp) {
       d.xa[k] = k < c->cfg.dim ? p.x_alt[k] : nullptr;
       d.u[k] = p.u[k];
       d.ua[k] = p.u_alt[k];
-      d.x0[k] = c->sp[s].x0[k];
+      d.x0[k] = scr[s].x0[k];
     }
     d.w = p.w;
     d.wa = p.w_alt;
     d.id = p.id;
     d.ida = p.id_alt;
     d.off = c->nb > 1 ? c->boff[s] : p.offset;
-    d.noff = c->sp[s].noff;
-    d.tag = c->sp[s].tag;
-    d.sstart = c->sp[s].sstart;
-    d.cnt = c->sp[s].cnt;
-    d.pre = c->sp[s].pre;
-    d.tot = c->sp[s].tot;
-    d.rbase = c->sp[s].rbase;
-    d.in = c->sp[s].in;
-    d.ubase = (int32_t)c->sp[s].ubase;
-    d.snext = c->sp[s].snext;
-    d.tmp = c->sp[s].tmp;
-    d.perm = c->sp[s].perm;
+    d.noff = scr[s].noff;
+    d.tag = scr[s].tag;
+    d.sstart = scr[s].sstart;
+    d.cnt = scr[s].cnt;
+    d.pre = scr[s].pre;
+    d.tot = scr[s].tot;
+    d.rbase = scr[s].rbase;
+    d.in = scr[s].in;
+    d.ubase = (int32_t)scr[s].ubase;
+    d.snext = scr[s].snext;
+    d.tmp = scr[s].tmp;
+    d.perm = scr[s].perm;
   }
   return a;
 }
@@ -432,23 +465,25 @@ bool fields_ok(const pic_ctx *c, const pic_fields *f, bool eb, bool j) {
 // materialize: the sort copies the particles into the other buffer set;
 // otherwise it only records the permutation.  The caller swaps the buffer
 // sets once per gather and once per materialize.
+// scr and units: the scratch and persistent work-unit list the kernels use.
 hipError_t enqueue_step(pic_ctx *c, const pic_species *sp, int32_t nsp, const pic_fields *f,
-                        hipStream_t st, bool gather, bool materialize) {
+                        hipStream_t st, bool gather, bool materialize, const SpScratch *scr,
+                        Unit *units) {
   int64_t ncell = 1;
   for (int a = 0; a < c->cfg.dim; a++) ncell *= c->cfg.n[a];
-  SpArgs a = make_args(c, sp, nsp);
+  SpArgs a = make_args(c, sp, nsp, scr);
   a.gather = gather ? 1 : 0;
   const bool pers = c->cfg.mode == PIC_MODE_PERSISTENT;
   hipError_t e = timed(c, PIC_KERNEL_ZERO, st, [&] { return launch_zero(f->j, ncell, st); });
   if (e == hipSuccess)
     e = timed(c, PIC_KERNEL_IPP, st, [&] {
-      return pers ? launch_ipp_persistent(c->g, a, f->e, f->b, f->j, c->err_dev, c->units,
-                                          c->qctl, c->pgrid, c->wgd, st)
+      return pers ? launch_ipp_persistent(c->g, a, f->e, f->b, f->j, c->err_dev, units, c->qctl,
+                                          c->pgrid, c->wgd, st)
                   : launch_ipp(c->g, a, f->e, f->b, f->j, c->err_dev, c->wgd, st);
     });
   if (e != hipSuccess) return e;
   // the sort reads the particles where the fused kernel wrote them
-  SpArgs r = make_args(c, sp, nsp);
+  SpArgs r = make_args(c, sp, nsp, scr);
   if (gather)
     for (int s = 0; s < nsp; s++) {
       std::swap(r.s[s].x, r.s[s].xa);
@@ -457,8 +492,8 @@ hipError_t enqueue_step(pic_ctx *c, const pic_species *sp, int32_t nsp, const pi
       std::swap(r.s[s].id, r.s[s].ida);
     }
   e = timed(c, PIC_KERNEL_REBIN, st, [&] {
-    hipError_t r2 = launch_rebin(c->g, r, c->err_dev, max_segments(c, nsp), !materialize, st);
-    if (r2 == hipSuccess && pers) r2 = launch_layout(c->g, r, c->units, c->qctl, st);
+    hipError_t r2 = launch_rebin(c->g, r, c->err_dev, max_segments(scr, nsp), !materialize, st);
+    if (r2 == hipSuccess && pers) r2 = launch_layout(c->g, r, units, c->qctl, st);
     return r2;
   });
   if (e == hipSuccess && c->cycle)
@@ -529,7 +564,7 @@ pic_status ensure_graph(pic_ctx *c, const pic_species *sp, int32_t nsp, const pi
     return hip_fail(c, e, "hipStreamBeginCapture");
   hipError_t eq = hipSuccess;
   for (int k = 0; k < 2 && eq == hipSuccess; k++) {
-    eq = enqueue_step(c, tmp, nsp, f, c->cap_stream, true, false);
+    eq = enqueue_step(c, tmp, nsp, f, c->cap_stream, true, false, c->sp, c->units);
     for (int s = 0; s < nsp; s++) swap_buffers(tmp[s]);
   }
   hipGraph_t g = nullptr;
@@ -801,7 +836,7 @@ pic_status sort_species(pic_ctx *c, pic_species *sp, int32_t nsp, bool general, 
         timed(c, PIC_KERNEL_TAG, st, [&] { return launch_tag(c->g, a, c->err_dev, c->wgd, st); });
     if (e == hipSuccess)
       e = timed(c, PIC_KERNEL_REBIN, st, [&] {
-        return launch_rebin(c->g, a, c->err_dev, max_segments(c, nsp), false, st);
+        return launch_rebin(c->g, a, c->err_dev, max_segments(c->sp, nsp), false, st);
       });
     if (e != hipSuccess) return hip_fail(c, e, "kernel launch");
   } else {
@@ -823,6 +858,54 @@ pic_status sort_species(pic_ctx *c, pic_species *sp, int32_t nsp, bool general, 
   }
   for (int s = 0; s < nsp; s++) swap_buffers(sp[s]);
   c->moved = false;
+  return PIC_OK;
+}
+
+// pic_step in the dense layout: the first step updates the particles in
+// place and records the sort as a permutation; middle steps gather through
+// it into the other buffer set; the last step's sort copies the particles
+// into their sorted places, so between calls the arrays are always sorted.
+// scr and units: the scratch and work-unit list the kernels use; graphs:
+// middle steps may replay a captured graph (PIC_FLAG_GRAPH).
+pic_status step_dense(pic_ctx *c, pic_species *sp, int32_t nsp, const pic_fields *f,
+                      int32_t nsteps, hipStream_t st, const SpScratch *scr, Unit *units,
+                      bool graphs) {
+  pic_status r;
+  auto step = [&](bool gather, bool materialize) -> pic_status {
+    hipError_t e = enqueue_step(c, sp, nsp, f, st, gather, materialize, scr, units);
+    if (e != hipSuccess) return hip_fail(c, e, "kernel launch");
+    for (int s = 0; s < nsp; s++) {
+      if (gather) swap_buffers(sp[s]);
+      if (materialize) swap_buffers(sp[s]);
+    }
+    return PIC_OK;
+  };
+  if ((r = step(false, nsteps == 1)) != PIC_OK) return r;
+  int middle = nsteps - 2;  // steps 1 .. nsteps-2
+  if (graphs && (c->cfg.flags & PIC_FLAG_GRAPH) && !c->tm.on && middle >= 2) {
+    hipGraphExec_t x = nullptr;
+    if ((r = ensure_graph(c, sp, nsp, f, &x)) != PIC_OK) return r;
+    for (; middle >= 2; middle -= 2) {
+      hipError_t e = hipGraphLaunch(x, st);
+      if (e != hipSuccess) return hip_fail(c, e, "hipGraphLaunch");
+    }
+  }
+  for (; middle > 0; middle--)
+    if ((r = step(true, false)) != PIC_OK) return r;
+  if (nsteps >= 2 && (r = step(true, true)) != PIC_OK) return r;
+  return PIC_OK;
+}
+
+// The context's segment starts (and persistent work units) are recomputed
+// from the caller's offsets when another scratch set last sorted the
+// particles (pic_step_noalloc).
+pic_status refresh_layout(pic_ctx *c, const pic_species *sp, int32_t nsp, hipStream_t st) {
+  if (!c->layout_stale) return PIC_OK;
+  const SpArgs a = make_args(c, sp, nsp);
+  const hipError_t e = launch_layout(
+      c->g, a, c->cfg.mode == PIC_MODE_PERSISTENT ? c->units : nullptr, c->qctl, st);
+  if (e != hipSuccess) return hip_fail(c, e, "kernel launch");
+  c->layout_stale = false;
   return PIC_OK;
 }
 
@@ -1001,6 +1084,7 @@ pic_status pic_init(const pic_config *cfg, int32_t device, pic_ctx **out) {
     return PIC_ERR_HIP;
   }
   if (c->cfg.mode == PIC_MODE_PERSISTENT) c->pgrid = persistent_grid(c->g, c->wgd);
+  c->noalloc = noalloc_scratch(device);  // checked by pic_step_noalloc
   *out = c;
   return PIC_OK;
 }
@@ -1116,6 +1200,7 @@ pic_status pic_interp_push(pic_ctx *c, pic_species *sp, int32_t nsp, const pic_f
   hipStream_t st = (hipStream_t)stream;
   if (hipSetDevice(c->device) != hipSuccess) return fail(c, PIC_ERR_HIP, "hipSetDevice");
   if ((r = ensure_scratch(c, sp, nsp, true, st)) != PIC_OK) return r;
+  if ((r = refresh_layout(c, sp, nsp, st)) != PIC_OK) return r;
   // x-bins: the particles arrive sorted by patch; the kernels need them by bin
   if (c->nb > 1 && (r = sort_species(c, sp, nsp, true, st)) != PIC_OK) return r;
   const SpArgs a = make_args(c, sp, nsp);
@@ -1154,6 +1239,7 @@ pic_status pic_step(pic_ctx *c, pic_species *sp, int32_t nsp, pic_fields *f, int
   hipStream_t st = (hipStream_t)stream;
   if (hipSetDevice(c->device) != hipSuccess) return fail(c, PIC_ERR_HIP, "hipSetDevice");
   if ((r = ensure_scratch(c, sp, nsp, false, st)) != PIC_OK) return r;
+  if ((r = refresh_layout(c, sp, nsp, st)) != PIC_OK) return r;
   if (nsteps == 0) return finish(c, st);
   // x-bins: the particles arrive sorted by patch; the kernels need them by bin
   if (c->nb > 1 && (r = sort_species(c, sp, nsp, true, st)) != PIC_OK) return r;
@@ -1165,32 +1251,7 @@ pic_status pic_step(pic_ctx *c, pic_species *sp, int32_t nsp, pic_fields *f, int
   if ((nsteps >= 3 || c->g.remove) && slab_fits(c, sp, nsp)) {
     if ((r = step_slab(c, sp, nsp, f, nsteps, st)) != PIC_OK) return r;
   } else {
-    // The first step updates the particles in place and records the sort as
-    // a permutation; middle steps gather through it into the other buffer
-    // set; the last step's sort copies the particles into their sorted
-    // places, so between calls the arrays are always sorted.
-    auto step = [&](bool gather, bool materialize) -> pic_status {
-      hipError_t e = enqueue_step(c, sp, nsp, f, st, gather, materialize);
-      if (e != hipSuccess) return hip_fail(c, e, "kernel launch");
-      for (int s = 0; s < nsp; s++) {
-        if (gather) swap_buffers(sp[s]);
-        if (materialize) swap_buffers(sp[s]);
-      }
-      return PIC_OK;
-    };
-    if ((r = step(false, nsteps == 1)) != PIC_OK) return r;
-    int middle = nsteps - 2;  // steps 1 .. nsteps-2
-    if ((c->cfg.flags & PIC_FLAG_GRAPH) && !c->tm.on && middle >= 2) {
-      hipGraphExec_t x = nullptr;
-      if ((r = ensure_graph(c, sp, nsp, f, &x)) != PIC_OK) return r;
-      for (; middle >= 2; middle -= 2) {
-        hipError_t e = hipGraphLaunch(x, st);
-        if (e != hipSuccess) return hip_fail(c, e, "hipGraphLaunch");
-      }
-    }
-    for (; middle > 0; middle--)
-      if ((r = step(true, false)) != PIC_OK) return r;
-    if (nsteps >= 2 && (r = step(true, true)) != PIC_OK) return r;
+    if ((r = step_dense(c, sp, nsp, f, nsteps, st, c->sp, c->units, true)) != PIC_OK) return r;
   }
   const hipError_t e = api_offsets(c, sp, nsp, st);
   if (e != hipSuccess) return hip_fail(c, e, "kernel launch");
@@ -1198,6 +1259,78 @@ pic_status pic_step(pic_ctx *c, pic_species *sp, int32_t nsp, pic_fields *f, int
   return update_counts(c, sp, nsp, st);
 }
 
+
+pic_status pic_step_noalloc(pic_ctx *c, pic_species *sp, int32_t nsp, pic_fields *f,
+                            int32_t nsteps, void *stream) {
+  pic_status r = check_species(c, sp, nsp, true);
+  if (r != PIC_OK) return r;
+  if (!fields_ok(c, f, true, true)) return fail(c, PIC_ERR_ARG, "null field pointer");
+  if (nsteps < 0) return fail(c, PIC_ERR_ARG, "nsteps < 0");
+  if (c->moved) return fail(c, PIC_ERR_STATE, "pic_step_noalloc with a sort pending (call pic_bin)");
+  if (c->nb > 1)
+    return fail(c, PIC_ERR_ARG, "pic_step_noalloc: x-bins need the per-call bin sort (pic_step)");
+  if (c->g.remove)
+    return fail(c, PIC_ERR_ARG, "pic_step_noalloc: removing walls need the slab layout (pic_step)");
+  if (!c->noalloc) return fail(c, PIC_ERR_HIP, "pic_step_noalloc: no static scratch on this device");
+  // the dense layout's scratch, carved from the static array in 256-byte
+  // aligned pieces: per species the tags and permutation (n each), the
+  // per-segment code counts and prefixes, the per-patch arrays; in
+  // persistent mode the work units of every species after them
+  const size_t np = (size_t)c->g.npatch, nc = (size_t)c->g.nc;
+  char *base = static_cast<char *>(c->noalloc);
+  size_t used = 0;
+  auto take = [&](size_t bytes) -> void * {
+    used = (used + 255) & ~(size_t)255;
+    void *p = base + used;
+    used += std::max<size_t>(bytes, 1);
+    return p;
+  };
+  SpScratch v[kMaxSpecies];
+  int64_t nunits = 0;
+  for (int s = 0; s < nsp; s++) {
+    SpScratch &S = v[s];
+    const size_t n = (size_t)sp[s].n;
+    const size_t maxseg = np + n / kSeg + 1;
+    S.cap = (int64_t)n;
+    S.maxseg = (int64_t)maxseg;
+    S.tag = static_cast<uint32_t *>(take(n * sizeof(uint32_t)));
+    S.perm = static_cast<int32_t *>(take(n * sizeof(int32_t)));
+    S.cnt = static_cast<int32_t *>(take(maxseg * kCntRow * sizeof(int32_t)));
+    S.pre = static_cast<int32_t *>(take(maxseg * nc * sizeof(int32_t)));
+    S.sstart = static_cast<int32_t *>(take((np + 1) * sizeof(int32_t)));
+    S.snext = static_cast<int32_t *>(take((np + 1) * sizeof(int32_t)));
+    S.tmp = static_cast<int64_t *>(take((np + 1) * sizeof(int64_t)));
+    S.tot = static_cast<int32_t *>(take(np * nc * sizeof(int32_t)));
+    S.rbase = static_cast<int64_t *>(take(np * nc * sizeof(int64_t)));
+    S.in = static_cast<int64_t *>(take(np * sizeof(int64_t)));
+    S.noff = static_cast<int64_t *>(take((np + 1) * sizeof(int64_t)));
+    S.maxunits = (int64_t)np + ((int64_t)maxseg + c->g.spc - 1) / c->g.spc + 1;
+    S.ubase = nunits;
+    nunits += S.maxunits;
+  }
+  const bool pers = c->cfg.mode == PIC_MODE_PERSISTENT;
+  Unit *units = pers ? static_cast<Unit *>(take((size_t)nunits * sizeof(Unit))) : nullptr;
+  if (used > kNoAllocBytes)
+    return fail(c, PIC_ERR_CAPACITY,
+                "pic_step_noalloc: these particles need %zu bytes of scratch, the static "
+                "array holds %zu",
+                used, kNoAllocBytes);
+  hipStream_t st = (hipStream_t)stream;
+  if (hipSetDevice(c->device) != hipSuccess) return fail(c, PIC_ERR_HIP, "hipSetDevice");
+  if (nsteps == 0) return finish(c, st);
+  // the static array holds whatever the last call on this GPU left there:
+  // segment starts (and work units, with a zero ticket) from the offsets
+  hipError_t e = launch_layout(c->g, make_args(c, sp, nsp, v), units, c->qctl, st);
+  if (e != hipSuccess) return hip_fail(c, e, "kernel launch");
+  // no timing events (their creation may allocate), no graph capture
+  const bool timing = c->tm.on;
+  c->tm.on = false;
+  r = step_dense(c, sp, nsp, f, nsteps, st, v, units, false);
+  c->tm.on = timing;
+  c->layout_stale = true;  // the context's own scratch no longer matches
+  if (r != PIC_OK) return r;
+  return finish(c, st);
+}
 
 pic_status pic_rho(pic_ctx *c, const pic_species *sp, int32_t nsp, double *rho, void *stream) {
   if (!c) return PIC_ERR_ARG;

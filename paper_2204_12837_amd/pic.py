@@ -59,7 +59,7 @@ ENTRY_POINTS = ("pic_validate_config", "pic_num_patches", "pic_bin_width", "pic_
                 "pic_bin",
                 "pic_interp_push", "pic_project", "pic_step", "pic_check", "pic_last_error",
                 "pic_timing_enable", "pic_timing_read", "pic_adjoint", "pic_maxwell",
-                "pic_maxwell_adjoint", "pic_rho", "pic_cycle")
+                "pic_maxwell_adjoint", "pic_rho", "pic_cycle", "pic_step_noalloc")
 KERNELS = {"zero": 0, "ipp": 1, "rebin": 2, "interp_push": 3, "project": 4, "tag": 5, "sort": 6,
            "adjoint": 7, "exchange": 8, "slab": 9, "maxwell": 10, "rho": 11}
 
@@ -95,6 +95,8 @@ def lib():
         L.pic_step.argtypes = [C.c_void_p, C.POINTER(SpeciesC), C.c_int32, C.POINTER(FieldsC),
                                C.c_int32, C.c_void_p]
         L.pic_step.restype = C.c_int
+        L.pic_step_noalloc.argtypes = L.pic_step.argtypes
+        L.pic_step_noalloc.restype = C.c_int
         L.pic_check.argtypes = [C.c_void_p, C.c_void_p]
         L.pic_check.restype = C.c_int
         L.pic_timing_enable.argtypes = [C.c_void_p, C.c_int32]
@@ -313,6 +315,12 @@ class Context:
     def step(self, species: Sequence[Species], E, B, J, nsteps: int = 1):
         f = fields_struct(E, B, J)
         self._call_sp(lib().pic_step, species, C.byref(f), int(nsteps), _stream())
+
+    def step_noalloc(self, species: Sequence[Species], E, B, J, nsteps: int = 1):
+        """pic_step_noalloc: pic_step in the dense layout with the library's
+        static device scratch (no allocation)."""
+        f = fields_struct(E, B, J)
+        self._call_sp(lib().pic_step_noalloc, species, C.byref(f), int(nsteps), _stream())
 
     def check(self):
         self._raise(lib().pic_check(self._h, _stream()))
