@@ -131,7 +131,9 @@ def run_gpu(wl, steps: int, warmup: int, mode: int = 0, chunk: int = 0, wg: int 
     E, B, J = pic.upload_fields(inp, "cuda:0")
     ctx.bin(sp)
     if warmup:
-        ctx.step(sp, E, B, J, nsteps=warmup)
+        # at least three steps, so that the slab layout's kernels (which
+        # calls of one or two steps do not use) are loaded before the timing
+        ctx.step(sp, E, B, J, nsteps=max(warmup, 3))
     torch.cuda.synchronize()
     ctx.check()
     timed = timing and not graph

@@ -113,8 +113,10 @@ typedef struct {
                           patch[0] if its tiles fit, else the widest divisor
                           of patch[0] whose tiles fit.  With more than one
                           bin per patch, the particles inside a patch are
-                          ordered by bin, and pic_step and pic_interp_push
-                          first sort them by bin (one general sort per call). */
+                          ordered by bin: pic_step and pic_interp_push first
+                          put them in bin order with a stable counting sort
+                          inside each patch (in pic_step's slab layout, as
+                          part of the copy into the slabs). */
   int32_t particle_bc[3]; /* particle boundary per axis, PIC_BC_* (ignored
                           for z in 2D); walls sit at 0 and L = n d.  Fields
                           and current stay periodic arrays: nodes beyond a

@@ -755,6 +755,17 @@ pic_status ensure_slab_graph(pic_ctx *c, const SlabArgs &a, const pic_fields *f,
   return PIC_OK;
 }
 
+// x-bins: the bin offsets of each species, allocated on first use.
+pic_status ensure_boff(pic_ctx *c, int32_t nsp) {
+  if (c->nb == 1) return PIC_OK;
+  for (int s = 0; s < nsp; s++)
+    if (!c->boff[s]) {
+      hipError_t e = realloc_dev(c->boff[s], (size_t)c->g.npatch + 1);
+      if (e != hipSuccess) return hip_fail(c, e, "hipMalloc");
+    }
+  return PIC_OK;
+}
+
 // pic_step in the slab layout: dense -> slabs, nsteps slab steps, slabs ->
 // dense (new offsets); the caller's first buffer set holds the result.
 // Enqueues only (the caller finishes the call).
@@ -771,9 +782,32 @@ pic_status step_slab(pic_ctx *c, pic_species *sp, int32_t nsp, pic_fields *f, in
       ncu = 1;
     c->pgrid_slab = slab_persistent_blocks_per_cu(c->g, c->wg) * ncu;
   }
+  // x-bins: the particles arrive sorted by patch; the copy into the slabs
+  // puts them in bin order (bin counts first, then the slab plan, then each
+  // particle straight into its bin's slab)
+  const bool bins = c->nb > 1 && bin_order_supported(c->nb);
+  if (bins) {
+    if ((r = ensure_boff(c, nsp)) != PIC_OK) return r;
+    for (int s = 0; s < nsp; s++) {
+      SpDev d = make_args(c, sp, nsp).s[s];
+      d.off = c->boff[s];
+      const hipError_t e = timed(c, PIC_KERNEL_SORT, st, [&] {
+        return bin_count(c->g, d, sp[s].offset, c->npatch_api, c->nb, sp[s].n, c->err_dev, st);
+      });
+      if (e != hipSuccess) return hip_fail(c, e, "bin count");
+    }
+  }
   const SlabArgs a = make_slab_args(c, sp, nsp);
-  hipError_t e = timed(c, PIC_KERNEL_SLAB, st,
-                       [&] { return launch_slab_begin(c->g, a, c->err_dev, st); });
+  hipError_t e = timed(c, PIC_KERNEL_SLAB, st, [&] {
+    hipError_t r2 = launch_slab_begin(c->g, a, c->err_dev, st, !bins);
+    for (int s = 0; bins && s < nsp && r2 == hipSuccess; s++) {
+      SpDev d = make_args(c, sp, nsp).s[s];
+      d.off = c->boff[s];
+      r2 = bin_place(c->g, d, sp[s].offset, c->npatch_api, c->nb, sp[s].n, c->slab[s].sb,
+                     c->slab[s].ctl, st);
+    }
+    return r2;
+  });
   if (e == hipSuccess && pers)
     e = timed(c, PIC_KERNEL_EXCHANGE, st, [&] {
       return launch_slab_units(c->g, a, c->g.spc * kSeg, c->units, c->qctl, st);
@@ -797,17 +831,6 @@ pic_status step_slab(pic_ctx *c, pic_species *sp, int32_t nsp, pic_fields *f, in
     return r2;
   });
   if (e != hipSuccess) return hip_fail(c, e, "kernel launch");
-  return PIC_OK;
-}
-
-// x-bins: the bin offsets of each species, allocated on first use.
-pic_status ensure_boff(pic_ctx *c, int32_t nsp) {
-  if (c->nb == 1) return PIC_OK;
-  for (int s = 0; s < nsp; s++)
-    if (!c->boff[s]) {
-      hipError_t e = realloc_dev(c->boff[s], (size_t)c->g.npatch + 1);
-      if (e != hipSuccess) return hip_fail(c, e, "hipMalloc");
-    }
   return PIC_OK;
 }
 
@@ -906,6 +929,30 @@ pic_status refresh_layout(pic_ctx *c, const pic_species *sp, int32_t nsp, hipStr
       c->g, a, c->cfg.mode == PIC_MODE_PERSISTENT ? c->units : nullptr, c->qctl, st);
   if (e != hipSuccess) return hip_fail(c, e, "kernel launch");
   c->layout_stale = false;
+  return PIC_OK;
+}
+
+// x-bins: particles sorted by patch put into bin order inside each patch
+// (a stable counting sort per patch), then segment starts (and work
+// units) and the buffer swap.  More bins per patch than the counting sort
+// serves: the general sort.
+pic_status order_bins(pic_ctx *c, pic_species *sp, int32_t nsp, hipStream_t st) {
+  if (!bin_order_supported(c->nb)) return sort_species(c, sp, nsp, true, st);
+  pic_status r;
+  if ((r = ensure_boff(c, nsp)) != PIC_OK) return r;
+  for (int s = 0; s < nsp; s++) {
+    SpDev d = make_args(c, sp, nsp).s[s];
+    d.off = c->boff[s];
+    hipError_t e = timed(c, PIC_KERNEL_SORT, st, [&] {
+      return bin_order(c->g, d, sp[s].offset, c->npatch_api, c->nb, sp[s].n, c->err_dev, st);
+    });
+    if (e != hipSuccess) return hip_fail(c, e, "bin order");
+  }
+  const SpArgs a = make_args(c, sp, nsp);
+  const hipError_t e = launch_layout(
+      c->g, a, c->cfg.mode == PIC_MODE_PERSISTENT ? c->units : nullptr, c->qctl, st);
+  if (e != hipSuccess) return hip_fail(c, e, "kernel launch");
+  for (int s = 0; s < nsp; s++) swap_buffers(sp[s]);
   return PIC_OK;
 }
 
@@ -1202,7 +1249,7 @@ pic_status pic_interp_push(pic_ctx *c, pic_species *sp, int32_t nsp, const pic_f
   if ((r = ensure_scratch(c, sp, nsp, true, st)) != PIC_OK) return r;
   if ((r = refresh_layout(c, sp, nsp, st)) != PIC_OK) return r;
   // x-bins: the particles arrive sorted by patch; the kernels need them by bin
-  if (c->nb > 1 && (r = sort_species(c, sp, nsp, true, st)) != PIC_OK) return r;
+  if (c->nb > 1 && (r = order_bins(c, sp, nsp, st)) != PIC_OK) return r;
   const SpArgs a = make_args(c, sp, nsp);
   hipError_t e = timed(c, PIC_KERNEL_INTERP_PUSH, st, [&] {
     return launch_interp_push(c->g, a, f->e, f->b, c->err_dev, c->wgd, st);
@@ -1241,14 +1288,18 @@ pic_status pic_step(pic_ctx *c, pic_species *sp, int32_t nsp, pic_fields *f, int
   if ((r = ensure_scratch(c, sp, nsp, false, st)) != PIC_OK) return r;
   if ((r = refresh_layout(c, sp, nsp, st)) != PIC_OK) return r;
   if (nsteps == 0) return finish(c, st);
-  // x-bins: the particles arrive sorted by patch; the kernels need them by bin
-  if (c->nb > 1 && (r = sort_species(c, sp, nsp, true, st)) != PIC_OK) return r;
   // removing walls delete particles only in the slab layout's exchange, so
   // every call takes it there
   if (c->g.remove && !slab_fits(c, sp, nsp))
     return fail(c, PIC_ERR_CAPACITY,
                 "removing walls need buffers with the slab layout's room (n + n/8 + 80 per slab)");
-  if ((nsteps >= 3 || c->g.remove) && slab_fits(c, sp, nsp)) {
+  const bool slab = (nsteps >= 3 || c->g.remove) && slab_fits(c, sp, nsp);
+  // x-bins: the particles arrive sorted by patch; the kernels need them by
+  // bin (the slab layout's first copy orders them itself)
+  if (c->nb > 1 && !(slab && bin_order_supported(c->nb)) &&
+      (r = order_bins(c, sp, nsp, st)) != PIC_OK)
+    return r;
+  if (slab) {
     if ((r = step_slab(c, sp, nsp, f, nsteps, st)) != PIC_OK) return r;
   } else {
     if ((r = step_dense(c, sp, nsp, f, nsteps, st, c->sp, c->units, true)) != PIC_OK) return r;

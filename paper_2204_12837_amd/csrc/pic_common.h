@@ -145,7 +145,9 @@ struct SlabArgs {
 static_assert(sizeof(SlabArgs) <= 4096, "kernel argument block too large");
 
 // Slab-layout launchers (pic_slab.hip).
-hipError_t launch_slab_begin(const GridDev &g, const SlabArgs &sa, int *err, hipStream_t st);
+// copy = false: only the slab plan (the caller fills the slabs).
+hipError_t launch_slab_begin(const GridDev &g, const SlabArgs &sa, int *err, hipStream_t st,
+                             bool copy = true);
 hipError_t launch_ipp_slab(const GridDev &g, const SlabArgs &sa, const double *const e[3],
                            const double *const b[3], double *const j[3], int *err, int wg,
                            hipStream_t st);
@@ -226,16 +228,33 @@ hipError_t launch_tag(const GridDev &g, const SpArgs &sa, int *err, int wg, hipS
 hipError_t launch_rebin(const GridDev &g, const SpArgs &sa, int *err, int64_t maxseg, bool to_perm,
                         hipStream_t st);
 
-// General sort (pic_sort.hip): wrap + key + stable sort of unsorted input.
+// General sort (pic_sort.hip): wrap + key + stable radix sort of unsorted
+// input, gather into the second buffer set, patch offsets.
 struct SortScratch {
-  void *temp = nullptr;
-  size_t temp_bytes = 0;
-  int32_t *keys = nullptr, *keys_out = nullptr;
-  int64_t *idx = nullptr, *idx_out = nullptr;
+  uint32_t *keys = nullptr, *keys_out = nullptr;
+  uint32_t *idx = nullptr, *idx_out = nullptr;
+  uint32_t *hist = nullptr;  // per radix pass: digit counts of every tile
   int64_t cap = 0;
 };
 hipError_t general_sort(const GridDev &g, SpDev &s, SortScratch &scr, int *err, hipStream_t st);
 void free_sort_scratch(SortScratch &scr);
+// x-bins (pic_sort.hip): stable counting sort of the n particles sorted by
+// API patch (offsets off_api, npatch_api patches of nb bins each) into bin
+// order in the second buffer set; writes the bin offsets to s.off and uses
+// s.sstart, s.cnt, s.tmp, s.in and s.noff as scratch (sized for the bins and
+// a capacity of at least n).  For at most 256 bins per patch
+// (bin_order_supported).
+bool bin_order_supported(int nb);
+hipError_t bin_order(const GridDev &g, SpDev &s, const int64_t *off_api, int64_t npatch_api, int nb,
+                     int64_t n, int *err, hipStream_t st);
+// Its two halves: bin counts and offsets (s.off), then the placement with
+// dst0[bin] as each bin's first slot in the second buffer set (s.off for
+// the dense bin order, the slab starts for pic_step's slab layout, whose
+// fit flag ctl[1] is checked first; ctl may be null).
+hipError_t bin_count(const GridDev &g, SpDev &s, const int64_t *off_api, int64_t npatch_api, int nb,
+                     int64_t n, int *err, hipStream_t st);
+hipError_t bin_place(const GridDev &g, SpDev &s, const int64_t *off_api, int64_t npatch_api, int nb,
+                     int64_t n, const int64_t *dst0, const int32_t *ctl, hipStream_t st);
 
 size_t lds_bytes_ipp(const GridDev &g);
 

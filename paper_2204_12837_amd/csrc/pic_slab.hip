@@ -783,10 +783,11 @@ __global__ void __launch_bounds__(256) k_slab_out(GridDev g, SlabArgs sa) {
 
 }  // namespace
 
-hipError_t launch_slab_begin(const GridDev &g, const SlabArgs &sa, int *err, hipStream_t st) {
+hipError_t launch_slab_begin(const GridDev &g, const SlabArgs &sa, int *err, hipStream_t st,
+                             bool copy) {
   hipLaunchKernelGGL(k_slab_plan, dim3(sa.nsp), dim3(1024), 0, st, g, sa, err);
   hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
+  if (e != hipSuccess || !copy) return e;
   if (g.dim == 2)
     hipLaunchKernelGGL(k_slab_in<2>, dim3(g.npatch, sa.nsp), dim3(256), 0, st, g, sa);
   else

@@ -100,6 +100,33 @@ def test_general_sort_from_any_order():
     compare(osp, None, None, g, None, exact_order=True)
 
 
+@pytest.mark.parametrize("case", ["two_passes", "three_passes"])
+def test_general_sort_many_patches(case):
+    """pic_bin's radix sort when the patch keys need more than one 8-bit
+    digit: 4,096 patches (two passes) and 65,536 patches plus the key of
+    particles deleted at a removing wall (three passes), on particles in
+    any order: the oracle's stable order, its offsets and its deletions."""
+    if case == "two_passes":
+        wl = I.custom(2, (384, 384), (6, 6), ppc=2, seed=114)
+    else:
+        wl = dataclasses.replace(I.custom(2, (1536, 1536), (6, 6), ppc=1, seed=112),
+                                 particle_bc=(2, 0, 0))
+    inp = I.generate(wl)
+    x = inp.species[0].x
+    rng = np.random.default_rng(113)
+    L = np.array([wl.n[0] * wl.d[0], wl.n[1] * wl.d[1]])
+    if case == "three_passes":
+        k = rng.random(x.shape[1]) < 0.01  # outside the removing walls: deleted
+        x[0, k] = np.where(rng.random(k.sum()) < 0.5, -0.37, L[0] + 0.25)
+        x[1] += rng.integers(-1, 2, x.shape[1]) * L[1] * 0.999999
+    else:
+        x += rng.integers(-1, 2, x.shape) * L[:, None] * 0.999999
+    say(f"case general sort {case}: {wl.n_patches} patches, {x.shape[1]} particles")
+    osp, _, _ = run_oracle(wl, inp, 0)
+    g, _ = run_gpu(wl, inp, 0)
+    compare(osp, None, None, g, None, exact_order=True)
+
+
 def test_edge_positions():
     """Particles exactly on patch and cell boundaries, on nodes, at the box
     edges and just below L."""
@@ -267,6 +294,54 @@ def test_x_bins_split_path_and_general_sort():
     osp, _, _ = run_oracle(wl, inp, 0)
     g, _ = run_gpu(wl, inp, 0)
     compare(osp, None, None, g, None, exact_order=False)
+
+
+@pytest.mark.parametrize("layout", list(LAYOUTS))
+@pytest.mark.parametrize("mode", [0, 1])
+def test_x_bins_from_patch_order(mode, layout):
+    """Particles sorted by patch but in any order inside it (here: pic_bin
+    of a context without bins, which keeps the generation order inside each
+    patch) handed to a context with 4-cell x-bins: its calls first put each
+    patch's particles into bin order (the per-patch counting sort), and the
+    result matches the oracle's patch-level run; also the split path."""
+    import torch
+
+    from paper_2204_12837_amd import pic
+
+    wl = I.custom(2, (96, 64), (32, 16), ppc=3, seed=520, sigma=0.3, n_species=2)
+    inp = I.generate(wl)
+    steps = 3 if layout == "slab" else 2
+    say(f"case x-bins from patch order mode={mode} {layout}")
+    osp, J, A = run_oracle(wl, inp, steps)
+    plain = pic.Context(wl, device=0)
+    binned = pic.Context(wl, device=0, mode=mode, chunk=512, bin_x=4, check=True)
+    assert plain.n_slabs * 8 == binned.n_slabs
+    sp = pic.upload(inp, "cuda:0", capacity_factor=LAYOUTS[layout]["capacity_factor"],
+                    n_slabs=binned.n_slabs)
+    E, B, Jt = pic.upload_fields(inp, "cuda:0")
+    plain.bin(sp)
+    torch.cuda.synchronize()
+    binned.step(sp, E, B, Jt, nsteps=steps)
+    torch.cuda.synchronize()
+    binned.check()
+    g = [dict(off=s.offset.cpu().numpy(), id=s.ids.cpu().numpy(), x=s.xs.cpu().numpy(),
+              u=s.us.cpu().numpy(), w=s.ws.cpu().numpy()) for s in sp]
+    compare(osp, J, A, g, Jt.cpu().numpy(), exact_order=False)
+    # split path: the bin order happens in pic_interp_push
+    sp2 = pic.upload(inp, "cuda:0", capacity_factor=1.0)
+    plain.bin(sp2)
+    for _ in range(steps):
+        Jt.zero_()
+        binned.interp_push(sp2, E, B)
+        binned.project(sp2, Jt)
+        binned.bin(sp2)
+    torch.cuda.synchronize()
+    binned.check()
+    g = [dict(off=s.offset.cpu().numpy(), id=s.ids.cpu().numpy(), x=s.xs.cpu().numpy(),
+              u=s.us.cpu().numpy(), w=s.ws.cpu().numpy()) for s in sp2]
+    compare(osp, J, A, g, Jt.cpu().numpy(), exact_order=False)
+    plain.close()
+    binned.close()
 
 
 @pytest.mark.parametrize("layout", list(LAYOUTS))
