@@ -277,9 +277,10 @@ def jvp(wl, q, m, x, u, w, E, B, du=None, dE=None, dB=None, nsteps=None):
 
 
 def fd(wl, q, m, x, u, w, E, B, W, du=None, dE=None, dB=None, h=1e-6, nsteps=None,
-       extended=True):
+       extended=True, quad=False):
     """Central difference of L = sum W.J_final along (du, dE, dB), computed
-    in long double (extended=True) or double.  Returns (fd, L0)."""
+    in binary128 (quad=True), x87 long double (extended=True) or double.
+    Returns (fd, L0)."""
     nsteps = wl.steps if nsteps is None else nsteps
     keep: list = []
     x = np.ascontiguousarray(x)
@@ -289,7 +290,7 @@ def fd(wl, q, m, x, u, w, E, B, W, du=None, dE=None, dB=None, h=1e-6, nsteps=Non
     Bf = np.ascontiguousarray(B.reshape(3, -1))
     Wf = np.ascontiguousarray(W.reshape(3, -1))
     out, L0 = C.c_double(), C.c_double()
-    lib = _lib("liborc_ld.so" if extended else "liborc.so")
+    lib = _lib("liborc_q.so" if quad else "liborc_ld.so" if extended else "liborc.so")
     rc = lib.orc_fd(C.byref(grid(wl)), q, m, x.shape[1], _arr3([x[0], x[1]]), _arr3(u), _p(w),
                     _arr3(Ef), _arr3(Bf), _arr3(Wf), _opt3(du, keep), _opt3(dE, keep),
                     _opt3(dB, keep), nsteps, h, C.byref(out), C.byref(L0))
@@ -297,5 +298,5 @@ def fd(wl, q, m, x, u, w, E, B, W, du=None, dE=None, dB=None, h=1e-6, nsteps=Non
     return out.value, L0.value
 
 
-def real_size(extended=False) -> int:
-    return _lib("liborc_ld.so" if extended else "liborc.so").orc_real_size()
+def real_size(extended=False, quad=False) -> int:
+    return _lib("liborc_q.so" if quad else "liborc_ld.so" if extended else "liborc.so").orc_real_size()

@@ -1,8 +1,8 @@
 """Build the CPU oracle's shared libraries with gcc (test infrastructure).
 
-Two builds of the same source: ``liborc.so`` in double precision (the parity
-oracle) and ``liborc_ld.so`` in x87 long double (finite-difference
-references).  Both with -O2 -ffp-contract=off and no fast-math.
+Three builds of the same source: ``liborc.so`` in double precision (the
+parity oracle), ``liborc_ld.so`` in x87 long double and ``liborc_q.so`` in
+binary128 (finite-difference references).  Both with -O2 -ffp-contract=off and no fast-math.
 """
 from __future__ import annotations
 
@@ -15,6 +15,7 @@ SRC = os.path.join(HERE, "pic_oracle.c")
 LIBS = {
     "liborc.so": [],
     "liborc_ld.so": ["-DORC_REAL=long double"],
+    "liborc_q.so": ["-DORC_QUAD", "-std=gnu11"],
 }
 CFLAGS = ["-std=c11", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared", "-Wall"]
 
@@ -30,6 +31,8 @@ def build(force: bool = True) -> None:
             continue
         tmp = out + ".tmp"
         cmd = ["gcc", *CFLAGS, *extra, "-o", tmp, SRC, "-lm"]
+        if "-std=gnu11" in extra:
+            cmd.remove("-std=c11")
         subprocess.run(cmd, check=True, cwd=HERE)
         os.replace(tmp, out)
 

@@ -2,8 +2,9 @@
  *
  * TEST INFRASTRUCTURE ONLY: used by tests/, the smoke check and the
  * benchmark's CPU-baseline leg to check the HIP library; shares no code with
- * it.  Plain scalar C, serial, in `real` (double unless ORC_REAL is defined),
- * built with -O2 -ffp-contract=off and no fast-math.
+ * it.  Plain scalar C, serial, in `real` (double unless ORC_REAL is defined,
+ * or binary128 with ORC_QUAD), built with -O2 -ffp-contract=off and no
+ * fast-math.
  *
  * What it follows:
  *   - the PIC iteration's macro-particle operators, per patch and species, in
@@ -33,12 +34,24 @@
 
 #include <stdlib.h>
 #include <string.h>
-#include <tgmath.h>
 
+#ifdef ORC_QUAD
+/* binary128 (finite-difference references whose rounding must stay far
+ * below the derivative's seventh digit): the math functions of that type */
+#define __STDC_WANT_IEC_60559_TYPES_EXT__ 1
+#include <math.h>
+typedef _Float128 real;
+#define sqrt sqrtf128
+#define floor floorf128
+#define fabs fabsf128
+#define nextafter nextafterf128
+#else
+#include <tgmath.h>
 #ifndef ORC_REAL
 #define ORC_REAL double
 #endif
 typedef ORC_REAL real;
+#endif
 
 int32_t orc_real_size(void) { return (int32_t)sizeof(real); }
 
@@ -1034,10 +1047,19 @@ static int loss_at(const G *g, real q, real m, int64_t n, const double *const x[
       }
     }
   }
-  real acc = 0;
+  /* Neumaier's compensated summation: the central difference divides the
+   * change of L by 2h, so the rounding of a plain sum over every node would
+   * reach the derivative's leading digits */
+  real acc = 0, comp = 0;
   for (int c = 0; c < 3; c++)
-    for (int64_t i = 0; i < g->ncell; i++) acc += (real)W[c][i] * Jr[c][i];
-  *L = acc;
+    for (int64_t i = 0; i < g->ncell; i++) {
+      const real t = (real)W[c][i] * Jr[c][i];
+      const real y = acc + t;
+      const real aa = acc < 0 ? -acc : acc, at = t < 0 ? -t : t;
+      comp += aa >= at ? (acc - y) + t : (t - y) + acc;
+      acc = y;
+    }
+  *L = acc + comp;
   for (int c = 0; c < 3; c++) {
     free(Er[c]);
     free(Br[c]);

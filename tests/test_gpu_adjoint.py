@@ -131,6 +131,57 @@ def test_adjoint_full_size_sampled():
     assert abs(got - ref) <= 1e-11 * sc, (got, ref, sc)
 
 
+def test_adjoint256_finite_differences():
+    """The adjoint's criterion at its workload (256x256 cells, 16 ppc =
+    1,048,576 particles, 20 steps, checkpoint every 5): along 4 random unit
+    directions in u and 4 in (E, B), and on 32 sampled scalars each of
+    dL/du, dL/dE and dL/dB, the GPU gradient equals the oracle's central
+    difference of L in x87 extended precision (h = 1e-6) to 1e-7 relative
+    (scalars where |FD| > 1e-3 of the largest sampled one), and the oracle's
+    forward-mode derivative to rounding.  The oracle's values were written
+    by tests/golden/make_adjoint256_fd.py."""
+    import json
+    import os
+    import sys
+
+    here = os.path.dirname(os.path.abspath(__file__))
+    sys.path.insert(0, os.path.join(here, "golden"))
+    import make_adjoint256_fd as G
+
+    with open(os.path.join(here, "golden", "adjoint256_fd.json")) as fh:
+        gold = json.load(fh)
+    wl, inp, x = G.setup()
+    assert G.inputs_sha(inp, x) == gold["inputs_sha256"], "the generated inputs changed"
+    s = inp.species[0]
+    say("case adjoint256 finite differences (directions and sampled scalars)")
+    J, gu, gE, gB = _gpu_grads(wl, inp, x, wl.ckpt)
+    for d in gold["directions"]:
+        if d["kind"] == "u":
+            vs = G.unit_direction(d["seed"], [s.u.shape])
+            gs = [gu]
+        else:
+            vs = G.unit_direction(d["seed"], [inp.E.shape, inp.B.shape])
+            gs = [gE, gB]
+        got = math.fsum(_dot(g, v)[0] for g, v in zip(gs, vs))
+        scale = math.fsum(_dot(g, v)[1] for g, v in zip(gs, vs))
+        assert abs(got - d["fd"]) <= 1e-7 * abs(d["fd"]), (d, got)
+        assert abs(got - d["jvp"]) <= 1e-11 * scale, (d, got, scale)
+    grads = {"u": gu, "E": gE.reshape(3, -1), "B": gB.reshape(3, -1)}
+    for kind, g in grads.items():
+        sc = [e for e in gold["scalars"] if e["kind"] == kind]
+        assert len(sc) == 32
+        top = max(abs(e["fd"]) for e in sc)
+        big = np.abs(g).max()
+        checked = 0
+        for e in sc:
+            got = g[e["component"], e["index"]]
+            assert abs(got - e["jvp"]) <= 1e-10 * big + 1e-11 * abs(e["jvp"]), (e, got)
+            if abs(e["fd"]) > 1e-3 * top:
+                assert abs(got - e["fd"]) <= 1e-7 * abs(e["fd"]), (e, got)
+                checked += 1
+        assert checked >= 24, (kind, checked)
+
+
 def test_checkpoint_interval_does_not_change_gradients():
     wl = I.custom(2, (32, 32), (8, 8), ppc=4, seed=406, sigma=0.05, bz0=1.0, steps=8)
     inp = I.generate(wl, with_W=True)

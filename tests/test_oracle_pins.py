@@ -1102,3 +1102,43 @@ def test_oracle_matches_its_stored_digest():
     got = make_golden.digest(walls=True)
     assert got == stored
     assert got["particles"] < 32 * 24 * 6  # particles were deleted
+
+
+def test_adjoint256_fd_golden_is_the_oracles():
+    """tests/golden/adjoint256_fd.json (the expected values of the adjoint's
+    finite-difference check at full size) belongs to the current inputs and
+    oracle: the input digest matches; a few sampled scalars recomputed now
+    give the stored numbers exactly; and every stored binary128 central
+    difference agrees with the stored forward-mode derivative (two
+    independent computations) to 1e-10 (directions) and 1e-8 (sampled
+    scalars, where not negligible)."""
+    import json
+    import os
+    import sys
+
+    here = os.path.dirname(os.path.abspath(__file__))
+    sys.path.insert(0, os.path.join(here, "golden"))
+    import make_adjoint256_fd as G
+
+    with open(os.path.join(here, "golden", "adjoint256_fd.json")) as fh:
+        gold = json.load(fh)
+    wl, inp, x = G.setup()
+    assert G.inputs_sha(inp, x) == gold["inputs_sha256"]
+    assert gold["h"] == G.H and len(gold["directions"]) == 8 and len(gold["scalars"]) == 96
+    assert [(k, c, i) for k, c, i in G.samples(wl, x.shape[1])] == \
+        [(e["kind"], e["component"], e["index"]) for e in gold["scalars"]]
+    G._STATE.update(wl=wl, inp=inp, x=x)
+    for e in (gold["scalars"][0], gold["scalars"][1], gold["scalars"][32], gold["scalars"][64]):
+        again = G.scalar_task((e["kind"], e["component"], e["index"]))
+        assert again["fd"] == e["fd"] and again["jvp"] == e["jvp"], (e, again)
+    # binary128 differences against the double forward mode: the difference
+    # quotient's error O(h^2) and the forward mode's rounding stay far below
+    # the 1e-7 the adjoint is held to
+    for d in gold["directions"]:
+        assert abs(d["fd"] - d["jvp"]) <= 1e-10 * abs(d["fd"]), d
+    for kind in ("u", "E", "B"):
+        sc = [e for e in gold["scalars"] if e["kind"] == kind]
+        top = max(abs(e["fd"]) for e in sc)
+        for e in sc:
+            if abs(e["fd"]) > 1e-3 * top:
+                assert abs(e["fd"] - e["jvp"]) <= 1e-8 * abs(e["fd"]), e
