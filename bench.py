@@ -550,6 +550,13 @@ def main(argv=None) -> int:
     ap.add_argument("--no-large-patches", action="store_true",
                     help="skip the 64x128-cell patches (x-bins) workload")
     ap.add_argument("--cpu-steps", type=int, default=8)
+    ap.add_argument("--mode", choices=("per_patch", "persistent"), default="per_patch",
+                    help="launch of the main workload's fused kernel")
+    ap.add_argument("--chunk", type=int, default=0, help="persistent mode: particles per unit")
+    ap.add_argument("--wg", type=int, default=0, help="threads per workgroup (0 = library default)")
+    ap.add_argument("--bin-x", type=int, default=0, help="x-bin width (0 = library default)")
+    ap.add_argument("--main-only", action="store_true",
+                    help="time only the main workload (e.g. for counter passes)")
     ap.add_argument("--copy-calibration", type=float, default=0.0, metavar="GIB",
                     help="only run a plain device copy of this many GiB (5 times), to scale "
                          "HBM traffic counters")
@@ -568,8 +575,10 @@ def main(argv=None) -> int:
     inp0 = I.generate(wl)
     # the per-kernel HIP events (roofline) come from one call; the headline
     # throughput from the same call without them (plain eager launches)
-    n, secs_ev, tim = run_gpu(wl, args.steps, args.warmup, inp=inp0)
-    _, secs, _ = run_gpu(wl, args.steps, args.warmup, inp=inp0, timing=False)
+    launch = dict(mode=1 if args.mode == "persistent" else 0, chunk=args.chunk, wg=args.wg,
+                  bin_x=args.bin_x)
+    n, secs_ev, tim = run_gpu(wl, args.steps, args.warmup, inp=inp0, **launch)
+    _, secs, _ = run_gpu(wl, args.steps, args.warmup, inp=inp0, timing=False, **launch)
     value = n * args.steps / secs
     ipp_ms, ipp_n = tim["ipp"]
     ipp_avg = ipp_ms / max(ipp_n, 1)
@@ -594,7 +603,7 @@ def main(argv=None) -> int:
         "data": "synthetic",
         "config": {"workload": args.workload, "dim": wl.dim, "cells": list(wl.n[:wl.dim]),
                    "patch": list(wl.patch[:wl.dim]), "particles": n,
-                   "species": len(wl.species), "mode": "per_patch", "layout": "slab"},
+                   "species": len(wl.species), "mode": args.mode, "layout": "slab"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": FUSED_KERNEL, "algorithmic_bytes": abytes, "avg_ms": ipp_avg,
@@ -610,8 +619,11 @@ def main(argv=None) -> int:
         "with_kernel_events": {"ms_per_step": secs_ev / args.steps * 1e3},
         "interp_push_project_rate": n / (ipp_avg * 1e-3),
     }
+    if args.main_only:
+        print(json.dumps(out), flush=True)
+        return 0
     # the same call replaying one captured graph per step (no per-kernel events)
-    _, secs_g, _ = run_gpu(wl, args.steps, args.warmup, inp=inp0, graph=True)
+    _, secs_g, _ = run_gpu(wl, args.steps, args.warmup, inp=inp0, graph=True, **launch)
     del inp0
     out["graph_replay"] = {"ms_per_step": secs_g / args.steps * 1e3,
                            "particle_steps_per_s": n * args.steps / secs_g}

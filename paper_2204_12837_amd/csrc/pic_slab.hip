@@ -338,10 +338,13 @@ __global__ void __launch_bounds__(kMaxWgSlab<DIM>, kSlabMinWaves<DIM>) k_ipp_sla
 
 // Persistent launch: workgroups pop (patch, particle range) units of each
 // species in turn (ticket qctl[2s], count qctl[2s+1], list at units +
-// ubase); E/B is restaged and J flushed only when the patch changes.
+// ubase), or, with combined, from one list whose units range over the
+// particles of every species of the patch (ticket qctl[0], count qctl[1],
+// list at units); E/B is restaged and J flushed only when the patch changes.
 template <int DIM, bool WALLS>
 __global__ void __launch_bounds__(kMaxWgSlab<DIM>, kSlabMinWaves<DIM>) k_ipp_slab_persistent(GridDev g, SlabArgs sa, Fields f, int *err,
-                                                                    const Unit *units, int *qctl) {
+                                                                    const Unit *units, int *qctl,
+                                                                    int combined) {
   extern __shared__ __align__(16) double lds[];
   __shared__ int s_unit;
   int curP = -1;
@@ -349,11 +352,12 @@ __global__ void __launch_bounds__(kMaxWgSlab<DIM>, kSlabMinWaves<DIM>) k_ipp_sla
   double *tEB = lds;
   double *tJ = lds + 6 * t.TE;
   int bad = 0;
-  for (int s = 0; s < sa.nsp; s++) {
+  const int nlist = combined ? 1 : sa.nsp;
+  for (int s = 0; s < nlist; s++) {
     const SlabDev &S = sa.s[s];
-    if (S.ctl[1] == 2) continue;
+    if (!combined && S.ctl[1] == 2) continue;
     const int n_units = qctl[2 * s + 1];
-    const Unit *ul = units + S.ubase;
+    const Unit *ul = units + (combined ? 0 : S.ubase);
     for (;;) {
       if (threadIdx.x == 0) s_unit = atomicAdd(&qctl[2 * s], 1);
       __syncthreads();
@@ -372,7 +376,22 @@ __global__ void __launch_bounds__(kMaxWgSlab<DIM>, kSlabMinWaves<DIM>) k_ipp_sla
         __syncthreads();
         curP = un.P;
       }
-      ipp_slab<DIM, WALLS>(g, S, t, tEB, tJ, un.P, (uint32_t)un.k0, (uint32_t)un.k1, bad, nullptr);
+      if (combined) {
+        // the unit's share of each species: [k0, k1) of the concatenation
+        int base = 0;
+        for (int r = 0; r < sa.nsp; r++) {
+          const SlabDev &R = sa.s[r];
+          if (R.ctl[1] == 2) continue;
+          const int c = R.cnt[un.P];
+          const int r0 = min(max(un.k0 - base, 0), c), r1 = min(max(un.k1 - base, 0), c);
+          if (r0 < r1)
+            ipp_slab<DIM, WALLS>(g, R, t, tEB, tJ, un.P, (uint32_t)r0, (uint32_t)r1, bad, nullptr);
+          base += c;
+        }
+      } else {
+        ipp_slab<DIM, WALLS>(g, S, t, tEB, tJ, un.P, (uint32_t)un.k0, (uint32_t)un.k1, bad,
+                             nullptr);
+      }
       __syncthreads();  // this unit's deposits are done before any flush
     }
   }
@@ -595,16 +614,16 @@ __global__ void __launch_bounds__(256) k_exch_in(GridDev g, SlabArgs sa) {
 }
 
 // Persistent mode: work units of chunk particles for the patch counts, every
-// full unit first, then the remainders (one workgroup per species, each
-// thread a contiguous run of patches).  first(P) gives patch P's count once
-// (it may also store it); again(P) gives it a second time.  The list goes
-// to units + ubase, its length to qctl[2s+1] (0 if the species stands
-// still) and a zero ticket to qctl[2s].
+// full unit first, then the remainders (one workgroup, each thread a
+// contiguous run of patches).  first(P) gives patch P's count once (it may
+// also store it); again(P) gives it a second time.  The list goes to ul
+// (units tagged with species s), its length to q[1] (0 if the species stands
+// still) and a zero ticket to q[0].
 constexpr int kUnitsCached = 8;  // counts a thread keeps in registers
 
 template <class First, class Again>
-__device__ void make_units(const SlabDev &S, int s, int n, int chunk, bool still, First first,
-                           Again again, Unit *units, int *qctl, int *wtot) {
+__device__ void make_units(int s, int n, int chunk, bool still, First first, Again again,
+                           Unit *ul, int *q, int *wtot) {
   const int per = (n + blockDim.x - 1) / blockDim.x;
   const int p0 = min(n, (int)threadIdx.x * per), p1 = min(n, p0 + per);
   int cc[kUnitsCached];
@@ -626,7 +645,6 @@ __device__ void make_units(const SlabDev &S, int s, int n, int chunk, bool still
   int tf = 0, tr = 0;
   int rf = block_excl_sum(nf, tf, wtot);
   int rr = tf + block_excl_sum(nr, tr, wtot);
-  Unit *ul = units + S.ubase;
   auto emit = [&](int P, int c) {
     Unit un;
     un.s = s;
@@ -647,8 +665,8 @@ __device__ void make_units(const SlabDev &S, int s, int n, int chunk, bool still
     if (p0 + k < p1) emit(p0 + k, cc[k]);
   for (int P = p0 + kUnitsCached; P < p1; P++) emit(P, again(P));
   if (threadIdx.x == 0) {
-    qctl[2 * s + 1] = still ? 0 : tf + tr;
-    qctl[2 * s] = 0;
+    q[1] = still ? 0 : tf + tr;
+    q[0] = 0;
   }
 }
 
@@ -667,14 +685,14 @@ __global__ void __launch_bounds__(1024) k_exch_fin(GridDev g, SlabArgs sa, int *
   if (flag == 0) {
     if (units) {  // the new counts, and the work units from them, in one pass
       make_units(
-          S, s, n, chunk, false,
+          s, n, chunk, false,
           [&](int P) {
             const int c = S.cnt2[P] + S.arr[P];
             S.cnt[P] = c;
             S.arr[P] = 0;
             return c;
           },
-          [&](int P) { return S.cnt[P]; }, units, qctl, wtot);
+          [&](int P) { return S.cnt[P]; }, units + S.ubase, qctl + 2 * s, wtot);
       return;
     }
     for (int P = threadIdx.x; P < n; P += blockDim.x) {
@@ -698,7 +716,7 @@ __global__ void __launch_bounds__(1024) k_exch_fin(GridDev g, SlabArgs sa, int *
   }
   if (units) {  // the counts the new plan's copies will set
     auto need = [&](int P) { return S.cnt2[P] + S.arr[P]; };
-    make_units(S, s, n, chunk, still, need, need, units, qctl, wtot);
+    make_units(s, n, chunk, still, need, need, units + S.ubase, qctl + 2 * s, wtot);
   }
 }
 
@@ -757,7 +775,25 @@ __global__ void __launch_bounds__(1024) k_slab_units(GridDev g, SlabArgs sa, int
   const int s = blockIdx.x;
   const SlabDev &S = sa.s[s];
   auto count = [&](int P) { return S.cnt[P]; };
-  make_units(S, s, g.npatch, chunk, S.ctl[1] == 2, count, count, units, qctl, wtot);
+  make_units(s, g.npatch, chunk, S.ctl[1] == 2, count, count, units + S.ubase, qctl + 2 * s, wtot);
+}
+
+// Persistent mode with several species: one list of units over every
+// species of a patch (the patch's particles of species 0, then of species
+// 1, ...: a unit may span species), so a workgroup stages a patch's fields
+// and flushes its current once for all species.  From the slab counts
+// after the exchange (one workgroup of 1024); a species that stands still
+// counts zero.  List at units, length in qctl[1], zero ticket in qctl[0].
+__global__ void __launch_bounds__(1024) k_units_all(GridDev g, SlabArgs sa, int chunk,
+                                                    Unit *units, int *qctl) {
+  __shared__ int wtot[16];
+  auto count = [&](int P) {
+    int c = 0;
+    for (int s = 0; s < sa.nsp; s++)
+      if (sa.s[s].ctl[1] != 2) c += sa.s[s].cnt[P];
+    return c;
+  };
+  make_units(-1, g.npatch, chunk, false, count, count, units, qctl, wtot);
 }
 
 // End of a call: dense offsets from the slab counts (one workgroup of 1024
@@ -826,7 +862,7 @@ void ipp_slab_pers_t(const GridDev &g, const SlabArgs &sa, const Fields &f, int 
     (void)hipFuncSetAttribute((const void *)k_ipp_slab_persistent<DIM, WALLS>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   hipLaunchKernelGGL((k_ipp_slab_persistent<DIM, WALLS>), dim3(grid), dim3(wg), lds, st, g, sa, f,
-                     err, units, qctl);
+                     err, units, qctl, sa.nsp > 1 ? 1 : 0);
 }
 
 hipError_t launch_ipp_slab_persistent(const GridDev &g, const SlabArgs &sa,
@@ -878,7 +914,10 @@ hipError_t launch_exchange(const GridDev &g, const SlabArgs &sa, int *err, Unit 
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_exch_fin, dim3(sa.nsp), dim3(1024), 0, st, g, sa, err, units, qctl, chunk);
+  // several species: one combined unit list, made once the counts are final
+  const bool combined = units && sa.nsp > 1;
+  hipLaunchKernelGGL(k_exch_fin, dim3(sa.nsp), dim3(1024), 0, st, g, sa, err,
+                     combined ? nullptr : units, qctl, chunk);
   const dim3 mg(2 * g.npatch, sa.nsp);
   if (g.dim == 2) {
     hipLaunchKernelGGL(k_reslab_move<2>, mg, dim3(256), 0, st, g, sa);
@@ -887,12 +926,17 @@ hipError_t launch_exchange(const GridDev &g, const SlabArgs &sa, int *err, Unit 
     hipLaunchKernelGGL(k_reslab_move<3>, mg, dim3(256), 0, st, g, sa);
     hipLaunchKernelGGL(k_reslab_back<3>, pg, dim3(256), 0, st, g, sa);
   }
+  if (combined)
+    hipLaunchKernelGGL(k_units_all, dim3(1), dim3(1024), 0, st, g, sa, chunk, units, qctl);
   return hipGetLastError();
 }
 
 hipError_t launch_slab_units(const GridDev &g, const SlabArgs &sa, int chunk, Unit *units,
                              int *qctl, hipStream_t st) {
-  hipLaunchKernelGGL(k_slab_units, dim3(sa.nsp), dim3(1024), 0, st, g, sa, chunk, units, qctl);
+  if (sa.nsp > 1)
+    hipLaunchKernelGGL(k_units_all, dim3(1), dim3(1024), 0, st, g, sa, chunk, units, qctl);
+  else
+    hipLaunchKernelGGL(k_slab_units, dim3(1), dim3(1024), 0, st, g, sa, chunk, units, qctl);
   return hipGetLastError();
 }
 
