@@ -172,6 +172,65 @@ def tune_persistent(wl, inp):
     return res
 
 
+def trace_summary(rec):
+    """Scheduling of one traced fused-kernel launch: its span, the work
+    items' total time over the span (mean concurrency), the peak
+    concurrency, their ratio (how busy the workgroups were on average),
+    and the part of the span during which fewer than half the peak ran
+    (the tail of the longest items)."""
+    import numpy as np
+
+    t0 = np.array([r[4] for r in rec], dtype=np.float64)
+    t1 = np.array([r[5] for r in rec], dtype=np.float64)
+    start, end = t0.min(), t1.max()
+    span = end - start
+    ev = np.concatenate([np.stack([t0, np.ones_like(t0)], 1), np.stack([t1, -np.ones_like(t1)], 1)])
+    ev = ev[np.lexsort((ev[:, 1], ev[:, 0]))]
+    active = np.cumsum(ev[:, 1])
+    peak = int(active.max())
+    dt = np.diff(ev[:, 0])
+    low = float(dt[active[:-1] < 0.5 * peak].sum())
+    mean = float((t1 - t0).sum() / span) if span > 0 else 0.0
+    out = {"items": len(rec), "span_us": span / 100.0, "mean_concurrency": mean,
+           "peak_concurrency": peak, "busy_fraction": mean / peak if peak else 0.0,
+           "tail_fraction": low / span if span > 0 else 0.0}
+    blocks = np.array([r[2] for r in rec])
+    if len(np.unique(blocks)) < len(rec):  # persistent: per-worker busy time
+        busy = np.bincount(blocks, weights=t1 - t0) / span
+        busy = busy[np.unique(blocks)]
+        out["workers"] = int(busy.size)
+        out["worker_busy_min"] = float(busy.min())
+        out["worker_busy_mean"] = float(busy.mean())
+    return out
+
+
+def run_trace(inp=None, chunk=2048, wg=256, steps=5):
+    """The imbalanced workload's fused kernel with PIC_FLAG_TRACE, per-patch
+    and persistent: how its work items fill the launch."""
+    import torch
+
+    from paper_2204_12837_amd import inputs as I
+    from paper_2204_12837_amd import pic
+
+    wl = I.workload("imbalanced")
+    inp = I.generate(wl) if inp is None else inp
+    out = {"workload": "imbalanced", "steps": steps}
+    for name, mode in (("per_patch", 0), ("persistent", 1)):
+        ctx = pic.Context(wl, device=0, mode=mode, chunk=chunk if mode else 0,
+                          wg_size=wg if mode else 0, trace=True)
+        sp = pic.upload(inp, "cuda:0", n_slabs=ctx.n_slabs)
+        E, B, J = pic.upload_fields(inp, "cuda:0")
+        ctx.bin(sp)
+        ctx.step(sp, E, B, J, nsteps=steps)
+        torch.cuda.synchronize()
+        ctx.check()
+        out[name] = trace_summary(ctx.trace_read())
+        ctx.close()
+        del sp, E, B, J
+        torch.cuda.empty_cache()
+    return out
+
+
 def run_expansion3d(steps: int, warmup: int):
     """The 3D two-species workload: per-patch launch and the persistent
     launch with an autotuned chunk."""
@@ -672,6 +731,7 @@ def main(argv=None) -> int:
         wlr = dataclasses.replace(wli, particle_bc=(2, 0, 0))
         _, sr, tr = run_gpu(wlr, args.steps, args.warmup, mode=1, chunk=tuned["chunk"],
                             wg=tuned["wg"], inp=inpi, bin_x=tuned.get("bin_x", 0))
+        out["imbalanced"]["trace"] = run_trace(inpi, tuned["chunk"], tuned["wg"])
         out["imbalanced"]["x_remove_persistent"] = {
             "ns_per_particle_step": sr / (ni * args.steps) * 1e9, "kernel_ms": per_k(tr),
             "ipp_ratio_vs_periodic": (tr["ipp"][0] / tr["ipp"][1]) / ipp_pe,

@@ -74,11 +74,19 @@ enum { PIC_BC_PERIODIC = 0, PIC_BC_REFLECT = 1, PIC_BC_REMOVE = 2 };
 
 enum {
   PIC_FLAG_CHECK = 1, /* every call waits for its stream and reports device errors */
-  PIC_FLAG_GRAPH = 2  /* pic_step replays a captured HIP graph of its steps
+  PIC_FLAG_GRAPH = 2, /* pic_step replays a captured HIP graph of its steps
                          (one step in the slab layout, two in the dense one,
                          whose buffer swap makes two steps the period); the
                          graph is recaptured when any array pointer or count
                          changes */
+  PIC_FLAG_TRACE = 4  /* the fused kernel of pic_step's slab layout records,
+                         for every work item of each launch (a (patch,
+                         species) workgroup in per-patch mode, a popped unit
+                         in persistent mode), its patch, workgroup and start
+                         and end times; pic_trace_read returns the last
+                         launch's records (the GPU counterpart of the
+                         paper's per-operation scheduling diagnostics,
+                         section "Task scheduling visualization") */
 };
 
 typedef struct {
@@ -389,6 +397,25 @@ pic_status pic_timing_enable(pic_ctx *ctx, int32_t on);
 /* Total milliseconds and number of launches of a kernel class since timing
  * was enabled.  Waits for the recorded events. */
 pic_status pic_timing_read(pic_ctx *ctx, int32_t kernel, double *total_ms, int64_t *launches);
+
+/* One work item of a traced fused-kernel launch (PIC_FLAG_TRACE). */
+typedef struct {
+  int32_t patch;   /* the kernels' patch (x-bin when patches are cut into bins) */
+  int32_t unit;    /* persistent mode: index of the unit in the launch's work
+                      list; per-patch mode: the species */
+  int32_t block;   /* workgroup that ran it (persistent mode: the worker) */
+  int32_t species; /* species, or -1 for a unit spanning every species */
+  uint64_t t0, t1; /* start and end, ticks of the device's constant 100 MHz
+                      clock (s_memrealtime) */
+} pic_trace_record;
+
+/* Records of the last traced fused-kernel launch on this context (the last
+ * step of the last pic_step or pic_cycle call in the slab layout with
+ * PIC_FLAG_TRACE): waits for the device, copies at most cap records to out
+ * (host memory; may be NULL when cap = 0) and sets *n to the launch's
+ * record count (0 before any traced launch).  The dense layout's kernels and
+ * the split entry points are not traced. */
+pic_status pic_trace_read(pic_ctx *ctx, pic_trace_record *out, int64_t cap, int64_t *n);
 
 /* Wait for `stream` and report the sticky device error word. */
 pic_status pic_check(pic_ctx *ctx, void *stream);

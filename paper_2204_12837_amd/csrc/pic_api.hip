@@ -135,7 +135,12 @@ struct pic_ctx {
   // (pic_step_noalloc sorted them with its own scratch)
   void *noalloc = nullptr;
   bool layout_stale = false;
+  // PIC_FLAG_TRACE: header (record count of the last launch) and records
+  uint64_t *trace = nullptr;
+  int64_t trace_cap = 0;  // records
 };
+
+static_assert(sizeof(pic_trace_record) == sizeof(TraceRec), "trace record layout");
 
 namespace {
 
@@ -643,6 +648,7 @@ pic_status ensure_slab(pic_ctx *c, const pic_species *sp, int32_t nsp, hipStream
 SlabArgs make_slab_args(pic_ctx *c, const pic_species *sp, int32_t nsp) {
   SlabArgs a{};
   a.nsp = nsp;
+  a.trace = (c->cfg.flags & PIC_FLAG_TRACE) ? c->trace : nullptr;
   for (int s = 0; s < nsp; s++) {
     const pic_species &p = sp[s];
     const SlabScratch &L = c->slab[s];
@@ -773,6 +779,17 @@ pic_status step_slab(pic_ctx *c, pic_species *sp, int32_t nsp, pic_fields *f, in
                      hipStream_t st) {
   pic_status r = ensure_slab(c, sp, nsp, st);
   if (r != PIC_OK) return r;
+  if (c->cfg.flags & PIC_FLAG_TRACE) {
+    // one record per (patch, species) workgroup or per unit of the list
+    const int64_t need = std::max<int64_t>((int64_t)c->g.npatch * nsp, c->units_cap);
+    if (need > c->trace_cap) {
+      hipError_t e = hipStreamSynchronize(st);
+      if (e == hipSuccess) e = realloc_dev(c->trace, 4 + 4 * (size_t)need);
+      if (e == hipSuccess) e = hipMemset(c->trace, 0, 4 * sizeof(uint64_t));
+      if (e != hipSuccess) return hip_fail(c, e, "trace buffer");
+      c->trace_cap = need;
+    }
+  }
   const bool pers = c->cfg.mode == PIC_MODE_PERSISTENT;
   if (pers && !c->pgrid_slab) {
     int dev = 0, ncu = 0;
@@ -1060,7 +1077,7 @@ pic_status pic_validate_config(const pic_config *c, char *msg, size_t len) {
     set_msg(msg, len, "wg_size must be 0 or a multiple of 64 in [64, 1024]");
     return PIC_ERR_ARG;
   }
-  if (c->flags & ~(uint32_t)(PIC_FLAG_CHECK | PIC_FLAG_GRAPH)) {
+  if (c->flags & ~(uint32_t)(PIC_FLAG_CHECK | PIC_FLAG_GRAPH | PIC_FLAG_TRACE)) {
     set_msg(msg, len, "unknown flag bits 0x%x", c->flags);
     return PIC_ERR_ARG;
   }
@@ -1175,6 +1192,7 @@ void pic_free(pic_ctx *c) {
   }
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   (void)hipFree(c->units);
+  (void)hipFree(c->trace);
   (void)hipFree(c->qctl);
   (void)hipFree(c->err_dev);
   delete c;
@@ -1198,6 +1216,23 @@ pic_status pic_timing_read(pic_ctx *c, int32_t kernel, double *total_ms, int64_t
   timing_collect(c);
   if (total_ms) *total_ms = c->tm.ms[kernel];
   if (launches) *launches = c->tm.launches[kernel];
+  return PIC_OK;
+}
+
+pic_status pic_trace_read(pic_ctx *c, pic_trace_record *out, int64_t cap, int64_t *n) {
+  if (!c || !n || cap < 0 || (cap > 0 && !out)) return PIC_ERR_ARG;
+  *n = 0;
+  if (hipSetDevice(c->device) != hipSuccess) return fail(c, PIC_ERR_HIP, "hipSetDevice");
+  if (!c->trace) return PIC_OK;
+  hipError_t e = hipDeviceSynchronize();
+  uint64_t count = 0;
+  if (e == hipSuccess) e = hipMemcpy(&count, c->trace, sizeof(count), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(c, e, "reading the trace");
+  const int64_t m = std::min<int64_t>({(int64_t)count, cap, c->trace_cap});
+  if (m > 0 && (e = hipMemcpy(out, c->trace + 4, (size_t)m * sizeof(pic_trace_record),
+                              hipMemcpyDeviceToHost)) != hipSuccess)
+    return hip_fail(c, e, "reading the trace");
+  *n = std::min<int64_t>((int64_t)count, c->trace_cap);
   return PIC_OK;
 }
 

@@ -138,9 +138,20 @@ struct SlabDev {
   int32_t ubase;                // persistent mode: first work unit of this species
 };
 
+// One traced work item of a fused-kernel launch (PIC_FLAG_TRACE): its
+// patch, unit (persistent mode; the species in per-patch mode), workgroup,
+// and start and end times of the device's constant 100 MHz clock.  The
+// buffer holds the count of the last launch's records in its first word,
+// then the records from byte 32.
+struct TraceRec {
+  int32_t patch, unit, block, species;
+  uint64_t t0, t1;
+};
+
 struct SlabArgs {
   int nsp;
   SlabDev s[kMaxSpecies];
+  uint64_t *trace;  // trace buffer, or null when tracing is off
 };
 static_assert(sizeof(SlabArgs) <= 4096, "kernel argument block too large");
 

@@ -315,6 +315,7 @@ __global__ void __launch_bounds__(kMaxWgSlab<DIM>, kSlabMinWaves<DIM>) k_ipp_sla
   __shared__ int wtot[16];
   const int P = blockIdx.x;
   const SlabDev &S = sa.s[blockIdx.y];
+  const uint64_t t0 = sa.trace ? __builtin_amdgcn_s_memrealtime() : 0;
   if (S.ctl[1] == 2) return;
   const TileGeom t = tile_geom<DIM>(g, P);
   double *tEB = lds;
@@ -334,6 +335,21 @@ __global__ void __launch_bounds__(kMaxWgSlab<DIM>, kSlabMinWaves<DIM>) k_ipp_sla
     depart_in_kernel<DIM>(g, S, P, c, bits, pre, wtot);
   else if (threadIdx.x == 0)
     S.dep[P] = -1;  // left to the departures kernel
+  if (sa.trace) {
+    __syncthreads();  // every thread's work is done
+    if (threadIdx.x == 0) {
+      TraceRec *rec = reinterpret_cast<TraceRec *>(sa.trace + 4);
+      TraceRec r;
+      r.patch = P;
+      r.unit = (int)blockIdx.y;
+      r.block = (int)(blockIdx.y * gridDim.x + blockIdx.x);
+      r.species = (int)blockIdx.y;
+      r.t0 = t0;
+      r.t1 = __builtin_amdgcn_s_memrealtime();
+      rec[blockIdx.y * gridDim.x + blockIdx.x] = r;
+      if (blockIdx.x == 0 && blockIdx.y == 0) sa.trace[0] = (uint64_t)gridDim.x * gridDim.y;
+    }
+  }
 }
 
 // Persistent launch: workgroups pop (patch, particle range) units of each
@@ -341,10 +357,10 @@ __global__ void __launch_bounds__(kMaxWgSlab<DIM>, kSlabMinWaves<DIM>) k_ipp_sla
 // ubase), or, with combined, from one list whose units range over the
 // particles of every species of the patch (ticket qctl[0], count qctl[1],
 // list at units); E/B is restaged and J flushed only when the patch changes.
-template <int DIM, bool WALLS>
+template <int DIM, bool WALLS, bool COMBINED>
 __global__ void __launch_bounds__(kMaxWgSlab<DIM>, kSlabMinWaves<DIM>) k_ipp_slab_persistent(GridDev g, SlabArgs sa, Fields f, int *err,
-                                                                    const Unit *units, int *qctl,
-                                                                    int combined) {
+                                                                    const Unit *units, int *qctl) {
+  constexpr bool combined = COMBINED;
   extern __shared__ __align__(16) double lds[];
   __shared__ int s_unit;
   int curP = -1;
@@ -363,7 +379,11 @@ __global__ void __launch_bounds__(kMaxWgSlab<DIM>, kSlabMinWaves<DIM>) k_ipp_sla
       __syncthreads();
       const int u = __builtin_amdgcn_readfirstlane(s_unit);
       __syncthreads();  // every thread has read s_unit before the next pop
-      if (u >= n_units) break;
+      const uint64_t t0 = sa.trace ? __builtin_amdgcn_s_memrealtime() : 0;
+      if (u >= n_units) {
+        if (sa.trace && threadIdx.x == 0 && u == n_units) sa.trace[0] = (uint64_t)n_units;
+        break;
+      }
       const Unit un = ul[u];
       if (un.P != curP) {
         if (curP >= 0) {
@@ -376,7 +396,7 @@ __global__ void __launch_bounds__(kMaxWgSlab<DIM>, kSlabMinWaves<DIM>) k_ipp_sla
         __syncthreads();
         curP = un.P;
       }
-      if (combined) {
+      if constexpr (COMBINED) {
         // the unit's share of each species: [k0, k1) of the concatenation
         int base = 0;
         for (int r = 0; r < sa.nsp; r++) {
@@ -393,6 +413,16 @@ __global__ void __launch_bounds__(kMaxWgSlab<DIM>, kSlabMinWaves<DIM>) k_ipp_sla
                              nullptr);
       }
       __syncthreads();  // this unit's deposits are done before any flush
+      if (sa.trace && threadIdx.x == 0) {
+        TraceRec r;
+        r.patch = un.P;
+        r.unit = u;
+        r.block = (int)blockIdx.x;
+        r.species = combined ? -1 : s;
+        r.t0 = t0;
+        r.t1 = __builtin_amdgcn_s_memrealtime();
+        reinterpret_cast<TraceRec *>(sa.trace + 4)[u] = r;
+      }
     }
   }
   if (curP >= 0) flush_j<DIM>(g, t, tJ, f.j);
@@ -858,11 +888,20 @@ hipError_t launch_ipp_slab(const GridDev &g, const SlabArgs &sa, const double *c
 template <int DIM, bool WALLS>
 void ipp_slab_pers_t(const GridDev &g, const SlabArgs &sa, const Fields &f, int *err,
                      const Unit *units, int *qctl, int grid, int wg, size_t lds, hipStream_t st) {
+  // several species: the instance whose units range over all of them
+  if (sa.nsp > 1) {
+    if (DIM == 3)
+      (void)hipFuncSetAttribute((const void *)k_ipp_slab_persistent<DIM, WALLS, true>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL((k_ipp_slab_persistent<DIM, WALLS, true>), dim3(grid), dim3(wg), lds, st, g,
+                       sa, f, err, units, qctl);
+    return;
+  }
   if (DIM == 3)
-    (void)hipFuncSetAttribute((const void *)k_ipp_slab_persistent<DIM, WALLS>,
+    (void)hipFuncSetAttribute((const void *)k_ipp_slab_persistent<DIM, WALLS, false>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  hipLaunchKernelGGL((k_ipp_slab_persistent<DIM, WALLS>), dim3(grid), dim3(wg), lds, st, g, sa, f,
-                     err, units, qctl, sa.nsp > 1 ? 1 : 0);
+  hipLaunchKernelGGL((k_ipp_slab_persistent<DIM, WALLS, false>), dim3(grid), dim3(wg), lds, st, g,
+                     sa, f, err, units, qctl);
 }
 
 hipError_t launch_ipp_slab_persistent(const GridDev &g, const SlabArgs &sa,
@@ -880,16 +919,23 @@ hipError_t launch_ipp_slab_persistent(const GridDev &g, const SlabArgs &sa,
   return hipGetLastError();
 }
 
-template <int DIM, bool WALLS>
-int slab_blocks_t(int wg, size_t lds) {
+template <int DIM, bool WALLS, bool COMBINED>
+int slab_blocks_one(int wg, size_t lds) {
   if (DIM == 3)
-    (void)hipFuncSetAttribute((const void *)k_ipp_slab_persistent<DIM, WALLS>,
+    (void)hipFuncSetAttribute((const void *)k_ipp_slab_persistent<DIM, WALLS, COMBINED>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   int n = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_ipp_slab_persistent<DIM, WALLS>, wg,
-                                                   lds) != hipSuccess)
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_ipp_slab_persistent<DIM, WALLS, COMBINED>,
+                                                   wg, lds) != hipSuccess)
     return 0;
   return n;
+}
+
+// resident workgroups per CU of both instances (one species, several)
+template <int DIM, bool WALLS>
+int slab_blocks_t(int wg, size_t lds) {
+  return std::min(slab_blocks_one<DIM, WALLS, false>(wg, lds),
+                  slab_blocks_one<DIM, WALLS, true>(wg, lds));
 }
 
 int slab_persistent_blocks_per_cu(const GridDev &g, int wg) {

@@ -21,7 +21,7 @@ STATUS_NAMES = {0: "PIC_OK", 1: "PIC_ERR_ARG", 2: "PIC_ERR_HIP", 3: "PIC_ERR_CAP
                 4: "PIC_ERR_CFL", 5: "PIC_ERR_POS", 6: "PIC_ERR_STATE"}
 BC_PERIODIC, BC_REFLECT, BC_REMOVE = 0, 1, 2
 MODE_PER_PATCH, MODE_PERSISTENT = 0, 1
-FLAG_CHECK, FLAG_GRAPH = 1, 2
+FLAG_CHECK, FLAG_GRAPH, FLAG_TRACE = 1, 2, 4
 
 _DP = C.POINTER(C.c_double)
 _I64P = C.POINTER(C.c_int64)
@@ -51,6 +51,11 @@ class FieldsC(C.Structure):
     _fields_ = [("e", C.c_void_p * 3), ("b", C.c_void_p * 3), ("j", C.c_void_p * 3)]
 
 
+class TraceRecordC(C.Structure):
+    _fields_ = [("patch", C.c_int32), ("unit", C.c_int32), ("block", C.c_int32),
+                ("species", C.c_int32), ("t0", C.c_uint64), ("t1", C.c_uint64)]
+
+
 class CotangentC(C.Structure):
     _fields_ = [("x", C.c_void_p * 3), ("u", C.c_void_p * 3), ("n", C.c_int64)]
 
@@ -59,7 +64,7 @@ ENTRY_POINTS = ("pic_validate_config", "pic_num_patches", "pic_bin_width", "pic_
                 "pic_bin",
                 "pic_interp_push", "pic_project", "pic_step", "pic_check", "pic_last_error",
                 "pic_timing_enable", "pic_timing_read", "pic_adjoint", "pic_maxwell",
-                "pic_maxwell_adjoint", "pic_rho", "pic_cycle", "pic_step_noalloc")
+                "pic_maxwell_adjoint", "pic_rho", "pic_cycle", "pic_step_noalloc", "pic_trace_read")
 KERNELS = {"zero": 0, "ipp": 1, "rebin": 2, "interp_push": 3, "project": 4, "tag": 5, "sort": 6,
            "adjoint": 7, "exchange": 8, "slab": 9, "maxwell": 10, "rho": 11}
 
@@ -118,6 +123,9 @@ def lib():
         L.pic_cycle.argtypes = [C.c_void_p, C.POINTER(SpeciesC), C.c_int32, C.c_void_p * 3,
                                 C.c_void_p * 3, C.c_void_p * 3, C.c_int32, C.c_void_p]
         L.pic_cycle.restype = C.c_int
+        L.pic_trace_read.argtypes = [C.c_void_p, C.POINTER(TraceRecordC), C.c_int64,
+                                     C.POINTER(C.c_int64)]
+        L.pic_trace_read.restype = C.c_int
         L.pic_last_error.argtypes = [C.c_void_p]
         L.pic_last_error.restype = C.c_char_p
         _lib_handle = L
@@ -265,9 +273,10 @@ class Context:
     BC_REMOVE the calls that delete particles update each Species.n)."""
 
     def __init__(self, wl, device: int = 0, mode=MODE_PER_PATCH, chunk=0, wg_size=0,
-                 check=False, graph=False, bin_x=0):
+                 check=False, graph=False, bin_x=0, trace=False):
         self.wl = wl
-        flags = (FLAG_CHECK if check else 0) | (FLAG_GRAPH if graph else 0)
+        flags = ((FLAG_CHECK if check else 0) | (FLAG_GRAPH if graph else 0)
+                 | (FLAG_TRACE if trace else 0))
         self.cfg = make_config(wl, mode, chunk, wg_size, flags, bin_x)
         rc, msg = validate(self.cfg)
         if rc:
@@ -373,6 +382,16 @@ class Context:
         rc = lib().pic_adjoint(self._h, arr, len(ckpt), C.byref(f), jb, int(nsteps),
                                int(with_deposit), cs, eb, bb, _stream())
         self._raise(rc)
+
+    def trace_read(self):
+        """Records of the last traced fused-kernel launch (PIC_FLAG_TRACE) as
+        a list of (patch, unit, block, species, t0, t1) tuples; t0, t1 in
+        ticks of the device's 100 MHz clock."""
+        n = C.c_int64()
+        self._raise(lib().pic_trace_read(self._h, None, 0, C.byref(n)))
+        buf = (TraceRecordC * max(n.value, 1))()
+        self._raise(lib().pic_trace_read(self._h, buf, n.value, C.byref(n)))
+        return [(r.patch, r.unit, r.block, r.species, r.t0, r.t1) for r in buf[:n.value]]
 
     def timing(self, on: bool = True):
         self._raise(lib().pic_timing_enable(self._h, 1 if on else 0))
