@@ -38,7 +38,8 @@
  *   Errors    host-detectable errors (bad config, null pointer, count above
  *             capacity, wrong call order) return at once with nothing
  *             enqueued.  Errors found by kernels (a particle moving more than
- *             one cell, a position outside the box) set a sticky error word
+ *             one cell, a position outside the box, a particle outside the
+ *             patch its offsets give it) set a sticky error word
  *             in the context; pic_check (or any call when PIC_FLAG_CHECK is
  *             set) waits for the stream and reports it.  After a device
  *             error the context refuses further work until pic_free.
@@ -63,8 +64,11 @@ typedef enum {
   PIC_ERR_HIP = 2,      /* a HIP runtime call failed */
   PIC_ERR_CAPACITY = 3, /* n above capacity, or too many patches/species */
   PIC_ERR_CFL = 4,      /* a particle moved more than one cell in a step */
-  PIC_ERR_POS = 5,      /* a position more than one period outside the box */
-  PIC_ERR_STATE = 6     /* wrong call order, or context poisoned by an error */
+  PIC_ERR_POS = 5,      /* a position more than one period outside the box, or
+                           outside [0, L) on an axis with reflecting walls */
+  PIC_ERR_STATE = 6,    /* wrong call order, or context poisoned by an error */
+  PIC_ERR_UNSORTED = 7  /* a particle lies outside the patch its offsets
+                           assign it to: the input was not sorted by patch */
 } pic_status;
 
 enum { PIC_MODE_PER_PATCH = 0, PIC_MODE_PERSISTENT = 1 };
@@ -79,6 +83,18 @@ enum {
                          whose buffer swap makes two steps the period); the
                          graph is recaptured when any array pointer or count
                          changes */
+  PIC_FLAG_DETERMINISTIC = 8, /* pic_step and pic_cycle give the same bits on
+                         every run: the dense layout (its counting sort is
+                         stable), the per-patch launch (also in persistent
+                         mode), every wave of a patch's workgroup depositing
+                         into a J tile of its own, the tiles summed in wave
+                         order and J at every node summed from the covering
+                         tiles in a fixed order (no float64 atomics).  Costs
+                         a tile buffer of npatch x species x 3 (p+5)^dim
+                         doubles and fewer waves per workgroup where the
+                         tiles do not fit (3D).  Not with removing walls
+                         (PIC_ERR_ARG).  pic_project and pic_rho keep their
+                         order-dependent float64 atomic sums. */
   PIC_FLAG_TRACE = 4  /* the fused kernel of pic_step's slab layout records,
                          for every work item of each launch (a (patch,
                          species) workgroup in per-patch mode, a popped unit

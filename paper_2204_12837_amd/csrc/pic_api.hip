@@ -138,6 +138,9 @@ struct pic_ctx {
   // PIC_FLAG_TRACE: header (record count of the last launch) and records
   uint64_t *trace = nullptr;
   int64_t trace_cap = 0;  // records
+  // PIC_FLAG_DETERMINISTIC: every (species, patch)'s J tile
+  double *jt = nullptr;
+  size_t jt_cap = 0;  // doubles
 };
 
 static_assert(sizeof(pic_trace_record) == sizeof(TraceRec), "trace record layout");
@@ -478,10 +481,19 @@ hipError_t enqueue_step(pic_ctx *c, const pic_species *sp, int32_t nsp, const pi
   for (int a = 0; a < c->cfg.dim; a++) ncell *= c->cfg.n[a];
   SpArgs a = make_args(c, sp, nsp, scr);
   a.gather = gather ? 1 : 0;
-  const bool pers = c->cfg.mode == PIC_MODE_PERSISTENT;
-  hipError_t e = timed(c, PIC_KERNEL_ZERO, st, [&] { return launch_zero(f->j, ncell, st); });
+  // deterministic: the per-patch launch with per-wave J tiles, then J from
+  // the tiles in a fixed order (no J <- 0 needed: the gather writes J)
+  const bool det = (c->cfg.flags & PIC_FLAG_DETERMINISTIC) != 0;
+  const bool pers = c->cfg.mode == PIC_MODE_PERSISTENT && !det;
+  a.jt = det ? c->jt : nullptr;
+  hipError_t e = hipSuccess;
+  if (!det) e = timed(c, PIC_KERNEL_ZERO, st, [&] { return launch_zero(f->j, ncell, st); });
   if (e == hipSuccess)
     e = timed(c, PIC_KERNEL_IPP, st, [&] {
+      if (det) {
+        hipError_t r2 = launch_ipp(c->g, a, f->e, f->b, f->j, c->err_dev, c->wgd, st);
+        return r2 == hipSuccess ? launch_j_gather(c->g, a, f->j, st) : r2;
+      }
       return pers ? launch_ipp_persistent(c->g, a, f->e, f->b, f->j, c->err_dev, units, c->qctl,
                                           c->pgrid, c->wgd, st)
                   : launch_ipp(c->g, a, f->e, f->b, f->j, c->err_dev, c->wgd, st);
@@ -1077,7 +1089,8 @@ pic_status pic_validate_config(const pic_config *c, char *msg, size_t len) {
     set_msg(msg, len, "wg_size must be 0 or a multiple of 64 in [64, 1024]");
     return PIC_ERR_ARG;
   }
-  if (c->flags & ~(uint32_t)(PIC_FLAG_CHECK | PIC_FLAG_GRAPH | PIC_FLAG_TRACE)) {
+  if (c->flags &
+      ~(uint32_t)(PIC_FLAG_CHECK | PIC_FLAG_GRAPH | PIC_FLAG_TRACE | PIC_FLAG_DETERMINISTIC)) {
     set_msg(msg, len, "unknown flag bits 0x%x", c->flags);
     return PIC_ERR_ARG;
   }
@@ -1087,6 +1100,14 @@ pic_status pic_validate_config(const pic_config *c, char *msg, size_t len) {
               a, c->particle_bc[a]);
       return PIC_ERR_ARG;
     }
+  if (c->flags & PIC_FLAG_DETERMINISTIC)
+    for (int a = 0; a < c->dim; a++)
+      if (c->particle_bc[a] == PIC_BC_REMOVE) {
+        set_msg(msg, len,
+                "PIC_FLAG_DETERMINISTIC keeps the dense layout, which cannot delete particles "
+                "(removing walls on axis %d)", a);
+        return PIC_ERR_ARG;
+      }
   if (c->bin_x < 0 || (c->bin_x > 0 && c->patch[0] % c->bin_x)) {
     set_msg(msg, len, "bin_x=%d must be 0 (auto) or divide patch[0]=%d", c->bin_x, c->patch[0]);
     return PIC_ERR_ARG;
@@ -1136,6 +1157,8 @@ pic_status pic_init(const pic_config *cfg, int32_t device, pic_ctx **out) {
   c->device = device;
   c->wg = cfg->wg_size ? cfg->wg_size : default_wg(&c->cfg);
   c->wgd = std::min(c->wg, c->cfg.dim == 2 ? 256 : 512);
+  // deterministic: as many waves as private J tiles fit beside the E/B tile
+  if (c->cfg.flags & PIC_FLAG_DETERMINISTIC) c->wgd = 64 * det_waves(c->g, c->wgd);
   const int chunk = cfg->chunk ? cfg->chunk : 2048;
   c->g.spc = std::max(1, chunk / kSeg);
   if (hipMalloc(&c->err_dev, sizeof(int)) != hipSuccess ||
@@ -1193,6 +1216,7 @@ void pic_free(pic_ctx *c) {
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   (void)hipFree(c->units);
   (void)hipFree(c->trace);
+  (void)hipFree(c->jt);
   (void)hipFree(c->qctl);
   (void)hipFree(c->err_dev);
   delete c;
@@ -1250,8 +1274,11 @@ pic_status pic_check(pic_ctx *c, void *stream) {
       return fail(c, PIC_ERR_CFL, "a particle moved more than one cell in one step");
     if (h & kErrCap)
       return fail(c, PIC_ERR_CAPACITY, "the per-patch slabs outgrew the particle buffers");
+    if (h & kErrUnsorted)
+      return fail(c, PIC_ERR_UNSORTED,
+                  "a particle lies outside the patch its offsets assign it to (not sorted by patch)");
     return fail(c, PIC_ERR_POS,
-                "a particle lies outside its patch or more than one period outside the box");
+                "a position lies more than one period outside the box (or outside a walled axis)");
   }
   if (c->poisoned) return PIC_ERR_STATE;
   return PIC_OK;
@@ -1328,7 +1355,20 @@ pic_status pic_step(pic_ctx *c, pic_species *sp, int32_t nsp, pic_fields *f, int
   if (c->g.remove && !slab_fits(c, sp, nsp))
     return fail(c, PIC_ERR_CAPACITY,
                 "removing walls need buffers with the slab layout's room (n + n/8 + 80 per slab)");
-  const bool slab = (nsteps >= 3 || c->g.remove) && slab_fits(c, sp, nsp);
+  const bool det = (c->cfg.flags & PIC_FLAG_DETERMINISTIC) != 0;
+  const bool slab = !det && (nsteps >= 3 || c->g.remove) && slab_fits(c, sp, nsp);
+  if (det) {
+    // one J tile per (species, patch)
+    size_t tj = 3;
+    for (int a = 0; a < c->cfg.dim; a++) tj *= (size_t)(c->g.patch[a] + 5);
+    const size_t need = tj * (size_t)c->g.npatch * (size_t)nsp;
+    if (need > c->jt_cap) {
+      hipError_t e = hipStreamSynchronize(st);
+      if (e == hipSuccess) e = realloc_dev(c->jt, need);
+      if (e != hipSuccess) return hip_fail(c, e, "hipMalloc");
+      c->jt_cap = need;
+    }
+  }
   // x-bins: the particles arrive sorted by patch; the kernels need them by
   // bin (the slab layout's first copy orders them itself)
   if (c->nb > 1 && !(slab && bin_order_supported(c->nb)) &&
@@ -1357,6 +1397,8 @@ pic_status pic_step_noalloc(pic_ctx *c, pic_species *sp, int32_t nsp, pic_fields
     return fail(c, PIC_ERR_ARG, "pic_step_noalloc: x-bins need the per-call bin sort (pic_step)");
   if (c->g.remove)
     return fail(c, PIC_ERR_ARG, "pic_step_noalloc: removing walls need the slab layout (pic_step)");
+  if (c->cfg.flags & PIC_FLAG_DETERMINISTIC)
+    return fail(c, PIC_ERR_ARG, "pic_step_noalloc: PIC_FLAG_DETERMINISTIC needs its tile buffer (pic_step)");
   if (!c->noalloc) return fail(c, PIC_ERR_HIP, "pic_step_noalloc: no static scratch on this device");
   // the dense layout's scratch, carved from the static array in 256-byte
   // aligned pieces: per species the tags and permutation (n each), the

@@ -13,6 +13,7 @@ constexpr int kCntRow = 64; // row length of the per-segment code counts (one pe
 constexpr int kErrCFL = 1;  // device error bits
 constexpr int kErrPos = 2;
 constexpr int kErrCap = 4;  // the slab layout does not fit the particle buffers
+constexpr int kErrUnsorted = 8;  // a particle outside the patch its offsets give it
 
 // Grid geometry as the kernels see it.  All derived values (inverse cell
 // sizes, box lengths, Esirkepov factors) are computed once on the host.
@@ -205,6 +206,8 @@ struct SpArgs {
   int gather;  // fused kernel: read particle j from perm[j] of the other buffer set
                // (the layout the previous sort computed) and write slot j
   SpDev s[kMaxSpecies];
+  double *jt;  // PIC_FLAG_DETERMINISTIC: each (species, patch)'s J tile
+               // [nsp][npatch][3][TJ], summed into J by k_j_gather; null otherwise
 };
 
 // Launch helpers (implemented in pic_kernels.hip).  Each returns the HIP
@@ -213,6 +216,11 @@ hipError_t launch_zero(double *const j[3], int64_t ncell, hipStream_t st);
 hipError_t launch_ipp(const GridDev &g, const SpArgs &sa, const double *const e[3],
                       const double *const b[3], double *const j[3], int *err, int wg,
                       hipStream_t st);
+// PIC_FLAG_DETERMINISTIC: waves of the per-patch fused kernel whose private
+// J tiles fit beside the E/B tile (at most wg / 64), and J <- the tiles in
+// sa.jt summed per node in a fixed order.
+int det_waves(const GridDev &g, int wg);
+hipError_t launch_j_gather(const GridDev &g, const SpArgs &sa, double *const j[3], hipStream_t st);
 // Persistent variant: `grid` workgroups pop units from units[0 .. qctl[1]) with
 // the ticket qctl[0] (reset by launch_layout).
 hipError_t launch_ipp_persistent(const GridDev &g, const SpArgs &sa, const double *const e[3],

@@ -641,7 +641,7 @@ __device__ __forceinline__ int step_particle(const GridDev &g, const TileGeom &t
 #pragma unroll
   for (int a = 0; a < DIM; a++) xi[a] = x[a] * g.inv_d[a];
   if (!in_patch<DIM>(t, xi)) {
-    bad |= kErrPos;
+    bad |= kErrUnsorted;
     return CENTER;
   }
   const Shapes sh = shapes_at<DIM>(xi, t.org);

@@ -140,22 +140,96 @@ __device__ __forceinline__ void ipp_segments(const GridDev &g, const SpDev &S, c
 
 // Per-patch launch: one workgroup per (patch, species), all its segments.
 // WALLS: instance with reflecting walls (the periodic one compiles them out).
+// With sa.jt (PIC_FLAG_DETERMINISTIC) every wave deposits into a J tile of
+// its own, so no two waves race on a node: the LDS atomics of one wave
+// apply in program order.  The tiles are then added in wave order and the
+// sum is stored as this (species, patch)'s tile in sa.jt instead of being
+// added to the grid with atomics.
 template <int DIM, bool GATHER, bool WALLS>
 __global__ void __launch_bounds__(kMaxWg<DIM>, kMinWaves<DIM>) k_ipp(GridDev g, SpArgs sa, Fields f, int *err) {
   extern __shared__ __align__(16) double lds[];
   const int P = blockIdx.x;
   const SpDev &S = sa.s[blockIdx.y];
   const TileGeom t = tile_geom<DIM>(g, P);
+  const int nw = blockDim.x >> 6;
+  const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   double *tEB = lds;
-  double *tJ = lds + 6 * t.TE;
+  double *tJ0 = lds + 6 * t.TE;
+  double *tJ = sa.jt ? tJ0 + (size_t)wv * 3 * t.TJ : tJ0;
   stage_eb<DIM>(g, t, f, tEB);
-  zero_tile<DIM>(tJ, 3 * t.TJ);
+  zero_tile<DIM>(tJ0, 3 * t.TJ * (sa.jt ? nw : 1));
   __syncthreads();
   int bad = 0;
   ipp_segments<DIM, GATHER, WALLS>(g, S, t, tEB, tJ, P, 0, S.sstart[P + 1] - S.sstart[P], bad);
   if (bad) atomicOr(err, bad);
   __syncthreads();
+  if (sa.jt) {
+    const int n3 = 3 * t.TJ;
+    double *out = sa.jt + ((size_t)blockIdx.y * g.npatch + P) * n3;
+    for (int r = threadIdx.x; r < n3; r += blockDim.x) {
+      double v = tJ0[r];
+      for (int k = 1; k < nw; k++) v += tJ0[(size_t)k * n3 + r];
+      out[r] = v;
+    }
+    return;
+  }
   flush_j<DIM>(g, t, tJ, f.j);
+}
+
+// PIC_FLAG_DETERMINISTIC: J at every node = the sum of the tile entries that
+// cover it, species by species, the covering patches in a fixed order.  A
+// patch's J tile spans nodes [P p - 2, P p + p + 3) along each axis, so a
+// node is covered by the patch of (node + 2) / p at tile index
+// r = (node + 2) - P p, and by the k-th patch before it (at r + k p) while
+// r + k p < p + 5 (x-bins can be as narrow as one cell: up to six patches;
+// with few patches along the axis, one patch may cover the node twice).
+template <int DIM>
+__global__ void __launch_bounds__(256) k_j_gather(GridDev g, SpArgs sa, Fields f) {
+  const int64_t ncell = (int64_t)g.n[0] * g.n[1] * g.n[2];
+  const int Jx = g.patch[0] + 5, Jy = g.patch[1] + 5, Jz = DIM == 3 ? g.patch[2] + 5 : 1;
+  const int64_t TJ = (int64_t)Jx * Jy * Jz;
+  for (int64_t node = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; node < ncell;
+       node += (int64_t)gridDim.x * blockDim.x) {
+    int gc[3];
+    gc[0] = (int)(node % g.n[0]);
+    const int64_t rest = node / g.n[0];
+    gc[1] = (int)(rest % g.n[1]);
+    gc[2] = (int)(rest / g.n[1]);
+    constexpr int kCover = 6;
+    int cp[3][kCover], cr[3][kCover], nc[3];
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+      nc[a] = 1;
+      cp[a][0] = 0;
+      cr[a][0] = 0;
+      if (a >= DIM) continue;
+      const int p = g.patch[a];
+      int q = (gc[a] + 2) / p;
+      int r = gc[a] + 2 - q * p;
+      if (q >= g.np[a]) q -= g.np[a];
+      nc[a] = 0;
+      while (nc[a] < kCover && r < p + 5) {
+        cp[a][nc[a]] = q;
+        cr[a][nc[a]] = r;
+        nc[a]++;
+        q = q == 0 ? g.np[a] - 1 : q - 1;
+        r += p;
+      }
+    }
+    double v[3] = {0.0, 0.0, 0.0};
+    for (int s = 0; s < sa.nsp; s++)
+      for (int kz = 0; kz < nc[2]; kz++)
+        for (int ky = 0; ky < nc[1]; ky++)
+          for (int kx = 0; kx < nc[0]; kx++) {
+            const int64_t P = cp[0][kx] + (int64_t)g.np[0] * (cp[1][ky] + (int64_t)g.np[1] * cp[2][kz]);
+            const int64_t r = cr[0][kx] + (int64_t)Jx * (cr[1][ky] + (int64_t)Jy * cr[2][kz]);
+            const double *T = sa.jt + ((int64_t)s * g.npatch + P) * 3 * TJ + r;
+#pragma unroll
+            for (int c = 0; c < 3; c++) v[c] += T[c * TJ];
+          }
+#pragma unroll
+    for (int c = 0; c < 3; c++) f.j[c][node] = v[c];
+  }
 }
 
 // Persistent launch: a fixed grid of workgroups pops (patch, segment range)
@@ -225,7 +299,7 @@ __global__ void __launch_bounds__(kMaxWg<DIM>) k_interp_push(GridDev g, SpArgs s
       S.x0[a][i] = x[a];
     }
     if (!in_patch<DIM>(t, xi)) {
-      bad |= kErrPos;
+      bad |= kErrUnsorted;
       continue;
     }
     u[0] = S.u[0][i];
@@ -266,7 +340,7 @@ __global__ void __launch_bounds__(kMaxWg<DIM>) k_project(GridDev g, SpArgs sa, F
 #pragma unroll
     for (int a = 0; a < DIM; a++) xi0[a] = S.x0[a][i] * g.inv_d[a];
     if (!in_patch<DIM>(t, xi0)) {
-      bad |= kErrPos;
+      bad |= kErrUnsorted;
       continue;
     }
     if (g.remove) {  // left through a removing wall: deleted, deposits nothing
@@ -579,18 +653,37 @@ hipError_t launch_zero(double *const j[3], int64_t ncell, hipStream_t st) {
 template <int DIM, bool GATHER, bool WALLS>
 void launch_ipp_t(const GridDev &g, const SpArgs &sa, const Fields &f, int *err, int wg,
                   size_t lds, hipStream_t st) {
-  if (DIM == 3)
+  if (DIM == 3 || sa.jt)
     (void)hipFuncSetAttribute((const void *)k_ipp<DIM, GATHER, WALLS>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   hipLaunchKernelGGL((k_ipp<DIM, GATHER, WALLS>), dim3(g.npatch, sa.nsp), dim3(wg), lds, st, g,
                      sa, f, err);
 }
 
+int det_waves(const GridDev &g, int wg) {
+  const size_t room = (size_t)160 * 1024 - 4352 - tile_eb_bytes(g);
+  const int fit = (int)(room / tile_j_bytes(g));
+  return std::max(1, std::min(wg / 64, fit));
+}
+
+hipError_t launch_j_gather(const GridDev &g, const SpArgs &sa, double *const j[3], hipStream_t st) {
+  const Fields f = mkfields(nullptr, nullptr, j);
+  const int64_t ncell = (int64_t)g.n[0] * g.n[1] * g.n[2];
+  const int blocks = (int)std::min<int64_t>((ncell + 255) / 256, 8192);
+  if (g.dim == 2)
+    hipLaunchKernelGGL(k_j_gather<2>, dim3(blocks), dim3(256), 0, st, g, sa, f);
+  else
+    hipLaunchKernelGGL(k_j_gather<3>, dim3(blocks), dim3(256), 0, st, g, sa, f);
+  return hipGetLastError();
+}
+
 hipError_t launch_ipp(const GridDev &g, const SpArgs &sa, const double *const e[3],
                       const double *const b[3], double *const j[3], int *err, int wg,
                       hipStream_t st) {
   const Fields f = mkfields(e, b, j);
-  const size_t lds = lds_bytes_ipp(g);
+  // deterministic mode: one J tile per wave
+  const size_t lds = sa.jt ? tile_eb_bytes(g) + (size_t)(wg / 64) * tile_j_bytes(g)
+                           : lds_bytes_ipp(g);
   const int v = (g.dim == 3 ? 4 : 0) + (sa.gather ? 2 : 0) + (has_walls(g) ? 1 : 0);
   switch (v) {
     case 0: launch_ipp_t<2, false, false>(g, sa, f, err, wg, lds, st); break;

@@ -83,7 +83,7 @@ __global__ void __launch_bounds__(kRhoWg) k_rho(RhoArgs a, int *err) {
           }
         }
   }
-  if (bad) atomicOr(err, kErrPos);
+  if (bad) atomicOr(err, kErrUnsorted);
   if constexpr (TILE) {
     __syncthreads();
     for (int k = threadIdx.x; k < tn; k += blockDim.x) {

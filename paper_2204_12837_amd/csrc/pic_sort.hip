@@ -10,9 +10,9 @@
 // a stable least-significant-digit radix sort of (key, index) pairs with
 // 8-bit digits, then a gather of the particles into the second buffer set and
 // the patch offsets.  Each radix pass is a counting sort written out by hand:
-// per-tile digit histograms, one scan over (digit, tile), and a scatter
-// whose ranks inside a tile come from wave ballots (the lanes holding the
-// same digit are found with eight ballots, one per digit bit).
+// per-tile digit histograms, a scan over the tiles of each digit, and a
+// scatter whose ranks inside a tile come from wave ballots (the lanes holding
+// the same digit are found with eight ballots, one per digit bit).
 //
 // Bin order, for particles already sorted by patch whose patches are cut
 // into x-bins (paper, section "Parallelization with OpenMP task": bins of
@@ -106,29 +106,46 @@ __global__ void __launch_bounds__(kRadixThreads) k_radix_hist(const uint32_t *ke
   hist[(int64_t)threadIdx.x * ntile + blockIdx.x] = h[threadIdx.x];
 }
 
-// Radix pass, step 2: exclusive scan of hist[0 .. m) in place (one workgroup
-// of 1024 threads, each summing a contiguous run).
-__global__ void __launch_bounds__(1024) k_radix_scan(uint32_t *hist, int64_t m) {
-  __shared__ uint32_t part[1024];
-  const int64_t per = (m + 1023) / 1024;
-  const int64_t b = (int64_t)threadIdx.x * per;
-  const int64_t e = b + per < m ? b + per : m;
-  uint32_t sum = 0;
-  for (int64_t k = b; k < e; k++) sum += hist[k];
-  part[threadIdx.x] = sum;
-  __syncthreads();
-  for (int off = 1; off < 1024; off <<= 1) {
-    const uint32_t v = threadIdx.x >= (unsigned)off ? part[threadIdx.x - off] : 0u;
+// Radix pass, step 2: for each digit (one workgroup each), the exclusive
+// scan of its tiles' counts in place, and the digit's total in dtot.
+__global__ void __launch_bounds__(kRadixThreads) k_radix_scan(uint32_t *hist, int ntile,
+                                                              uint32_t *dtot) {
+  constexpr int kWaves = kRadixThreads / 64;
+  constexpr int kPer = 4;  // consecutive entries per thread and chunk
+  __shared__ uint32_t ws[kWaves];
+  uint32_t *h = hist + (int64_t)blockIdx.x * ntile;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  uint32_t carry = 0;
+  for (int c0 = 0; c0 < ntile; c0 += kRadixThreads * kPer) {
+    const int b = c0 + (int)threadIdx.x * kPer;
+    uint32_t v[kPer], sum = 0;
+#pragma unroll
+    for (int k = 0; k < kPer; k++) {
+      v[k] = b + k < ntile ? h[b + k] : 0u;
+      sum += v[k];
+    }
+    uint32_t x = sum;  // inclusive scan of the threads' sums inside the wave
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint32_t y = __shfl_up(x, o, 64);
+      if (lane >= o) x += y;
+    }
+    if (lane == 63) ws[wv] = x;
     __syncthreads();
-    part[threadIdx.x] += v;
-    __syncthreads();
+    uint32_t run = carry + x - sum, all = 0;
+    for (int w = 0; w < kWaves; w++) {
+      if (w < wv) run += ws[w];
+      all += ws[w];
+    }
+#pragma unroll
+    for (int k = 0; k < kPer; k++) {
+      if (b + k < ntile) h[b + k] = run;
+      run += v[k];
+    }
+    carry += all;
+    __syncthreads();  // ws is read before the next chunk writes it
   }
-  uint32_t run = part[threadIdx.x] - sum;
-  for (int64_t k = b; k < e; k++) {
-    const uint32_t v = hist[k];
-    hist[k] = run;
-    run += v;
-  }
+  if (threadIdx.x == 0) dtot[blockIdx.x] = carry;
 }
 
 // Radix pass, step 3: stable scatter of each tile.  The tile is taken in
@@ -139,12 +156,28 @@ __global__ void __launch_bounds__(1024) k_radix_scan(uint32_t *hist, int64_t m) 
 // positions (first pass).
 __global__ void __launch_bounds__(kRadixThreads) k_radix_scatter(
     const uint32_t *keys_in, const uint32_t *idx_in, uint32_t *keys_out, uint32_t *idx_out,
-    int64_t n, int shift, const uint32_t *hist, int ntile) {
+    int64_t n, int shift, const uint32_t *hist, const uint32_t *dtot, int ntile) {
   constexpr int kWaves = kRadixThreads / 64;
   __shared__ uint32_t run[kRadixBins];
   __shared__ uint32_t wc[kWaves][kRadixBins];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  run[threadIdx.x] = hist[(int64_t)threadIdx.x * ntile + blockIdx.x];
+  {
+    // this tile's first slot of each digit: the earlier digits' totals (an
+    // exclusive scan over the 256 digits) plus the earlier tiles' counts
+    const uint32_t t = dtot[threadIdx.x];
+    uint32_t x = t;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint32_t y = __shfl_up(x, o, 64);
+      if (lane >= o) x += y;
+    }
+    if (lane == 63) wc[0][wv] = x;
+    __syncthreads();
+    uint32_t base = x - t;
+    for (int w = 0; w < wv; w++) base += wc[0][w];
+    run[threadIdx.x] = base + hist[(int64_t)threadIdx.x * ntile + blockIdx.x];
+    __syncthreads();  // wc is cleared by the first chunk below
+  }
   const int64_t t0 = (int64_t)blockIdx.x * kRadixTile;
   const int64_t t1 = t0 + kRadixTile < n ? t0 + kRadixTile : n;
   for (int64_t base = t0; base < t1; base += kRadixThreads) {
@@ -280,7 +313,7 @@ __global__ void __launch_bounds__(kBinThreads) k_bin_hist(GridDev g, SpDev s, co
     for (int a = 0; a < DIM; a++) x[a] = s.x[a][i];
     int b = bin_in_patch<DIM>(g, nb, pc, x);
     if (b < 0) {
-      bad |= kErrPos;
+      bad |= kErrUnsorted;
       b = 0;
     }
     atomicAdd(&h[b], 1);
@@ -409,8 +442,8 @@ hipError_t general_sort(const GridDev &g, SpDev &s, SortScratch &scr, int *err, 
     if ((e = grow(scr.keys_out, n)) != hipSuccess) return e;
     if ((e = grow(scr.idx, n)) != hipSuccess) return e;
     if ((e = grow(scr.idx_out, n)) != hipSuccess) return e;
-    if ((e = grow(scr.hist, (int64_t)kRadixBins * ((n + kRadixTile - 1) / kRadixTile))) !=
-        hipSuccess)
+    if ((e = grow(scr.hist, (int64_t)kRadixBins * ((n + kRadixTile - 1) / kRadixTile) +
+                                kRadixBins)) != hipSuccess)
       return e;
     scr.cap = n;
   }
@@ -430,11 +463,12 @@ hipError_t general_sort(const GridDev &g, SpDev &s, SortScratch &scr, int *err, 
       hipLaunchKernelGGL(k_radix_hist, dim3(ntile), dim3(kRadixThreads), 0, st, kin, n, shift,
                          scr.hist, ntile);
       if ((e = hipGetLastError()) != hipSuccess) return e;
-      hipLaunchKernelGGL(k_radix_scan, dim3(1), dim3(1024), 0, st, scr.hist,
-                         (int64_t)kRadixBins * ntile);
+      uint32_t *dtot = scr.hist + (int64_t)kRadixBins * ntile;  // per-digit totals
+      hipLaunchKernelGGL(k_radix_scan, dim3(kRadixBins), dim3(kRadixThreads), 0, st, scr.hist,
+                         ntile, dtot);
       if ((e = hipGetLastError()) != hipSuccess) return e;
       hipLaunchKernelGGL(k_radix_scatter, dim3(ntile), dim3(kRadixThreads), 0, st, kin, iin, kout,
-                         iout, n, shift, scr.hist, ntile);
+                         iout, n, shift, scr.hist, dtot, ntile);
       if ((e = hipGetLastError()) != hipSuccess) return e;
       std::swap(kin, kout);
       iin = iout;

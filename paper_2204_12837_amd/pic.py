@@ -16,12 +16,13 @@ import torch
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libpic.so")
 
-PIC_OK, PIC_ERR_ARG, PIC_ERR_HIP, PIC_ERR_CAPACITY, PIC_ERR_CFL, PIC_ERR_POS, PIC_ERR_STATE = range(7)
+(PIC_OK, PIC_ERR_ARG, PIC_ERR_HIP, PIC_ERR_CAPACITY, PIC_ERR_CFL, PIC_ERR_POS, PIC_ERR_STATE,
+ PIC_ERR_UNSORTED) = range(8)
 STATUS_NAMES = {0: "PIC_OK", 1: "PIC_ERR_ARG", 2: "PIC_ERR_HIP", 3: "PIC_ERR_CAPACITY",
-                4: "PIC_ERR_CFL", 5: "PIC_ERR_POS", 6: "PIC_ERR_STATE"}
+                4: "PIC_ERR_CFL", 5: "PIC_ERR_POS", 6: "PIC_ERR_STATE", 7: "PIC_ERR_UNSORTED"}
 BC_PERIODIC, BC_REFLECT, BC_REMOVE = 0, 1, 2
 MODE_PER_PATCH, MODE_PERSISTENT = 0, 1
-FLAG_CHECK, FLAG_GRAPH, FLAG_TRACE = 1, 2, 4
+FLAG_CHECK, FLAG_GRAPH, FLAG_TRACE, FLAG_DETERMINISTIC = 1, 2, 4, 8
 
 _DP = C.POINTER(C.c_double)
 _I64P = C.POINTER(C.c_int64)
@@ -273,10 +274,10 @@ class Context:
     BC_REMOVE the calls that delete particles update each Species.n)."""
 
     def __init__(self, wl, device: int = 0, mode=MODE_PER_PATCH, chunk=0, wg_size=0,
-                 check=False, graph=False, bin_x=0, trace=False):
+                 check=False, graph=False, bin_x=0, trace=False, deterministic=False):
         self.wl = wl
         flags = ((FLAG_CHECK if check else 0) | (FLAG_GRAPH if graph else 0)
-                 | (FLAG_TRACE if trace else 0))
+                 | (FLAG_TRACE if trace else 0) | (FLAG_DETERMINISTIC if deterministic else 0))
         self.cfg = make_config(wl, mode, chunk, wg_size, flags, bin_x)
         rc, msg = validate(self.cfg)
         if rc:

@@ -178,3 +178,19 @@ def test_invalid_particle_boundaries_rejected(bc):
     for ok in ((1, 2, 0), (2, 2, 0), (0, 1, 0)):
         wl = dataclasses.replace(wl, particle_bc=ok)
         assert pic.validate(pic.make_config(wl))[0] == pic.PIC_OK
+
+
+def test_deterministic_flag_refuses_removing_walls():
+    """PIC_FLAG_DETERMINISTIC keeps the dense layout, which cannot delete
+    particles: a removing wall is refused; reflecting walls are accepted."""
+    import dataclasses
+
+    base = I.custom(2, (32, 32), (8, 8), ppc=1)
+    rc, msg = pic.validate(pic.make_config(dataclasses.replace(base, particle_bc=(2, 0, 0)),
+                                           flags=pic.FLAG_DETERMINISTIC))
+    assert rc == pic.PIC_ERR_ARG and "DETERMINISTIC" in msg, msg
+    rc, msg = pic.validate(pic.make_config(dataclasses.replace(base, particle_bc=(1, 0, 0)),
+                                           flags=pic.FLAG_DETERMINISTIC))
+    assert rc == pic.PIC_OK, msg
+    rc, msg = pic.validate(pic.make_config(base, flags=16))
+    assert rc == pic.PIC_ERR_ARG

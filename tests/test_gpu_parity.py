@@ -347,7 +347,7 @@ def test_x_bins_from_patch_order(mode, layout):
 @pytest.mark.parametrize("layout", list(LAYOUTS))
 def test_particle_outside_its_patch_is_reported(layout):
     """Offsets that hand patch 0 the particles of its x-neighbour: the fused
-    kernel's tile bounds check reports PIC_ERR_POS at the next check, and the
+    kernel's tile bounds check reports PIC_ERR_UNSORTED at the next check, and the
     context then refuses work (PIC_ERR_STATE) until it is freed."""
     import torch
 
@@ -367,7 +367,7 @@ def test_particle_outside_its_patch_is_reported(layout):
     ctx.step(sp, E, B, J, nsteps=3)
     with pytest.raises(pic.PicError) as ei:
         ctx.check()
-    assert ei.value.status == pic.PIC_ERR_POS
+    assert ei.value.status == pic.PIC_ERR_UNSORTED
     with pytest.raises(pic.PicError) as ei:
         ctx.step(sp, E, B, J, nsteps=1)
     assert ei.value.status == pic.PIC_ERR_STATE

@@ -90,7 +90,7 @@ def test_rho_after_steps_and_empty_patches():
 
 def test_rho_flags_a_particle_outside_its_patch():
     """Offsets that hand patch 0 the particles of patch 1: the kernel's tile
-    bounds check turns them into the position error."""
+    bounds check reports unsorted input."""
     wl = I.custom(2, (32, 32), (8, 8), ppc=2, seed=812)
     inp = I.generate(wl)
     ctx = pic.Context(wl)
@@ -103,5 +103,5 @@ def test_rho_flags_a_particle_outside_its_patch():
     ctx.rho(sp, rho)
     with pytest.raises(pic.PicError) as ei:
         ctx.check()
-    assert ei.value.status == pic.PIC_ERR_POS
+    assert ei.value.status == pic.PIC_ERR_UNSORTED
     ctx.close()
