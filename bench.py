@@ -113,6 +113,32 @@ def cpu_model() -> str:
     return platform.processor() or "unknown"
 
 
+def host_cpu() -> dict:
+    """The benchmark host's CPU: model, logical CPUs online (os.cpu_count,
+    as nproc), the CPUs this process may run on, and lscpu's topology lines
+    when lscpu is there."""
+    import shutil
+    import subprocess
+
+    info = {"model": cpu_model(), "logical_cpus": os.cpu_count()}
+    try:
+        info["usable_cpus"] = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        pass
+    if shutil.which("lscpu"):
+        try:
+            out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+            keep = ("Model name", "Socket(s)", "Core(s) per socket", "Thread(s) per core",
+                    "CPU max MHz", "L3 cache", "NUMA node(s)")
+            for line in out.splitlines():
+                k, _, v = line.partition(":")
+                if k.strip() in keep:
+                    info["lscpu " + k.strip()] = v.strip()
+        except (OSError, subprocess.SubprocessError):
+            pass
+    return info
+
+
 def run_gpu(wl, steps: int, warmup: int, mode: int = 0, chunk: int = 0, wg: int = 0,
             inp=None, graph: bool = False, bin_x: int = 0, timing: bool = True):
     """Timed pic_step on fresh device copies of the generated inputs.  With
@@ -549,8 +575,12 @@ def cpu_baseline(sample_steps: int):
     return {"value": n * sample_steps / dt, "unit": "particle-steps/s", "cores": 1,
             "kind": "oracle",
             "sample": f"uniform plasma strip 1024x64 cells, 32 ppc ({n} particles), "
-                      f"{sample_steps} steps, serial scalar C on {cpu_model()}",
-            "seconds": round(dt, 3)}
+                      f"{sample_steps} steps, serial scalar C (one thread) on {cpu_model()}",
+            "seconds": round(dt, 3), "host": host_cpu(),
+            # the paper's own figure, derived from its one-core timing of the
+            # 3D plasma-expansion case on a Xeon Gold 6230 (context only)
+            "paper_context": {"value": 2.0e6, "unit": "particle-steps/s per core",
+                              "cpu": "Intel Xeon Gold 6230 (one core)"}}
 
 
 def copy_bandwidth(gib: float = 2.0, reps: int = 5) -> float:

@@ -2,8 +2,9 @@
 particles), the workgroup size and (in 3D) the x-bin width for a workload
 by timing a step's fused kernel and exchange on the live particles, and
 caches the choice in a JSON file keyed by the GPU architecture, the
-dimension, the patch shape and a coarse histogram of the per-patch
-populations.
+library build (a digest of libpic.so, so a rebuilt kernel is tuned again),
+the dimension, the patch shape, the number of species and a coarse
+histogram of the per-patch populations.
 
 The paper tunes its task granularity (the bin width) by hand per physical
 set-up; this does the same search automatically.  All timing is done by
@@ -49,10 +50,28 @@ def population_key(counts: np.ndarray) -> str:
     return f"m{lm}_s{sk}_e{ef}"
 
 
+_LIB_DIGEST: Optional[str] = None
+
+
+def library_digest() -> str:
+    """Short digest of the built library (its kernels decide the timings)."""
+    global _LIB_DIGEST
+    if _LIB_DIGEST is None:
+        import hashlib
+
+        h = hashlib.sha256()
+        with open(pic.LIB_PATH, "rb") as fh:
+            for block in iter(lambda: fh.read(1 << 20), b""):
+                h.update(block)
+        _LIB_DIGEST = h.hexdigest()[:16]
+    return _LIB_DIGEST
+
+
 def _key(wl, counts) -> str:
     arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
     patch = "x".join(str(p) for p in wl.patch[:wl.dim])
-    return f"{arch}|{wl.dim}d|p{patch}|{population_key(counts)}"
+    return (f"{arch}|lib{library_digest()}|{wl.dim}d|p{patch}|s{len(wl.species)}|"
+            f"{population_key(counts)}")
 
 
 def _load(path: str) -> Dict:
