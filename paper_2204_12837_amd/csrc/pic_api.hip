@@ -827,8 +827,12 @@ pic_status step_slab(pic_ctx *c, pic_species *sp, int32_t nsp, pic_fields *f, in
     }
   }
   const SlabArgs a = make_slab_args(c, sp, nsp);
+  // without x-bins the first step's fused kernel reads the dense layout
+  // itself and fills the slabs (the call makes no separate copy into them)
+  SlabArgs first = a;
+  first.from_dense = bins ? 0 : 1;
   hipError_t e = timed(c, PIC_KERNEL_SLAB, st, [&] {
-    hipError_t r2 = launch_slab_begin(c->g, a, c->err_dev, st, !bins);
+    hipError_t r2 = launch_slab_begin(c->g, a, c->err_dev, st, false);
     for (int s = 0; bins && s < nsp && r2 == hipSuccess; s++) {
       SpDev d = make_args(c, sp, nsp).s[s];
       d.off = c->boff[s];
@@ -842,13 +846,19 @@ pic_status step_slab(pic_ctx *c, pic_species *sp, int32_t nsp, pic_fields *f, in
       return launch_slab_units(c->g, a, c->g.spc * kSeg, c->units, c->qctl, st);
     });
   if (e != hipSuccess) return hip_fail(c, e, "kernel launch");
-  if ((c->cfg.flags & PIC_FLAG_GRAPH) && !c->tm.on) {
+  int k0 = 0;
+  if (first.from_dense && nsteps > 0) {
+    if ((e = enqueue_slab_step(c, first, f, st)) != hipSuccess)
+      return hip_fail(c, e, "kernel launch");
+    k0 = 1;
+  }
+  if ((c->cfg.flags & PIC_FLAG_GRAPH) && !c->tm.on && k0 < nsteps) {
     hipGraphExec_t x = nullptr;
     if ((r = ensure_slab_graph(c, a, f, &x)) != PIC_OK) return r;
-    for (int k = 0; k < nsteps; k++)
+    for (int k = k0; k < nsteps; k++)
       if ((e = hipGraphLaunch(x, st)) != hipSuccess) return hip_fail(c, e, "hipGraphLaunch");
   } else {
-    for (int k = 0; k < nsteps; k++)
+    for (int k = k0; k < nsteps; k++)
       if ((e = enqueue_slab_step(c, a, f, st)) != hipSuccess) return hip_fail(c, e, "kernel launch");
   }
   e = timed(c, PIC_KERNEL_SLAB, st, [&] {

@@ -153,6 +153,9 @@ struct SlabArgs {
   int nsp;
   SlabDev s[kMaxSpecies];
   uint64_t *trace;  // trace buffer, or null when tracing is off
+  int from_dense;   // first step of a call: the fused kernel reads each patch's
+                    // particles from the dense layout (offsets off) and writes
+                    // them, updated, into the slabs (with weights and ids)
 };
 static_assert(sizeof(SlabArgs) <= 4096, "kernel argument block too large");
 

@@ -127,33 +127,46 @@ __global__ void __launch_bounds__(256) k_slab_in(GridDev g, SlabArgs sa) {
 // block's particles while it computes the current one; every global access
 // of a full block is unconditional (a prefetch past the range reloads its
 // last particle), so the memory-counter waits stay exact.  The neighbour code
-// of each particle goes to code[].
-template <int DIM, bool WALLS>
+// of each particle goes to code[].  from_dense (the first step of a call):
+// particle j of the patch is read from the dense layout at off[P] + j and
+// written, with its weight and id, to slot j of the slab, so the call needs
+// no separate copy into the slabs.
+template <int DIM, bool WALLS, bool FROM_DENSE>
 __device__ __forceinline__ void ipp_slab(const GridDev &g, const SlabDev &S, const TileGeom &t,
                                          const double *tEB, double *tJ, int P, uint32_t r0,
                                          uint32_t r1, int &bad, uint32_t *bits) {
+  constexpr bool from_dense = FROM_DENSE;
   constexpr int CENTER = DIM == 2 ? 4 : 13;
   const int nw = blockDim.x >> 6, lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   const uint32_t sbP = (uint32_t)S.sb[P];
+  const uint32_t srcP = from_dense ? (uint32_t)S.off[P] : sbP;
   const double q = S.q, alpha = S.alpha;
   uint32_t base = r0 + 64u * (uint32_t)wv;
   if (base >= r1) return;
   const uint32_t step = 64u * (uint32_t)nw;
   auto slot = [&](uint32_t b) -> uint32_t {
     const uint32_t i = b + (uint32_t)lane;
-    return sbP + (i < r1 ? i : r1 - 1);
+    return srcP + (i < r1 ? i : r1 - 1);
   };
+  const double *sx[DIM], *su[3], *sw;
+#pragma unroll
+  for (int a = 0; a < DIM; a++) sx[a] = from_dense ? S.x[a] : S.xs[a];
+#pragma unroll
+  for (int a = 0; a < 3; a++) su[a] = from_dense ? S.u[a] : S.us[a];
+  sw = from_dense ? S.w : S.ws;
   struct PartS {
     double x[DIM], u[3], w;
+    int64_t id;
   };
   auto load = [&](uint32_t k, PartS &p) {
 #pragma unroll
-    for (int a = 0; a < DIM; a++) p.x[a] = at(S.xs[a], k);
-    p.u[0] = at(S.us[0], k);
-    p.u[1] = at(S.us[1], k);
-    p.u[2] = at(S.us[2], k);
-    p.w = at(S.ws, k);
+    for (int a = 0; a < DIM; a++) p.x[a] = at(sx[a], k);
+    p.u[0] = at(su[0], k);
+    p.u[1] = at(su[1], k);
+    p.u[2] = at(su[2], k);
+    p.w = at(sw, k);
+    if constexpr (FROM_DENSE) p.id = at(S.id, k);
   };
   PartS pc, pn;
   load(slot(base), pc);
@@ -174,6 +187,10 @@ __device__ __forceinline__ void ipp_slab(const GridDev &g, const SlabDev &S, con
     at(S.us[1], i) = u[1];
     at(S.us[2], i) = u[2];
     at(S.code, i) = (uint8_t)code;
+    if constexpr (FROM_DENSE) {
+      at(S.ws, i) = pc.w;
+      at(S.ids, i) = pc.id;
+    }
     if (bits && __ballot(code != CENTER)) {  // mark departures (slab-relative slot)
       const uint32_t j = base + (uint32_t)lane;
       if (code != CENTER) atomicOr(&bits[j >> 5], 1u << (j & 31));
@@ -197,6 +214,10 @@ __device__ __forceinline__ void ipp_slab(const GridDev &g, const SlabDev &S, con
       at(S.us[1], i) = u[1];
       at(S.us[2], i) = u[2];
       at(S.code, i) = (uint8_t)code;
+      if constexpr (FROM_DENSE) {
+        at(S.ws, i) = pc.w;
+        at(S.ids, i) = pc.id;
+      }
       if (bits && code != CENTER) {
         const uint32_t j = base + (uint32_t)lane;
         atomicOr(&bits[j >> 5], 1u << (j & 31));
@@ -307,7 +328,7 @@ constexpr int kSlabMinWaves = DIM == 2 ? 4 : 2;
 
 // Per-patch launch: one workgroup per (patch, species).  WALLS: instance
 // with reflecting walls (the periodic one compiles them out).
-template <int DIM, bool WALLS>
+template <int DIM, bool WALLS, bool FD>
 __global__ void __launch_bounds__(kMaxWgSlab<DIM>, kSlabMinWaves<DIM>) k_ipp_slab(GridDev g, SlabArgs sa, Fields f, int *err) {
   extern __shared__ __align__(16) double lds[];
   __shared__ uint32_t bits[kBitWords];
@@ -327,7 +348,7 @@ __global__ void __launch_bounds__(kMaxWgSlab<DIM>, kSlabMinWaves<DIM>) k_ipp_sla
   for (int k = threadIdx.x; k < kBitWords; k += blockDim.x) bits[k] = 0u;
   __syncthreads();
   int bad = 0;
-  ipp_slab<DIM, WALLS>(g, S, t, tEB, tJ, P, 0u, (uint32_t)c, bad, mark ? bits : nullptr);
+  ipp_slab<DIM, WALLS, FD>(g, S, t, tEB, tJ, P, 0u, (uint32_t)c, bad, mark ? bits : nullptr);
   if (bad) atomicOr(err, bad);
   __syncthreads();
   flush_j<DIM>(g, t, tJ, f.j);
@@ -357,7 +378,7 @@ __global__ void __launch_bounds__(kMaxWgSlab<DIM>, kSlabMinWaves<DIM>) k_ipp_sla
 // ubase), or, with combined, from one list whose units range over the
 // particles of every species of the patch (ticket qctl[0], count qctl[1],
 // list at units); E/B is restaged and J flushed only when the patch changes.
-template <int DIM, bool WALLS, bool COMBINED>
+template <int DIM, bool WALLS, bool COMBINED, bool FD>
 __global__ void __launch_bounds__(kMaxWgSlab<DIM>, kSlabMinWaves<DIM>) k_ipp_slab_persistent(GridDev g, SlabArgs sa, Fields f, int *err,
                                                                     const Unit *units, int *qctl) {
   constexpr bool combined = COMBINED;
@@ -405,12 +426,13 @@ __global__ void __launch_bounds__(kMaxWgSlab<DIM>, kSlabMinWaves<DIM>) k_ipp_sla
           const int c = R.cnt[un.P];
           const int r0 = min(max(un.k0 - base, 0), c), r1 = min(max(un.k1 - base, 0), c);
           if (r0 < r1)
-            ipp_slab<DIM, WALLS>(g, R, t, tEB, tJ, un.P, (uint32_t)r0, (uint32_t)r1, bad, nullptr);
+            ipp_slab<DIM, WALLS, FD>(g, R, t, tEB, tJ, un.P, (uint32_t)r0, (uint32_t)r1, bad,
+                                     nullptr);
           base += c;
         }
       } else {
-        ipp_slab<DIM, WALLS>(g, S, t, tEB, tJ, un.P, (uint32_t)un.k0, (uint32_t)un.k1, bad,
-                             nullptr);
+        ipp_slab<DIM, WALLS, FD>(g, S, t, tEB, tJ, un.P, (uint32_t)un.k0, (uint32_t)un.k1, bad,
+                                 nullptr);
       }
       __syncthreads();  // this unit's deposits are done before any flush
       if (sa.trace && threadIdx.x == 0) {
@@ -864,11 +886,21 @@ hipError_t launch_slab_begin(const GridDev &g, const SlabArgs &sa, int *err, hip
 template <int DIM, bool WALLS>
 void ipp_slab_t(const GridDev &g, const SlabArgs &sa, const Fields &f, int *err, int wg, size_t lds,
                 hipStream_t st) {
+  // the call's first step reads the dense layout (its own instance, so the
+  // steps after it keep the in-place kernel's registers)
+  if (sa.from_dense) {
+    if (DIM == 3)
+      (void)hipFuncSetAttribute((const void *)k_ipp_slab<DIM, WALLS, true>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL((k_ipp_slab<DIM, WALLS, true>), dim3(g.npatch, sa.nsp), dim3(wg), lds, st, g,
+                       sa, f, err);
+    return;
+  }
   if (DIM == 3)
-    (void)hipFuncSetAttribute((const void *)k_ipp_slab<DIM, WALLS>,
+    (void)hipFuncSetAttribute((const void *)k_ipp_slab<DIM, WALLS, false>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  hipLaunchKernelGGL((k_ipp_slab<DIM, WALLS>), dim3(g.npatch, sa.nsp), dim3(wg), lds, st, g, sa, f,
-                     err);
+  hipLaunchKernelGGL((k_ipp_slab<DIM, WALLS, false>), dim3(g.npatch, sa.nsp), dim3(wg), lds, st, g,
+                     sa, f, err);
 }
 
 hipError_t launch_ipp_slab(const GridDev &g, const SlabArgs &sa, const double *const e[3],
@@ -885,23 +917,28 @@ hipError_t launch_ipp_slab(const GridDev &g, const SlabArgs &sa, const double *c
   return hipGetLastError();
 }
 
+template <int DIM, bool WALLS, bool COMBINED, bool FD>
+void ipp_slab_pers_one(const GridDev &g, const SlabArgs &sa, const Fields &f, int *err,
+                       const Unit *units, int *qctl, int grid, int wg, size_t lds,
+                       hipStream_t st) {
+  if (DIM == 3)
+    (void)hipFuncSetAttribute((const void *)k_ipp_slab_persistent<DIM, WALLS, COMBINED, FD>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  hipLaunchKernelGGL((k_ipp_slab_persistent<DIM, WALLS, COMBINED, FD>), dim3(grid), dim3(wg), lds,
+                     st, g, sa, f, err, units, qctl);
+}
+
 template <int DIM, bool WALLS>
 void ipp_slab_pers_t(const GridDev &g, const SlabArgs &sa, const Fields &f, int *err,
                      const Unit *units, int *qctl, int grid, int wg, size_t lds, hipStream_t st) {
-  // several species: the instance whose units range over all of them
-  if (sa.nsp > 1) {
-    if (DIM == 3)
-      (void)hipFuncSetAttribute((const void *)k_ipp_slab_persistent<DIM, WALLS, true>,
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL((k_ipp_slab_persistent<DIM, WALLS, true>), dim3(grid), dim3(wg), lds, st, g,
-                       sa, f, err, units, qctl);
-    return;
-  }
-  if (DIM == 3)
-    (void)hipFuncSetAttribute((const void *)k_ipp_slab_persistent<DIM, WALLS, false>,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  hipLaunchKernelGGL((k_ipp_slab_persistent<DIM, WALLS, false>), dim3(grid), dim3(wg), lds, st, g,
-                     sa, f, err, units, qctl);
+  // several species: the instance whose units range over all of them; the
+  // call's first step reads the dense layout
+  if (sa.nsp > 1)
+    sa.from_dense ? ipp_slab_pers_one<DIM, WALLS, true, true>(g, sa, f, err, units, qctl, grid, wg, lds, st)
+                  : ipp_slab_pers_one<DIM, WALLS, true, false>(g, sa, f, err, units, qctl, grid, wg, lds, st);
+  else
+    sa.from_dense ? ipp_slab_pers_one<DIM, WALLS, false, true>(g, sa, f, err, units, qctl, grid, wg, lds, st)
+                  : ipp_slab_pers_one<DIM, WALLS, false, false>(g, sa, f, err, units, qctl, grid, wg, lds, st);
 }
 
 hipError_t launch_ipp_slab_persistent(const GridDev &g, const SlabArgs &sa,
@@ -919,23 +956,26 @@ hipError_t launch_ipp_slab_persistent(const GridDev &g, const SlabArgs &sa,
   return hipGetLastError();
 }
 
-template <int DIM, bool WALLS, bool COMBINED>
+template <int DIM, bool WALLS, bool COMBINED, bool FD>
 int slab_blocks_one(int wg, size_t lds) {
   if (DIM == 3)
-    (void)hipFuncSetAttribute((const void *)k_ipp_slab_persistent<DIM, WALLS, COMBINED>,
+    (void)hipFuncSetAttribute((const void *)k_ipp_slab_persistent<DIM, WALLS, COMBINED, FD>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   int n = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_ipp_slab_persistent<DIM, WALLS, COMBINED>,
-                                                   wg, lds) != hipSuccess)
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+          &n, k_ipp_slab_persistent<DIM, WALLS, COMBINED, FD>, wg, lds) != hipSuccess)
     return 0;
   return n;
 }
 
-// resident workgroups per CU of both instances (one species, several)
+// resident workgroups per CU of every instance (one species or several;
+// first step of a call or not): the grid must fit all of them
 template <int DIM, bool WALLS>
 int slab_blocks_t(int wg, size_t lds) {
-  return std::min(slab_blocks_one<DIM, WALLS, false>(wg, lds),
-                  slab_blocks_one<DIM, WALLS, true>(wg, lds));
+  return std::min(std::min(slab_blocks_one<DIM, WALLS, false, false>(wg, lds),
+                           slab_blocks_one<DIM, WALLS, true, false>(wg, lds)),
+                  std::min(slab_blocks_one<DIM, WALLS, false, true>(wg, lds),
+                           slab_blocks_one<DIM, WALLS, true, true>(wg, lds)));
 }
 
 int slab_persistent_blocks_per_cu(const GridDev &g, int wg) {
