@@ -88,9 +88,9 @@ def measured_lds(workload: str):
 
 
 def measured_valu(workload: str):
-    """Per-particle float64 operations and LDS instructions of the 3D fused
-    kernel from the committed rocprofv3 counter summary, if it was taken on
-    the current kernel source."""
+    """Per-particle float64 operations and LDS instructions (and the HBM bytes
+    per launch) of the 3D persistent fused kernel from the committed rocprofv3
+    counter summary, if it was taken on the current kernel source."""
     path = os.path.join(ROOT, "profiles", "k_ipp_slab3d_expansion3d_valu.json")
     try:
         with open(path) as fh:
@@ -282,7 +282,12 @@ def run_expansion3d(steps: int, warmup: int):
                "frac": tf / FP64_PEAK_TFLOPS,
                "fp64_flops_per_particle": valu["fp64_flops_per_particle"],
                "lds_instructions_per_particle": valu["lds_per_particle"],
-               "lds_instructions_per_s": valu["lds_per_particle"] * n / (min(ipp_pp, ipp_pe) * 1e-3)}
+               "lds_instructions_per_s": valu["lds_per_particle"] * n / (min(ipp_pp, ipp_pe) * 1e-3),
+               # HBM bytes per launch of the persistent kernel from the counters
+               # (FETCH_SIZE x 2 + WRITE_SIZE), against the algorithmic bytes
+               "traffic": valu.get("hbm_bytes_per_launch"),
+               "traffic_over_algorithmic": (valu["hbm_bytes_per_launch"] / abytes
+                                            if valu.get("hbm_bytes_per_launch") else None)}
     return {"workload": "expansion3d", "particles": n, "species": 2, "steps": steps, "alu": alu,
             "per_patch": {"ns_per_particle_step": s_pp / (n * steps) * 1e9, "ipp_ms": ipp_pp},
             "persistent": {"ns_per_particle_step": s_pe / (n * steps) * 1e9, "ipp_ms": ipp_pe,

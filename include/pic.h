@@ -399,7 +399,10 @@ enum {
   PIC_KERNEL_SORT = 6,        /* general sort of unsorted input */
   PIC_KERNEL_ADJOINT = 7,     /* adjoint segment */
   PIC_KERNEL_EXCHANGE = 8,    /* slab layout: departures, arrivals, counts, work units */
-  PIC_KERNEL_SLAB = 9,        /* slab layout: dense -> slabs and back, once per call */
+  PIC_KERNEL_SLAB = 9,        /* slab layout, once per call: the slab plan, the first
+                                 step's fused kernel (which fills the slabs from the
+                                 dense layout; with x-bins, the bin placement), and
+                                 slabs -> dense */
   PIC_KERNEL_MAXWELL = 10,    /* field solver step (Ampere and Faraday) */
   PIC_KERNEL_RHO = 11,        /* charge density */
   PIC_KERNEL_COUNT = 12

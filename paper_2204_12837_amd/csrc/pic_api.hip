@@ -710,8 +710,10 @@ hipError_t enqueue_slab_step(pic_ctx *c, const SlabArgs &a, const pic_fields *f,
   for (int d = 0; d < c->cfg.dim; d++) ncell *= c->cfg.n[d];
   const bool pers = c->cfg.mode == PIC_MODE_PERSISTENT;
   hipError_t e = timed(c, PIC_KERNEL_ZERO, st, [&] { return launch_zero(f->j, ncell, st); });
+  // the call's first fused kernel also fills the slabs from the dense
+  // layout: it is timed with the layout copies
   if (e == hipSuccess)
-    e = timed(c, PIC_KERNEL_IPP, st, [&] {
+    e = timed(c, a.from_dense ? PIC_KERNEL_SLAB : PIC_KERNEL_IPP, st, [&] {
       return pers ? launch_ipp_slab_persistent(c->g, a, f->e, f->b, f->j, c->err_dev, c->units,
                                                c->qctl, c->pgrid_slab, c->wg, st)
                   : launch_ipp_slab(c->g, a, f->e, f->b, f->j, c->err_dev, c->wg, st);
