@@ -643,12 +643,14 @@ def main(argv=None) -> int:
                     help="skip the field solver and the charge density")
     ap.add_argument("--no-large-patches", action="store_true",
                     help="skip the 64x128-cell patches (x-bins) workload")
-    ap.add_argument("--cpu-steps", type=int, default=8)
+    ap.add_argument("--cpu-steps", type=int, default=24)
     ap.add_argument("--mode", choices=("per_patch", "persistent"), default="per_patch",
                     help="launch of the main workload's fused kernel")
     ap.add_argument("--chunk", type=int, default=0, help="persistent mode: particles per unit")
     ap.add_argument("--wg", type=int, default=0, help="threads per workgroup (0 = library default)")
     ap.add_argument("--bin-x", type=int, default=0, help="x-bin width (0 = library default)")
+    ap.add_argument("--order", choices=("random", "cell_interleaved"), default="random",
+                    help="particle order inside each patch of the main workload's inputs")
     ap.add_argument("--main-only", action="store_true",
                     help="time only the main workload (e.g. for counter passes)")
     ap.add_argument("--copy-calibration", type=float, default=0.0, metavar="GIB",
@@ -666,7 +668,7 @@ def main(argv=None) -> int:
     from paper_2204_12837_amd import inputs as I
 
     wl = I.workload(args.workload)
-    inp0 = I.generate(wl)
+    inp0 = I.generate(wl, order=args.order)
     # the per-kernel HIP events (roofline) come from one call; the headline
     # throughput from the same call without them (plain eager launches)
     launch = dict(mode=1 if args.mode == "persistent" else 0, chunk=args.chunk, wg=args.wg,
@@ -695,7 +697,8 @@ def main(argv=None) -> int:
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": args.workload, "dim": wl.dim, "cells": list(wl.n[:wl.dim]),
+        "config": {"workload": args.workload, "order": args.order, "dim": wl.dim,
+                   "cells": list(wl.n[:wl.dim]),
                    "patch": list(wl.patch[:wl.dim]), "particles": n,
                    "species": len(wl.species), "mode": args.mode, "layout": "slab"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",

@@ -22,7 +22,11 @@ Recipe (seed = 1000 + workload number):
   2. momenta: u_x, u_y, u_z arrays, each ``N(0, sigma^2)`` of the species;
   3. a random permutation of the particle order (a PIC code's particle order
      inside a patch is arbitrary; generation order would put every particle
-     of a cell next to each other); ids are the positions after it;
+     of a cell next to each other); ids are the positions after it.  Option
+     order="cell_interleaved" then reorders the particles stably by (patch,
+     rank of the particle among its cell's, cell inside the patch), so that
+     64 consecutive particles of a patch sit in 64 different cells (a layout
+     experiment; the default is the random order);
   4. fields Ex, Ey, Ez, Bx, By, Bz: i.i.d. ``U(-A, A)`` per node, then a
      uniform background added to Bz;
   5. W (the adjoint workload's loss weights): ``N(0, 1)`` per node per J
@@ -172,7 +176,27 @@ class Inputs:
     W: Optional[np.ndarray]  # (3, nz, ny, nx) float64 or None
 
 
-def _draw_species(rng: np.random.Generator, wl: Workload, sp: SpeciesSpec) -> ParticleSet:
+def _interleave(wl: Workload, cell: np.ndarray) -> np.ndarray:
+    """Stable order of particles (given their generation cells, x fastest) by
+    patch, then by their rank among their cell's particles, then by cell
+    inside the patch."""
+    nx, ny = wl.n[0], wl.n[1]
+    cx, rest = cell % nx, cell // nx
+    cy, cz = rest % ny, rest // ny
+    px, py, pz = wl.patch
+    npx, npy = nx // px, ny // py
+    patch = (cx // px) + npx * ((cy // py) + npy * (cz // pz))
+    local = (cx % px) + px * ((cy % py) + py * (cz % pz))
+    key = patch * (px * py * pz) + local
+    o = np.argsort(key, kind="stable")
+    ks = key[o]
+    rank = np.empty_like(key)
+    rank[o] = np.arange(key.size) - np.searchsorted(ks, ks, side="left")
+    return np.lexsort((local, rank, patch))
+
+
+def _draw_species(rng: np.random.Generator, wl: Workload, sp: SpeciesSpec,
+                  order: str = "random") -> ParticleSet:
     nx, ny, nz = wl.n
     dim = wl.dim
     ix = np.arange(nx)
@@ -190,11 +214,16 @@ def _draw_species(rng: np.random.Generator, wl: Workload, sp: SpeciesSpec) -> Pa
     for a in range(dim):
         U = rng.random(N)
         x[a] = (idx[a].astype(np.float64) + U) * wl.d[a]
-    del cell, cx, cy, cz, rest, idx
+    del cx, cy, cz, rest, idx
     u = np.empty((3, N), dtype=np.float64)
     for a in range(3):
         u[a] = rng.normal(0.0, sp.sigma, N) if sp.sigma > 0 else 0.0
     perm = rng.permutation(N)
+    if order == "cell_interleaved":
+        perm = perm[_interleave(wl, cell[perm])]
+    elif order != "random":
+        raise ValueError(f"unknown particle order {order!r}")
+    del cell
     x = np.ascontiguousarray(x[:, perm])
     u = np.ascontiguousarray(u[:, perm])
     wt = np.full(N, sp.w, dtype=np.float64)
@@ -202,11 +231,12 @@ def _draw_species(rng: np.random.Generator, wl: Workload, sp: SpeciesSpec) -> Pa
     return ParticleSet(sp.q, sp.m, sp.w, x, u, wt, pid)
 
 
-def generate(wl: Workload, with_W: Optional[bool] = None) -> Inputs:
-    """Draw one workload's particles, fields and (optionally) loss weights."""
+def generate(wl: Workload, with_W: Optional[bool] = None, order: str = "random") -> Inputs:
+    """Draw one workload's particles, fields and (optionally) loss weights;
+    order: "random" or "cell_interleaved" (step 3 of the recipe)."""
     root = np.random.default_rng(wl.seed)
     children = root.spawn(len(wl.species) + 1)
-    species = [_draw_species(children[s], wl, sp) for s, sp in enumerate(wl.species)]
+    species = [_draw_species(children[s], wl, sp, order) for s, sp in enumerate(wl.species)]
     frng = children[-1]
     nx, ny, nz = wl.n
     shape = (nz if wl.dim == 3 else 1, ny, nx)
