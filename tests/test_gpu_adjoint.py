@@ -136,7 +136,7 @@ def test_adjoint256_finite_differences():
     1,048,576 particles, 20 steps, checkpoint every 5): along 4 random unit
     directions in u and 4 in (E, B), and on 32 sampled scalars each of
     dL/du, dL/dE and dL/dB, the GPU gradient equals the oracle's central
-    difference of L in x87 extended precision (h = 1e-6) to 1e-7 relative
+    difference of L in binary128 (h = 1e-6) to 1e-7 relative
     (scalars where |FD| > 1e-3 of the largest sampled one), and the oracle's
     forward-mode derivative to rounding.  The oracle's values were written
     by tests/golden/make_adjoint256_fd.py."""
