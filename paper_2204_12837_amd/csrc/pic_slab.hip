@@ -228,8 +228,13 @@ __device__ __forceinline__ void ipp_slab(const GridDev &g, const SlabDev &S, con
 
 constexpr int kBitSlots = 16384;           // largest patch whose departures the fused
 constexpr int kBitWords = kBitSlots / 32;  // kernel handles itself
-constexpr int kExchBitSlots = 65536;       // the departures kernel's bitmap path
-constexpr int kExchBitWords = kExchBitSlots / 32;
+// the departures kernel's bitmap path: slabs of up to this many particles
+// (2D: the 32768-particle bins of large patches; 3D: a small bitmap, so
+// that more of the many small bins' workgroups fit in a CU's LDS)
+template <int DIM>
+constexpr int kExchBitSlots = DIM == 2 ? 65536 : 16384;
+template <int DIM>
+constexpr int kExchBitWords = kExchBitSlots<DIM> / 32;
 
 // Exclusive prefix sum of v over the workgroup (any size up to 1024, a
 // multiple of 64); total in tot.  wtot: 16 shared ints.
@@ -451,27 +456,11 @@ __global__ void __launch_bounds__(kMaxWgSlab<DIM>, kSlabMinWaves<DIM>) k_ipp_sla
   if (bad) atomicOr(err, bad);
 }
 
-// Exclusive prefix sum of v over a workgroup of 256 threads; total in tot.
-// Uses the 4-entry shared array w4.
-__device__ __forceinline__ int excl_sum_256(int v, int &tot, int *w4) {
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  int x = v;  // inclusive scan inside the wave
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    const int y = __shfl_up(x, o, 64);
-    if (lane >= o) x += y;
-  }
-  __syncthreads();
-  if (lane == 63) w4[wv] = x;
-  __syncthreads();
-  int base = 0;
-  for (int k = 0; k < wv; k++) base += w4[k];
-  tot = w4[0] + w4[1] + w4[2] + w4[3];
-  return base + x - v;
-}
-
-constexpr int kExchPer = 64;               // slab slots per thread and tile
-constexpr int kExchTile = 256 * kExchPer;  // slots per tile of the large-patch path
+constexpr int kExchPer = 64;  // slab slots per thread and tile of the large-patch path
+// threads per workgroup of the departures kernel: its large 2D patches
+// need many lanes in flight; the 3D bins' small slabs need few
+constexpr int kExchWgMax = 1024;
+constexpr int kExchWg2 = 256, kExchWg3 = 64;
 
 // The 64 codes of this thread's slots j0 .. j0+63 as 16 words; slots at or
 // past c read as CENTER.  Slabs start on 16-slot boundaries and j0 is a
@@ -504,7 +493,7 @@ __device__ __forceinline__ int code_at(const uint32_t w[16], int k) {
   return (int)((w[k >> 2] >> (8 * (k & 3))) & 0xffu);
 }
 
-// Departure bitmap of a slab of c <= kExchBitSlots particles from its code
+// Departure bitmap of a slab of c <= kExchBitSlots<DIM> particles from its code
 // bytes: bit j of word j/32 set if slot j leaves the patch.  Slabs start on
 // 16-slot boundaries, so the 16-byte loads are aligned; the last word's
 // loads stay inside the slab's room (at least c + 64 slots).
@@ -528,29 +517,29 @@ __device__ __forceinline__ void code_bits(const uint8_t *code, int c, uint32_t *
   }
 }
 
-// Departures of patch P (grid: patches x species, 256 threads; with
-// only_marked, only the patches the fused kernel left, dep[P] < 0): the
-// particles whose code leaves the patch are copied to the patch's outbox
-// region (from sb[P]) with their destination patch; the stayers in the
-// slab's tail [c2, c) then fill the holes the departures left below
-// c2 = c - departures.  Up to kExchBitSlots particles: the departure
-// bitmap in LDS and the fused kernel's epilogue.  Larger patches: tiles of
-// 16384 slots, each thread copying its own departures and movers in turn.
+// Departures of patch P (grid: patches x species, kExchWg2 or kExchWg3
+// threads; with only_marked, only the patches the fused kernel left,
+// dep[P] < 0): the particles whose code leaves the patch are copied to the
+// patch's outbox region (from sb[P]) with their destination patch; the
+// stayers in the slab's tail [c2, c) then fill the holes the departures left
+// below c2 = c - departures.  Up to kExchBitSlots<DIM> particles: the
+// departure bitmap in LDS and the fused kernel's epilogue.  Larger patches:
+// tiles of kExchPer slots per thread, each thread copying its own
+// departures and movers in turn.
 template <int DIM>
-__global__ void __launch_bounds__(256) k_exch_out(GridDev g, SlabArgs sa, int only_marked) {
+__global__ void __launch_bounds__(kExchWgMax) k_exch_out(GridDev g, SlabArgs sa, int only_marked) {
   constexpr int CENTER = DIM == 2 ? 4 : 13;
   const SlabDev &S = sa.s[blockIdx.y];
   const int P = blockIdx.x;
-  __shared__ int w4[4];
-  __shared__ uint32_t bits[kExchBitWords];
-  __shared__ int pre[kExchBitWords];
+  __shared__ uint32_t bits[kExchBitWords<DIM>];
+  __shared__ int pre[kExchBitWords<DIM>];
   __shared__ int wtot[16];
   if (S.ctl[1] == 2) return;
   if (P == 0 && threadIdx.x == 0) S.ctl[1] = 0;  // the previous step's overflow is resolved
   if (only_marked && S.dep[P] >= 0) return;     // done by the fused kernel
   const int c = S.cnt[P];
   const int64_t sbP = S.sb[P];
-  if (c <= kExchBitSlots) {
+  if (c <= kExchBitSlots<DIM>) {
     code_bits<CENTER>(S.code + sbP, c, bits);
     __syncthreads();
     depart_in_kernel<DIM>(g, S, P, c, bits, pre, wtot);
@@ -560,15 +549,16 @@ __global__ void __launch_bounds__(256) k_exch_out(GridDev g, SlabArgs sa, int on
   patch_coords(g, P, pc);
   uint32_t w[16];
   int tot = 0;
-  // Large case: tiles of 16384 slots; each thread copies its own departures
-  // and movers in slot order.
+  // Large case: tiles of kExchPer slots per thread; each thread copies its
+  // own departures and movers in slot order.
+  const int tile = (int)blockDim.x * kExchPer;
   int m = 0;
-  for (int t0 = 0; t0 < c; t0 += kExchTile) {
+  for (int t0 = 0; t0 < c; t0 += tile) {
     load_codes<CENTER>(S.code, sbP, t0 + kExchPer * (int)threadIdx.x, c, w);
     int k = 0;
 #pragma unroll
     for (int i = 0; i < kExchPer; i++) k += code_at(w, i) != CENTER;
-    (void)excl_sum_256(k, tot, w4);
+    (void)block_excl_sum(k, tot, wtot);
     m += tot;
   }
   if (threadIdx.x == 0) S.dep[P] = m;
@@ -578,13 +568,13 @@ __global__ void __launch_bounds__(256) k_exch_out(GridDev g, SlabArgs sa, int on
   }
   const int c2 = c - m;
   int run = 0;
-  for (int t0 = 0; t0 < c; t0 += kExchTile) {
+  for (int t0 = 0; t0 < c; t0 += tile) {
     const int j0 = t0 + kExchPer * (int)threadIdx.x;
     load_codes<CENTER>(S.code, sbP, j0, c, w);
     int k = 0;
 #pragma unroll
     for (int i = 0; i < kExchPer; i++) k += code_at(w, i) != CENTER;
-    int r = run + excl_sum_256(k, tot, w4);
+    int r = run + block_excl_sum(k, tot, wtot);
     run += tot;
     for (int i = 0; i < kExchPer && k > 0; i++) {
       const int cd = code_at(w, i);
@@ -601,13 +591,13 @@ __global__ void __launch_bounds__(256) k_exch_out(GridDev g, SlabArgs sa, int on
   __threadfence_block();
   __syncthreads();  // departures copied and holes listed before the tail moves in
   run = 0;
-  for (int t0 = c2 / kExchTile * kExchTile; t0 < c; t0 += kExchTile) {
+  for (int t0 = c2 / tile * tile; t0 < c; t0 += tile) {
     const int j0 = t0 + kExchPer * (int)threadIdx.x;
     load_codes<CENTER>(S.code, sbP, j0, c, w);
     int k = 0;
 #pragma unroll
     for (int i = 0; i < kExchPer; i++) k += j0 + i >= c2 && j0 + i < c && code_at(w, i) == CENTER;
-    int r = run + excl_sum_256(k, tot, w4);
+    int r = run + block_excl_sum(k, tot, wtot);
     run += tot;
     for (int i = 0; i < kExchPer && k > 0; i++) {
       const int j = j0 + i;
@@ -772,50 +762,62 @@ __global__ void __launch_bounds__(1024) k_exch_fin(GridDev g, SlabArgs sa, int *
   }
 }
 
-// Overflow, part 1 (grid: 2 x patches, x species): every particle goes to
-// its place in the new plan, inside the first buffer set.
+// The re-plan kernels return at once without an overflow, which is almost
+// every step: they run on a small grid whose workgroups loop over the
+// patches when there is one.
+constexpr int kReslabGrid = 512;  // workgroups per species
+
+// Overflow, part 1 (grid: up to kReslabGrid x species; workgroup b takes
+// items b, b + gridDim.x, ... of 2 x patches): every particle goes to its
+// place in the new plan, inside the first buffer set -- item P < patches
+// copies slab P, item patches + Q the outbox entries of patch Q that found
+// no room.
 template <int DIM>
 __global__ void __launch_bounds__(256) k_reslab_move(GridDev g, SlabArgs sa) {
   const SlabDev &S = sa.s[blockIdx.y];
   if (S.ctl[1] != 1) return;
   const int n = g.npatch;
-  if ((int)blockIdx.x < n) {
-    const int P = blockIdx.x;
-    const int placed = min(S.arr[P], S.cap[P] - S.cnt2[P]);
-    const int64_t c = (int64_t)S.cnt2[P] + placed;
-    copy_run<DIM>(S.x, S.u, S.w, S.id, S.sb2[P], S.xs, S.us, S.ws, S.ids, S.sb[P], c);
-    return;
-  }
-  const int Q = blockIdx.x - n;  // the outbox of patch Q
-  const int m = S.dep[Q];
-  const int64_t ob = S.sb[Q];
-  for (int r = threadIdx.x; r < m; r += blockDim.x) {
-    const int64_t e = ob + r;
-    const int dv = S.odest[e];
-    if (dv < 0 || !(dv & kUnplaced)) continue;  // deleted, or placed
-    const int D = dv & ~kUnplaced;
-    const int placed = min(S.arr[D], S.cap[D] - S.cnt2[D]);
-    const int64_t pos = (int64_t)S.cnt2[D] + placed + atomicAdd(&S.arr2[D], 1);
-    copy_particle<DIM>(S.x, S.u, S.w, S.id, S.sb2[D] + pos, S.ox, S.ou, S.ow, S.oid, e);
+  for (int v = blockIdx.x; v < 2 * n; v += gridDim.x) {
+    if (v < n) {
+      const int P = v;
+      const int placed = min(S.arr[P], S.cap[P] - S.cnt2[P]);
+      const int64_t c = (int64_t)S.cnt2[P] + placed;
+      copy_run<DIM>(S.x, S.u, S.w, S.id, S.sb2[P], S.xs, S.us, S.ws, S.ids, S.sb[P], c);
+      continue;
+    }
+    const int Q = v - n;  // the outbox of patch Q
+    const int m = S.dep[Q];
+    const int64_t ob = S.sb[Q];
+    for (int r = threadIdx.x; r < m; r += blockDim.x) {
+      const int64_t e = ob + r;
+      const int dv = S.odest[e];
+      if (dv < 0 || !(dv & kUnplaced)) continue;  // deleted, or placed
+      const int D = dv & ~kUnplaced;
+      const int placed = min(S.arr[D], S.cap[D] - S.cnt2[D]);
+      const int64_t pos = (int64_t)S.cnt2[D] + placed + atomicAdd(&S.arr2[D], 1);
+      copy_particle<DIM>(S.x, S.u, S.w, S.id, S.sb2[D] + pos, S.ox, S.ou, S.ow, S.oid, e);
+    }
   }
 }
 
-// Overflow, part 2 (grid: patches x species): back into the slab buffers at
-// the new plan's places; the plan becomes current.
+// Overflow, part 2 (grid: up to kReslabGrid x species, looping over the
+// patches): back into the slab buffers at the new plan's places; the plan
+// becomes current.
 template <int DIM>
 __global__ void __launch_bounds__(256) k_reslab_back(GridDev g, SlabArgs sa) {
   const SlabDev &S = sa.s[blockIdx.y];
   if (S.ctl[1] != 1) return;
-  const int P = blockIdx.x;
-  const int64_t c = (int64_t)S.cnt2[P] + S.arr[P], d0 = S.sb2[P];
-  copy_run<DIM>(S.xs, S.us, S.ws, S.ids, d0, S.x, S.u, S.w, S.id, d0, c);
-  __syncthreads();  // every thread has read arr[P] before it is cleared
-  if (threadIdx.x == 0) {
-    S.cnt[P] = (int32_t)c;
-    S.cap[P] = S.cap2[P];
-    S.sb[P] = d0;
-    S.arr[P] = 0;
-    if (P == 0) S.sb[g.npatch] = S.sb2[g.npatch];
+  for (int P = blockIdx.x; P < g.npatch; P += gridDim.x) {
+    const int64_t c = (int64_t)S.cnt2[P] + S.arr[P], d0 = S.sb2[P];
+    copy_run<DIM>(S.xs, S.us, S.ws, S.ids, d0, S.x, S.u, S.w, S.id, d0, c);
+    __syncthreads();  // every thread has read arr[P] before it is cleared
+    if (threadIdx.x == 0) {
+      S.cnt[P] = (int32_t)c;
+      S.cap[P] = S.cap2[P];
+      S.sb[P] = d0;
+      S.arr[P] = 0;
+      if (P == 0) S.sb[g.npatch] = S.sb2[g.npatch];
+    }
   }
 }
 
@@ -992,10 +994,10 @@ hipError_t launch_exchange(const GridDev &g, const SlabArgs &sa, int *err, Unit 
   const dim3 pg(g.npatch, sa.nsp);
   const int only_marked = units ? 0 : 1;  // the per-patch fused kernel did the departures
   if (g.dim == 2) {
-    hipLaunchKernelGGL(k_exch_out<2>, pg, dim3(256), 0, st, g, sa, only_marked);
+    hipLaunchKernelGGL(k_exch_out<2>, pg, dim3(kExchWg2), 0, st, g, sa, only_marked);
     hipLaunchKernelGGL(k_exch_in<2>, pg, dim3(256), 0, st, g, sa);
   } else {
-    hipLaunchKernelGGL(k_exch_out<3>, pg, dim3(256), 0, st, g, sa, only_marked);
+    hipLaunchKernelGGL(k_exch_out<3>, pg, dim3(kExchWg3), 0, st, g, sa, only_marked);
     hipLaunchKernelGGL(k_exch_in<3>, pg, dim3(256), 0, st, g, sa);
   }
   hipError_t e = hipGetLastError();
@@ -1004,13 +1006,14 @@ hipError_t launch_exchange(const GridDev &g, const SlabArgs &sa, int *err, Unit 
   const bool combined = units && sa.nsp > 1;
   hipLaunchKernelGGL(k_exch_fin, dim3(sa.nsp), dim3(1024), 0, st, g, sa, err,
                      combined ? nullptr : units, qctl, chunk);
-  const dim3 mg(2 * g.npatch, sa.nsp);
+  const dim3 mg(std::min(2 * g.npatch, kReslabGrid), sa.nsp);
+  const dim3 bg(std::min(g.npatch, kReslabGrid), sa.nsp);
   if (g.dim == 2) {
     hipLaunchKernelGGL(k_reslab_move<2>, mg, dim3(256), 0, st, g, sa);
-    hipLaunchKernelGGL(k_reslab_back<2>, pg, dim3(256), 0, st, g, sa);
+    hipLaunchKernelGGL(k_reslab_back<2>, bg, dim3(256), 0, st, g, sa);
   } else {
     hipLaunchKernelGGL(k_reslab_move<3>, mg, dim3(256), 0, st, g, sa);
-    hipLaunchKernelGGL(k_reslab_back<3>, pg, dim3(256), 0, st, g, sa);
+    hipLaunchKernelGGL(k_reslab_back<3>, bg, dim3(256), 0, st, g, sa);
   }
   if (combined)
     hipLaunchKernelGGL(k_units_all, dim3(1), dim3(1024), 0, st, g, sa, chunk, units, qctl);
