@@ -258,6 +258,22 @@ def test_patch_beyond_the_departure_bitmap(mode, ppc):
     run_cmp(wl, inp, steps, "slab", osp, J, A, mode=mode, chunk=2048)
 
 
+@pytest.mark.parametrize("mode", [0, 1])
+def test_3d_patch_beyond_the_departure_bitmap(mode):
+    """3D patches of more than 16384 particles: the departures kernel's 3D
+    instance (64-thread workgroups, a 16384-slot bitmap) takes them on its
+    tiled large-patch path."""
+    wl = I.custom(3, (24, 16, 16), (8, 8, 8), ppc=1, seed=330 + mode, sigma=0.2)
+    wl.species[0].ppc = lambda ix: np.where(ix < 8, 40, 1).astype(np.int64)
+    inp = I.generate(wl)
+    steps = 3
+    osp, J, A = run_oracle(wl, inp, steps)
+    counts = np.diff(osp[0].off)
+    say(f"case 3D large patches mode={mode}: max patch count {counts.max()}")
+    assert counts.max() > 16384
+    run_cmp(wl, inp, steps, "slab", osp, J, A, mode=mode, chunk=4096)
+
+
 BIN_CASES = [
     # dim, n, patch, bin_x, ppc, nspecies, sigma, steps, seed
     (2, (128, 64), (64, 64), 0, 2, 1, 0.3, 4, 501),        # automatic 16-cell bins
