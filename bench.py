@@ -158,8 +158,10 @@ def run_gpu(wl, steps: int, warmup: int, mode: int = 0, chunk: int = 0, wg: int 
     ctx.bin(sp)
     if warmup:
         # at least three steps, so that the slab layout's kernels (which
-        # calls of one or two steps do not use) are loaded before the timing
-        ctx.step(sp, E, B, J, nsteps=max(warmup, 3))
+        # calls of one or two steps do not use) are loaded before the timing;
+        # with graphs ten, so that the eight-step and the one-step graph are
+        # both captured before it
+        ctx.step(sp, E, B, J, nsteps=max(warmup, 10 if graph else 3))
     torch.cuda.synchronize()
     ctx.check()
     timed = timing and not graph
@@ -719,7 +721,7 @@ def main(argv=None) -> int:
     if args.main_only:
         print(json.dumps(out), flush=True)
         return 0
-    # the same call replaying one captured graph per step (no per-kernel events)
+    # the same call replaying captured graphs of eight steps (no per-kernel events)
     _, secs_g, _ = run_gpu(wl, args.steps, args.warmup, inp=inp0, graph=True, **launch)
     del inp0
     out["graph_replay"] = {"ms_per_step": secs_g / args.steps * 1e3,
@@ -736,7 +738,7 @@ def main(argv=None) -> int:
         pers = dict(mode=1, chunk=tuned["chunk"], wg=tuned["wg"], bin_x=tuned.get("bin_x", 0))
         _, sp_, _ = run_gpu(wli, args.steps, args.warmup, inp=inpi, timing=False, **pers)
         _, sp_ev, tp = run_gpu(wli, args.steps, args.warmup, inp=inpi, **pers)
-        # the persistent call replaying one captured graph per step
+        # the persistent call replaying captured graphs of eight steps
         _, sp_g, _ = run_gpu(wli, args.steps, args.warmup, inp=inpi, graph=True, **pers)
         ns_u = secs / (n * args.steps) * 1e9
         ipp_u = ipp_avg / n * 1e6

@@ -78,11 +78,12 @@ enum { PIC_BC_PERIODIC = 0, PIC_BC_REFLECT = 1, PIC_BC_REMOVE = 2 };
 
 enum {
   PIC_FLAG_CHECK = 1, /* every call waits for its stream and reports device errors */
-  PIC_FLAG_GRAPH = 2, /* pic_step replays a captured HIP graph of its steps
-                         (one step in the slab layout, two in the dense one,
-                         whose buffer swap makes two steps the period); the
-                         graph is recaptured when any array pointer or count
-                         changes */
+  PIC_FLAG_GRAPH = 2, /* pic_step replays captured HIP graphs of its steps
+                         (in the slab layout one of eight steps as often as
+                         the call allows, then one of one step for the rest;
+                         in the dense layout one of two steps, whose buffer
+                         swap makes two steps the period); a graph is
+                         recaptured when any array pointer or count changes */
   PIC_FLAG_DETERMINISTIC = 8, /* pic_step and pic_cycle give the same bits on
                          every run: the dense layout (its counting sort is
                          stable), the per-patch launch (also in persistent

@@ -91,6 +91,10 @@ struct Timing {
 };
 
 // A captured two-step graph and the pointers/counts it was captured with.
+// Steps one captured slab-layout graph holds (a call replays it, then
+// one-step graphs for the remainder): fewer graph launches per step.
+constexpr int kGraphSteps = 8;
+
 struct GraphCache {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -119,7 +123,7 @@ struct pic_ctx {
   int *qctl = nullptr;    // per species: ticket, number of units
   int pgrid = 0;          // persistent grid size
   SlabScratch slab[kMaxSpecies];
-  GraphCache slab_gc;     // one captured slab-layout step
+  GraphCache slab_gc[2];  // captured slab-layout steps: kGraphSteps of them, one
   int pgrid_slab = 0;     // persistent grid size of the slab-layout kernel
   // x-bins: the kernels' "patches" (GridDev) are the bins; with more than one
   // bin per patch the bin offsets live here and the caller's offset arrays
@@ -730,7 +734,7 @@ hipError_t enqueue_slab_step(pic_ctx *c, const SlabArgs &a, const pic_fields *f,
 
 // The captured slab step for these arguments (captured anew when any
 // pointer, count or field differs from the cached one).
-pic_status ensure_slab_graph(pic_ctx *c, const SlabArgs &a, const pic_fields *f,
+pic_status ensure_slab_graph(pic_ctx *c, const SlabArgs &a, const pic_fields *f, int steps,
                              hipGraphExec_t *out) {
   std::vector<uintptr_t> key((sizeof(SlabArgs) + sizeof(uintptr_t) - 1) / sizeof(uintptr_t), 0);
   std::memcpy(key.data(), &a, sizeof(SlabArgs));
@@ -742,7 +746,8 @@ pic_status ensure_slab_graph(pic_ctx *c, const SlabArgs &a, const pic_fields *f,
   key.push_back((uintptr_t)c->units);
   key.push_back((uintptr_t)c->pgrid_slab);
   key.push_back((uintptr_t)c->cycle);
-  GraphCache &gc = c->slab_gc;
+  key.push_back((uintptr_t)steps);
+  GraphCache &gc = c->slab_gc[steps == 1 ? 1 : 0];
   if (gc.exec && key == gc.key) {
     *out = gc.exec;
     return PIC_OK;
@@ -756,7 +761,8 @@ pic_status ensure_slab_graph(pic_ctx *c, const SlabArgs &a, const pic_fields *f,
     return hip_fail(c, e, "hipStreamCreate");
   if ((e = hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal)) != hipSuccess)
     return hip_fail(c, e, "hipStreamBeginCapture");
-  const hipError_t eq = enqueue_slab_step(c, a, f, c->cap_stream);
+  hipError_t eq = hipSuccess;
+  for (int k = 0; k < steps && eq == hipSuccess; k++) eq = enqueue_slab_step(c, a, f, c->cap_stream);
   hipGraph_t g = nullptr;
   e = hipStreamEndCapture(c->cap_stream, &g);
   if (eq != hipSuccess || e != hipSuccess) {
@@ -855,10 +861,20 @@ pic_status step_slab(pic_ctx *c, pic_species *sp, int32_t nsp, pic_fields *f, in
     k0 = 1;
   }
   if ((c->cfg.flags & PIC_FLAG_GRAPH) && !c->tm.on && k0 < nsteps) {
-    hipGraphExec_t x = nullptr;
-    if ((r = ensure_slab_graph(c, a, f, &x)) != PIC_OK) return r;
-    for (int k = k0; k < nsteps; k++)
-      if ((e = hipGraphLaunch(x, st)) != hipSuccess) return hip_fail(c, e, "hipGraphLaunch");
+    // graphs of kGraphSteps steps, then one-step graphs for the rest
+    int k = k0;
+    if (nsteps - k >= kGraphSteps) {
+      hipGraphExec_t x = nullptr;
+      if ((r = ensure_slab_graph(c, a, f, kGraphSteps, &x)) != PIC_OK) return r;
+      for (; nsteps - k >= kGraphSteps; k += kGraphSteps)
+        if ((e = hipGraphLaunch(x, st)) != hipSuccess) return hip_fail(c, e, "hipGraphLaunch");
+    }
+    if (k < nsteps) {
+      hipGraphExec_t x = nullptr;
+      if ((r = ensure_slab_graph(c, a, f, 1, &x)) != PIC_OK) return r;
+      for (; k < nsteps; k++)
+        if ((e = hipGraphLaunch(x, st)) != hipSuccess) return hip_fail(c, e, "hipGraphLaunch");
+    }
   } else {
     for (int k = k0; k < nsteps; k++)
       if ((e = enqueue_slab_step(c, a, f, st)) != hipSuccess) return hip_fail(c, e, "kernel launch");
@@ -1218,8 +1234,10 @@ void pic_free(pic_ctx *c) {
       (void)hipFree(L.ou[a]);
     }
   }
-  if (c->slab_gc.exec) (void)hipGraphExecDestroy(c->slab_gc.exec);
-  if (c->slab_gc.graph) (void)hipGraphDestroy(c->slab_gc.graph);
+  for (GraphCache &gc : c->slab_gc) {
+    if (gc.exec) (void)hipGraphExecDestroy(gc.exec);
+    if (gc.graph) (void)hipGraphDestroy(gc.graph);
+  }
   for (hipEvent_t e : c->tm.pool) (void)hipEventDestroy(e);
   for (GraphCache &gc : c->gc) {
     if (gc.exec) (void)hipGraphExecDestroy(gc.exec);

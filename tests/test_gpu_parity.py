@@ -210,15 +210,17 @@ def test_persistent_imbalanced_profile():
 @pytest.mark.parametrize("layout", list(LAYOUTS))
 @pytest.mark.parametrize("mode", [0, 1])
 def test_graph_replay_matches_oracle(mode, layout):
-    """Steps replayed from captured graphs (slab steps, or pairs of dense
-    steps), interleaved with eager steps and host synchronisations, agree
-    with the oracle after every call sequence."""
+    """Steps replayed from captured graphs (runs of eight slab steps and
+    single slab steps, or pairs of dense steps), interleaved with eager
+    steps and host synchronisations, agree with the oracle after every call
+    sequence; the calls of ten steps replay an eight-step graph (the second
+    one from the cache)."""
     wl = I.custom(2, (48, 32), (8, 8), ppc=5, seed=300 + mode, sigma=0.2)
     inp = I.generate(wl)
     say(f"case graph mode={mode} {layout}")
-    osp, J, A = run_oracle(wl, inp, 11)
-    run_cmp(wl, inp, 11, layout, osp, J, A, mode=mode, chunk=512, graph=True,
-            step_sizes=[4, 1, 2, 3, 1])
+    osp, J, A = run_oracle(wl, inp, 27)
+    run_cmp(wl, inp, 27, layout, osp, J, A, mode=mode, chunk=512, graph=True,
+            step_sizes=[10, 1, 2, 3, 10, 1])
 
 
 @pytest.mark.parametrize("mode", [0, 1])
