@@ -90,11 +90,11 @@ struct Timing {
   int64_t launches[PIC_KERNEL_COUNT] = {0};
 };
 
-// A captured two-step graph and the pointers/counts it was captured with.
-// Steps one captured slab-layout graph holds (a call replays it, then
-// one-step graphs for the remainder): fewer graph launches per step.
+// Steps one captured slab-layout graph holds (a call replays it, then a
+// one-step graph for the remainder): fewer graph launches per step.
 constexpr int kGraphSteps = 8;
 
+// A captured graph and the pointers/counts it was captured with.
 struct GraphCache {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -123,7 +123,7 @@ struct pic_ctx {
   int *qctl = nullptr;    // per species: ticket, number of units
   int pgrid = 0;          // persistent grid size
   SlabScratch slab[kMaxSpecies];
-  GraphCache slab_gc[2];  // captured slab-layout steps: kGraphSteps of them, one
+  GraphCache slab_gc[2];  // slab-layout graphs: [0] kGraphSteps steps, [1] one step
   int pgrid_slab = 0;     // persistent grid size of the slab-layout kernel
   // x-bins: the kernels' "patches" (GridDev) are the bins; with more than one
   // bin per patch the bin offsets live here and the caller's offset arrays
@@ -732,8 +732,9 @@ hipError_t enqueue_slab_step(pic_ctx *c, const SlabArgs &a, const pic_fields *f,
   return e;
 }
 
-// The captured slab step for these arguments (captured anew when any
-// pointer, count or field differs from the cached one).
+// The captured run of `steps` slab steps (kGraphSteps or one) for these
+// arguments (captured anew when any pointer, count or field differs from
+// the cached one).
 pic_status ensure_slab_graph(pic_ctx *c, const SlabArgs &a, const pic_fields *f, int steps,
                              hipGraphExec_t *out) {
   std::vector<uintptr_t> key((sizeof(SlabArgs) + sizeof(uintptr_t) - 1) / sizeof(uintptr_t), 0);
