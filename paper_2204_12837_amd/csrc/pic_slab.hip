@@ -259,12 +259,55 @@ __device__ __forceinline__ int block_excl_sum(int v, int &tot, int *wtot) {
   return base + x - v;
 }
 
-// Departures of patch P handled by the fused kernel's workgroup after its
-// particle loop: `bits` marks the departing slots, `pre` receives the
-// departures before each bitmap word.  Copies the departures to the outbox
-// region (in slot order) and refills the holes below c2 = c - departures
-// with the stayers of [c2, c): the q-th stayer of the tail takes the slot of
-// the q-th departure.
+// The slot of the n-th set bit of a bitmap whose words hold pre[i] set bits
+// before word i (words 0 .. W-1).
+__device__ __forceinline__ int nth_set(const uint32_t *bits, const int *pre, int W, int n) {
+  int lo = 0, hi = W - 1;  // the last word with pre <= n holds it
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (pre[mid] <= n)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  uint32_t b = bits[lo];
+  for (int d = n - pre[lo]; d > 0; d--) b &= b - 1;
+  return 32 * lo + __ffs(b) - 1;
+}
+
+// The slot of the n-th particle that stays among slots [c2, c) (bit clear),
+// given the H departures below c2.
+__device__ __forceinline__ int nth_tail_stayer(const uint32_t *bits, const int *pre, int W, int c2,
+                                               int c, int H, int n) {
+  // stayers of [c2, 32 w) for a word w past c2's: 32 w - c2 - (pre[w] - H)
+  int lo = c2 >> 5, hi = W - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (32 * mid - c2 - (pre[mid] - H) <= n)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  uint32_t b = ~bits[lo];
+  int before = 0;
+  if (lo == (c2 >> 5))
+    b &= ~((1u << (c2 & 31)) - 1u);  // (c2 & 31 == 0 keeps the word)
+  else
+    before = 32 * lo - c2 - (pre[lo] - H);
+  if (lo == W - 1 && (c & 31)) b &= (1u << (c & 31)) - 1u;
+  for (int d = n - before; d > 0; d--) b &= b - 1;
+  return 32 * lo + __ffs(b) - 1;
+}
+
+// Departures of patch P from its departure bitmap (`bits`: bit j set if
+// slot j leaves; `pre` receives the departures before each word): the q-th
+// departure (slot order) goes to entry q of the patch's outbox region with
+// its destination patch, and the departures below c2 = c - departures are
+// the holes that the stayers of the slab's tail [c2, c) fill, the q-th
+// stayer taking the q-th hole.  Each thread takes departures q, q + threads,
+// ...: it loads the departure and, for a hole, its stayer before any store
+// (one memory round trip per departure; the hole's old contents are read
+// by the thread that overwrites them).
 template <int DIM>
 __device__ void depart_in_kernel(const GridDev &g, const SlabDev &S, int P, int c,
                                  const uint32_t *bits, int *pre, int *wtot) {
@@ -286,41 +329,53 @@ __device__ void depart_in_kernel(const GridDev &g, const SlabDev &S, int P, int 
     if (threadIdx.x == 0) S.cnt2[P] = c;
     return;
   }
+  __syncthreads();  // pre[] complete
   const int c2 = c - m;
+  // departures below c2
+  const int H = (c2 >> 5) < W ? pre[c2 >> 5] + __popc(bits[c2 >> 5] & ((1u << (c2 & 31)) - 1u)) : m;
   int pc[3];
   patch_coords(g, P, pc);
-  for (int i = w0; i < w1; i++) {
-    uint32_t b = bits[i];
-    int rr = pre[i];
-    while (b) {
-      const int j = 32 * i + __ffs(b) - 1;
-      b &= b - 1;
-      const int64_t o = sbP + rr++;
-      copy_particle<DIM>(S.ox, S.ou, S.ow, S.oid, o, S.xs, S.us, S.ws, S.ids, sbP + j);
-      S.odest[o] = dest_patch(g, pc, (int)S.code[sbP + j]);
+  for (int q = threadIdx.x; q < m; q += nt) {
+    const int h = nth_set(bits, pre, W, q);
+    const int j = q < H ? nth_tail_stayer(bits, pre, W, c2, c, H, q) : -1;
+    const int64_t sh = sbP + h;
+    double xh[DIM], uh[3], xj[DIM], uj[3], wj = 0.0;
+    int64_t idj = 0;
+#pragma unroll
+    for (int a = 0; a < DIM; a++) xh[a] = S.xs[a][sh];
+    uh[0] = S.us[0][sh];
+    uh[1] = S.us[1][sh];
+    uh[2] = S.us[2][sh];
+    const double wh = S.ws[sh];
+    const int64_t idh = S.ids[sh];
+    const int cd = (int)S.code[sh];
+    if (j >= 0) {
+      const int64_t sj = sbP + j;
+#pragma unroll
+      for (int a = 0; a < DIM; a++) xj[a] = S.xs[a][sj];
+      uj[0] = S.us[0][sj];
+      uj[1] = S.us[1][sj];
+      uj[2] = S.us[2][sj];
+      wj = S.ws[sj];
+      idj = S.ids[sj];
     }
-  }
-  __syncthreads();  // pre[] complete, departures read before the holes are refilled
-  int qrun = 0, tot = 0;
-  for (int j0 = c2; j0 < c; j0 += nt) {
-    const int j = j0 + (int)threadIdx.x;
-    const bool stay = j < c && !((bits[j >> 5] >> (j & 31)) & 1u);
-    const int q = qrun + block_excl_sum(stay ? 1 : 0, tot, wtot);
-    qrun += tot;
-    if (stay) {
-      // the q-th departure: word i with pre[i] <= q < pre[i + 1], then its bit
-      int lo = 0, hi = W - 1;
-      while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (pre[mid] <= q)
-          lo = mid;
-        else
-          hi = mid - 1;
-      }
-      uint32_t b = bits[lo];
-      for (int d = q - pre[lo]; d > 0; d--) b &= b - 1;
-      const int h = 32 * lo + __ffs(b) - 1;
-      copy_particle<DIM>(S.xs, S.us, S.ws, S.ids, sbP + h, S.xs, S.us, S.ws, S.ids, sbP + j);
+    const int64_t o = sbP + q;
+#pragma unroll
+    for (int a = 0; a < DIM; a++) S.ox[a][o] = xh[a];
+    S.ou[0][o] = uh[0];
+    S.ou[1][o] = uh[1];
+    S.ou[2][o] = uh[2];
+    S.ow[o] = wh;
+    S.oid[o] = idh;
+    S.odest[o] = dest_patch(g, pc, cd);
+    if (j >= 0) {
+#pragma unroll
+      for (int a = 0; a < DIM; a++) S.xs[a][sh] = xj[a];
+      S.us[0][sh] = uj[0];
+      S.us[1][sh] = uj[1];
+      S.us[2][sh] = uj[2];
+      S.ws[sh] = wj;
+      S.ids[sh] = idj;
     }
   }
   if (threadIdx.x == 0) S.cnt2[P] = c2;
@@ -501,9 +556,8 @@ template <int CENTER>
 __device__ __forceinline__ void code_bits(const uint8_t *code, int c, uint32_t *bits) {
   constexpr uint32_t kC = CENTER * 0x01010101u;
   const int W = (c + 31) >> 5;
-  for (int i = threadIdx.x; i < W; i += blockDim.x) {
-    const uint4 *p = reinterpret_cast<const uint4 *>(code) + 2 * i;
-    const uint4 a = p[0], b = p[1];
+  const int nt = blockDim.x;
+  auto word = [&](const uint4 &a, const uint4 &b, int i) {
     const uint32_t v[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
     uint32_t m = 0;
 #pragma unroll
@@ -514,6 +568,19 @@ __device__ __forceinline__ void code_bits(const uint8_t *code, int c, uint32_t *
     }
     const int valid = c - 32 * i;
     bits[i] = valid >= 32 ? m : m & ((1u << valid) - 1u);
+  };
+  // two words per thread and memory round trip
+  for (int i = threadIdx.x; i < W; i += 2 * nt) {
+    const uint4 *p = reinterpret_cast<const uint4 *>(code) + 2 * i;
+    const uint4 a0 = p[0], b0 = p[1];
+    const int i1 = i + nt;
+    uint4 a1 = a0, b1 = b0;
+    if (i1 < W) {
+      a1 = p[2 * nt];
+      b1 = p[2 * nt + 1];
+    }
+    word(a0, b0, i);
+    if (i1 < W) word(a1, b1, i1);
   }
 }
 
