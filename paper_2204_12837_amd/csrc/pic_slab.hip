@@ -678,11 +678,16 @@ __global__ void __launch_bounds__(kExchWgMax) k_exch_out(GridDev g, SlabArgs sa,
   if (threadIdx.x == 0) S.cnt2[P] = c2;
 }
 
-// Arrivals (grid: source patches x species): each departure of patch Q
-// takes the next free slot of its destination slab; one that finds the slab
-// full stays in the outbox, marked, and raises the overflow flag.
+// Arrivals (grid: source patches x species, kExchInWg threads): each
+// departure of patch Q takes the next free slot of its destination slab; one
+// that finds the slab full stays in the outbox, marked, and raises the
+// overflow flag.  A wave's departures to one destination take their slots
+// with one atomic add (a patch's departures go to at most 8 or 26
+// neighbours), so the arrival counters see a few adds per source wave.
+constexpr int kExchInWg = 128;
+
 template <int DIM>
-__global__ void __launch_bounds__(256) k_exch_in(GridDev g, SlabArgs sa) {
+__global__ void __launch_bounds__(kExchInWg) k_exch_in(GridDev g, SlabArgs sa) {
   const SlabDev &S = sa.s[blockIdx.y];
   const int Q = blockIdx.x;
   // the state flag, the departure count and the outbox start are read
@@ -691,21 +696,44 @@ __global__ void __launch_bounds__(256) k_exch_in(GridDev g, SlabArgs sa) {
   const int m = S.dep[Q];
   const int64_t ob = S.sb[Q];
   if (flag == 2) return;
-  for (int r = threadIdx.x; r < m; r += blockDim.x) {
-    const int64_t e = ob + r;
+  const int lane = threadIdx.x & 63;
+  // whole waves iterate together (the ballots below need every lane)
+  for (int rb = (int)threadIdx.x - lane; rb < m; rb += blockDim.x) {
+    const int r = rb + lane;
+    const bool valid = r < m;
+    const int64_t e = ob + (valid ? r : 0);
     // the departure's state is loaded with its destination, so only the
     // stores wait for the slot the destination's arrival counter hands out
-    double x[DIM], u[3];
+    double x[DIM], u[3], w = 0.0;
+    int64_t id = 0;
+    int D = -1;
+    if (valid) {
 #pragma unroll
-    for (int a = 0; a < DIM; a++) x[a] = S.ox[a][e];
-    u[0] = S.ou[0][e];
-    u[1] = S.ou[1][e];
-    u[2] = S.ou[2][e];
-    const double w = S.ow[e];
-    const int64_t id = S.oid[e];
-    const int D = S.odest[e];
-    if (D < 0) continue;  // deleted at a removing wall
-    const int pos = S.cnt2[D] + atomicAdd(&S.arr[D], 1);
+      for (int a = 0; a < DIM; a++) x[a] = S.ox[a][e];
+      u[0] = S.ou[0][e];
+      u[1] = S.ou[1][e];
+      u[2] = S.ou[2][e];
+      w = S.ow[e];
+      id = S.oid[e];
+      D = S.odest[e];  // < 0: deleted at a removing wall
+    }
+    const bool live = D >= 0;
+    // group the live lanes by destination; the group's first lane leads
+    uint64_t todo = __ballot(live);
+    uint64_t group = 0;
+    while (todo) {
+      const int l = __ffsll((unsigned long long)todo) - 1;
+      const int Dl = __shfl(D, l, 64);
+      const uint64_t mk = __ballot(live && D == Dl);
+      if (live && D == Dl) group = mk;
+      todo &= ~mk;
+    }
+    const int leader = live ? __ffsll((unsigned long long)group) - 1 : lane;
+    int got = 0;
+    if (live && leader == lane) got = atomicAdd(&S.arr[D], __popcll(group));
+    const int gbase = __shfl(got, leader, 64);
+    if (!live) continue;
+    const int pos = S.cnt2[D] + gbase + __popcll(group & ((1ull << lane) - 1ull));
     if (pos < S.cap[D]) {
       const int64_t d = S.sb[D] + pos;
 #pragma unroll
@@ -1062,10 +1090,10 @@ hipError_t launch_exchange(const GridDev &g, const SlabArgs &sa, int *err, Unit 
   const int only_marked = units ? 0 : 1;  // the per-patch fused kernel did the departures
   if (g.dim == 2) {
     hipLaunchKernelGGL(k_exch_out<2>, pg, dim3(kExchWg2), 0, st, g, sa, only_marked);
-    hipLaunchKernelGGL(k_exch_in<2>, pg, dim3(256), 0, st, g, sa);
+    hipLaunchKernelGGL(k_exch_in<2>, pg, dim3(kExchInWg), 0, st, g, sa);
   } else {
     hipLaunchKernelGGL(k_exch_out<3>, pg, dim3(kExchWg3), 0, st, g, sa, only_marked);
-    hipLaunchKernelGGL(k_exch_in<3>, pg, dim3(256), 0, st, g, sa);
+    hipLaunchKernelGGL(k_exch_in<3>, pg, dim3(kExchInWg), 0, st, g, sa);
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
