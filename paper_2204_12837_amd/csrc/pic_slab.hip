@@ -752,30 +752,31 @@ __global__ void __launch_bounds__(kExchInWg) k_exch_in(GridDev g, SlabArgs sa) {
 
 // Persistent mode: work units of chunk particles for the patch counts, every
 // full unit first, then the remainders (one workgroup, each thread a
-// contiguous run of patches).  first(P) gives patch P's count once (it may
-// also store it); again(P) gives it a second time.  The list goes to ul
-// (units tagged with species s), its length to q[1] (0 if the species stands
-// still) and a zero ticket to q[0].
-constexpr int kUnitsCached = 8;  // counts a thread keeps in registers
-
-template <class First, class Again>
-__device__ void make_units(int s, int n, int chunk, bool still, First first, Again again,
-                           Unit *ul, int *q, int *wtot) {
+// contiguous run of patches).  count(P) loads patch P's count; keep(P, c)
+// stores what the caller derives from it (the loads of a thread's first
+// kUnitsCached patches are issued before any of their stores); again(P)
+// gives the count a second time, after keep.  The list goes to ul (units
+// tagged with species s), its length to q[1] (0 if the species stands
+// still) and a zero ticket to q[0].  kUnitsCached: counts a thread keeps in
+// registers.
+template <int kUnitsCached, class Count, class Keep, class Again>
+__device__ void make_units(int s, int n, int chunk, bool still, Count count, Keep keep,
+                           Again again, Unit *ul, int *q, int *wtot) {
   const int per = (n + blockDim.x - 1) / blockDim.x;
   const int p0 = min(n, (int)threadIdx.x * per), p1 = min(n, p0 + per);
   int cc[kUnitsCached];
   int nf = 0, nr = 0;
 #pragma unroll
+  for (int k = 0; k < kUnitsCached; k++) cc[k] = p0 + k < p1 ? count(p0 + k) : 0;
+#pragma unroll
   for (int k = 0; k < kUnitsCached; k++) {
-    cc[k] = 0;
-    if (p0 + k < p1) {
-      cc[k] = first(p0 + k);
-      nf += cc[k] / chunk;
-      nr += cc[k] % chunk != 0;
-    }
+    if (p0 + k < p1) keep(p0 + k, cc[k]);
+    nf += cc[k] / chunk;
+    nr += cc[k] % chunk != 0;
   }
   for (int P = p0 + kUnitsCached; P < p1; P++) {
-    const int c = first(P);
+    const int c = count(P);
+    keep(P, c);
     nf += c / chunk;
     nr += c % chunk != 0;
   }
@@ -821,20 +822,33 @@ __global__ void __launch_bounds__(1024) k_exch_fin(GridDev g, SlabArgs sa, int *
   if (flag == 2) return;
   if (flag == 0) {
     if (units) {  // the new counts, and the work units from them, in one pass
-      make_units(
-          s, n, chunk, false,
-          [&](int P) {
-            const int c = S.cnt2[P] + S.arr[P];
+      make_units<8>(
+          s, n, chunk, false, [&](int P) { return S.cnt2[P] + S.arr[P]; },
+          [&](int P, int c) {
             S.cnt[P] = c;
             S.arr[P] = 0;
-            return c;
           },
           [&](int P) { return S.cnt[P]; }, units + S.ubase, qctl + 2 * s, wtot);
       return;
     }
-    for (int P = threadIdx.x; P < n; P += blockDim.x) {
-      S.cnt[P] = S.cnt2[P] + S.arr[P];
-      S.arr[P] = 0;
+    // four patches per thread and memory round trip
+    constexpr int kB = 4;
+    const int nt = blockDim.x;
+    for (int P0 = threadIdx.x; P0 < n; P0 += kB * nt) {
+      int c[kB];
+#pragma unroll
+      for (int k = 0; k < kB; k++) {
+        const int P = P0 + k * nt;
+        c[k] = P < n ? S.cnt2[P] + S.arr[P] : 0;
+      }
+#pragma unroll
+      for (int k = 0; k < kB; k++) {
+        const int P = P0 + k * nt;
+        if (P < n) {
+          S.cnt[P] = c[k];
+          S.arr[P] = 0;
+        }
+      }
     }
     return;
   }
@@ -853,7 +867,8 @@ __global__ void __launch_bounds__(1024) k_exch_fin(GridDev g, SlabArgs sa, int *
   }
   if (units) {  // the counts the new plan's copies will set
     auto need = [&](int P) { return S.cnt2[P] + S.arr[P]; };
-    make_units(s, n, chunk, still, need, need, units + S.ubase, qctl + 2 * s, wtot);
+    make_units<8>(s, n, chunk, still, need, [](int, int) {}, need, units + S.ubase, qctl + 2 * s,
+                  wtot);
   }
 }
 
@@ -924,7 +939,8 @@ __global__ void __launch_bounds__(1024) k_slab_units(GridDev g, SlabArgs sa, int
   const int s = blockIdx.x;
   const SlabDev &S = sa.s[s];
   auto count = [&](int P) { return S.cnt[P]; };
-  make_units(s, g.npatch, chunk, S.ctl[1] == 2, count, count, units + S.ubase, qctl + 2 * s, wtot);
+  make_units<16>(s, g.npatch, chunk, S.ctl[1] == 2, count, [](int, int) {}, count,
+                 units + S.ubase, qctl + 2 * s, wtot);
 }
 
 // Persistent mode with several species: one list of units over every
@@ -942,7 +958,7 @@ __global__ void __launch_bounds__(1024) k_units_all(GridDev g, SlabArgs sa, int 
       if (sa.s[s].ctl[1] != 2) c += sa.s[s].cnt[P];
     return c;
   };
-  make_units(-1, g.npatch, chunk, false, count, count, units, qctl, wtot);
+  make_units<16>(-1, g.npatch, chunk, false, count, [](int, int) {}, count, units, qctl, wtot);
 }
 
 // End of a call: dense offsets from the slab counts (one workgroup of 1024
