@@ -397,11 +397,12 @@ __global__ void __launch_bounds__(kMaxWgSlab<DIM>, kSlabMinWaves<DIM>) k_ipp_sla
   const int P = blockIdx.x;
   const SlabDev &S = sa.s[blockIdx.y];
   const uint64_t t0 = sa.trace ? __builtin_amdgcn_s_memrealtime() : 0;
-  if (S.ctl[1] == 2) return;
+  const int flag = S.ctl[1];
+  const int c = S.cnt[P];  // (loaded with the flag)
+  if (flag == 2) return;
   const TileGeom t = tile_geom<DIM>(g, P);
   double *tEB = lds;
   double *tJ = lds + 6 * t.TE;
-  const int c = S.cnt[P];
   const bool mark = c <= kBitSlots;
   stage_eb<DIM>(g, t, f, tEB);
   zero_tile<DIM>(tJ, 3 * t.TJ);
@@ -601,11 +602,14 @@ __global__ void __launch_bounds__(kExchWgMax) k_exch_out(GridDev g, SlabArgs sa,
   __shared__ uint32_t bits[kExchBitWords<DIM>];
   __shared__ int pre[kExchBitWords<DIM>];
   __shared__ int wtot[16];
-  if (S.ctl[1] == 2) return;
-  if (P == 0 && threadIdx.x == 0) S.ctl[1] = 0;  // the previous step's overflow is resolved
-  if (only_marked && S.dep[P] >= 0) return;     // done by the fused kernel
+  // the patch's words are loaded together, before the tests that use them
+  const int flag = S.ctl[1];
+  const int dp = S.dep[P];
   const int c = S.cnt[P];
   const int64_t sbP = S.sb[P];
+  if (flag == 2) return;
+  if (P == 0 && threadIdx.x == 0) S.ctl[1] = 0;  // the previous step's overflow is resolved
+  if (only_marked && dp >= 0) return;           // done by the fused kernel
   if (c <= kExchBitSlots<DIM>) {
     code_bits<CENTER>(S.code + sbP, c, bits);
     __syncthreads();
@@ -753,9 +757,9 @@ __global__ void __launch_bounds__(kExchInWg) k_exch_in(GridDev g, SlabArgs sa) {
 // Persistent mode: work units of chunk particles for the patch counts, every
 // full unit first, then the remainders (one workgroup, each thread a
 // contiguous run of patches).  count(P) loads patch P's count; keep(P, c)
-// stores what the caller derives from it (the loads of a thread's first
-// kUnitsCached patches are issued before any of their stores); again(P)
-// gives the count a second time, after keep.  The list goes to ul (units
+// stores what the caller derives from it (for a thread's first kUnitsCached
+// patches: all loads first, the stores after the scans); again(P) gives the
+// count a second time, after keep.  The list goes to ul (units
 // tagged with species s), its length to q[1] (0 if the species stands
 // still) and a zero ticket to q[0].  kUnitsCached: counts a thread keeps in
 // registers.
@@ -770,7 +774,6 @@ __device__ void make_units(int s, int n, int chunk, bool still, Count count, Kee
   for (int k = 0; k < kUnitsCached; k++) cc[k] = p0 + k < p1 ? count(p0 + k) : 0;
 #pragma unroll
   for (int k = 0; k < kUnitsCached; k++) {
-    if (p0 + k < p1) keep(p0 + k, cc[k]);
     nf += cc[k] / chunk;
     nr += cc[k] % chunk != 0;
   }
@@ -783,6 +786,11 @@ __device__ void make_units(int s, int n, int chunk, bool still, Count count, Kee
   int tf = 0, tr = 0;
   int rf = block_excl_sum(nf, tf, wtot);
   int rr = tf + block_excl_sum(nr, tr, wtot);
+  // the cached patches' stores after the scans, whose barriers then need
+  // not wait for them
+#pragma unroll
+  for (int k = 0; k < kUnitsCached; k++)
+    if (p0 + k < p1) keep(p0 + k, cc[k]);
   auto emit = [&](int P, int c) {
     Unit un;
     un.s = s;
