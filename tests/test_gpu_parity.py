@@ -261,6 +261,28 @@ def test_patch_beyond_the_departure_bitmap(mode, ppc):
 
 
 @pytest.mark.parametrize("mode", [0, 1])
+def test_many_departures_per_patch(mode):
+    """Hot particles in small patches: several hundred departures per patch
+    and step, more than one per thread of the departures' and the arrivals'
+    workgroups, so each thread takes several departures (and their hole
+    fills) in turn and a wave's arrivals spread over every neighbour."""
+    wl = I.custom(2, (64, 64), (8, 8), ppc=128, seed=340 + mode, sigma=0.6)
+    inp = I.generate(wl)
+    # departures of the first step, free streaming (the fields are weak)
+    s = inp.species[0]
+    v = s.u / np.sqrt(1.0 + (s.u ** 2).sum(0))
+    side = wl.patch[0] * wl.d[0]
+    p0 = np.floor(s.x[:2] / side).astype(np.int64) % 8
+    p1 = np.floor((s.x[:2] + v[:2] * wl.dt) / side).astype(np.int64) % 8
+    dep = np.bincount(p0[1] * 8 + p0[0], weights=(p0 != p1).any(0), minlength=64)
+    assert dep.min() > 256
+    steps = 3
+    osp, J, A = run_oracle(wl, inp, steps)
+    say(f"case many departures mode={mode}: {int(dep.min())}..{int(dep.max())} per patch")
+    run_cmp(wl, inp, steps, "slab", osp, J, A, mode=mode, chunk=2048)
+
+
+@pytest.mark.parametrize("mode", [0, 1])
 def test_3d_patch_beyond_the_departure_bitmap(mode):
     """3D patches of more than 16384 particles: the departures kernel's 3D
     instance (64-thread workgroups, a 16384-slot bitmap) takes them on its
