@@ -343,11 +343,13 @@ def run_split(steps: int = 10):
             "kernel_ms": {k: round(v[0] / max(v[1], 1), 4) for k, v in tim.items() if v[1]}}
 
 
-def run_short_calls(calls: int = 10):
-    """pic_step calls of one step each on the uniform workload: the dense
-    layout (fused kernel writing neighbour-code tags, then the counting
-    sort that restores per-patch order), as a caller that steps one at a
-    time sees it."""
+def run_short_calls(calls: int = 10, resident: bool = False):
+    """pic_step calls of one step each on the uniform workload, as a caller
+    that steps one at a time sees it.  Without resident: the dense layout
+    (fused kernel writing neighbour-code tags, then the counting sort that
+    restores per-patch order).  With resident (PIC_FLAG_RESIDENT): the
+    particles stay in the slab layout between calls; the timed region ends
+    with the pic_sync that writes the dense layout back."""
     import torch
 
     from paper_2204_12837_amd import inputs as I
@@ -356,17 +358,24 @@ def run_short_calls(calls: int = 10):
     wl = I.workload("uniform1024")
     inp = I.generate(wl)
     n = sum(s.x.shape[1] for s in inp.species)
-    ctx = pic.Context(wl, device=0)
-    sp = pic.upload(inp, "cuda:0", capacity_factor=1.0)
+    ctx = pic.Context(wl, device=0, resident=resident)
+    if resident:
+        sp = pic.upload(inp, "cuda:0", n_slabs=ctx.n_slabs)
+    else:
+        sp = pic.upload(inp, "cuda:0", capacity_factor=1.0)
     E, B, J = pic.upload_fields(inp, "cuda:0")
     ctx.bin(sp)
     for _ in range(2):
         ctx.step(sp, E, B, J, nsteps=1)
+    if resident:
+        ctx.sync()
     torch.cuda.synchronize()
     ctx.timing(True)
     t0 = time.perf_counter()
     for _ in range(calls):
         ctx.step(sp, E, B, J, nsteps=1)
+    if resident:
+        ctx.sync()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ctx.check()
@@ -375,7 +384,8 @@ def run_short_calls(calls: int = 10):
     ctx.close()
     del sp, E, B, J
     torch.cuda.empty_cache()
-    return {"workload": "uniform1024", "particles": n, "calls": calls, "layout": "dense",
+    return {"workload": "uniform1024", "particles": n, "calls": calls,
+            "layout": "slab, resident" if resident else "dense",
             "ms_per_step": (t1 - t0) / calls * 1e3,
             "kernel_ms": {k: round(v[0] / max(v[1], 1), 4) for k, v in tim.items() if v[1]}}
 
@@ -794,6 +804,7 @@ def main(argv=None) -> int:
         out["large_patches"] = run_large_patches(min(args.steps, 50), args.warmup)
     out["split_entry_points"] = run_split()
     out["one_step_calls"] = run_short_calls()
+    out["one_step_calls_resident"] = run_short_calls(resident=True)
     if not args.no_maxwell:
         out["maxwell"] = run_maxwell()
         out["rho"] = run_rho()

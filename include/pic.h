@@ -96,6 +96,24 @@ enum {
                          tiles do not fit (3D).  Not with removing walls
                          (PIC_ERR_ARG).  pic_project and pic_rho keep their
                          order-dependent float64 atomic sums. */
+  PIC_FLAG_RESIDENT = 16, /* pic_step (and pic_cycle) leave the particles in
+                         their slabs (second buffer set) at the end of the
+                         call, and the next pic_step on the same species
+                         arrays continues from there: no slab plan, no first
+                         step from the dense layout and no slabs -> dense
+                         copy per call, so calls of one or two steps cost
+                         what a step of a long call costs.  Every call of
+                         one step or more takes the slab layout (buffers
+                         with its room; otherwise the call runs in the
+                         dense layout and nothing stays resident).  While
+                         resident, the first buffer set and the offsets are
+                         stale: pic_sync writes them (the dense layout, in
+                         the first set, as a call without the flag leaves
+                         it), and so does every other entry point that
+                         takes particles, and pic_step on other arrays,
+                         before it starts.  pic_free writes nothing back.
+                         Not with PIC_FLAG_DETERMINISTIC or removing walls
+                         (PIC_ERR_ARG). */
   PIC_FLAG_TRACE = 4  /* the fused kernel of pic_step's slab layout records,
                          for every work item of each launch (a (patch,
                          species) workgroup in per-patch mode, a popped unit
@@ -269,12 +287,19 @@ pic_status pic_project(pic_ctx *ctx, const pic_species *sp, int32_t nsp, pic_fie
  * sorts by neighbour code (stable: the order inside a patch is the previous
  * order).  In persistent mode the fused kernel runs on a fixed grid that pulls
  * (patch, particle range) units from a device queue.  With PIC_FLAG_GRAPH
- * (and timing off) the steps replay a captured HIP graph (one step in the
- * slab layout, two otherwise).  The context owns an outbox of capacity
+ * (and timing off) the steps replay captured HIP graphs (of eight steps and
+ * of one in the slab layout, of two otherwise).  With PIC_FLAG_RESIDENT the
+ * particles stay in the slabs between calls (see the flag).  The context owns an outbox of capacity
  * particles per species for the slab layout.  With removing walls every
  * call takes the slab layout and updates sp[s].n on return. */
 pic_status pic_step(pic_ctx *ctx, pic_species *sp, int32_t nsp, pic_fields *f, int32_t nsteps,
                     void *stream);
+
+/* PIC_FLAG_RESIDENT: write the particles that pic_step left in their slabs
+ * back to the dense layout (first buffer set, offsets, as a pic_step
+ * without the flag leaves them), enqueued on stream.  No-op when nothing is
+ * resident.  With PIC_FLAG_CHECK it waits for the stream. */
+pic_status pic_sync(pic_ctx *ctx, void *stream);
 
 /* pic_step without any device allocation, for callers that cannot
  * allocate: code under HIP graph capture, tight serving loops, harnesses

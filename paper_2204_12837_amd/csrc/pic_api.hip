@@ -133,6 +133,12 @@ struct pic_ctx {
   int64_t *boff[kMaxSpecies] = {};      // [bins + 1] per species
   // pic_cycle: every step ends with a field step on the step's fields
   bool cycle = false;
+  // PIC_FLAG_RESIDENT: the particles of these species live in their slabs
+  // (second buffer set) since the last pic_step; the first set and the
+  // offsets are stale until resident_flush
+  bool resident = false;
+  int32_t res_nsp = 0;
+  pic_species res_sp[kMaxSpecies];
   YeeArgs yee{};
   // pic_step_noalloc: this device's static scratch; layout_stale: the
   // segment starts and work units in sp[] do not describe the particles
@@ -796,8 +802,11 @@ pic_status ensure_boff(pic_ctx *c, int32_t nsp) {
 // pic_step in the slab layout: dense -> slabs, nsteps slab steps, slabs ->
 // dense (new offsets); the caller's first buffer set holds the result.
 // Enqueues only (the caller finishes the call).
+// cont: the particles are already in the slabs (a resident call after a
+// resident call on the same species): no slab plan and no first step from
+// the dense layout.  keep: leave them there (no slabs -> dense copy).
 pic_status step_slab(pic_ctx *c, pic_species *sp, int32_t nsp, pic_fields *f, int32_t nsteps,
-                     hipStream_t st) {
+                     hipStream_t st, bool cont, bool keep) {
   pic_status r = ensure_slab(c, sp, nsp, st);
   if (r != PIC_OK) return r;
   if (c->cfg.flags & PIC_FLAG_TRACE) {
@@ -824,7 +833,7 @@ pic_status step_slab(pic_ctx *c, pic_species *sp, int32_t nsp, pic_fields *f, in
   // puts them in bin order (bin counts first, then the slab plan, then each
   // particle straight into its bin's slab)
   const bool bins = c->nb > 1 && bin_order_supported(c->nb);
-  if (bins) {
+  if (bins && !cont) {
     if ((r = ensure_boff(c, nsp)) != PIC_OK) return r;
     for (int s = 0; s < nsp; s++) {
       SpDev d = make_args(c, sp, nsp).s[s];
@@ -839,8 +848,8 @@ pic_status step_slab(pic_ctx *c, pic_species *sp, int32_t nsp, pic_fields *f, in
   // without x-bins the first step's fused kernel reads the dense layout
   // itself and fills the slabs (the call makes no separate copy into them)
   SlabArgs first = a;
-  first.from_dense = bins ? 0 : 1;
-  hipError_t e = timed(c, PIC_KERNEL_SLAB, st, [&] {
+  first.from_dense = bins || cont ? 0 : 1;
+  hipError_t e = cont ? hipSuccess : timed(c, PIC_KERNEL_SLAB, st, [&] {
     hipError_t r2 = launch_slab_begin(c->g, a, c->err_dev, st, false);
     for (int s = 0; bins && s < nsp && r2 == hipSuccess; s++) {
       SpDev d = make_args(c, sp, nsp).s[s];
@@ -850,7 +859,8 @@ pic_status step_slab(pic_ctx *c, pic_species *sp, int32_t nsp, pic_fields *f, in
     }
     return r2;
   });
-  if (e == hipSuccess && pers)
+  // (a continued call's units are the last step's, made for the next one)
+  if (e == hipSuccess && pers && !cont)
     e = timed(c, PIC_KERNEL_EXCHANGE, st, [&] {
       return launch_slab_units(c->g, a, c->g.spc * kSeg, c->units, c->qctl, st);
     });
@@ -880,6 +890,7 @@ pic_status step_slab(pic_ctx *c, pic_species *sp, int32_t nsp, pic_fields *f, in
     for (int k = k0; k < nsteps; k++)
       if ((e = enqueue_slab_step(c, a, f, st)) != hipSuccess) return hip_fail(c, e, "kernel launch");
   }
+  if (keep) return PIC_OK;
   e = timed(c, PIC_KERNEL_SLAB, st, [&] {
     hipError_t r2 = launch_slab_end(c->g, a, st);
     // the dense layout's segment starts (and persistent work units) for
@@ -900,6 +911,43 @@ hipError_t api_offsets(pic_ctx *c, const pic_species *sp, int32_t nsp, hipStream
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
+}
+
+// PIC_FLAG_RESIDENT: the resident species' slabs -> dense layout, offsets,
+// segment starts (and work units) -- what pic_step's slab layout does at the
+// end of a call -- enqueued on st; then nothing is resident.
+pic_status resident_flush(pic_ctx *c, hipStream_t st) {
+  if (!c->resident) return PIC_OK;
+  c->resident = false;
+  const pic_species *sp = c->res_sp;
+  const int32_t nsp = c->res_nsp;
+  const SlabArgs a = make_slab_args(c, sp, nsp);
+  const bool pers = c->cfg.mode == PIC_MODE_PERSISTENT;
+  hipError_t e = timed(c, PIC_KERNEL_SLAB, st, [&] {
+    hipError_t r2 = launch_slab_end(c->g, a, st);
+    if (r2 == hipSuccess)
+      r2 = launch_layout(c->g, make_args(c, sp, nsp), pers ? c->units : nullptr, c->qctl, st);
+    return r2;
+  });
+  if (e == hipSuccess) e = api_offsets(c, sp, nsp, st);
+  if (e != hipSuccess) return hip_fail(c, e, "kernel launch");
+  return PIC_OK;
+}
+
+// The same species arrays (and counts) as the resident ones.
+bool same_as_resident(const pic_ctx *c, const pic_species *sp, int32_t nsp) {
+  if (!c->resident || nsp != c->res_nsp) return false;
+  for (int s = 0; s < nsp; s++) {
+    const pic_species &a = sp[s], &b = c->res_sp[s];
+    bool same = a.n == b.n && a.capacity == b.capacity && a.q == b.q && a.m == b.m &&
+                a.w == b.w && a.id == b.id && a.w_alt == b.w_alt && a.id_alt == b.id_alt &&
+                a.offset == b.offset;
+    for (int k = 0; k < 3; k++)
+      same = same && a.x[k] == b.x[k] && a.u[k] == b.u[k] && a.x_alt[k] == b.x_alt[k] &&
+             a.u_alt[k] == b.u_alt[k];
+    if (!same) return false;
+  }
+  return true;
 }
 
 // The synchronisation-phase sort of pic_bin: with general, wrap + key +
@@ -1119,7 +1167,8 @@ pic_status pic_validate_config(const pic_config *c, char *msg, size_t len) {
     return PIC_ERR_ARG;
   }
   if (c->flags &
-      ~(uint32_t)(PIC_FLAG_CHECK | PIC_FLAG_GRAPH | PIC_FLAG_TRACE | PIC_FLAG_DETERMINISTIC)) {
+      ~(uint32_t)(PIC_FLAG_CHECK | PIC_FLAG_GRAPH | PIC_FLAG_TRACE | PIC_FLAG_DETERMINISTIC |
+                  PIC_FLAG_RESIDENT)) {
     set_msg(msg, len, "unknown flag bits 0x%x", c->flags);
     return PIC_ERR_ARG;
   }
@@ -1137,6 +1186,19 @@ pic_status pic_validate_config(const pic_config *c, char *msg, size_t len) {
                 "(removing walls on axis %d)", a);
         return PIC_ERR_ARG;
       }
+  if (c->flags & PIC_FLAG_RESIDENT) {
+    if (c->flags & PIC_FLAG_DETERMINISTIC) {
+      set_msg(msg, len, "PIC_FLAG_RESIDENT keeps the slab layout, PIC_FLAG_DETERMINISTIC the dense one");
+      return PIC_ERR_ARG;
+    }
+    for (int a = 0; a < c->dim; a++)
+      if (c->particle_bc[a] == PIC_BC_REMOVE) {
+        set_msg(msg, len,
+                "PIC_FLAG_RESIDENT: removing walls change the counts that each call reports "
+                "(removing walls on axis %d)", a);
+        return PIC_ERR_ARG;
+      }
+  }
   if (c->bin_x < 0 || (c->bin_x > 0 && c->patch[0] % c->bin_x)) {
     set_msg(msg, len, "bin_x=%d must be 0 (auto) or divide patch[0]=%d", c->bin_x, c->patch[0]);
     return PIC_ERR_ARG;
@@ -1209,6 +1271,7 @@ void pic_free(pic_ctx *c) {
   if (!c) return;
   (void)hipSetDevice(c->device);
   (void)hipDeviceSynchronize();
+  // (resident particles are not written back: their buffers may be gone)
   for (int s = 0; s < kMaxSpecies; s++) {
     SpScratch &S = c->sp[s];
     (void)hipFree(S.tag);
@@ -1317,11 +1380,22 @@ pic_status pic_check(pic_ctx *c, void *stream) {
 
 const char *pic_last_error(const pic_ctx *c) { return c ? c->msg : "null context"; }
 
+pic_status pic_sync(pic_ctx *c, void *stream) {
+  if (!c) return PIC_ERR_ARG;
+  if (c->poisoned) return fail(c, PIC_ERR_STATE, "context unusable after a device error");
+  hipStream_t st = (hipStream_t)stream;
+  if (hipSetDevice(c->device) != hipSuccess) return fail(c, PIC_ERR_HIP, "hipSetDevice");
+  const pic_status r = resident_flush(c, st);
+  if (r != PIC_OK) return r;
+  return finish(c, st);
+}
+
 pic_status pic_bin(pic_ctx *c, pic_species *sp, int32_t nsp, void *stream) {
   pic_status r = check_species(c, sp, nsp, false);
   if (r != PIC_OK) return r;
   hipStream_t st = (hipStream_t)stream;
   if (hipSetDevice(c->device) != hipSuccess) return fail(c, PIC_ERR_HIP, "hipSetDevice");
+  if ((r = resident_flush(c, st)) != PIC_OK) return r;  // PIC_FLAG_RESIDENT: dense layout first
   if (c->moved && nsp != c->moved_nsp)
     return fail(c, PIC_ERR_STATE, "pic_bin after pic_interp_push needs the same species");
   // removing walls: the general sort, whose keys drop deleted particles past
@@ -1339,6 +1413,7 @@ pic_status pic_interp_push(pic_ctx *c, pic_species *sp, int32_t nsp, const pic_f
   if (c->moved) return fail(c, PIC_ERR_STATE, "pic_interp_push twice without a sort");
   hipStream_t st = (hipStream_t)stream;
   if (hipSetDevice(c->device) != hipSuccess) return fail(c, PIC_ERR_HIP, "hipSetDevice");
+  if ((r = resident_flush(c, st)) != PIC_OK) return r;  // PIC_FLAG_RESIDENT: dense layout first
   if ((r = ensure_scratch(c, sp, nsp, true, st)) != PIC_OK) return r;
   if ((r = refresh_layout(c, sp, nsp, st)) != PIC_OK) return r;
   // x-bins: the particles arrive sorted by patch; the kernels need them by bin
@@ -1362,6 +1437,7 @@ pic_status pic_project(pic_ctx *c, const pic_species *sp, int32_t nsp, pic_field
     return fail(c, PIC_ERR_STATE, "pic_project needs a preceding pic_interp_push");
   hipStream_t st = (hipStream_t)stream;
   if (hipSetDevice(c->device) != hipSuccess) return fail(c, PIC_ERR_HIP, "hipSetDevice");
+  if ((r = resident_flush(c, st)) != PIC_OK) return r;  // PIC_FLAG_RESIDENT: dense layout first
   const SpArgs a = make_args(c, sp, nsp);
   hipError_t e = timed(c, PIC_KERNEL_PROJECT, st,
                        [&] { return launch_project(c->g, a, f->j, c->err_dev, c->wgd, st); });
@@ -1378,8 +1454,13 @@ pic_status pic_step(pic_ctx *c, pic_species *sp, int32_t nsp, pic_fields *f, int
   if (c->moved) return fail(c, PIC_ERR_STATE, "pic_step with a sort pending (call pic_bin)");
   hipStream_t st = (hipStream_t)stream;
   if (hipSetDevice(c->device) != hipSuccess) return fail(c, PIC_ERR_HIP, "hipSetDevice");
+  // PIC_FLAG_RESIDENT: a call on the resident species continues in their
+  // slabs; any other call first writes the resident species back
+  const bool res = (c->cfg.flags & PIC_FLAG_RESIDENT) && (c->nb == 1 || bin_order_supported(c->nb));
+  const bool cont = res && same_as_resident(c, sp, nsp);
+  if (c->resident && !cont && (r = resident_flush(c, st)) != PIC_OK) return r;
   if ((r = ensure_scratch(c, sp, nsp, false, st)) != PIC_OK) return r;
-  if ((r = refresh_layout(c, sp, nsp, st)) != PIC_OK) return r;
+  if (!cont && (r = refresh_layout(c, sp, nsp, st)) != PIC_OK) return r;
   if (nsteps == 0) return finish(c, st);
   // removing walls delete particles only in the slab layout's exchange, so
   // every call takes it there
@@ -1387,7 +1468,7 @@ pic_status pic_step(pic_ctx *c, pic_species *sp, int32_t nsp, pic_fields *f, int
     return fail(c, PIC_ERR_CAPACITY,
                 "removing walls need buffers with the slab layout's room (n + n/8 + 80 per slab)");
   const bool det = (c->cfg.flags & PIC_FLAG_DETERMINISTIC) != 0;
-  const bool slab = !det && (nsteps >= 3 || c->g.remove) && slab_fits(c, sp, nsp);
+  const bool slab = !det && (nsteps >= 3 || c->g.remove || res) && slab_fits(c, sp, nsp);
   if (det) {
     // one J tile per (species, patch)
     size_t tj = 3;
@@ -1406,7 +1487,13 @@ pic_status pic_step(pic_ctx *c, pic_species *sp, int32_t nsp, pic_fields *f, int
       (r = order_bins(c, sp, nsp, st)) != PIC_OK)
     return r;
   if (slab) {
-    if ((r = step_slab(c, sp, nsp, f, nsteps, st)) != PIC_OK) return r;
+    if ((r = step_slab(c, sp, nsp, f, nsteps, st, cont, res)) != PIC_OK) return r;
+    if (res) {  // the particles stay in the slabs (offsets and first set stale)
+      c->resident = true;
+      c->res_nsp = nsp;
+      for (int s = 0; s < nsp; s++) c->res_sp[s] = sp[s];
+      return finish(c, st);
+    }
   } else {
     if ((r = step_dense(c, sp, nsp, f, nsteps, st, c->sp, c->units, true)) != PIC_OK) return r;
   }
@@ -1476,6 +1563,7 @@ pic_status pic_step_noalloc(pic_ctx *c, pic_species *sp, int32_t nsp, pic_fields
                 used, kNoAllocBytes);
   hipStream_t st = (hipStream_t)stream;
   if (hipSetDevice(c->device) != hipSuccess) return fail(c, PIC_ERR_HIP, "hipSetDevice");
+  if ((r = resident_flush(c, st)) != PIC_OK) return r;  // PIC_FLAG_RESIDENT: dense layout first
   if (nsteps == 0) return finish(c, st);
   // the static array holds whatever the last call on this GPU left there:
   // segment starts (and work units, with a zero ticket) from the offsets
@@ -1522,6 +1610,7 @@ pic_status pic_rho(pic_ctx *c, const pic_species *sp, int32_t nsp, double *rho, 
   for (int k = 0; k < c->cfg.dim; k++) tile *= (size_t)(a.patch[k] + 3);
   hipStream_t st = (hipStream_t)stream;
   if (hipSetDevice(c->device) != hipSuccess) return fail(c, PIC_ERR_HIP, "hipSetDevice");
+  if (const pic_status r = resident_flush(c, st); r != PIC_OK) return r;  // PIC_FLAG_RESIDENT: dense layout first
   const hipError_t e =
       timed(c, PIC_KERNEL_RHO, st, [&] { return launch_rho(a, c->err_dev, tile, st); });
   if (e != hipSuccess) return hip_fail(c, e, "kernel launch");
@@ -1615,6 +1704,7 @@ pic_status pic_adjoint(pic_ctx *c, const pic_species *ck, int32_t nsp, const pic
   }
   hipStream_t st = (hipStream_t)stream;
   if (hipSetDevice(c->device) != hipSuccess) return fail(c, PIC_ERR_HIP, "hipSetDevice");
+  if (const pic_status r = resident_flush(c, st); r != PIC_OK) return r;  // PIC_FLAG_RESIDENT: dense layout first
   hipError_t e = timed(c, PIC_KERNEL_ADJOINT, st, [&] {
     return launch_adjoint(c->g, a, f->e, f->b, with_deposit ? jbar : nullptr, ebar, bbar, nsteps,
                           with_deposit, c->err_dev, st);

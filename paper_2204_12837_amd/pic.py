@@ -22,7 +22,7 @@ STATUS_NAMES = {0: "PIC_OK", 1: "PIC_ERR_ARG", 2: "PIC_ERR_HIP", 3: "PIC_ERR_CAP
                 4: "PIC_ERR_CFL", 5: "PIC_ERR_POS", 6: "PIC_ERR_STATE", 7: "PIC_ERR_UNSORTED"}
 BC_PERIODIC, BC_REFLECT, BC_REMOVE = 0, 1, 2
 MODE_PER_PATCH, MODE_PERSISTENT = 0, 1
-FLAG_CHECK, FLAG_GRAPH, FLAG_TRACE, FLAG_DETERMINISTIC = 1, 2, 4, 8
+FLAG_CHECK, FLAG_GRAPH, FLAG_TRACE, FLAG_DETERMINISTIC, FLAG_RESIDENT = 1, 2, 4, 8, 16
 
 _DP = C.POINTER(C.c_double)
 _I64P = C.POINTER(C.c_int64)
@@ -65,7 +65,8 @@ ENTRY_POINTS = ("pic_validate_config", "pic_num_patches", "pic_bin_width", "pic_
                 "pic_bin",
                 "pic_interp_push", "pic_project", "pic_step", "pic_check", "pic_last_error",
                 "pic_timing_enable", "pic_timing_read", "pic_adjoint", "pic_maxwell",
-                "pic_maxwell_adjoint", "pic_rho", "pic_cycle", "pic_step_noalloc", "pic_trace_read")
+                "pic_maxwell_adjoint", "pic_rho", "pic_cycle", "pic_step_noalloc", "pic_trace_read",
+                "pic_sync")
 KERNELS = {"zero": 0, "ipp": 1, "rebin": 2, "interp_push": 3, "project": 4, "tag": 5, "sort": 6,
            "adjoint": 7, "exchange": 8, "slab": 9, "maxwell": 10, "rho": 11}
 
@@ -105,6 +106,8 @@ def lib():
         L.pic_step_noalloc.restype = C.c_int
         L.pic_check.argtypes = [C.c_void_p, C.c_void_p]
         L.pic_check.restype = C.c_int
+        L.pic_sync.argtypes = [C.c_void_p, C.c_void_p]
+        L.pic_sync.restype = C.c_int
         L.pic_timing_enable.argtypes = [C.c_void_p, C.c_int32]
         L.pic_timing_enable.restype = C.c_int
         L.pic_timing_read.argtypes = [C.c_void_p, C.c_int32, C.POINTER(C.c_double),
@@ -271,13 +274,18 @@ def _stream():
 class Context:
     """A library context (pic_init / pic_free) for the workload's grid,
     patches and particle boundaries (wl.particle_bc, BC_* per axis; with
-    BC_REMOVE the calls that delete particles update each Species.n)."""
+    BC_REMOVE the calls that delete particles update each Species.n).
+    resident=True (PIC_FLAG_RESIDENT): step() leaves the particles in the
+    slab layout between calls; sync() (or any other call that takes the
+    particles) writes the dense layout back before the arrays are read."""
 
     def __init__(self, wl, device: int = 0, mode=MODE_PER_PATCH, chunk=0, wg_size=0,
-                 check=False, graph=False, bin_x=0, trace=False, deterministic=False):
+                 check=False, graph=False, bin_x=0, trace=False, deterministic=False,
+                 resident=False):
         self.wl = wl
         flags = ((FLAG_CHECK if check else 0) | (FLAG_GRAPH if graph else 0)
-                 | (FLAG_TRACE if trace else 0) | (FLAG_DETERMINISTIC if deterministic else 0))
+                 | (FLAG_TRACE if trace else 0) | (FLAG_DETERMINISTIC if deterministic else 0)
+                 | (FLAG_RESIDENT if resident else 0))
         self.cfg = make_config(wl, mode, chunk, wg_size, flags, bin_x)
         rc, msg = validate(self.cfg)
         if rc:
@@ -334,6 +342,11 @@ class Context:
 
     def check(self):
         self._raise(lib().pic_check(self._h, _stream()))
+
+    def sync(self):
+        """pic_sync: the particles that resident steps left in their slabs
+        back to the dense layout (first buffer set, offsets)."""
+        self._raise(lib().pic_sync(self._h, _stream()))
 
     def maxwell(self, E, B, J, nsteps: int = 1):
         """pic_maxwell: nsteps Yee updates of E and B (in place) with current J

@@ -23,16 +23,17 @@ def run_oracle(wl, inp, steps, with_abs=True):
 
 
 def run_gpu(wl, inp, steps, mode=0, chunk=0, wg_size=0, split=False, device="cuda:0",
-            graph=False, step_sizes=None, capacity_factor=None, bin_x=0):
+            graph=False, step_sizes=None, capacity_factor=None, bin_x=0, resident=False):
     """capacity_factor None gives the buffers room for pic_step's slab
     layout (used for calls of three steps or more); 1.0 keeps the dense
-    layout with the permutation sort."""
+    layout with the permutation sort.  resident: PIC_FLAG_RESIDENT, the
+    dense layout written back by pic_sync after the last call."""
     import torch
 
     from paper_2204_12837_amd import pic
 
     ctx = pic.Context(wl, device=0, mode=mode, chunk=chunk, wg_size=wg_size, check=True,
-                      graph=graph, bin_x=bin_x)
+                      graph=graph, bin_x=bin_x, resident=resident)
     sp = pic.upload(inp, device, capacity_factor=capacity_factor, n_slabs=ctx.n_slabs)
     E, B, J = pic.upload_fields(inp, device)
     ctx.bin(sp)
@@ -49,6 +50,8 @@ def run_gpu(wl, inp, steps, mode=0, chunk=0, wg_size=0, split=False, device="cud
             torch.cuda.synchronize()
     else:
         ctx.step(sp, E, B, J, nsteps=steps)
+    if resident:
+        ctx.sync()
     torch.cuda.synchronize()
     ctx.check()
     out = []

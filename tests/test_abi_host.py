@@ -192,5 +192,23 @@ def test_deterministic_flag_refuses_removing_walls():
     rc, msg = pic.validate(pic.make_config(dataclasses.replace(base, particle_bc=(1, 0, 0)),
                                            flags=pic.FLAG_DETERMINISTIC))
     assert rc == pic.PIC_OK, msg
-    rc, msg = pic.validate(pic.make_config(base, flags=16))
+    rc, msg = pic.validate(pic.make_config(base, flags=32))
     assert rc == pic.PIC_ERR_ARG
+
+
+def test_resident_flag_refusals():
+    """PIC_FLAG_RESIDENT keeps the slab layout between calls: refused with
+    PIC_FLAG_DETERMINISTIC (dense layout) and with removing walls (whose
+    counts each call reports); accepted with reflecting walls."""
+    import dataclasses
+
+    base = I.custom(2, (32, 32), (8, 8), ppc=1)
+    assert pic.validate(pic.make_config(base, flags=pic.FLAG_RESIDENT))[0] == pic.PIC_OK
+    rc, msg = pic.validate(pic.make_config(base, flags=pic.FLAG_RESIDENT | pic.FLAG_DETERMINISTIC))
+    assert rc == pic.PIC_ERR_ARG and "RESIDENT" in msg, msg
+    rc, msg = pic.validate(pic.make_config(dataclasses.replace(base, particle_bc=(0, 2, 0)),
+                                           flags=pic.FLAG_RESIDENT))
+    assert rc == pic.PIC_ERR_ARG and "removing" in msg, msg
+    rc, msg = pic.validate(pic.make_config(dataclasses.replace(base, particle_bc=(1, 0, 0)),
+                                           flags=pic.FLAG_RESIDENT))
+    assert rc == pic.PIC_OK, msg

@@ -223,6 +223,95 @@ def test_graph_replay_matches_oracle(mode, layout):
             step_sizes=[10, 1, 2, 3, 10, 1])
 
 
+RESIDENT_CASES = [
+    # dim, n, patch, bin_x, ppc, nspecies, sigma, seed, call lengths
+    (2, (48, 32), (8, 8), 0, 5, 1, 0.2, 350, [1, 1, 2, 1, 3, 1]),
+    (2, (96, 48), (48, 24), 8, 3, 2, 0.3, 351, [2, 1, 1, 3]),    # x-bins of 8 cells
+    (3, (24, 16, 16), (8, 8, 8), 0, 2, 2, 0.2, 352, [1, 2, 1]),
+]
+
+
+@pytest.mark.parametrize("graph", [False, True])
+@pytest.mark.parametrize("mode", [0, 1])
+@pytest.mark.parametrize("case", RESIDENT_CASES)
+def test_resident_short_calls(case, mode, graph):
+    """PIC_FLAG_RESIDENT: calls of one to three steps that continue in the
+    slabs, then pic_sync, give the oracle's particles and current."""
+    dim, n, patch, bin_x, ppc, nsp, sigma, seed, sizes = case
+    wl = I.custom(dim, n, patch, ppc=ppc, seed=seed + 10 * mode, sigma=sigma, n_species=nsp)
+    inp = I.generate(wl)
+    steps = sum(sizes)
+    say(f"case resident {case} mode={mode} graph={graph}")
+    osp, J, A = run_oracle(wl, inp, steps)
+    run_cmp(wl, inp, steps, "slab", osp, J, A, mode=mode, chunk=512, graph=graph,
+            step_sizes=sizes, bin_x=bin_x, resident=True)
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_resident_then_split_entry_points(mode):
+    """Resident calls interleaved with the split entry points, each of which
+    writes the resident particles back first: the oracle's particles and
+    current after the sequence."""
+    import torch
+
+    from paper_2204_12837_amd import pic
+
+    wl = I.custom(2, (48, 32), (8, 8), ppc=4, seed=360 + mode, sigma=0.2)
+    inp = I.generate(wl)
+    say(f"case resident + split mode={mode}")
+    osp, J, A = run_oracle(wl, inp, 6)
+    ctx = pic.Context(wl, device=0, mode=mode, chunk=512, check=True, resident=True)
+    sp = pic.upload(inp, "cuda:0", n_slabs=ctx.n_slabs)
+    E, B, Jg = pic.upload_fields(inp, "cuda:0")
+    ctx.bin(sp)
+    ctx.step(sp, E, B, Jg, nsteps=2)      # resident
+    Jg.zero_()                            # one split step (the first call writes back)
+    ctx.interp_push(sp, E, B)
+    ctx.project(sp, Jg)
+    ctx.bin(sp)
+    ctx.step(sp, E, B, Jg, nsteps=1)      # resident again
+    ctx.step(sp, E, B, Jg, nsteps=2)      # continues in the slabs
+    ctx.sync()
+    torch.cuda.synchronize()
+    ctx.check()
+    out = [dict(off=s.offset.cpu().numpy(), id=s.ids.cpu().numpy(), x=s.xs.cpu().numpy(),
+                u=s.us.cpu().numpy(), w=s.ws.cpu().numpy()) for s in sp]
+    compare(osp, J, A, out, Jg.cpu().numpy())
+    ctx.close()
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_resident_alternating_arrays(mode):
+    """pic_step on other particle arrays writes the resident ones back first
+    (two copies of a plasma stepped alternately on one context in the slab
+    layout): each copy ends where the oracle puts it."""
+    import torch
+
+    from paper_2204_12837_amd import pic
+
+    wl = I.custom(2, (48, 32), (8, 8), ppc=4, seed=370 + mode, sigma=0.2)
+    inp = I.generate(wl)
+    say(f"case resident alternating mode={mode}")
+    ctx = pic.Context(wl, device=0, mode=mode, chunk=512, check=True, resident=True)
+    a = pic.upload(inp, "cuda:0", n_slabs=ctx.n_slabs)
+    b = pic.upload(inp, "cuda:0", n_slabs=ctx.n_slabs)
+    E, B, Jg = pic.upload_fields(inp, "cuda:0")
+    ctx.bin(a)
+    ctx.bin(b)
+    ctx.step(a, E, B, Jg, nsteps=2)   # a resident
+    ctx.step(b, E, B, Jg, nsteps=1)   # a written back, b resident
+    ctx.step(a, E, B, Jg, nsteps=1)   # b written back, a resident (three steps)
+    ctx.sync()
+    torch.cuda.synchronize()
+    ctx.check()
+    for sp, steps in ((a, 3), (b, 1)):
+        osp, _, _ = run_oracle(wl, inp, steps)
+        out = [dict(off=s.offset.cpu().numpy(), id=s.ids.cpu().numpy(), x=s.xs.cpu().numpy(),
+                    u=s.us.cpu().numpy(), w=s.ws.cpu().numpy()) for s in sp]
+        compare(osp, None, None, out, None)
+    ctx.close()
+
+
 @pytest.mark.parametrize("mode", [0, 1])
 def test_slab_overflow_replans(mode):
     """A drifting half-box beam floods initially empty patches faster than
