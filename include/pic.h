@@ -107,11 +107,13 @@ enum {
                          with its room; otherwise the call runs in the
                          dense layout and nothing stays resident).  While
                          resident, the first buffer set and the offsets are
-                         stale: pic_sync writes them (the dense layout, in
-                         the first set, as a call without the flag leaves
-                         it), and so does every other entry point that
-                         takes particles, and pic_step on other arrays,
-                         before it starts.  pic_free writes nothing back.
+                         stale and the caller must not write any of the
+                         species' arrays: pic_sync writes them (the dense
+                         layout, in the first set, as a call without the
+                         flag leaves it), and so does every other entry
+                         point that takes particles, and pic_step on other
+                         arrays, before it starts.  pic_free writes nothing
+                         back.
                          Not with PIC_FLAG_DETERMINISTIC or removing walls
                          (PIC_ERR_ARG). */
   PIC_FLAG_TRACE = 4  /* the fused kernel of pic_step's slab layout records,
