@@ -131,6 +131,7 @@ def test_null_arguments():
     assert L.pic_init(None, 0, None) == pic.PIC_ERR_ARG
     L.pic_free(None)  # no-op
     assert L.pic_check(None, None) == pic.PIC_ERR_ARG
+    assert L.pic_sync(None, None) == pic.PIC_ERR_ARG
     assert L.pic_last_error(None) == b"null context"
 
 
