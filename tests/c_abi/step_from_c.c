@@ -1,7 +1,9 @@
 /* A C program that drives the library through its C ABI alone (no Python,
  * no torch): host-only configuration checks, and with "gpu" a short run of
  * free-streaming particles on the device whose total current and final
- * positions have closed forms.  Prints "ok" and exits 0 on success. */
+ * positions have closed forms -- once as one pic_step call, once as
+ * one-step calls with PIC_FLAG_RESIDENT and a closing pic_sync.  Prints
+ * "ok" and exits 0 on success. */
 #include <hip/hip_runtime_api.h>
 #include <math.h>
 #include <stdio.h>
@@ -54,8 +56,11 @@ static int host_checks(void) {
     if ((call) != hipSuccess) return fail(#call);    \
   } while (0)
 
-static int gpu_run(void) {
-  const pic_config c = config();
+static int gpu_run(int resident) {
+  pic_config c = config();
+  if (resident) c.flags |= PIC_FLAG_RESIDENT;
+  /* resident calls need the slab layout's room: n + n/8 + 80 per patch */
+  const int64_t cap = resident ? NP + NP / 8 + 80 * (int64_t)pic_num_patches(&c) + 64 : NP;
   const size_t cells = (size_t)NX * NY;
   const double q = -1.0, w = 1.0 / PPC, u[3] = {0.3, -0.2, 0.1};
   double *hx = malloc(2 * NP * sizeof(double)), *hw = malloc(NP * sizeof(double));
@@ -72,26 +77,27 @@ static int gpu_run(void) {
   memset(&s, 0, sizeof s);
   s.q = q;
   s.m = 1.0;
-  s.n = s.capacity = NP;
+  s.n = NP;
+  s.capacity = cap;
   double *fld;
   CHECK(hipMalloc((void **)&fld, 9 * cells * sizeof(double)));
   CHECK(hipMemset(fld, 0, 9 * cells * sizeof(double)));
   for (int a = 0; a < 2; a++) {
-    CHECK(hipMalloc((void **)&s.x[a], NP * sizeof(double)));
-    CHECK(hipMalloc((void **)&s.x_alt[a], NP * sizeof(double)));
+    CHECK(hipMalloc((void **)&s.x[a], cap * sizeof(double)));
+    CHECK(hipMalloc((void **)&s.x_alt[a], cap * sizeof(double)));
     CHECK(hipMemcpy(s.x[a], hx + a * NP, NP * sizeof(double), hipMemcpyHostToDevice));
   }
   double *hu = malloc(NP * sizeof(double));
   for (int a = 0; a < 3; a++) {
     for (int p = 0; p < NP; p++) hu[p] = u[a];
-    CHECK(hipMalloc((void **)&s.u[a], NP * sizeof(double)));
-    CHECK(hipMalloc((void **)&s.u_alt[a], NP * sizeof(double)));
+    CHECK(hipMalloc((void **)&s.u[a], cap * sizeof(double)));
+    CHECK(hipMalloc((void **)&s.u_alt[a], cap * sizeof(double)));
     CHECK(hipMemcpy(s.u[a], hu, NP * sizeof(double), hipMemcpyHostToDevice));
   }
-  CHECK(hipMalloc((void **)&s.w, NP * sizeof(double)));
-  CHECK(hipMalloc((void **)&s.w_alt, NP * sizeof(double)));
-  CHECK(hipMalloc((void **)&s.id, NP * sizeof(int64_t)));
-  CHECK(hipMalloc((void **)&s.id_alt, NP * sizeof(int64_t)));
+  CHECK(hipMalloc((void **)&s.w, cap * sizeof(double)));
+  CHECK(hipMalloc((void **)&s.w_alt, cap * sizeof(double)));
+  CHECK(hipMalloc((void **)&s.id, cap * sizeof(int64_t)));
+  CHECK(hipMalloc((void **)&s.id_alt, cap * sizeof(int64_t)));
   CHECK(hipMalloc((void **)&s.offset, (pic_num_patches(&c) + 1) * sizeof(int64_t)));
   CHECK(hipMemcpy(s.w, hw, NP * sizeof(double), hipMemcpyHostToDevice));
   CHECK(hipMemcpy(s.id, hid, NP * sizeof(int64_t), hipMemcpyHostToDevice));
@@ -104,7 +110,13 @@ static int gpu_run(void) {
   pic_ctx *ctx = NULL;
   if (pic_init(&c, 0, &ctx) != PIC_OK) return fail("pic_init");
   if (pic_bin(ctx, &s, 1, NULL) != PIC_OK) return fail(pic_last_error(ctx));
-  if (pic_step(ctx, &s, 1, &f, STEPS, NULL) != PIC_OK) return fail(pic_last_error(ctx));
+  if (resident) {
+    for (int k = 0; k < STEPS; k++)
+      if (pic_step(ctx, &s, 1, &f, 1, NULL) != PIC_OK) return fail(pic_last_error(ctx));
+    if (pic_sync(ctx, NULL) != PIC_OK) return fail(pic_last_error(ctx));
+  } else if (pic_step(ctx, &s, 1, &f, STEPS, NULL) != PIC_OK) {
+    return fail(pic_last_error(ctx));
+  }
   if (pic_check(ctx, NULL) != PIC_OK) return fail(pic_last_error(ctx));
   /* closed forms: without fields every particle moves at v = u / gamma */
   const double gam = sqrt(1.0 + (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]));
@@ -134,14 +146,36 @@ static int gpu_run(void) {
     }
   }
   pic_free(ctx);
-  printf("ok: %d particles, %d steps\n", NP, STEPS);
+  for (int a = 0; a < 2; a++) {
+    CHECK(hipFree(s.x[a]));
+    CHECK(hipFree(s.x_alt[a]));
+  }
+  for (int a = 0; a < 3; a++) {
+    CHECK(hipFree(s.u[a]));
+    CHECK(hipFree(s.u_alt[a]));
+  }
+  CHECK(hipFree(s.w));
+  CHECK(hipFree(s.w_alt));
+  CHECK(hipFree(s.id));
+  CHECK(hipFree(s.id_alt));
+  CHECK(hipFree(s.offset));
+  CHECK(hipFree(fld));
+  free(hx);
+  free(hw);
+  free(hid);
+  free(hu);
+  free(hj);
   return 0;
 }
 
 int main(int argc, char **argv) {
   int rc = host_checks();
   if (rc) return rc;
-  if (argc > 1 && strcmp(argv[1], "gpu") == 0) return gpu_run();
+  if (argc > 1 && strcmp(argv[1], "gpu") == 0) {
+    if ((rc = gpu_run(0)) != 0 || (rc = gpu_run(1)) != 0) return rc;
+    printf("ok: %d particles, %d steps, one call and resident one-step calls\n", NP, STEPS);
+    return 0;
+  }
   printf("ok: host checks\n");
   return 0;
 }
