@@ -754,38 +754,71 @@ __global__ void __launch_bounds__(kExchInWg) k_exch_in(GridDev g, SlabArgs sa) {
   }
 }
 
-// Persistent mode: work units of chunk particles for the patch counts, every
-// full unit first, then the remainders (one workgroup, each thread a
-// contiguous run of patches).  count(P) loads patch P's count; keep(P, c)
-// stores what the caller derives from it (for a thread's first kUnitsCached
-// patches: all loads first, the stores after the scans); again(P) gives the
-// count a second time, after keep.  The list goes to ul (units
-// tagged with species s), its length to q[1] (0 if the species stands
-// still) and a zero ticket to q[0].  kUnitsCached: counts a thread keeps in
-// registers.
+// Persistent mode: work units of chunk particles for the patch counts (one
+// workgroup of at most kUnitsWg threads, each a contiguous run of patches):
+// every full unit first, then the remainders from the largest to the
+// smallest in kRemClasses size classes, each class in patch order.  A
+// worker pops the next unit when it finishes one, so the list's end sets
+// the launch's tail: with the smallest units last, the workers finish
+// nearly together (largest units first is the classic list-scheduling
+// rule).  count(P) loads patch P's count; keep(P, c) stores what the
+// caller derives from it (for a thread's first kUnitsCached patches: all
+// loads first, the stores after the scans); again(P) gives the count a
+// second time, after keep.  The list goes to ul (units tagged with species
+// s), its length to q[1] (0 if the species stands still) and a zero ticket
+// to q[0].  kUnitsCached: counts a thread keeps in registers; cls:
+// kRemClasses x kUnitsWg ints of LDS.
+constexpr int kRemClasses = 8, kUnitsWg = 1024;
+
 template <int kUnitsCached, class Count, class Keep, class Again>
 __device__ void make_units(int s, int n, int chunk, bool still, Count count, Keep keep,
-                           Again again, Unit *ul, int *q, int *wtot) {
-  const int per = (n + blockDim.x - 1) / blockDim.x;
-  const int p0 = min(n, (int)threadIdx.x * per), p1 = min(n, p0 + per);
+                           Again again, Unit *ul, int *q, int *wtot, int *cls) {
+  const int nt = blockDim.x, t = threadIdx.x;
+  const int per = (n + nt - 1) / nt;
+  const int p0 = min(n, t * per), p1 = min(n, p0 + per);
+  // size class of a remainder: 0 for the largest
+  auto klass = [&](int c) { return (int)((int64_t)(chunk - c % chunk) * kRemClasses - 1) / chunk; };
   int cc[kUnitsCached];
-  int nf = 0, nr = 0;
+  int nf = 0, nr[kRemClasses];
+#pragma unroll
+  for (int k = 0; k < kRemClasses; k++) nr[k] = 0;
 #pragma unroll
   for (int k = 0; k < kUnitsCached; k++) cc[k] = p0 + k < p1 ? count(p0 + k) : 0;
 #pragma unroll
   for (int k = 0; k < kUnitsCached; k++) {
     nf += cc[k] / chunk;
-    nr += cc[k] % chunk != 0;
+    if (cc[k] % chunk) nr[klass(cc[k])]++;
   }
   for (int P = p0 + kUnitsCached; P < p1; P++) {
     const int c = count(P);
     keep(P, c);
     nf += c / chunk;
-    nr += c % chunk != 0;
+    if (c % chunk) nr[klass(c)]++;
   }
   int tf = 0, tr = 0;
   int rf = block_excl_sum(nf, tf, wtot);
-  int rr = tf + block_excl_sum(nr, tr, wtot);
+  // the remainders' starts: an exclusive scan of the class-major array
+  // [class][thread] through LDS, each thread summing kRemClasses
+  // consecutive elements of it
+#pragma unroll
+  for (int k = 0; k < kRemClasses; k++) cls[k * nt + t] = nr[k];
+  __syncthreads();
+  int v[kRemClasses], sum = 0;
+#pragma unroll
+  for (int j = 0; j < kRemClasses; j++) {
+    v[j] = cls[t * kRemClasses + j];
+    sum += v[j];
+  }
+  int base = block_excl_sum(sum, tr, wtot);  // (its barriers order the reads before the writes)
+#pragma unroll
+  for (int j = 0; j < kRemClasses; j++) {
+    cls[t * kRemClasses + j] = base;
+    base += v[j];
+  }
+  __syncthreads();
+  int rr[kRemClasses];
+#pragma unroll
+  for (int k = 0; k < kRemClasses; k++) rr[k] = tf + cls[k * nt + t];
   // the cached patches' stores after the scans, whose barriers then need
   // not wait for them
 #pragma unroll
@@ -803,7 +836,10 @@ __device__ void make_units(int s, int n, int chunk, bool still, Count count, Kee
     if (c % chunk) {
       un.k0 = c / chunk * chunk;
       un.k1 = c;
-      ul[rr++] = un;
+      const int k = klass(c);
+#pragma unroll
+      for (int x = 0; x < kRemClasses; x++)  // (a register index known at run time)
+        if (x == k) ul[rr[x]++] = un;
     }
   };
 #pragma unroll
@@ -819,10 +855,11 @@ __device__ void make_units(int s, int n, int chunk, bool still, Count count, Kee
 // End of the exchange (one workgroup of 1024 per species): new counts; on
 // an overflow, a new slab plan for the counts every patch needs.  With
 // units (persistent mode), also the next step's work units.
-__global__ void __launch_bounds__(1024) k_exch_fin(GridDev g, SlabArgs sa, int *err, Unit *units,
-                                                   int *qctl, int chunk) {
+__global__ void __launch_bounds__(kUnitsWg) k_exch_fin(GridDev g, SlabArgs sa, int *err, Unit *units,
+                                                       int *qctl, int chunk) {
   __shared__ int64_t part[1024];
   __shared__ int wtot[16];
+  __shared__ int cls[kRemClasses * kUnitsWg];
   const int s = blockIdx.x;
   const SlabDev &S = sa.s[s];
   const int n = g.npatch;
@@ -836,7 +873,7 @@ __global__ void __launch_bounds__(1024) k_exch_fin(GridDev g, SlabArgs sa, int *
             S.cnt[P] = c;
             S.arr[P] = 0;
           },
-          [&](int P) { return S.cnt[P]; }, units + S.ubase, qctl + 2 * s, wtot);
+          [&](int P) { return S.cnt[P]; }, units + S.ubase, qctl + 2 * s, wtot, cls);
       return;
     }
     // four patches per thread and memory round trip
@@ -876,7 +913,7 @@ __global__ void __launch_bounds__(1024) k_exch_fin(GridDev g, SlabArgs sa, int *
   if (units) {  // the counts the new plan's copies will set
     auto need = [&](int P) { return S.cnt2[P] + S.arr[P]; };
     make_units<8>(s, n, chunk, still, need, [](int, int) {}, need, units + S.ubase, qctl + 2 * s,
-                  wtot);
+                  wtot, cls);
   }
 }
 
@@ -941,14 +978,15 @@ __global__ void __launch_bounds__(256) k_reslab_back(GridDev g, SlabArgs sa) {
 
 // Persistent mode, start of a call: work units from the slab counts (one
 // workgroup of 1024 per species).
-__global__ void __launch_bounds__(1024) k_slab_units(GridDev g, SlabArgs sa, int chunk,
-                                                     Unit *units, int *qctl) {
+__global__ void __launch_bounds__(kUnitsWg) k_slab_units(GridDev g, SlabArgs sa, int chunk,
+                                                         Unit *units, int *qctl) {
   __shared__ int wtot[16];
+  __shared__ int cls[kRemClasses * kUnitsWg];
   const int s = blockIdx.x;
   const SlabDev &S = sa.s[s];
   auto count = [&](int P) { return S.cnt[P]; };
   make_units<16>(s, g.npatch, chunk, S.ctl[1] == 2, count, [](int, int) {}, count,
-                 units + S.ubase, qctl + 2 * s, wtot);
+                 units + S.ubase, qctl + 2 * s, wtot, cls);
 }
 
 // Persistent mode with several species: one list of units over every
@@ -957,16 +995,17 @@ __global__ void __launch_bounds__(1024) k_slab_units(GridDev g, SlabArgs sa, int
 // and flushes its current once for all species.  From the slab counts
 // after the exchange (one workgroup of 1024); a species that stands still
 // counts zero.  List at units, length in qctl[1], zero ticket in qctl[0].
-__global__ void __launch_bounds__(1024) k_units_all(GridDev g, SlabArgs sa, int chunk,
-                                                    Unit *units, int *qctl) {
+__global__ void __launch_bounds__(kUnitsWg) k_units_all(GridDev g, SlabArgs sa, int chunk,
+                                                        Unit *units, int *qctl) {
   __shared__ int wtot[16];
+  __shared__ int cls[kRemClasses * kUnitsWg];
   auto count = [&](int P) {
     int c = 0;
     for (int s = 0; s < sa.nsp; s++)
       if (sa.s[s].ctl[1] != 2) c += sa.s[s].cnt[P];
     return c;
   };
-  make_units<16>(-1, g.npatch, chunk, false, count, [](int, int) {}, count, units, qctl, wtot);
+  make_units<16>(-1, g.npatch, chunk, false, count, [](int, int) {}, count, units, qctl, wtot, cls);
 }
 
 // End of a call: dense offsets from the slab counts (one workgroup of 1024
@@ -1123,7 +1162,7 @@ hipError_t launch_exchange(const GridDev &g, const SlabArgs &sa, int *err, Unit 
   if (e != hipSuccess) return e;
   // several species: one combined unit list, made once the counts are final
   const bool combined = units && sa.nsp > 1;
-  hipLaunchKernelGGL(k_exch_fin, dim3(sa.nsp), dim3(1024), 0, st, g, sa, err,
+  hipLaunchKernelGGL(k_exch_fin, dim3(sa.nsp), dim3(kUnitsWg), 0, st, g, sa, err,
                      combined ? nullptr : units, qctl, chunk);
   const dim3 mg(std::min(2 * g.npatch, kReslabGrid), sa.nsp);
   const dim3 bg(std::min(g.npatch, kReslabGrid), sa.nsp);
@@ -1135,16 +1174,16 @@ hipError_t launch_exchange(const GridDev &g, const SlabArgs &sa, int *err, Unit 
     hipLaunchKernelGGL(k_reslab_back<3>, bg, dim3(256), 0, st, g, sa);
   }
   if (combined)
-    hipLaunchKernelGGL(k_units_all, dim3(1), dim3(1024), 0, st, g, sa, chunk, units, qctl);
+    hipLaunchKernelGGL(k_units_all, dim3(1), dim3(kUnitsWg), 0, st, g, sa, chunk, units, qctl);
   return hipGetLastError();
 }
 
 hipError_t launch_slab_units(const GridDev &g, const SlabArgs &sa, int chunk, Unit *units,
                              int *qctl, hipStream_t st) {
   if (sa.nsp > 1)
-    hipLaunchKernelGGL(k_units_all, dim3(1), dim3(1024), 0, st, g, sa, chunk, units, qctl);
+    hipLaunchKernelGGL(k_units_all, dim3(1), dim3(kUnitsWg), 0, st, g, sa, chunk, units, qctl);
   else
-    hipLaunchKernelGGL(k_slab_units, dim3(1), dim3(1024), 0, st, g, sa, chunk, units, qctl);
+    hipLaunchKernelGGL(k_slab_units, dim3(1), dim3(kUnitsWg), 0, st, g, sa, chunk, units, qctl);
   return hipGetLastError();
 }
 
