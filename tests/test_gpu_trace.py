@@ -4,8 +4,9 @@ per-patch mode, a popped unit in persistent mode -- with its start and end
 times (the GPU counterpart of the paper's per-operation scheduling
 diagnostics, section "Task scheduling visualization").  Checked: every
 item appears exactly once, ends after it starts, the items cover every
-patch that holds particles, and tracing leaves the results equal to the
-oracle's."""
+patch that holds particles, the persistent unit list has its documented
+order (full units, then remainders by size class), and tracing leaves the
+results equal to the oracle's."""
 import dataclasses
 
 import numpy as np
@@ -80,6 +81,15 @@ def test_trace_covers_every_work_item(mode):
         assert sorted(unit.tolist()) == list(range(len(rec)))  # each unit once
         assert set(patch.tolist()) == full
         assert len(rec) >= len(full)
+        # the list's order: every patch's full units in patch order, then
+        # the remainders from the largest to the smallest in eight size
+        # classes, each class in patch order
+        chunk = 512
+        counts = np.diff(osp_prev[0].off)
+        want = [P for P, c in enumerate(counts) for _ in range(c // chunk)]
+        rems = [(((chunk - c % chunk) * 8 - 1) // chunk, P) for P, c in enumerate(counts) if c % chunk]
+        want += [P for _, P in sorted(rems)]
+        assert patch[np.argsort(unit)].tolist() == want
 
 
 def test_trace_units_span_species():
