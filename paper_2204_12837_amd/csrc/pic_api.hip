@@ -65,7 +65,7 @@ struct SlabScratch {
   int64_t cap = 0;  // particle capacity the outbox was sized for
   int64_t *sb = nullptr, *sb2 = nullptr;
   int32_t *room = nullptr, *room2 = nullptr, *cnt = nullptr, *cnt2 = nullptr;
-  int32_t *arr = nullptr, *arr2 = nullptr, *dep = nullptr, *ctl = nullptr;
+  int32_t *arr = nullptr, *arr2 = nullptr, *dep = nullptr, *ctl = nullptr, *porder = nullptr;
   double *ox[3] = {nullptr, nullptr, nullptr}, *ou[3] = {nullptr, nullptr, nullptr};
   double *ow = nullptr;
   int64_t *oid = nullptr;
@@ -646,8 +646,15 @@ pic_status ensure_slab(pic_ctx *c, const pic_species *sp, int32_t nsp, hipStream
           (e = realloc_dev(L.cnt2, np)) != hipSuccess ||
           (e = realloc_dev(L.arr, np)) != hipSuccess ||
           (e = realloc_dev(L.arr2, np)) != hipSuccess || (e = realloc_dev(L.dep, np)) != hipSuccess ||
+          (e = realloc_dev(L.porder, np)) != hipSuccess ||
           (e = realloc_dev(L.ctl, 2)) != hipSuccess)
         return hip_fail(c, e, "hipMalloc");
+      // a valid patch order before any unit list writes one
+      std::vector<int32_t> ident(np);
+      for (size_t P = 0; P < np; P++) ident[P] = (int32_t)P;
+      if ((e = hipMemcpy(L.porder, ident.data(), np * sizeof(int32_t), hipMemcpyHostToDevice)) !=
+          hipSuccess)
+        return hip_fail(c, e, "hipMemcpy");
     }
     const int64_t cap = sp[s].capacity;
     if (cap > L.cap) {
@@ -704,6 +711,7 @@ SlabArgs make_slab_args(pic_ctx *c, const pic_species *sp, int32_t nsp) {
     d.arr = L.arr;
     d.arr2 = L.arr2;
     d.dep = L.dep;
+    d.porder = L.porder;
     d.ctl = L.ctl;
     d.code = reinterpret_cast<uint8_t *>(c->sp[s].tag);
     d.hole = c->sp[s].perm;
@@ -1290,7 +1298,7 @@ void pic_free(pic_ctx *c) {
     (void)hipFree(c->boff[s]);
     SlabScratch &L = c->slab[s];
     for (void *p : {(void *)L.sb, (void *)L.sb2, (void *)L.room, (void *)L.room2, (void *)L.cnt,
-                    (void *)L.cnt2, (void *)L.arr, (void *)L.arr2, (void *)L.dep,
+                    (void *)L.cnt2, (void *)L.arr, (void *)L.arr2, (void *)L.dep, (void *)L.porder,
                     (void *)L.ctl, (void *)L.ow, (void *)L.oid, (void *)L.odest})
       (void)hipFree(p);
     for (int a = 0; a < 3; a++) {

@@ -129,6 +129,8 @@ struct SlabDev {
   int32_t *cnt, *cnt2;          // [npatch] live particles (after the step, after departures)
   int32_t *arr, *arr2;          // [npatch] arrivals of the step, arrivals of a new plan
   int32_t *dep;                 // [npatch] departures of the step
+  int32_t *porder;              // [npatch] persistent mode, one species: the patches in the
+                                // departures kernel's order (crowded ones first)
   uint8_t *code;                // [capacity] neighbour code of each slab slot
   int32_t *hole;                // [capacity] hole lists (patch P's at sb[P])
   double *ox[3], *ou[3], *ow;   // outbox of departures [capacity], patch P's

@@ -595,10 +595,12 @@ __device__ __forceinline__ void code_bits(const uint8_t *code, int c, uint32_t *
 // tiles of kExchPer slots per thread, each thread copying its own
 // departures and movers in turn.
 template <int DIM>
-__global__ void __launch_bounds__(kExchWgMax) k_exch_out(GridDev g, SlabArgs sa, int only_marked) {
+__global__ void __launch_bounds__(kExchWgMax) k_exch_out(GridDev g, SlabArgs sa, int only_marked,
+                                                        int in_order) {
   constexpr int CENTER = DIM == 2 ? 4 : 13;
   const SlabDev &S = sa.s[blockIdx.y];
-  const int P = blockIdx.x;
+  // persistent mode with one species: the crowded patches first (porder)
+  const int P = in_order ? S.porder[blockIdx.x] : (int)blockIdx.x;
   __shared__ uint32_t bits[kExchBitWords<DIM>];
   __shared__ int pre[kExchBitWords<DIM>];
   __shared__ int wtot[16];
@@ -767,19 +769,24 @@ __global__ void __launch_bounds__(kExchInWg) k_exch_in(GridDev g, SlabArgs sa) {
 // second time, after keep.  The list goes to ul (units tagged with species
 // s), its length to q[1] (0 if the species stands still) and a zero ticket
 // to q[0].  kUnitsCached: counts a thread keeps in registers; cls:
-// kRemClasses x kUnitsWg ints of LDS.
+// kRemClasses x kUnitsWg ints of LDS.  porder (if not null): the patches
+// with at least chunk/2 particles, then the others, each in patch order --
+// the order in which the departures kernel takes them, so that the
+// crowded patches' workgroups, its longest, start first.
 constexpr int kRemClasses = 8, kUnitsWg = 1024;
 
 template <int kUnitsCached, class Count, class Keep, class Again>
 __device__ void make_units(int s, int n, int chunk, bool still, Count count, Keep keep,
-                           Again again, Unit *ul, int *q, int *wtot, int *cls) {
+                           Again again, Unit *ul, int *q, int *wtot, int *cls,
+                           int32_t *porder = nullptr) {
   const int nt = blockDim.x, t = threadIdx.x;
   const int per = (n + nt - 1) / nt;
   const int p0 = min(n, t * per), p1 = min(n, p0 + per);
   // size class of a remainder: 0 for the largest
   auto klass = [&](int c) { return (int)((int64_t)(chunk - c % chunk) * kRemClasses - 1) / chunk; };
   int cc[kUnitsCached];
-  int nf = 0, nr[kRemClasses];
+  int nf = 0, nh = 0, nr[kRemClasses];
+  const int heavy = max(chunk / 2, 1);
 #pragma unroll
   for (int k = 0; k < kRemClasses; k++) nr[k] = 0;
 #pragma unroll
@@ -787,16 +794,21 @@ __device__ void make_units(int s, int n, int chunk, bool still, Count count, Kee
 #pragma unroll
   for (int k = 0; k < kUnitsCached; k++) {
     nf += cc[k] / chunk;
+    nh += cc[k] >= heavy;
     if (cc[k] % chunk) nr[klass(cc[k])]++;
   }
   for (int P = p0 + kUnitsCached; P < p1; P++) {
     const int c = count(P);
     keep(P, c);
     nf += c / chunk;
+    nh += c >= heavy;
     if (c % chunk) nr[klass(c)]++;
   }
-  int tf = 0, tr = 0;
+  int tf = 0, tr = 0, th = 0;
   int rf = block_excl_sum(nf, tf, wtot);
+  // crowded patches before this thread's; the others before it: p0 - that
+  int hp = porder ? block_excl_sum(nh, th, wtot) : 0;
+  int lp = th + (p0 - hp);
   // the remainders' starts: an exclusive scan of the class-major array
   // [class][thread] through LDS, each thread summing kRemClasses
   // consecutive elements of it
@@ -825,6 +837,7 @@ __device__ void make_units(int s, int n, int chunk, bool still, Count count, Kee
   for (int k = 0; k < kUnitsCached; k++)
     if (p0 + k < p1) keep(p0 + k, cc[k]);
   auto emit = [&](int P, int c) {
+    if (porder) porder[c >= heavy ? hp++ : lp++] = P;
     Unit un;
     un.s = s;
     un.P = P;
@@ -873,7 +886,8 @@ __global__ void __launch_bounds__(kUnitsWg) k_exch_fin(GridDev g, SlabArgs sa, i
             S.cnt[P] = c;
             S.arr[P] = 0;
           },
-          [&](int P) { return S.cnt[P]; }, units + S.ubase, qctl + 2 * s, wtot, cls);
+          [&](int P) { return S.cnt[P]; }, units + S.ubase, qctl + 2 * s, wtot, cls,
+          sa.nsp == 1 ? S.porder : nullptr);
       return;
     }
     // four patches per thread and memory round trip
@@ -913,7 +927,7 @@ __global__ void __launch_bounds__(kUnitsWg) k_exch_fin(GridDev g, SlabArgs sa, i
   if (units) {  // the counts the new plan's copies will set
     auto need = [&](int P) { return S.cnt2[P] + S.arr[P]; };
     make_units<8>(s, n, chunk, still, need, [](int, int) {}, need, units + S.ubase, qctl + 2 * s,
-                  wtot, cls);
+                  wtot, cls, sa.nsp == 1 ? S.porder : nullptr);
   }
 }
 
@@ -986,7 +1000,7 @@ __global__ void __launch_bounds__(kUnitsWg) k_slab_units(GridDev g, SlabArgs sa,
   const SlabDev &S = sa.s[s];
   auto count = [&](int P) { return S.cnt[P]; };
   make_units<16>(s, g.npatch, chunk, S.ctl[1] == 2, count, [](int, int) {}, count,
-                 units + S.ubase, qctl + 2 * s, wtot, cls);
+                 units + S.ubase, qctl + 2 * s, wtot, cls, sa.nsp == 1 ? S.porder : nullptr);
 }
 
 // Persistent mode with several species: one list of units over every
@@ -1151,11 +1165,12 @@ hipError_t launch_exchange(const GridDev &g, const SlabArgs &sa, int *err, Unit 
                            int chunk, hipStream_t st) {
   const dim3 pg(g.npatch, sa.nsp);
   const int only_marked = units ? 0 : 1;  // the per-patch fused kernel did the departures
+  const int in_order = units && sa.nsp == 1 ? 1 : 0;  // porder made by the unit list
   if (g.dim == 2) {
-    hipLaunchKernelGGL(k_exch_out<2>, pg, dim3(kExchWg2), 0, st, g, sa, only_marked);
+    hipLaunchKernelGGL(k_exch_out<2>, pg, dim3(kExchWg2), 0, st, g, sa, only_marked, in_order);
     hipLaunchKernelGGL(k_exch_in<2>, pg, dim3(kExchInWg), 0, st, g, sa);
   } else {
-    hipLaunchKernelGGL(k_exch_out<3>, pg, dim3(kExchWg3), 0, st, g, sa, only_marked);
+    hipLaunchKernelGGL(k_exch_out<3>, pg, dim3(kExchWg3), 0, st, g, sa, only_marked, in_order);
     hipLaunchKernelGGL(k_exch_in<3>, pg, dim3(kExchInWg), 0, st, g, sa);
   }
   hipError_t e = hipGetLastError();
