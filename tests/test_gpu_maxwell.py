@@ -176,6 +176,36 @@ def _oracle_loop(wl, inp, cycles):
     return sps, Eo, Bo
 
 
+@pytest.mark.parametrize("mode", [0, 1])
+def test_resident_cycle_calls(mode):
+    """pic_cycle with PIC_FLAG_RESIDENT: one-step calls that continue in the
+    slabs (with the field step of every call), then pic_sync, follow the
+    oracle's loop to 1e-9."""
+    wl = I.custom(2, (64, 32), (8, 8), ppc=4, seed=950 + mode, sigma=0.2, field_amp=0.05)
+    inp = I.generate(wl)
+    say(f"case resident cycle mode={mode}")
+    cycles = 5
+    sps, Eo, Bo = _oracle_loop(wl, inp, cycles)
+    ctx = pic.Context(wl, check=True, mode=mode, chunk=512, resident=True)
+    sp = pic.upload(inp, "cuda:0", n_slabs=ctx.n_slabs)
+    E, B, J = pic.upload_fields(inp, "cuda:0")
+    ctx.bin(sp)
+    for k in (1, 1, 2, 1):
+        ctx.cycle(sp, E, B, J, k)
+    ctx.sync()
+    torch.cuda.synchronize()
+    ctx.check()
+    Eg, Bg = E.cpu().numpy(), B.cpu().numpy()
+    assert np.abs(Eg - Eo).max() <= 1e-9 * np.abs(Eo).max()
+    assert np.abs(Bg - Bo).max() <= 1e-9 * np.abs(Bo).max()
+    for s, o in zip(sp, sps):
+        assert np.array_equal(s.offset.cpu().numpy(), o.off)
+        gi, oi = np.argsort(s.ids.cpu().numpy()), np.argsort(o.id)
+        assert np.abs(s.xs.cpu().numpy()[:, gi] - o.x[:, oi]).max() <= 1e-9
+        assert np.abs(s.us.cpu().numpy()[:, gi] - o.u[:, oi]).max() <= 1e-9 * max(np.abs(o.u).max(), 1e-3)
+    ctx.close()
+
+
 CYCLE_CASES = [
     # workload args, cycles, mode, chunk, graph, capacity_factor
     ((2, (64, 32), (8, 8), 4, 1, 0.2), 6, 0, 0, False, None),
